@@ -1,0 +1,510 @@
+/*
+ * CPU oracle for closest-hit ray traversal of a triangle BVH.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the GPU product path links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the HIP library.
+ *
+ * What it computes (paper: "Decoupling Data Layouts from Bounding Volume
+ * Hierarchies", PLDI 2026):
+ *   - orc_mt_f32        Moller-Trumbore ray/triangle test in FP32, in the
+ *                       operation order of App. G (intersectsp_ray_tri_mt).
+ *   - orc_brute_*       closest hit by exhaustive search over all triangles:
+ *                       the plain definition of Fig. 4 / App. G closest_hit
+ *                       (minimum t over every triangle the MT test accepts),
+ *                       ties broken by lowest primitive id.
+ *   - orc_bvh_*         a median-split BVH (top-down, largest-extent axis,
+ *                       leaves of at most 4 triangles, the construction
+ *                       pattern of Sec. 6.3 "Collision Detection") with a
+ *                       scalar 64-entry stack traversal (Sec. 6.1) in three
+ *                       modes: closest, top-2 (runner-up tracking for the
+ *                       ambiguity mask) and any-hit.
+ *   - orc_grad_f64      closed-form FP64 gradient of L = sum(w_t t + w_u u +
+ *                       w_v v) with the hit primitive held fixed, from
+ *                       implicit differentiation of the hit-point identity
+ *                       o + t d = (1-u-v) p0 + u p1 + v p2 (App. G MT
+ *                       parameterisation: u weights p1, v weights p2).
+ *   - orc_tuv_f64       the same (t,u,v) at a fixed primitive in FP64, for
+ *                       finite differences.
+ *
+ * Parity status: every function here is pinned by the CPU test suite
+ * (hand-built rays with exactly representable answers, FP64 linear solves,
+ * brute force on small scenes, gradient identities and finite differences).
+ *
+ * Build: gcc -O3 -fopenmp -ffp-contract=off (no FMA contraction, so the FP32
+ * MT rounds each product and sum separately, exactly as written).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* ------------------------------------------------------------------------ */
+/* FP32 vector helpers, written out component by component.                 */
+/* ------------------------------------------------------------------------ */
+typedef struct { float x, y, z; } v3;
+
+static inline v3 v3_load(const float *p) { v3 r = { p[0], p[1], p[2] }; return r; }
+static inline v3 v3_sub(v3 a, v3 b) { v3 r = { a.x - b.x, a.y - b.y, a.z - b.z }; return r; }
+/* cross(a, b) in the textbook order. */
+static inline v3 v3_cross(v3 a, v3 b) {
+    v3 r;
+    r.x = a.y * b.z - a.z * b.y;
+    r.y = a.z * b.x - a.x * b.z;
+    r.z = a.x * b.y - a.y * b.x;
+    return r;
+}
+/* dot(a, b) = (a.x b.x + a.y b.y) + a.z b.z, left to right. */
+static inline float v3_dot(v3 a, v3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+
+static inline uint32_t f2u(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+static inline float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+
+/* ------------------------------------------------------------------------ */
+/* Moller-Trumbore, App. G intersectsp_ray_tri_mt.                          */
+/*   e1 = p0 - p1, e2 = p2 - p0, ng = e2 x e1                                */
+/*   c = p0 - o, r = c x d, D = ng . d; D == 0 is a miss                     */
+/*   U, V, T = (r.e2, r.e1, ng.c) with the sign bit of D xor-ed in           */
+/*   accept iff U >= 0, V >= 0, U + V <= |D|, |D|*0 < T <= |D|*tmax          */
+/*   t, u, v = (T, U, V) * (1/|D|)                                           */
+/* The sign fold of T is applied to its bits, as for U and V (the listing's  */
+/* cast order for T is garbled; the fold only makes sense on the bits).      */
+/* Returns 1 on a hit and writes t, u, v.                                    */
+/* ------------------------------------------------------------------------ */
+static inline int mt_f32(v3 o, v3 d, float tmax, v3 p0, v3 p1, v3 p2,
+                         float *t_out, float *u_out, float *v_out) {
+    v3 e1 = v3_sub(p0, p1);
+    v3 e2 = v3_sub(p2, p0);
+    v3 ng = v3_cross(e2, e1);
+    v3 c = v3_sub(p0, o);
+    v3 r = v3_cross(c, d);
+    float D = v3_dot(ng, d);
+    if (D == 0.0f) return 0;
+    float absD = fabsf(D);
+    uint32_t sgnD = f2u(D) & 0x80000000u;
+    float U = u2f(f2u(v3_dot(r, e2)) ^ sgnD);
+    float V = u2f(f2u(v3_dot(r, e1)) ^ sgnD);
+    if (!(U >= 0.0f && V >= 0.0f && U + V <= absD)) return 0;
+    float T = u2f(f2u(v3_dot(ng, c)) ^ sgnD);
+    if (!(absD * 0.0f < T && T <= absD * tmax)) return 0;
+    float inv = 1.0f / absD;
+    *t_out = T * inv;
+    *u_out = U * inv;
+    *v_out = V * inv;
+    return 1;
+}
+
+int orc_mt_f32(const float *o, const float *d, float tmax, const float *p0,
+               const float *p1, const float *p2, float *tuv) {
+    float t, u, v;
+    int hit = mt_f32(v3_load(o), v3_load(d), tmax, v3_load(p0), v3_load(p1),
+                     v3_load(p2), &t, &u, &v);
+    if (hit) { tuv[0] = t; tuv[1] = u; tuv[2] = v; }
+    return hit;
+}
+
+/* Ray record: o.xyz, tmin, d.xyz, tmax (8 floats).  tmin must be 0: the MT
+ * acceptance is the strict 0 < t of App. G. */
+#define RAY_STRIDE 8
+
+static inline void tri_fetch(const float *verts, const int32_t *tris, int64_t i,
+                             v3 *p0, v3 *p1, v3 *p2) {
+    *p0 = v3_load(verts + 3 * (int64_t)tris[3 * i + 0]);
+    *p1 = v3_load(verts + 3 * (int64_t)tris[3 * i + 1]);
+    *p2 = v3_load(verts + 3 * (int64_t)tris[3 * i + 2]);
+}
+
+/* (t, id) lexicographic order: lower t wins, then lower id. */
+static inline int lex_less(float ta, int32_t ia, float tb, int32_t ib) {
+    return ta < tb || (ta == tb && ia < ib);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Brute force (the plain definition).                                       */
+/* out_prim[n], out_tuv[n*3]; a miss is prim -1, t +inf, u = v = 0.         */
+/* ------------------------------------------------------------------------ */
+void orc_brute_closest(const float *verts, const int32_t *tris, int64_t ntris,
+                       const float *rays, int64_t nrays, int32_t *out_prim,
+                       float *out_tuv, int nthreads) {
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrays; r++) {
+        const float *ray = rays + RAY_STRIDE * r;
+        v3 o = v3_load(ray), d = v3_load(ray + 4);
+        float tmax = ray[7];
+        int32_t best = -1;
+        float bt = INFINITY, bu = 0.0f, bv = 0.0f;
+        for (int64_t i = 0; i < ntris; i++) {
+            v3 p0, p1, p2;
+            tri_fetch(verts, tris, i, &p0, &p1, &p2);
+            float t, u, v;
+            if (mt_f32(o, d, tmax, p0, p1, p2, &t, &u, &v) &&
+                lex_less(t, (int32_t)i, bt, best < 0 ? INT32_MAX : best)) {
+                best = (int32_t)i; bt = t; bu = u; bv = v;
+            }
+        }
+        out_prim[r] = best;
+        out_tuv[3 * r + 0] = bt;
+        out_tuv[3 * r + 1] = bu;
+        out_tuv[3 * r + 2] = bv;
+    }
+}
+
+/* Best and runner-up over distinct primitives, by brute force.
+ * out[n*2] prims (second = -1 if none), out_t[n*2]. */
+void orc_brute_top2(const float *verts, const int32_t *tris, int64_t ntris,
+                    const float *rays, int64_t nrays, int32_t *out_prim,
+                    float *out_t, int nthreads) {
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrays; r++) {
+        const float *ray = rays + RAY_STRIDE * r;
+        v3 o = v3_load(ray), d = v3_load(ray + 4);
+        float tmax = ray[7];
+        int32_t i1 = -1, i2 = -1;
+        float t1 = INFINITY, t2 = INFINITY;
+        for (int64_t i = 0; i < ntris; i++) {
+            v3 p0, p1, p2;
+            tri_fetch(verts, tris, i, &p0, &p1, &p2);
+            float t, u, v;
+            if (!mt_f32(o, d, tmax, p0, p1, p2, &t, &u, &v)) continue;
+            int32_t id = (int32_t)i;
+            if (lex_less(t, id, t1, i1 < 0 ? INT32_MAX : i1)) {
+                t2 = t1; i2 = i1; t1 = t; i1 = id;
+            } else if (lex_less(t, id, t2, i2 < 0 ? INT32_MAX : i2)) {
+                t2 = t; i2 = id;
+            }
+        }
+        out_prim[2 * r + 0] = i1; out_prim[2 * r + 1] = i2;
+        out_t[2 * r + 0] = t1;    out_t[2 * r + 1] = t2;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Median-split BVH.                                                         */
+/* ------------------------------------------------------------------------ */
+#define ORC_LEAF_MAX 4
+#define ORC_STACK 64
+
+typedef struct {
+    float lo[3], hi[3];
+    int32_t left, right;   /* child node indices; -1 for a leaf */
+    int32_t first, count;  /* leaf: range into perm[] */
+} orc_node;
+
+typedef struct {
+    orc_node *nodes;
+    int32_t nnodes, cap;
+    int32_t *perm;         /* triangle ids in leaf order */
+    int64_t ntris;
+    int32_t depth;
+    const float *verts;    /* borrowed */
+    const int32_t *tris;   /* borrowed */
+    float *centroid;       /* 3 per triangle */
+} orc_bvh;
+
+static int32_t new_node(orc_bvh *b) {
+    if (b->nnodes == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 1024;
+        b->nodes = (orc_node *)realloc(b->nodes, (size_t)b->cap * sizeof(orc_node));
+    }
+    return b->nnodes++;
+}
+
+/* Order key for the median split: centroid on the axis, then triangle id. */
+static inline int key_less(const orc_bvh *b, int axis, int32_t x, int32_t y) {
+    float cx = b->centroid[3 * (int64_t)x + axis], cy = b->centroid[3 * (int64_t)y + axis];
+    return cx < cy || (cx == cy && x < y);
+}
+
+/* Quickselect: after the call perm[lo..k) <= perm[k] <= perm(k..hi) in key order. */
+static void select_kth(orc_bvh *b, int axis, int32_t *a, int64_t lo, int64_t hi, int64_t k) {
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        /* median of three as pivot */
+        int32_t x = a[lo], y = a[mid], z = a[hi - 1], piv;
+        if (key_less(b, axis, x, y)) {
+            if (key_less(b, axis, y, z)) piv = y;
+            else if (key_less(b, axis, x, z)) piv = z;
+            else piv = x;
+        } else {
+            if (key_less(b, axis, x, z)) piv = x;
+            else if (key_less(b, axis, y, z)) piv = z;
+            else piv = y;
+        }
+        /* three-way partition: [lo,lt) < piv, [lt,gt) == piv, [gt,hi) > piv */
+        int64_t lt = lo, i = lo, gt = hi;
+        while (i < gt) {
+            if (key_less(b, axis, a[i], piv)) { int32_t t = a[lt]; a[lt] = a[i]; a[i] = t; lt++; i++; }
+            else if (key_less(b, axis, piv, a[i])) { gt--; int32_t t = a[gt]; a[gt] = a[i]; a[i] = t; }
+            else i++;
+        }
+        if (k < lt) hi = lt;
+        else if (k >= gt) lo = gt;
+        else return;
+    }
+}
+
+static void node_bounds(orc_bvh *b, orc_node *n, int64_t first, int64_t count) {
+    for (int a = 0; a < 3; a++) { n->lo[a] = INFINITY; n->hi[a] = -INFINITY; }
+    for (int64_t i = first; i < first + count; i++) {
+        int32_t t = b->perm[i];
+        for (int k = 0; k < 3; k++) {
+            const float *p = b->verts + 3 * (int64_t)b->tris[3 * (int64_t)t + k];
+            for (int a = 0; a < 3; a++) {
+                if (p[a] < n->lo[a]) n->lo[a] = p[a];
+                if (p[a] > n->hi[a]) n->hi[a] = p[a];
+            }
+        }
+    }
+}
+
+static int32_t build_rec(orc_bvh *b, int64_t first, int64_t count, int32_t depth) {
+    int32_t id = new_node(b);
+    if (depth > b->depth) b->depth = depth;
+    orc_node *n = &b->nodes[id];
+    node_bounds(b, n, first, count);
+    if (count <= ORC_LEAF_MAX) {
+        n->left = n->right = -1;
+        n->first = (int32_t)first;
+        n->count = (int32_t)count;
+        return id;
+    }
+    /* split axis: largest extent of the centroid bounds (lowest axis on ties) */
+    float clo[3] = { INFINITY, INFINITY, INFINITY }, chi[3] = { -INFINITY, -INFINITY, -INFINITY };
+    for (int64_t i = first; i < first + count; i++) {
+        const float *c = b->centroid + 3 * (int64_t)b->perm[i];
+        for (int a = 0; a < 3; a++) {
+            if (c[a] < clo[a]) clo[a] = c[a];
+            if (c[a] > chi[a]) chi[a] = c[a];
+        }
+    }
+    int axis = 0;
+    for (int a = 1; a < 3; a++)
+        if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+    int64_t half = count / 2;
+    select_kth(b, axis, b->perm, first, first + count, first + half);
+    int32_t l = build_rec(b, first, half, depth + 1);
+    int32_t r = build_rec(b, first + half, count - half, depth + 1);
+    n = &b->nodes[id]; /* nodes may have moved */
+    n->left = l; n->right = r; n->first = (int32_t)first; n->count = (int32_t)count;
+    return id;
+}
+
+void *orc_bvh_build(const float *verts, const int32_t *tris, int64_t ntris) {
+    orc_bvh *b = (orc_bvh *)calloc(1, sizeof(orc_bvh));
+    b->verts = verts; b->tris = tris; b->ntris = ntris;
+    b->perm = (int32_t *)malloc((size_t)(ntris > 0 ? ntris : 1) * sizeof(int32_t));
+    b->centroid = (float *)malloc((size_t)(ntris > 0 ? ntris : 1) * 3 * sizeof(float));
+    for (int64_t i = 0; i < ntris; i++) {
+        b->perm[i] = (int32_t)i;
+        for (int a = 0; a < 3; a++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s += verts[3 * (int64_t)tris[3 * i + k] + a];
+            b->centroid[3 * i + a] = (float)(s / 3.0);
+        }
+    }
+    if (ntris > 0) build_rec(b, 0, ntris, 1);
+    return b;
+}
+
+void orc_bvh_free(void *h) {
+    orc_bvh *b = (orc_bvh *)h;
+    if (!b) return;
+    free(b->nodes); free(b->perm); free(b->centroid); free(b);
+}
+
+int32_t orc_bvh_depth(void *h) { return ((orc_bvh *)h)->depth; }
+int32_t orc_bvh_nnodes(void *h) { return ((orc_bvh *)h)->nnodes; }
+
+/* Copies node records out for structural tests: per node 6 floats (lo, hi) and
+ * 4 ints (left, right, first, count); perm (leaf order) as well. */
+void orc_bvh_export(void *h, float *boxes, int32_t *links, int32_t *perm) {
+    orc_bvh *b = (orc_bvh *)h;
+    for (int32_t i = 0; i < b->nnodes; i++) {
+        for (int a = 0; a < 3; a++) { boxes[6 * i + a] = b->nodes[i].lo[a]; boxes[6 * i + 3 + a] = b->nodes[i].hi[a]; }
+        links[4 * i + 0] = b->nodes[i].left;  links[4 * i + 1] = b->nodes[i].right;
+        links[4 * i + 2] = b->nodes[i].first; links[4 * i + 3] = b->nodes[i].count;
+    }
+    memcpy(perm, b->perm, (size_t)b->ntris * sizeof(int32_t));
+}
+
+/* Conservative slab-test widening: the far distance is scaled by 1 + 2^-21,
+ * which exceeds 1 + 2*gamma_3 (gamma_3 = 3u/(1-3u), u = 2^-24), the bound on
+ * the relative rounding error of the three-operation slab distance (Ize 2013,
+ * "Robust BVH Ray Traversal").  Hence a box that the exact ray meets before
+ * the current best distance is never culled. */
+#define ORC_FAR_SCALE 1.000000476837158203125f
+
+/* App. G intersectsp_ray_aabb with the node-cull test folded in:
+ *   rdir = 1/d; near/far planes chosen by the sign bit of d;
+ *   t_near = max(0, max over axes), t_far = min(t_cur, min over axes);
+ *   visit iff t_near <= t_far * FAR_SCALE.
+ * fmaxf/fminf drop the NaN of 0*inf (a ray lying in a slab plane). */
+static inline int slab(v3 o, v3 rd, const int neg[3], const orc_node *n, float tcur) {
+    const float *ov = &o.x, *rv = &rd.x;
+    float tn[3], tf[3];
+    for (int a = 0; a < 3; a++) {
+        float nearp = neg[a] ? n->hi[a] : n->lo[a];
+        float farp = neg[a] ? n->lo[a] : n->hi[a];
+        tn[a] = (nearp - ov[a]) * rv[a];
+        tf[a] = (farp - ov[a]) * rv[a];
+    }
+    float t_near = fmaxf(0.0f, fmaxf(tn[0], fmaxf(tn[1], tn[2])));
+    float t_far = fminf(tcur, fminf(tf[0], fminf(tf[1], tf[2])));
+    return t_near <= t_far * ORC_FAR_SCALE;
+}
+
+enum { ORC_CLOSEST = 0, ORC_TOP2 = 1, ORC_ANY = 2 };
+
+/* Traces one ray.  Closest: (i1, t1, u1, v1).  Top-2 additionally (i2, t2),
+ * culling with the runner-up distance.  Any: the first accepted hit. */
+static void trace_one(const orc_bvh *b, const float *ray, int mode, int32_t *i1o,
+                      float *tuv1, int32_t *i2o, float *t2o) {
+    v3 o = v3_load(ray), d = v3_load(ray + 4);
+    float tmax = ray[7];
+    v3 rd = { 1.0f / d.x, 1.0f / d.y, 1.0f / d.z };
+    int neg[3] = { signbit(d.x) != 0, signbit(d.y) != 0, signbit(d.z) != 0 };
+    int32_t i1 = -1, i2 = -1;
+    float t1 = INFINITY, u1 = 0.0f, v1 = 0.0f, t2 = INFINITY;
+    int32_t stack[ORC_STACK];
+    int sp = 0;
+    if (b->nnodes > 0) stack[sp++] = 0;
+    while (sp > 0) {
+        const orc_node *n = &b->nodes[stack[--sp]];
+        float tcur = (mode == ORC_TOP2) ? t2 : (mode == ORC_CLOSEST ? t1 : tmax);
+        if (mode == ORC_CLOSEST && tmax < tcur) tcur = tmax;
+        if (mode == ORC_TOP2 && tmax < tcur) tcur = tmax;
+        if (!slab(o, rd, neg, n, tcur)) continue;
+        if (n->left < 0) {
+            for (int32_t k = n->first; k < n->first + n->count; k++) {
+                int32_t id = b->perm[k];
+                v3 p0, p1, p2;
+                tri_fetch(b->verts, b->tris, id, &p0, &p1, &p2);
+                float t, u, v;
+                if (!mt_f32(o, d, tmax, p0, p1, p2, &t, &u, &v)) continue;
+                if (mode == ORC_ANY) {
+                    *i1o = id; tuv1[0] = t; tuv1[1] = u; tuv1[2] = v;
+                    return;
+                }
+                if (lex_less(t, id, t1, i1 < 0 ? INT32_MAX : i1)) {
+                    t2 = t1; i2 = i1;
+                    t1 = t; u1 = u; v1 = v; i1 = id;
+                } else if (lex_less(t, id, t2, i2 < 0 ? INT32_MAX : i2)) {
+                    t2 = t; i2 = id;
+                }
+            }
+        } else {
+            /* both children pushed; the order cannot change the result */
+            stack[sp++] = n->right;
+            stack[sp++] = n->left;
+        }
+    }
+    *i1o = i1; tuv1[0] = t1; tuv1[1] = u1; tuv1[2] = v1;
+    if (i2o) { *i2o = i2; *t2o = t2; }
+}
+
+/* mode: 0 closest, 1 top-2, 2 any-hit.  out_prim2/out_t2 only for top-2 (may
+ * be NULL otherwise).  nthreads <= 0 keeps the OpenMP default. */
+void orc_bvh_trace(void *h, const float *rays, int64_t nrays, int mode,
+                   int32_t *out_prim, float *out_tuv, int32_t *out_prim2,
+                   float *out_t2, int nthreads) {
+    const orc_bvh *b = (const orc_bvh *)h;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrays; r++) {
+        int32_t i2 = -1;
+        float t2 = INFINITY;
+        trace_one(b, rays + RAY_STRIDE * r, mode, &out_prim[r], &out_tuv[3 * r],
+                  &i2, &t2);
+        if (mode == ORC_TOP2) { out_prim2[r] = i2; out_t2[r] = t2; }
+    }
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------ */
+/* FP64 hit parameters and gradient at a fixed primitive.                    */
+/* The hit point satisfies F = o + t d - p0 - u (p1 - p0) - v (p2 - p0) = 0. */
+/* dF/d(t,u,v) = J = [d | p0-p1 | p0-p2] (columns).  For L with gradient     */
+/* g = dL/d(t,u,v), solve J^T lam = g; then dL/dx = -lam^T dF/dx:            */
+/*   dL/do = -lam, dL/dd = -t lam, dL/dp0 = (1-u-v) lam,                     */
+/*   dL/dp1 = u lam, dL/dp2 = v lam.                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct { double x, y, z; } d3;
+static inline d3 d3_load(const float *p) { d3 r = { p[0], p[1], p[2] }; return r; }
+static inline d3 d3_sub(d3 a, d3 b) { d3 r = { a.x - b.x, a.y - b.y, a.z - b.z }; return r; }
+static inline d3 d3_cross(d3 a, d3 b) {
+    d3 r = { a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x };
+    return r;
+}
+static inline double d3_dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+/* Solves J (t,u,v) = p0 - o by Cramer's rule with J = [d | p0-p1 | p0-p2].
+ * Returns 0 when the system is singular (ray parallel to the plane). */
+static int tuv_f64(d3 o, d3 d, d3 p0, d3 p1, d3 p2, double *t, double *u, double *v) {
+    d3 a = d, b = d3_sub(p0, p1), c = d3_sub(p0, p2), rhs = d3_sub(p0, o);
+    double det = d3_dot(a, d3_cross(b, c));
+    if (det == 0.0) return 0;
+    *t = d3_dot(rhs, d3_cross(b, c)) / det;
+    *u = d3_dot(a, d3_cross(rhs, c)) / det;
+    *v = d3_dot(a, d3_cross(b, rhs)) / det;
+    return 1;
+}
+
+/* (t,u,v) in FP64 for rays[i] against prims[i] (prims[i] < 0 gives NaNs). */
+void orc_tuv_f64(const double *verts, const int32_t *tris, const double *rays,
+                 const int32_t *prims, int64_t n, double *out) {
+    for (int64_t i = 0; i < n; i++) {
+        out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = NAN;
+        if (prims[i] < 0) continue;
+        const int32_t *tr = tris + 3 * (int64_t)prims[i];
+        d3 p0 = { verts[3 * (int64_t)tr[0]], verts[3 * (int64_t)tr[0] + 1], verts[3 * (int64_t)tr[0] + 2] };
+        d3 p1 = { verts[3 * (int64_t)tr[1]], verts[3 * (int64_t)tr[1] + 1], verts[3 * (int64_t)tr[1] + 2] };
+        d3 p2 = { verts[3 * (int64_t)tr[2]], verts[3 * (int64_t)tr[2] + 1], verts[3 * (int64_t)tr[2] + 2] };
+        const double *ry = rays + 8 * i;
+        d3 o = { ry[0], ry[1], ry[2] }, d = { ry[4], ry[5], ry[6] };
+        tuv_f64(o, d, p0, p1, p2, &out[3 * i], &out[3 * i + 1], &out[3 * i + 2]);
+    }
+}
+
+/* Gradient of L = sum_i g_i . (t_i, u_i, v_i) at fixed prims.
+ * grad_verts (nverts*3) is accumulated (+=), grad_rays (n*6: dL/do, dL/dd) is
+ * overwritten, tuv (n*3) receives the FP64 hit parameters. */
+void orc_grad_f64(const float *verts, const int32_t *tris, const float *rays,
+                  const int32_t *prims, const float *grad_hits, int64_t n,
+                  double *grad_verts, double *grad_rays, double *tuv) {
+    for (int64_t i = 0; i < n; i++) {
+        double *gr = grad_rays + 6 * i;
+        for (int k = 0; k < 6; k++) gr[k] = 0.0;
+        tuv[3 * i] = tuv[3 * i + 1] = tuv[3 * i + 2] = NAN;
+        if (prims[i] < 0) continue;
+        const int32_t *tr = tris + 3 * (int64_t)prims[i];
+        d3 p0 = d3_load(verts + 3 * (int64_t)tr[0]);
+        d3 p1 = d3_load(verts + 3 * (int64_t)tr[1]);
+        d3 p2 = d3_load(verts + 3 * (int64_t)tr[2]);
+        const float *ry = rays + RAY_STRIDE * i;
+        d3 o = d3_load(ry), d = d3_load(ry + 4);
+        double t, u, v;
+        if (!tuv_f64(o, d, p0, p1, p2, &t, &u, &v)) continue;
+        tuv[3 * i] = t; tuv[3 * i + 1] = u; tuv[3 * i + 2] = v;
+        /* J^T lam = g: rows of J^T are a = d, b = p0-p1, c = p0-p2.
+         * lam = (g_t (b x c) + g_u (c x a) + g_v (a x b)) / (a . (b x c)). */
+        d3 a = d, b = d3_sub(p0, p1), c = d3_sub(p0, p2);
+        d3 bc = d3_cross(b, c), ca = d3_cross(c, a), ab = d3_cross(a, b);
+        double det = d3_dot(a, bc);
+        double gt = grad_hits[3 * i], gu = grad_hits[3 * i + 1], gv = grad_hits[3 * i + 2];
+        d3 lam = { (gt * bc.x + gu * ca.x + gv * ab.x) / det,
+                   (gt * bc.y + gu * ca.y + gv * ab.y) / det,
+                   (gt * bc.z + gu * ca.z + gv * ab.z) / det };
+        gr[0] = -lam.x; gr[1] = -lam.y; gr[2] = -lam.z;
+        gr[3] = -t * lam.x; gr[4] = -t * lam.y; gr[5] = -t * lam.z;
+        double w[3] = { 1.0 - u - v, u, v };
+        for (int k = 0; k < 3; k++) {
+            double *gv3 = grad_verts + 3 * (int64_t)tr[k];
+            gv3[0] += w[k] * lam.x; gv3[1] += w[k] * lam.y; gv3[2] += w[k] * lam.z;
+        }
+    }
+}
