@@ -1,0 +1,271 @@
+/*
+ * bvh.h - C ABI of the MI355X (gfx950) closest-hit BVH library.
+ *
+ * The library builds a bounding volume hierarchy over an indexed triangle
+ * mesh on the GPU and traces rays through it.  The node layout is chosen at
+ * build time and is independent of the traversal code: one traversal routine
+ * is instantiated per layout, the separation of logical tree and physical
+ * layout argued in Sec. 3-4 of "Decoupling Data Layouts from Bounding Volume
+ * Hierarchies" (PLDI 2026).
+ *
+ * Conventions shared by every call
+ *   - Pointers named "device" are device (HBM) addresses on the current HIP
+ *     device; pointers named "host" are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Calls that take a stream are stream-ordered and asynchronous: they
+ *     enqueue work and return; buffers must stay valid until the stream has
+ *     reached that point.  bvh_build is the exception: it synchronises
+ *     `stream` before it returns.
+ *   - Every call returns BVH_OK (0) or a negative error code and never
+ *     aborts.  bvh_last_error() gives a message for the calling thread's
+ *     most recent failure.  Arguments are validated before any work is
+ *     enqueued; a call that fails validation enqueues nothing.
+ *   - The caller owns every buffer it passes in.  A handle owns only what it
+ *     allocated itself (nodes, leaf triangles) and frees it in bvh_destroy.
+ *   - All records are little-endian and naturally aligned.
+ */
+#ifndef BVH_H
+#define BVH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define BVH_OK 0
+#define BVH_EINVAL (-1)       /* bad argument (null pointer, size, enum, index) */
+#define BVH_ENOMEM (-2)       /* a device allocation failed */
+#define BVH_EHIP (-3)         /* a HIP runtime call failed */
+#define BVH_ENODEV (-4)       /* no HIP device */
+#define BVH_EUNSUPPORTED (-5) /* valid input beyond a documented limit */
+
+/* ---- enums -------------------------------------------------------------- */
+/* Node layouts (record formats below). */
+#define BVH_LAYOUT_AABB2 0    /* binary, node stores its own f32 box, 32 B */
+#define BVH_LAYOUT_BVH4 1     /* 4-wide, f32 child boxes in SoA, 128 B */
+#define BVH_LAYOUT_BVH8_Q8 2  /* 8-wide, u8 child boxes in the parent frame, 128 B */
+#define BVH_LAYOUT_BVH8_Q16 3 /* 8-wide, u16 child boxes in the parent frame, 160 B */
+#define BVH_NUM_LAYOUTS 4
+
+/* Leaf storage. */
+#define BVH_LEAF_COMPACT 0 /* triangles copied into leaf order (bvh_tri records) */
+#define BVH_LEAF_INDEXED 1 /* leaf order holds primitive ids; vertices gathered */
+
+/* Trace modes. */
+#define BVH_TRACE_CLOSEST 0 /* nearest hit, ties to the lowest primitive id */
+#define BVH_TRACE_ANY 1     /* any hit with t <= tmax (occlusion) */
+
+/* Buffers readable with bvh_read_buffer. */
+#define BVH_BUF_NODES 0
+#define BVH_BUF_LEAF 1 /* COMPACT: bvh_tri[n_tris]; INDEXED: int32 prim id[n_tris] */
+
+/* ---- records ------------------------------------------------------------ */
+/* A ray: o + t d for tmin < t <= tmax.  tmin must be 0 (the intersection
+ * test accepts 0 < t, App. G).  tmax = +inf means unbounded.  d need not be
+ * unit length; t is measured in units of |d|. */
+typedef struct bvh_ray {
+    float o[3];
+    float tmin;
+    float d[3];
+    float tmax;
+} bvh_ray; /* 32 B */
+
+/* A hit: the hit point is (1-u-v) p0 + u p1 + v p2 = o + t d (App. G's
+ * barycentrics b0 = 1-u-v, b1 = u, b2 = v).  A miss is {-1, +inf, 0, 0}. */
+typedef struct bvh_hit {
+    int32_t prim_id;
+    float t, u, v;
+} bvh_hit; /* 16 B */
+
+/* Build options; a zero field selects the default. */
+typedef struct bvh_build_opts {
+    int32_t leaf_size;   /* max triangles per leaf, 1..16 (default 4) */
+    int32_t leaf_mode;   /* BVH_LEAF_COMPACT (default) or BVH_LEAF_INDEXED */
+    int32_t reserved[6]; /* must be zero */
+} bvh_build_opts;
+
+typedef struct bvh_stats {
+    int32_t layout, leaf_mode, arity, leaf_size;
+    int64_t n_tris;            /* triangles in the scene */
+    int64_t n_nodes;           /* node records */
+    int64_t n_leaves;          /* leaves (each 1..leaf_size triangles) */
+    int64_t node_bytes;        /* size of one node record */
+    int64_t nodes_buffer_bytes;
+    int64_t leaf_buffer_bytes; /* bvh_tri array or prim-id array */
+    int64_t extra_bytes;       /* INDEXED: the handle's copies of verts and tris */
+    int32_t depth;             /* nodes on the longest root-to-leaf path */
+    int32_t max_stack;         /* worst-case traversal stack entries */
+    float scene_lo[3], scene_hi[3];
+} bvh_stats;
+
+/* Compacted leaf triangle (BVH_LEAF_COMPACT), 48 B, in leaf order. */
+typedef struct bvh_tri {
+    float p0[3], p1[3], p2[3];
+    int32_t prim_id; /* index of the triangle in the caller's `tris` */
+    int32_t pad[2];
+} bvh_tri;
+
+/*
+ * Node records.  Node 0 is the root.
+ *
+ * BVH_LAYOUT_AABB2 (after the PBRTv4 LinearBVH node of Fig. 5): nodes in
+ * preorder; the left child of interior node I is I+1 and the right child is
+ * I + offset.  meta bits 0..15 = number of triangles (0 for an interior
+ * node), bits 16..17 = split axis of an interior node (x, y, z = 0, 1, 2: the
+ * left subtree lies on the low side).  A leaf's triangles are leaf-order
+ * entries offset .. offset+n-1.
+ */
+typedef struct bvh_node_aabb2 {
+    float lo[3], hi[3];
+    uint32_t offset;
+    uint32_t meta;
+} bvh_node_aabb2; /* 32 B */
+
+/*
+ * Wide layouts (BVH4, BVH8_Q8, BVH8_Q16) store the boxes of the children in
+ * the parent, structure-of-arrays across the children (App. D.2 uses the same
+ * child-box-in-parent form for bvh8-q8-ci).  Child slots 0..nchild-1 are
+ * valid; the rest hold an empty box and ref 0xFFFFFFFF.
+ *
+ * Child reference (u32, tagged as in App. D.2's compressed index):
+ *   bit 0 = 1: interior child, node index = ref >> 1.
+ *   bit 0 = 0: leaf, nprims - 1 = bits 1..4 (1..16 triangles),
+ *              first leaf-order triangle = bits 5..31 (so at most 2^27 - 1
+ *              triangles per scene).
+ *
+ * Quantised boxes (after App. D.2, but with a rounding rule that makes the
+ * dequantised box always contain the exact child box): the dequantised
+ * plane value is fmaf((float)q, scale[a], origin[a]) (one correctly rounded
+ * fused multiply-add), where origin is the exact lower corner of the node's
+ * box and q lies in 0..255 (Q8) or 0..65535 (Q16).  The builder picks the
+ * largest lower and smallest upper q whose dequantised planes still
+ * enclose the child.  An axis of zero extent has scale 0.
+ */
+typedef struct bvh_node_bvh4 {
+    float lo_x[4], lo_y[4], lo_z[4];
+    float hi_x[4], hi_y[4], hi_z[4];
+    uint32_t child[4];
+    uint32_t nchild;
+    uint32_t pad[3];
+} bvh_node_bvh4; /* 128 B */
+
+typedef struct bvh_node_bvh8_q8 {
+    float origin[3];
+    float scale[3];
+    uint8_t qlo_x[8], qlo_y[8], qlo_z[8];
+    uint8_t qhi_x[8], qhi_y[8], qhi_z[8];
+    uint32_t child[8];
+    uint32_t nchild;
+    uint32_t pad[5];
+} bvh_node_bvh8_q8; /* 128 B */
+
+typedef struct bvh_node_bvh8_q16 {
+    float origin[3];
+    float scale[3];
+    uint16_t qlo_x[8], qlo_y[8], qlo_z[8];
+    uint16_t qhi_x[8], qhi_y[8], qhi_z[8];
+    uint32_t child[8];
+    uint32_t nchild;
+    uint32_t pad;
+} bvh_node_bvh8_q16; /* 160 B */
+
+typedef struct bvh_handle_s *bvh_handle_t;
+
+/* ---- calls -------------------------------------------------------------- */
+
+/* Message for the calling thread's most recent failed call ("" if none).
+ * The string stays valid until the thread's next failing call. */
+const char *bvh_last_error(void);
+
+/* Library ABI version (this header: 1). */
+int32_t bvh_version(void);
+
+/*
+ * Builds a BVH over n_tris triangles (Sec. 5's two phases: a logical binary
+ * tree first, then its packing into the chosen layout).  The logical tree is
+ * a linear BVH: 63-bit Morton codes of the triangle box centres, a radix
+ * sort, the hierarchy of the sorted codes, a bottom-up box refit, then
+ * collapse of every subtree of at most leaf_size triangles into one leaf.
+ *   verts   device, n_verts x 3 float (x, y, z)
+ *   tris    device, n_tris x 3 int32 vertex indices, each in [0, n_verts)
+ *   layout  BVH_LAYOUT_*
+ *   opts    host, may be NULL for defaults
+ *   out     host; receives the handle on success, NULL on failure
+ * Errors: EINVAL for null pointers with a nonzero count, negative counts,
+ * an unknown layout or leaf mode, leaf_size outside 1..16, nonzero reserved
+ * fields, or (detected on the device, reported before returning) a vertex
+ * index outside [0, n_verts); EUNSUPPORTED for n_tris >= 2^27 or a tree whose
+ * traversal stack would exceed the kernel's limit; ENOMEM; EHIP; ENODEV.
+ * n_tris = 0 gives a valid empty handle whose traces all miss.
+ * Synchronises `stream` before returning.  verts and tris are not retained.
+ */
+int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                  int32_t layout, const bvh_build_opts *opts, void *stream, bvh_handle_t *out);
+
+/* Frees everything the handle owns (synchronises the device first).  NULL is
+ * accepted and ignored. */
+int32_t bvh_destroy(bvh_handle_t h);
+
+/* Sizes and shape of a built BVH.  out: host. */
+int32_t bvh_get_stats(bvh_handle_t h, bvh_stats *out);
+
+/* Copies up to `capacity` bytes of a handle buffer (BVH_BUF_*) to host
+ * memory (synchronous); *bytes_total receives the buffer's full size.
+ * host_dst may be NULL with capacity 0 to query the size only. */
+int32_t bvh_read_buffer(bvh_handle_t h, int32_t which, void *host_dst, int64_t capacity,
+                        int64_t *bytes_total);
+
+/*
+ * Traces n rays (closest_hit of Fig. 4 / App. G).  CLOSEST returns the hit
+ * with the smallest t, ties to the lowest primitive id; ANY returns some hit
+ * with t <= tmax, or a miss.  Ray-triangle test: Moller-Trumbore in the
+ * operation order of App. G (edges inclusive, 0 < t <= tmax).
+ *   rays  device, n records;  hits  device, n records (written)
+ * Errors: EINVAL for a null handle, n < 0, null pointers with n > 0, an
+ * unknown mode.  Rays with tmin != 0 are traced as if tmin were 0.
+ * Concurrent traces on one handle are allowed (the handle is read-only).
+ */
+int32_t bvh_trace(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit *hits, int32_t mode,
+                  void *stream);
+
+/*
+ * bvh_trace plus per-ray work counters, for measurement: counts[2i] = node
+ * records fetched, counts[2i+1] = triangles tested.  Same hits as bvh_trace.
+ *   counts  device, 2n uint32 (written)
+ */
+int32_t bvh_trace_counts(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit *hits,
+                         int32_t mode, uint32_t *counts, void *stream);
+
+/*
+ * Gradient of a loss L through closest-hit results with each ray's hit
+ * primitive held fixed.  For ray i with prim p = hits[i].prim_id >= 0 the
+ * Moller-Trumbore quantities of p are recomputed from verts/tris; with
+ * g = grad_hits[i] = dL/d(t,u,v) and J = [d | p0-p1 | p0-p2] the solution of
+ * J^T lam = g gives
+ *   dL/do = -lam, dL/dd = -t lam, dL/dp0 = (1-u-v) lam, dL/dp1 = u lam,
+ *   dL/dp2 = v lam
+ * (implicit differentiation of o + t d = (1-u-v) p0 + u p1 + v p2).  No
+ * traversal state is stored or needed.
+ *   verts       device, n_verts x 3 float;  tris  device, n_tris x 3 int32
+ *   rays, hits  device, n records (hits from bvh_trace CLOSEST)
+ *   grad_hits   device, n x 3 float (dL/dt, dL/du, dL/dv)
+ *   grad_verts  device, n_verts x 3 float, ACCUMULATED (+=) with float atomics,
+ *               so the summation order (last bits) varies between runs
+ *   grad_rays   device, n x 6 float (dL/do, dL/dd), OVERWRITTEN; a miss or
+ *               a skipped ray gets zeros
+ * Rays whose prim_id is outside [0, n_tris), whose triangle has a vertex
+ * index outside [0, n_verts), or whose system is singular contribute nothing.
+ * Errors: EINVAL for negative sizes or null pointers with a nonzero count.
+ */
+int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                           const bvh_ray *rays, int64_t n, const bvh_hit *hits,
+                           const float *grad_hits, float *grad_verts, float *grad_rays,
+                           void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BVH_H */

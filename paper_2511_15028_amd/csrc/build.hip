@@ -1,0 +1,983 @@
+// GPU construction of the BVH: a linear BVH (Morton order) as the logical
+// tree, then packing into one of the node layouts.  The paper fixes the
+// topology first and specialises only the physical packing to a layout
+// (Sec. 5, two-phase construction); the packing kernels here play the part of
+// its generated constructors (count pass, then fill pass, App. F).
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace bvhlib {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+
+struct Box {
+    float4 lo;  // w unused
+    float4 hi;  // w unused
+};
+
+struct BuildInfo {
+    float slo[3], shi[3];   // scene box
+    float clo[3], chi[3];   // box of the primitive-box centres
+    uint32_t err;           // bit 0: vertex index out of range; bit 1: non-finite extent
+    uint32_t n_leaves;      // leaves of the collapsed binary tree
+    uint32_t max_depth;     // nodes on the longest root-to-leaf path
+    uint32_t max_stack;     // worst-case traversal stack entries
+    uint32_t next_count;    // wide packing: size of the next frontier
+    uint32_t pad[3];
+};
+
+inline unsigned grid_for(uint64_t n, int per_block = kBlock) {
+    return (unsigned)((n + per_block - 1) / per_block);
+}
+
+// ---------------------------------------------------------------------------
+// Wave / block reductions and scans (wave64)
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over the block; *total = block sum.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t *wsum) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; i++) {
+        uint32_t s = wsum[i];
+        off += (i < w) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__device__ inline float wave_min(float v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ inline float wave_max(float v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of uint32 arrays: per-tile sums, a single-block scan of the
+// tile sums, then per-tile scans.  Works in place.
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, uint32_t n,
+                                                        uint32_t *tile_sums) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++)
+        if (base + k < n) s += in[base + k];
+    uint32_t tot;
+    block_excl_scan(s, &tot, wsum);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *tile_sums, uint32_t ntiles,
+                                                       uint32_t *total_out) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < ntiles; c += kBlock) {
+        const uint32_t i = c + threadIdx.x;
+        uint32_t v = i < ntiles ? tile_sums[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, &tot, wsum);
+        if (i < ntiles) tile_sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_final(const uint32_t *in, uint32_t *out,
+                                                       uint32_t n, const uint32_t *tile_sums) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, &tot, wsum) + tile_sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// Exclusive scan of n values; total (device) receives the sum if non-null.
+// tile_sums must hold ceil(n / kScanTile) entries.
+void scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tile_sums,
+              uint32_t *total, hipStream_t s) {
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles > 0) k_scan_reduce<<<ntiles, kBlock, 0, s>>>(in, n, tile_sums);
+    k_scan_tiles<<<1, kBlock, 0, s>>>(tile_sums, ntiles, total);
+    if (ntiles > 0) k_scan_final<<<ntiles, kBlock, 0, s>>>(in, out, n, tile_sums);
+}
+
+// ---------------------------------------------------------------------------
+// a1: triangle boxes, scene box and centre box
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_prim_bounds(const float *verts, int64_t n_verts,
+                                                        const int32_t *tris, uint32_t n,
+                                                        Box *pbox, float *partial,
+                                                        BuildInfo *info) {
+    __shared__ float red[12][kBlock / kWave];
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float c[3] = {INFINITY, INFINITY, INFINITY}, cm[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (i < n) {
+        int32_t idx[3] = {tris[3 * (size_t)i], tris[3 * (size_t)i + 1], tris[3 * (size_t)i + 2]};
+        bool ok = true;
+        for (int k = 0; k < 3; k++) ok = ok && idx[k] >= 0 && (int64_t)idx[k] < n_verts;
+        if (!ok) {
+            atomicOr(&info->err, 1u);
+            for (int a = 0; a < 3; a++) lo[a] = hi[a] = 0.0f;
+        } else {
+            for (int k = 0; k < 3; k++) {
+                const float *p = verts + 3 * (size_t)idx[k];
+                for (int a = 0; a < 3; a++) {
+                    lo[a] = fminf(lo[a], p[a]);
+                    hi[a] = fmaxf(hi[a], p[a]);
+                }
+            }
+        }
+        Box b;
+        b.lo = make_float4(lo[0], lo[1], lo[2], 0.0f);
+        b.hi = make_float4(hi[0], hi[1], hi[2], 0.0f);
+        pbox[i] = b;
+        for (int a = 0; a < 3; a++) c[a] = cm[a] = 0.5f * lo[a] + 0.5f * hi[a];
+    }
+    float v[12] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], c[0], c[1], c[2], cm[0], cm[1], cm[2]};
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int k = 0; k < 12; k++) {
+        bool is_min = (k < 3) || (k >= 6 && k < 9);
+        float r = is_min ? wave_min(v[k]) : wave_max(v[k]);
+        if (lane == 0) red[k][w] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int k = threadIdx.x;
+        bool is_min = (k < 3) || (k >= 6 && k < 9);
+        float r = red[k][0];
+        for (int j = 1; j < kBlock / kWave; j++) r = is_min ? fminf(r, red[k][j]) : fmaxf(r, red[k][j]);
+        partial[12 * (size_t)blockIdx.x + k] = r;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bounds_final(const float *partial, uint32_t nparts,
+                                                         BuildInfo *info) {
+    __shared__ float red[12][kBlock / kWave];
+    float v[12];
+    for (int k = 0; k < 12; k++) {
+        bool is_min = (k < 3) || (k >= 6 && k < 9);
+        v[k] = is_min ? INFINITY : -INFINITY;
+    }
+    for (uint32_t p = threadIdx.x; p < nparts; p += kBlock)
+        for (int k = 0; k < 12; k++) {
+            bool is_min = (k < 3) || (k >= 6 && k < 9);
+            float x = partial[12 * (size_t)p + k];
+            v[k] = is_min ? fminf(v[k], x) : fmaxf(v[k], x);
+        }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int k = 0; k < 12; k++) {
+        bool is_min = (k < 3) || (k >= 6 && k < 9);
+        float r = is_min ? wave_min(v[k]) : wave_max(v[k]);
+        if (lane == 0) red[k][w] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int k = threadIdx.x;
+        bool is_min = (k < 3) || (k >= 6 && k < 9);
+        float r = red[k][0];
+        for (int j = 1; j < kBlock / kWave; j++) r = is_min ? fminf(r, red[k][j]) : fmaxf(r, red[k][j]);
+        if (k < 3) info->slo[k] = r;
+        else if (k < 6) info->shi[k - 3] = r;
+        else if (k < 9) info->clo[k - 6] = r;
+        else info->chi[k - 9] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a2: 63-bit Morton codes (21 bits per axis) of the box centres
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t quant21(float x, float lo, float inv_ext) {
+    float u = (x - lo) * inv_ext * 2097152.0f;
+    u = fminf(fmaxf(u, 0.0f), 2097151.0f);
+    return (uint32_t)u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton(const Box *pbox, uint32_t n,
+                                                   const BuildInfo *info, uint64_t *keys,
+                                                   uint32_t *vals) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Box b = pbox[i];
+    float c[3] = {0.5f * b.lo.x + 0.5f * b.hi.x, 0.5f * b.lo.y + 0.5f * b.hi.y,
+                  0.5f * b.lo.z + 0.5f * b.hi.z};
+    uint32_t q[3];
+    for (int a = 0; a < 3; a++) {
+        float ext = info->chi[a] - info->clo[a];
+        float inv = ext > 0.0f ? 1.0f / ext : 0.0f;
+        q[a] = quant21(c[a], info->clo[a], inv);
+    }
+    // bit b of x, y, z goes to key bit 3b+2, 3b+1, 3b
+    uint64_t key = 0;
+    for (int bit = 0; bit < 21; bit++) {
+        key |= (uint64_t)((q[0] >> bit) & 1u) << (3 * bit + 2);
+        key |= (uint64_t)((q[1] >> bit) & 1u) << (3 * bit + 1);
+        key |= (uint64_t)((q[2] >> bit) & 1u) << (3 * bit);
+    }
+    keys[i] = key;
+    vals[i] = i;
+}
+
+// ---------------------------------------------------------------------------
+// a3: stable LSD radix sort of (u64 key, u32 value), 8 bits per pass.
+// Per pass: per-tile digit histograms, one exclusive scan over the
+// digit-major histogram matrix, then a stable scatter that ranks equal
+// digits inside a tile with wave ballots.
+// ---------------------------------------------------------------------------
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kBlock * kSortItems;
+constexpr int kRadix = 256;
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t *keys, uint32_t n, int shift,
+                                                       uint32_t *hist, uint32_t ntiles) {
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kSortTile;
+    for (int k = 0; k < kSortItems; k++) {
+        uint32_t i = base + k * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *keys_in,
+                                                          const uint32_t *vals_in,
+                                                          uint64_t *keys_out, uint32_t *vals_out,
+                                                          uint32_t n, int shift,
+                                                          const uint32_t *offsets,
+                                                          uint32_t ntiles) {
+    __shared__ uint32_t run[kRadix];
+    __shared__ uint32_t wcnt[kBlock / kWave][kRadix];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    run[threadIdx.x] = offsets[(size_t)threadIdx.x * ntiles + blockIdx.x];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const uint32_t base = blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        const uint32_t i = base + r * kBlock + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        uint32_t val = 0, d = 0;
+        if (valid) {
+            key = keys_in[i];
+            val = vals_in[i];
+            d = (uint32_t)(key >> shift) & (kRadix - 1);
+        }
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        for (int k = 0; k < kBlock / kWave; k++) wcnt[k][threadIdx.x] = 0;
+        __syncthreads();
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int k = 0; k < w; k++) pos += wcnt[k][d];
+            if (pos < n) {  // always true for a consistent histogram; guards the write
+                keys_out[pos] = key;
+                vals_out[pos] = val;
+            }
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int k = 0; k < kBlock / kWave; k++) add += wcnt[k][threadIdx.x];
+        run[threadIdx.x] += add;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a4: hierarchy of the sorted codes (Karras 2012).  Internal node i covers a
+// key range [first, last] and splits it at the highest differing bit; equal
+// keys are separated by their positions.  Node ids: internal i -> i, sorted
+// leaf j -> (n - 1) + j; the root is id 0.
+// ---------------------------------------------------------------------------
+__device__ inline int common_prefix(const uint64_t *keys, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    const uint64_t a = keys[i], b = keys[j];
+    if (a != b) return __clzll((long long)(a ^ b));
+    return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+
+__global__ __launch_bounds__(kBlock) void k_karras(const uint64_t *keys, int n, int32_t *ileft,
+                                                   int32_t *iright, uint32_t *ifirst,
+                                                   uint32_t *icount, uint8_t *iaxis,
+                                                   int32_t *parent) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (common_prefix(keys, n, i, i + 1) - common_prefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = common_prefix(keys, n, i, i - d);
+    int lmax = 2;
+    while (common_prefix(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int l = 0;
+    for (int t = lmax / 2; t >= 1; t /= 2)
+        if (common_prefix(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = common_prefix(keys, n, i, j);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (common_prefix(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int first = min(i, j), last = max(i, j);
+    const int lc = (first == gamma) ? (n - 1) + gamma : gamma;
+    const int rc = (last == gamma + 1) ? (n - 1) + gamma + 1 : gamma + 1;
+    ileft[i] = lc;
+    iright[i] = rc;
+    parent[lc] = i;
+    parent[rc] = i;
+    ifirst[i] = (uint32_t)first;
+    icount[i] = (uint32_t)(last - first + 1);
+    // split axis: key bit 63 - dnode (bit 3b+2 is x, 3b+1 is y, 3b is z)
+    uint8_t axis = 0;
+    if (dnode < 64) {
+        const int p = 63 - dnode;
+        axis = (p % 3 == 2) ? 0 : (p % 3 == 1 ? 1 : 2);
+    }
+    iaxis[i] = axis;
+    if (i == 0) parent[0] = -1;
+}
+
+// ---------------------------------------------------------------------------
+// a5: bottom-up box refit.  Each leaf walks towards the root; the second
+// child to arrive at a node (agent-scope acquire/release counter) forms the
+// union of both child boxes and continues.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_refit(const Box *pbox, const uint32_t *perm, int n,
+                                                  const int32_t *ileft, const int32_t *iright,
+                                                  const int32_t *parent, uint32_t *flags,
+                                                  Box *nbox) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    int x = (n - 1) + j;
+    nbox[x] = pbox[perm[j]];
+    for (int guard = 0; x != 0 && guard < 4 * 64 + 64; guard++) {
+        const int p = parent[x];
+        if (p < 0 || p >= n - 1) return;  // malformed hierarchy: stop rather than fault
+        const uint32_t old =
+            __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        const Box a = nbox[ileft[p]], b = nbox[iright[p]];
+        Box u;
+        u.lo = make_float4(fminf(a.lo.x, b.lo.x), fminf(a.lo.y, b.lo.y), fminf(a.lo.z, b.lo.z), 0.0f);
+        u.hi = make_float4(fmaxf(a.hi.x, b.hi.x), fmaxf(a.hi.y, b.hi.y), fmaxf(a.hi.z, b.hi.z), 0.0f);
+        nbox[p] = u;
+        x = p;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a6: collapse.  A node is kept ("alive") if it is the root or its parent
+// holds more than L triangles; an alive node with at most L triangles is a
+// leaf covering its sorted range.  mark[first] = 1 for every leaf.
+// ---------------------------------------------------------------------------
+struct TreeView {
+    int n;                 // triangles
+    int leaf_size;
+    const int32_t *ileft, *iright, *parent;
+    const uint32_t *ifirst, *icount;
+    const uint8_t *iaxis;
+    const Box *nbox;
+    __device__ bool is_prim(int x) const { return x >= n - 1; }
+    __device__ uint32_t count(int x) const { return is_prim(x) ? 1u : icount[x]; }
+    __device__ uint32_t first(int x) const { return is_prim(x) ? (uint32_t)(x - (n - 1)) : ifirst[x]; }
+    __device__ bool alive(int x) const {
+        if (x == 0) return true;
+        const int p = parent[x];
+        return p >= 0 && p < n - 1 && icount[p] > (uint32_t)leaf_size;
+    }
+    __device__ bool is_leaf(int x) const { return count(x) <= (uint32_t)leaf_size; }
+};
+
+__global__ __launch_bounds__(kBlock) void k_mark_leaves(TreeView tv, uint32_t *mark) {
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    if (x >= 2 * tv.n - 1) return;
+    if (tv.alive(x) && tv.is_leaf(x)) mark[tv.first(x)] = 1u;
+}
+
+// ---------------------------------------------------------------------------
+// a7 (AABB2): preorder packing.  With leaf_before(x) = number of leaves that
+// precede x's range (exclusive scan of mark) and lturns(x) = number of
+// left-child steps on the root-to-x path, the preorder index of x in the
+// collapsed tree is lturns(x) + 2 * leaf_before(x), and the right child of
+// interior x sits 2 * (leaf_before(right) - leaf_before(x)) after x.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_emit_aabb2(TreeView tv, const uint32_t *lbefore,
+                                                       bvh_node_aabb2 *nodes, uint32_t n_nodes,
+                                                       BuildInfo *info) {
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    if (x >= 2 * tv.n - 1 || !tv.alive(x)) return;
+    uint32_t lturns = 0, depth = 1;
+    for (int y = x; y != 0; depth++) {
+        const int p = tv.parent[y];
+        if (p < 0 || p >= tv.n - 1 || depth >= 1024) {
+            atomicOr(&info->err, 4u);
+            return;
+        }
+        lturns += (tv.ileft[p] == y) ? 1u : 0u;
+        y = p;
+    }
+    const uint32_t f = tv.first(x);
+    const uint32_t idx = lturns + 2u * lbefore[f];
+    if (idx >= n_nodes) {
+        atomicOr(&info->err, 4u);
+        return;
+    }
+    bvh_node_aabb2 nd;
+    const Box b = tv.nbox[x];
+    nd.lo[0] = b.lo.x; nd.lo[1] = b.lo.y; nd.lo[2] = b.lo.z;
+    nd.hi[0] = b.hi.x; nd.hi[1] = b.hi.y; nd.hi[2] = b.hi.z;
+    if (tv.is_leaf(x)) {
+        nd.offset = f;
+        nd.meta = tv.count(x);
+    } else {
+        const int r = tv.iright[x];
+        nd.offset = 2u * (lbefore[tv.first(r)] - lbefore[f]);
+        nd.meta = (uint32_t)tv.iaxis[x] << 16;
+    }
+    nodes[idx] = nd;
+    atomicMax(&info->max_depth, depth);
+    if (tv.is_leaf(x)) atomicMax(&info->max_stack, depth - 1);
+}
+
+// ---------------------------------------------------------------------------
+// a7 (wide): top-down, one frontier level per step.  Each frontier item is an
+// alive interior binary node that becomes a wide node: its child list starts
+// as its two children and repeatedly replaces the interior candidate of
+// largest surface area by that candidate's two children, up to K children.
+// Pass A forms the lists and counts interior children; an exclusive scan
+// places them; pass B writes the node and the next frontier.
+// ---------------------------------------------------------------------------
+__device__ inline float surface_area(const Box &b) {
+    const float dx = b.hi.x - b.lo.x, dy = b.hi.y - b.lo.y, dz = b.hi.z - b.lo.z;
+    return dx * dy + dy * dz + dz * dx;
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_wide_open(TreeView tv, uint32_t count,
+                                                      const int32_t *fr_node, int32_t *cand,
+                                                      uint32_t *ninterior) {
+    const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= count) return;
+    const int x = fr_node[f];
+    int c[K];
+    int nc;
+    if (tv.is_leaf(x)) {  // only for a root that is a single leaf
+        c[0] = x;
+        nc = 1;
+    } else {
+        c[0] = tv.ileft[x];
+        c[1] = tv.iright[x];
+        nc = 2;
+        while (nc < K) {
+            int best = -1;
+            float best_a = -1.0f;
+            for (int k = 0; k < nc; k++) {
+                if (tv.is_leaf(c[k])) continue;
+                const float a = surface_area(tv.nbox[c[k]]);
+                if (a > best_a) { best_a = a; best = k; }
+            }
+            if (best < 0) break;
+            const int y = c[best];
+            for (int k = nc; k > best + 1; k--) c[k] = c[k - 1];
+            c[best] = tv.ileft[y];
+            c[best + 1] = tv.iright[y];
+            nc++;
+        }
+    }
+    uint32_t ni = 0;
+    for (int k = 0; k < K; k++) {
+        const int v = k < nc ? c[k] : -1;
+        cand[(size_t)f * K + k] = v;
+        if (v >= 0 && !tv.is_leaf(v)) ni++;
+    }
+    ninterior[f] = ni;
+}
+
+// Quantisation of one axis of up to K child intervals to QMAX steps of the
+// parent interval [plo, phi].  Returns the scale; q values are chosen so that
+// fmaf(qlo, s, plo) <= clo and fmaf(qhi, s, plo) >= chi exactly.
+template <int K, int QMAX>
+__device__ inline float quantize_axis(float plo, float phi, const float *clo, const float *chi,
+                                      int nc, uint32_t *qlo, uint32_t *qhi, uint32_t *err) {
+    const float ext = phi - plo;
+    float s = 0.0f;
+    if (!(ext >= 0.0f) || !isfinite(ext)) {
+        atomicOr(err, 2u);
+    } else if (ext > 0.0f) {
+        s = ext / (float)QMAX;
+        for (int g = 0; g < 64 && fmaf((float)QMAX, s, plo) < phi; g++) s = nextafterf(s, INFINITY);
+    }
+    for (int k = 0; k < K; k++) {
+        uint32_t a = QMAX, b = 0;  // empty slot: lo above hi
+        if (k < nc) {
+            if (s == 0.0f) {
+                a = 0;
+                b = 0;
+            } else {
+                float fl = floorf((clo[k] - plo) / s);
+                fl = fminf(fmaxf(fl, 0.0f), (float)QMAX);
+                a = (uint32_t)fl;
+                while (a > 0 && fmaf((float)a, s, plo) > clo[k]) a--;
+                while (a < (uint32_t)QMAX && fmaf((float)(a + 1), s, plo) <= clo[k]) a++;
+                float fh = ceilf((chi[k] - plo) / s);
+                fh = fminf(fmaxf(fh, 0.0f), (float)QMAX);
+                b = (uint32_t)fh;
+                while (b < (uint32_t)QMAX && fmaf((float)b, s, plo) < chi[k]) b++;
+                while (b > 0 && fmaf((float)(b - 1), s, plo) >= chi[k]) b--;
+            }
+        }
+        qlo[k] = a;
+        qhi[k] = b;
+    }
+    return s;
+}
+
+template <int Layout>
+struct WideOut;
+
+template <>
+struct WideOut<BVH_LAYOUT_BVH4> {
+    static constexpr int K = 4;
+    __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
+                                 const uint32_t *ref, int nc, uint32_t *err) {
+        (void)pb;
+        (void)err;
+        bvh_node_bvh4 nd;
+        for (int k = 0; k < K; k++) {
+            const bool v = k < nc;
+            nd.lo_x[k] = v ? cb[k].lo.x : INFINITY;
+            nd.lo_y[k] = v ? cb[k].lo.y : INFINITY;
+            nd.lo_z[k] = v ? cb[k].lo.z : INFINITY;
+            nd.hi_x[k] = v ? cb[k].hi.x : -INFINITY;
+            nd.hi_y[k] = v ? cb[k].hi.y : -INFINITY;
+            nd.hi_z[k] = v ? cb[k].hi.z : -INFINITY;
+            nd.child[k] = v ? ref[k] : kRefEmpty;
+        }
+        nd.nchild = (uint32_t)nc;
+        nd.pad[0] = nd.pad[1] = nd.pad[2] = 0;
+        static_cast<bvh_node_bvh4 *>(nodes)[w] = nd;
+    }
+};
+
+template <typename NodeT, int QMAX, typename QT>
+__device__ inline void write_quantized(NodeT &nd, const Box &pb, const Box *cb, const uint32_t *ref,
+                                       int nc, uint32_t *err) {
+    constexpr int K = 8;
+    float clo[K], chi[K];
+    uint32_t qlo[K], qhi[K];
+    const float plo[3] = {pb.lo.x, pb.lo.y, pb.lo.z}, phi[3] = {pb.hi.x, pb.hi.y, pb.hi.z};
+    QT *dst_lo[3] = {nd.qlo_x, nd.qlo_y, nd.qlo_z};
+    QT *dst_hi[3] = {nd.qhi_x, nd.qhi_y, nd.qhi_z};
+    for (int a = 0; a < 3; a++) {
+        for (int k = 0; k < K; k++) {
+            const bool v = k < nc;
+            clo[k] = v ? (a == 0 ? cb[k].lo.x : a == 1 ? cb[k].lo.y : cb[k].lo.z) : 0.0f;
+            chi[k] = v ? (a == 0 ? cb[k].hi.x : a == 1 ? cb[k].hi.y : cb[k].hi.z) : 0.0f;
+        }
+        const float s = quantize_axis<K, QMAX>(plo[a], phi[a], clo, chi, nc, qlo, qhi, err);
+        nd.origin[a] = plo[a];
+        nd.scale[a] = s;
+        for (int k = 0; k < K; k++) {
+            dst_lo[a][k] = (QT)qlo[k];
+            dst_hi[a][k] = (QT)qhi[k];
+        }
+    }
+    for (int k = 0; k < K; k++) nd.child[k] = k < nc ? ref[k] : kRefEmpty;
+    nd.nchild = (uint32_t)nc;
+}
+
+template <>
+struct WideOut<BVH_LAYOUT_BVH8_Q8> {
+    static constexpr int K = 8;
+    __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
+                                 const uint32_t *ref, int nc, uint32_t *err) {
+        bvh_node_bvh8_q8 nd;
+        write_quantized<bvh_node_bvh8_q8, 255, uint8_t>(nd, pb, cb, ref, nc, err);
+        for (int k = 0; k < 5; k++) nd.pad[k] = 0;
+        static_cast<bvh_node_bvh8_q8 *>(nodes)[w] = nd;
+    }
+};
+
+template <>
+struct WideOut<BVH_LAYOUT_BVH8_Q16> {
+    static constexpr int K = 8;
+    __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
+                                 const uint32_t *ref, int nc, uint32_t *err) {
+        bvh_node_bvh8_q16 nd;
+        write_quantized<bvh_node_bvh8_q16, 65535, uint16_t>(nd, pb, cb, ref, nc, err);
+        nd.pad = 0;
+        static_cast<bvh_node_bvh8_q16 *>(nodes)[w] = nd;
+    }
+};
+
+template <int Layout>
+__global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base, uint32_t count,
+                                                      uint32_t cap, const int32_t *fr_node,
+                                                      const uint32_t *fr_aux, const int32_t *cand,
+                                                      const uint32_t *noff, void *nodes,
+                                                      int32_t *next_node, uint32_t *next_aux,
+                                                      BuildInfo *info) {
+    constexpr int K = WideOut<Layout>::K;
+    const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= count) return;
+    if (base + f >= cap || noff[f] + K > cap + K) {
+        atomicOr(&info->err, 4u);
+        return;
+    }
+    const int x = fr_node[f];
+    const uint32_t aux = fr_aux[f];  // bits 0..15 stack need so far, 16..31 depth
+    Box cb[K];
+    uint32_t ref[K];
+    int nc = 0;
+    uint32_t r = 0;
+    const uint32_t next_base = base + count;
+    for (int k = 0; k < K; k++) {
+        const int c = cand[(size_t)f * K + k];
+        if (c < 0) continue;
+        cb[nc] = tv.nbox[c];
+        if (tv.is_leaf(c)) {
+            ref[nc] = ref_leaf(tv.first(c), tv.count(c));
+        } else {
+            const uint32_t pos = noff[f] + r;
+            if (pos >= cap || next_base + pos >= cap) {
+                atomicOr(&info->err, 4u);
+                return;
+            }
+            ref[nc] = ref_interior(next_base + pos);
+            next_node[pos] = c;
+            r++;
+        }
+        nc++;
+    }
+    const uint32_t stack_need = (aux & 0xFFFFu) + (uint32_t)(nc - 1);
+    const uint32_t depth = (aux >> 16) + 1;
+    for (uint32_t k = 0; k < r; k++) next_aux[noff[f] + k] = (stack_need & 0xFFFFu) | (depth << 16);
+    WideOut<Layout>::write(nodes, base + f, tv.nbox[x], cb, ref, nc, &info->err);
+    atomicMax(&info->max_stack, stack_need);
+    atomicMax(&info->max_depth, depth + 1);  // + the leaf level below
+}
+
+// ---------------------------------------------------------------------------
+// Leaf data
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, const int32_t *tris,
+                                                         const uint32_t *perm, uint32_t n,
+                                                         bvh_tri *out) {
+    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t t = perm[j];
+    bvh_tri r;
+    for (int k = 0; k < 3; k++) {
+        const float *p = verts + 3 * (size_t)tris[3 * (size_t)t + k];
+        float *dst = k == 0 ? r.p0 : (k == 1 ? r.p1 : r.p2);
+        dst[0] = p[0];
+        dst[1] = p[1];
+        dst[2] = p[2];
+    }
+    r.prim_id = (int32_t)t;
+    r.pad[0] = r.pad[1] = 0;
+    out[j] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct DeviceTemps {
+    std::vector<void *> ptrs;
+    ~DeviceTemps() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    int32_t alloc(T **out, size_t count) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(BVH_ENOMEM, "hipMalloc(%zu bytes) failed: %s",
+                             std::max<size_t>(count, 1) * sizeof(T), hipGetErrorString(e));
+        }
+        ptrs.push_back(p);
+        *out = static_cast<T *>(p);
+        return BVH_OK;
+    }
+};
+
+int32_t check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(BVH_EHIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+    return BVH_OK;
+}
+
+template <int Layout>
+int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, BuildInfo *info_host,
+                  bvh_handle_s *h, DeviceTemps &tmp, hipStream_t s) {
+    constexpr int K = WideOut<Layout>::K;
+    const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
+    void *wnodes;
+    int32_t *fr_node[2], *cand;
+    uint32_t *fr_aux[2], *noff, *tile;
+    uint8_t *raw;
+    BVH_TRY(tmp.alloc(&raw, (size_t)cap * h->node_bytes));
+    wnodes = raw;
+    BVH_TRY(tmp.alloc(&fr_node[0], cap));
+    BVH_TRY(tmp.alloc(&fr_node[1], cap));
+    BVH_TRY(tmp.alloc(&fr_aux[0], cap));
+    BVH_TRY(tmp.alloc(&fr_aux[1], cap));
+    BVH_TRY(tmp.alloc(&cand, (size_t)cap * K));
+    BVH_TRY(tmp.alloc(&noff, cap));
+    BVH_TRY(tmp.alloc(&tile, (cap + kScanTile - 1) / kScanTile + 1));
+    const int32_t root = 0;
+    const uint32_t zero = 0;
+    BVH_HIP_TRY(hipMemcpyAsync(fr_node[0], &root, sizeof(root), hipMemcpyHostToDevice, s));
+    BVH_HIP_TRY(hipMemcpyAsync(fr_aux[0], &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    uint32_t base = 0, count = 1;
+    int cur = 0;
+    for (int level = 0; count > 0; level++) {
+        if (level > 4096) return set_error(BVH_EHIP, "wide packing did not terminate");
+        k_wide_open<K><<<grid_for(count), kBlock, 0, s>>>(tv, count, fr_node[cur], cand, noff);
+        scan_u32(noff, noff, count, tile, &info->next_count, s);
+        k_wide_emit<Layout><<<grid_for(count), kBlock, 0, s>>>(
+            tv, base, count, cap, fr_node[cur], fr_aux[cur], cand, noff, wnodes, fr_node[cur ^ 1],
+            fr_aux[cur ^ 1], info);
+        BVH_TRY(check_launch("wide packing"));
+        uint32_t next = 0;
+        BVH_HIP_TRY(hipMemcpyAsync(&next, &info->next_count, sizeof(next), hipMemcpyDeviceToHost, s));
+        BVH_HIP_TRY(hipStreamSynchronize(s));
+        base += count;
+        if (base + next > cap) return set_error(BVH_EHIP, "wide packing overflow");
+        count = next;
+        cur ^= 1;
+    }
+    h->n_nodes = base;
+    BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)base * h->node_bytes));
+    BVH_HIP_TRY(hipMemcpyAsync(h->nodes, wnodes, (size_t)base * h->node_bytes,
+                               hipMemcpyDeviceToDevice, s));
+    (void)info_host;
+    return BVH_OK;
+}
+
+int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                   bvh_handle_s *h, hipStream_t s) {
+    const int n = (int)n_tris;
+    const int L = h->leaf_size;
+    DeviceTemps tmp;
+    Box *pbox, *nbox;
+    float *partial;
+    BuildInfo *info;
+    uint64_t *keys[2];
+    uint32_t *vals[2], *hist, *tile, *ifirst, *icount, *flags, *mark;
+    int32_t *ileft, *iright, *parent;
+    uint8_t *iaxis;
+    const uint32_t nb = grid_for(n);
+    const uint32_t nsort = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    const uint32_t nhist = nsort * kRadix;
+    const uint32_t max_scan = std::max<uint32_t>(nhist, (uint32_t)n);
+    BVH_TRY(tmp.alloc(&pbox, n));
+    BVH_TRY(tmp.alloc(&partial, (size_t)nb * 12));
+    BVH_TRY(tmp.alloc(&info, 1));
+    BVH_TRY(tmp.alloc(&keys[0], n));
+    BVH_TRY(tmp.alloc(&keys[1], n));
+    BVH_TRY(tmp.alloc(&vals[0], n));
+    BVH_TRY(tmp.alloc(&vals[1], n));
+    BVH_TRY(tmp.alloc(&hist, nhist));
+    BVH_TRY(tmp.alloc(&tile, (max_scan + kScanTile - 1) / kScanTile + 1));
+    BVH_TRY(tmp.alloc(&ileft, n - 1));
+    BVH_TRY(tmp.alloc(&iright, n - 1));
+    BVH_TRY(tmp.alloc(&ifirst, n - 1));
+    BVH_TRY(tmp.alloc(&icount, n - 1));
+    BVH_TRY(tmp.alloc(&iaxis, n - 1));
+    BVH_TRY(tmp.alloc(&flags, n - 1));
+    BVH_TRY(tmp.alloc(&parent, 2 * (size_t)n - 1));
+    BVH_TRY(tmp.alloc(&nbox, 2 * (size_t)n - 1));
+    BVH_TRY(tmp.alloc(&mark, n));
+
+    BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
+    BVH_HIP_TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t) * std::max(n - 1, 1), s));
+    BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
+    BVH_HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), s));
+
+    // a1, a2
+    k_prim_bounds<<<nb, kBlock, 0, s>>>(verts, n_verts, tris, n, pbox, partial, info);
+    k_bounds_final<<<1, kBlock, 0, s>>>(partial, nb, info);
+    k_morton<<<nb, kBlock, 0, s>>>(pbox, n, info, keys[0], vals[0]);
+    BVH_TRY(check_launch("bounds/morton"));
+    // a3: 8 passes of 8 bits
+    int cur = 0;
+    for (int shift = 0; shift < 64; shift += 8) {
+        k_radix_hist<<<nsort, kBlock, 0, s>>>(keys[cur], n, shift, hist, nsort);
+        scan_u32(hist, hist, nhist, tile, nullptr, s);
+        k_radix_scatter<<<nsort, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1],
+                                                 n, shift, hist, nsort);
+        cur ^= 1;
+    }
+    BVH_TRY(check_launch("radix sort"));
+    const uint32_t *perm = vals[cur];
+    // a4, a5
+    if (n > 1)
+        k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
+                                                    iaxis, parent);
+    k_refit<<<nb, kBlock, 0, s>>>(pbox, perm, n, ileft, iright, parent, flags, nbox);
+    BVH_TRY(check_launch("hierarchy/refit"));
+    // a6
+    TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox};
+    k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
+    scan_u32(mark, mark, n, tile, &info->n_leaves, s);
+    BVH_TRY(check_launch("collapse"));
+    BuildInfo hi;
+    BVH_HIP_TRY(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, s));
+    BVH_HIP_TRY(hipStreamSynchronize(s));
+    if (hi.err & 1u) return set_error(BVH_EINVAL, "bvh_build: a vertex index is outside [0, n_verts)");
+    for (int a = 0; a < 3; a++) {
+        h->scene_lo[a] = hi.slo[a];
+        h->scene_hi[a] = hi.shi[a];
+    }
+    h->n_leaves = hi.n_leaves;
+
+    // a7
+    if (h->layout == BVH_LAYOUT_AABB2) {
+        h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
+        BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)h->n_nodes * sizeof(bvh_node_aabb2)));
+        k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(
+            tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
+        BVH_TRY(check_launch("aabb2 packing"));
+    } else if (h->layout == BVH_LAYOUT_BVH4) {
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, &hi, h, tmp, s));
+    } else if (h->layout == BVH_LAYOUT_BVH8_Q8) {
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, &hi, h, tmp, s));
+    } else {
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, &hi, h, tmp, s));
+    }
+
+    // leaf data
+    if (h->leaf_mode == BVH_LEAF_COMPACT) {
+        BVH_HIP_TRY(hipMalloc(&h->leaf, (size_t)n * sizeof(bvh_tri)));
+        k_leaf_compact<<<nb, kBlock, 0, s>>>(verts, tris, perm, n, static_cast<bvh_tri *>(h->leaf));
+    } else {
+        BVH_HIP_TRY(hipMalloc(&h->leaf, (size_t)n * sizeof(int32_t)));
+        BVH_HIP_TRY(hipMalloc(&h->verts, (size_t)n_verts * 3 * sizeof(float)));
+        BVH_HIP_TRY(hipMalloc(&h->tris, (size_t)n * 3 * sizeof(int32_t)));
+        BVH_HIP_TRY(hipMemcpyAsync(h->leaf, perm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        BVH_HIP_TRY(hipMemcpyAsync(h->verts, verts, (size_t)n_verts * 3 * sizeof(float),
+                                   hipMemcpyDeviceToDevice, s));
+        BVH_HIP_TRY(hipMemcpyAsync(h->tris, tris, (size_t)n * 3 * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+    }
+    BVH_TRY(check_launch("leaf packing"));
+    BVH_HIP_TRY(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, s));
+    BVH_HIP_TRY(hipStreamSynchronize(s));
+    if (hi.err & 4u) return set_error(BVH_EHIP, "bvh_build: internal error (malformed hierarchy)");
+    if (hi.err & 2u)
+        return set_error(BVH_EUNSUPPORTED, "bvh_build: non-finite box extent (coordinates too large?)");
+    h->depth = (int32_t)hi.max_depth;
+    h->max_stack = (int32_t)hi.max_stack;
+    if (h->max_stack > kStackMax)
+        return set_error(BVH_EUNSUPPORTED, "bvh_build: traversal stack bound %d exceeds %d",
+                         h->max_stack, kStackMax);
+    return BVH_OK;
+}
+
+}  // namespace
+}  // namespace bvhlib
+
+using namespace bvhlib;
+
+extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t *tris,
+                             int64_t n_tris, int32_t layout, const bvh_build_opts *opts,
+                             void *stream, bvh_handle_t *out) {
+    if (!out) return set_error(BVH_EINVAL, "bvh_build: out is null");
+    *out = nullptr;
+    if (n_tris < 0 || n_verts < 0) return set_error(BVH_EINVAL, "bvh_build: negative size");
+    if (n_tris > 0 && (!verts || !tris)) return set_error(BVH_EINVAL, "bvh_build: null mesh pointer");
+    if (n_tris > 0 && n_verts == 0) return set_error(BVH_EINVAL, "bvh_build: triangles without vertices");
+    if (layout < 0 || layout >= BVH_NUM_LAYOUTS)
+        return set_error(BVH_EINVAL, "bvh_build: unknown layout %d", layout);
+    int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT;
+    if (opts) {
+        for (int k = 0; k < 6; k++)
+            if (opts->reserved[k] != 0) return set_error(BVH_EINVAL, "bvh_build: reserved option set");
+        if (opts->leaf_size != 0) leaf_size = opts->leaf_size;
+        if (opts->leaf_mode != 0) leaf_mode = opts->leaf_mode;
+    }
+    if (leaf_size < 1 || leaf_size > kMaxLeafSize)
+        return set_error(BVH_EINVAL, "bvh_build: leaf_size %d outside 1..%d", leaf_size, kMaxLeafSize);
+    if (leaf_mode != BVH_LEAF_COMPACT && leaf_mode != BVH_LEAF_INDEXED)
+        return set_error(BVH_EINVAL, "bvh_build: unknown leaf mode %d", leaf_mode);
+    if (n_tris > kMaxTris)
+        return set_error(BVH_EUNSUPPORTED, "bvh_build: %lld triangles exceed %lld",
+                         (long long)n_tris, (long long)kMaxTris);
+    BVH_TRY(require_device());
+    int dev = 0;
+    BVH_HIP_TRY(hipGetDevice(&dev));
+    bvh_handle_s *h = new bvh_handle_s;
+    h->device = dev;
+    h->layout = layout;
+    h->leaf_mode = leaf_mode;
+    h->leaf_size = leaf_size;
+    h->arity = layout_arity(layout);
+    h->n_tris = n_tris;
+    h->n_verts = n_verts;
+    h->node_bytes = node_record_bytes(layout);
+    if (n_tris == 0) {
+        *out = h;
+        return BVH_OK;
+    }
+    int32_t rc = build_impl(verts, n_verts, tris, n_tris, h, static_cast<hipStream_t>(stream));
+    if (rc != BVH_OK) {
+        std::string msg = bvh_last_error();
+        bvh_destroy(h);
+        return set_error(rc, "%s", msg.c_str());
+    }
+    *out = h;
+    return BVH_OK;
+}

@@ -1,0 +1,110 @@
+// Internal definitions shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "bvh.h"
+
+namespace bvhlib {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+int32_t set_error(int32_t code, const char *fmt, ...);
+
+#define BVH_HIP_TRY(expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            if (e_ == hipErrorOutOfMemory)                                                  \
+                return ::bvhlib::set_error(BVH_ENOMEM, "%s: %s", #expr, hipGetErrorString(e_)); \
+            return ::bvhlib::set_error(BVH_EHIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+        }                                                                                   \
+    } while (0)
+
+#define BVH_TRY(expr)                       \
+    do {                                    \
+        int32_t rc_ = (expr);               \
+        if (rc_ != BVH_OK) return rc_;      \
+    } while (0)
+
+// Fails with ENODEV when no HIP device is present.
+int32_t require_device();
+
+// ---------------------------------------------------------------------------
+// Limits shared by build and trace
+// ---------------------------------------------------------------------------
+constexpr int kMaxLeafSize = 16;
+constexpr int64_t kMaxTris = (int64_t(1) << 27) - 1;   // leaf ref has 27 offset bits
+// Traversal stack: kStackLds entries per lane in LDS, then a private
+// overflow area of kStackOvf entries.
+constexpr int kStackLds = 16;
+constexpr int kStackOvf = 240;
+constexpr int kStackMax = kStackLds + kStackOvf;
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+}  // namespace bvhlib
+
+struct bvh_handle_s {
+    int device = 0;
+    int32_t layout = 0;
+    int32_t leaf_mode = 0;
+    int32_t leaf_size = 4;
+    int32_t arity = 2;
+    int64_t n_tris = 0;
+    int64_t n_verts = 0;
+    int64_t n_nodes = 0;
+    int64_t n_leaves = 0;
+    int64_t node_bytes = 0;
+    int32_t depth = 0;
+    int32_t max_stack = 0;
+    float scene_lo[3] = {0, 0, 0};
+    float scene_hi[3] = {0, 0, 0};
+    void *nodes = nullptr;       // node records
+    void *leaf = nullptr;        // bvh_tri[n_tris] or int32 prim id[n_tris]
+    float *verts = nullptr;      // INDEXED: own copy of the vertices
+    int32_t *tris = nullptr;     // INDEXED: own copy of the triangle indices
+};
+
+namespace bvhlib {
+
+inline int64_t node_record_bytes(int32_t layout) {
+    switch (layout) {
+        case BVH_LAYOUT_AABB2: return sizeof(bvh_node_aabb2);
+        case BVH_LAYOUT_BVH4: return sizeof(bvh_node_bvh4);
+        case BVH_LAYOUT_BVH8_Q8: return sizeof(bvh_node_bvh8_q8);
+        case BVH_LAYOUT_BVH8_Q16: return sizeof(bvh_node_bvh8_q16);
+        default: return 0;
+    }
+}
+
+inline int32_t layout_arity(int32_t layout) {
+    switch (layout) {
+        case BVH_LAYOUT_AABB2: return 2;
+        case BVH_LAYOUT_BVH4: return 4;
+        default: return 8;
+    }
+}
+
+static_assert(sizeof(bvh_ray) == 32, "bvh_ray");
+static_assert(sizeof(bvh_hit) == 16, "bvh_hit");
+static_assert(sizeof(bvh_tri) == 48, "bvh_tri");
+static_assert(sizeof(bvh_node_aabb2) == 32, "aabb2 node");
+static_assert(sizeof(bvh_node_bvh4) == 128, "bvh4 node");
+static_assert(sizeof(bvh_node_bvh8_q8) == 128, "bvh8 q8 node");
+static_assert(sizeof(bvh_node_bvh8_q16) == 160, "bvh8 q16 node");
+
+// Child reference encoding (see bvh.h).
+__host__ __device__ inline uint32_t ref_interior(uint32_t node) { return (node << 1) | 1u; }
+__host__ __device__ inline uint32_t ref_leaf(uint32_t first, uint32_t n) {
+    return (first << 5) | ((n - 1u) << 1);
+}
+constexpr uint32_t kRefEmpty = 0xFFFFFFFFu;
+
+}  // namespace bvhlib

@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function declared in include/bvh.h, and rejects invalid arguments with
+the documented error codes before it touches a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bvh.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2511_15028_amd import bvh
+    if not os.path.exists(bvh.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return bvh.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bvh_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("bvh_build", "bvh_trace", "bvh_trace_backward", "bvh_destroy", "bvh_get_stats",
+              "bvh_read_buffer", "bvh_trace_counts", "bvh_last_error", "bvh_version"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_version(L):
+    assert L.bvh_version() == 1
+
+
+def test_build_argument_validation(L):
+    from paper_2511_15028_amd import bvh
+    h = ctypes.c_void_p(123)
+    opts = bvh.BuildOpts(4, 0)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(opts), None, None) == bvh.EINVAL
+    assert L.bvh_build(fake, 3, fake, -1, 0, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
+    assert h.value is None
+    assert L.bvh_build(None, 3, fake, 1, 0, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
+    assert L.bvh_build(fake, 0, fake, 1, 0, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
+    assert L.bvh_build(fake, 3, fake, 1, 7, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
+    assert b"layout" in L.bvh_last_error()
+    for bad in (bvh.BuildOpts(0, 5), bvh.BuildOpts(17, 0), bvh.BuildOpts(-1, 0)):
+        assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(bad), None, ctypes.byref(h)) == bvh.EINVAL
+    res = bvh.BuildOpts(4, 0)
+    res.reserved[2] = 1
+    assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(res), None, ctypes.byref(h)) == bvh.EINVAL
+    assert L.bvh_build(fake, 3, fake, 1 << 27, 0, None, None, ctypes.byref(h)) == bvh.EUNSUPPORTED
+
+
+def test_trace_and_backward_argument_validation(L):
+    from paper_2511_15028_amd import bvh
+    fake = ctypes.c_void_p(0x1000)
+    assert L.bvh_trace(None, fake, 1, fake, 0, None) == bvh.EINVAL
+    assert L.bvh_trace_counts(None, fake, 1, fake, 0, fake, None) == bvh.EINVAL
+    assert L.bvh_trace_backward(fake, -1, fake, 1, fake, 1, fake, fake, fake, fake, None) == bvh.EINVAL
+    assert L.bvh_trace_backward(fake, 3, fake, 1, None, 1, fake, fake, fake, fake, None) == bvh.EINVAL
+    assert L.bvh_trace_backward(None, 0, None, 0, None, 0, None, None, None, None, None) == bvh.OK
+    assert L.bvh_get_stats(None, None) == bvh.EINVAL
+    assert L.bvh_read_buffer(None, 0, None, 0, None) == bvh.EINVAL
+    assert L.bvh_destroy(None) == bvh.OK

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Bar (from the project's stated tolerances): the GPU prim_id equals the
+oracle's on every ray whose runner-up hit is more than 1e-5 relative farther
+(ties broken by lowest t, then lowest id); t, u, v agree within 2e-6
+relative (u, v with a unit floor, as barycentrics lie in [0,1]).  Both sides
+run the same FP32 Moller-Trumbore operation order without FMA contraction,
+so t, u, v are in fact expected bit-equal, and that is checked too.  Rays
+that are not graded on prim_id must still return a genuine hit whose t is
+within 1e-5 of the best.
+"""
+import numpy as np
+import pytest
+
+from paper_2511_15028_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = ["aabb2", "bvh4", "bvh8_q8", "bvh8_q16"]
+
+
+def B():
+    from paper_2511_15028_amd import bvh
+    return bvh
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_build(verts, tris, layout, leaf_mode="compact", leaf_size=4):
+    return B().build(dev(verts), dev(tris), layout, leaf_size, leaf_mode)
+
+
+def gpu_trace(h, rays, mode=0):
+    hits = h.trace(dev(rays), mode)
+    torch.cuda.synchronize()
+    hh = hits.cpu().numpy()
+    return hh[:, 0].view(np.int32).copy(), hh[:, 1:4].copy()
+
+
+def oracle_ref(orc, verts, tris, rays, brute=True, bvh=None):
+    """(p1, tuv1, p2, t2) from the oracle."""
+    if brute:
+        p1, tuv1 = orc.brute_closest(verts, tris, rays)
+        pp, tt = orc.brute_top2(verts, tris, rays)
+        assert np.array_equal(pp[:, 0], p1)
+        return p1, tuv1, pp[:, 1], tt[:, 1]
+    bvh = bvh or orc.OracleBVH(verts, tris)
+    return bvh.trace(rays, orc.TOP2)
+
+
+def check_closest(orc, verts, tris, rays, prim, tuv, ref):
+    p1, tuv1, p2, t2 = ref
+    graded = orc.ambiguity_mask(tuv1[:, 0], p2, t2)
+    assert graded.mean() > 0.5
+    bad = np.nonzero(graded & (prim != p1))[0]
+    assert bad.size == 0, f"{bad.size} graded rays differ, e.g. ray {bad[:5]}: gpu {prim[bad[:5]]} oracle {p1[bad[:5]]}"
+    hit = graded & (p1 >= 0)
+    t_ok = np.abs(tuv[hit, 0] - tuv1[hit, 0]) <= 2e-6 * np.abs(tuv1[hit, 0])
+    uv_ok = np.abs(tuv[hit, 1:] - tuv1[hit, 1:]) <= 2e-6 * np.maximum(np.abs(tuv1[hit, 1:]), 1.0)
+    assert t_ok.all() and uv_ok.all()
+    # identical FP32 operation order on both sides: bit-equal
+    assert np.array_equal(tuv[hit].view(np.uint32), tuv1[hit].view(np.uint32))
+    miss = p1 < 0
+    assert (prim[miss] == -1).all() and np.isinf(tuv[miss, 0]).all()
+    assert (tuv[miss, 1:] == 0).all()
+    # ungraded rays: a genuine hit within the tie window of the best
+    for r in np.nonzero(~graded)[0][:200]:
+        assert prim[r] >= 0
+        assert abs(tuv[r, 0] - tuv1[r, 0]) <= 1e-5 * tuv1[r, 0]
+        p = verts[tris[prim[r]]]
+        mt = orc.mt_f32(rays[r, 0:3], rays[r, 4:7], float(rays[r, 7]), p[0], p[1], p[2])
+        assert mt is not None and np.array_equal(np.float32(mt), tuv[r])
+    return graded
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("leaf_mode", ["compact", "indexed"])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_soup_parity(orc, layout, leaf_mode):
+    w = W.soup_workload()
+    rays = np.concatenate([w["rays"], W.uniform_rays(5000, 11)])   # 9096 rays: ragged tail
+    ref = oracle_ref(orc, w["verts"], w["tris"], rays)
+    h = gpu_build(w["verts"], w["tris"], layout, leaf_mode)
+    prim, tuv = gpu_trace(h, rays)
+    check_closest(orc, w["verts"], w["tris"], rays, prim, tuv, ref)
+    # the 64x64 camera part is exactly the soup workload's 4,096 rays
+    assert (ref[0][:4096] >= 0).sum() > 500
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_terrain_primary_and_bounce_parity(orc, layout):
+    w = W.terrain_workload(cells=96, width=192, height=108)
+    v, t = w["verts"], w["tris"]
+    p1, tuv1 = orc.brute_closest(v, t, w["rays"])
+    assert (p1 >= 0).all()
+    bounce, _ = W.bounce_rays(w["rays"], p1, tuv1[:, 0], v, t, seed=21)
+    rays = np.concatenate([w["rays"], bounce])
+    bvh = orc.OracleBVH(v, t)
+    ref = oracle_ref(orc, v, t, rays, brute=False, bvh=bvh)
+    h = gpu_build(v, t, layout)
+    prim, tuv = gpu_trace(h, rays)
+    check_closest(orc, v, t, rays, prim, tuv, ref)
+
+
+def _small_spheres():
+    return W.spheres_workload(n_rays=20000, n_spheres=40, n_slivers=3000,
+                              quota=((2, 14), (3, 12), (4, 8), (5, 4), (6, 2)))
+
+
+@pytest.mark.parametrize("leaf_mode", ["compact", "indexed"])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_spheres_parity_closest_and_any(orc, layout, leaf_mode):
+    w = _small_spheres()
+    v, t = w["verts"], w["tris"]
+    bvh = orc.OracleBVH(v, t)
+    ref = oracle_ref(orc, v, t, w["rays"], brute=False, bvh=bvh)
+    h = gpu_build(v, t, layout, leaf_mode)
+    prim, tuv = gpu_trace(h, w["rays"])
+    check_closest(orc, v, t, w["rays"], prim, tuv, ref)
+    # any-hit shadow rays: occlusion boolean where the closest hit is not at tmax
+    sh = w["shadow"]
+    pc, tc, _, _ = bvh.trace(sh, orc.TOP2)
+    pa, ta = gpu_trace(h, sh, mode=1)
+    tmax = sh[:, 7]
+    graded = (pc < 0) | (np.abs(tc[:, 0] - tmax) > 1e-5 * tmax)
+    assert np.array_equal((pa >= 0)[graded], (pc >= 0)[graded])
+    occ = pa >= 0
+    assert (ta[occ, 0] <= tmax[occ]).all() and (ta[occ, 0] > 0).all()
+    for r in np.nonzero(occ)[0][:300]:
+        p = v[t[pa[r]]]
+        mt = orc.mt_f32(sh[r, 0:3], sh[r, 4:7], float(sh[r, 7]), p[0], p[1], p[2])
+        assert mt is not None and np.array_equal(np.float32(mt), ta[r])
+    assert 0.05 < occ.mean() < 0.95
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("leaf_size", [1, 2, 7, 16])
+def test_leaf_sizes(orc, layout, leaf_size):
+    w = W.soup_workload(n_tris=700, seed=5)
+    rays = np.concatenate([w["rays"], W.uniform_rays(3000, 12)])
+    ref = oracle_ref(orc, w["verts"], w["tris"], rays)
+    h = gpu_build(w["verts"], w["tris"], layout, leaf_size=leaf_size)
+    st = h.stats()
+    assert st["leaf_size"] == leaf_size
+    prim, tuv = gpu_trace(h, rays)
+    check_closest(orc, w["verts"], w["tris"], rays, prim, tuv, ref)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_edge_cases(orc, layout):
+    rays = np.concatenate([W.soup_camera_rays(16, 16), W.uniform_rays(301, 13)])
+    # tiny scenes: 1 triangle, a single leaf, one more than a leaf
+    for n in (1, 3, 4, 5, 9):
+        v, t = W.soup_scene(n, seed=40 + n, spread=0.3)
+        ref = oracle_ref(orc, v, t, rays)
+        prim, tuv = gpu_trace(gpu_build(v, t, layout), rays)
+        check_closest(orc, v, t, rays, prim, tuv, ref)
+    # empty scene: every ray misses
+    v, t = W.soup_scene(4, seed=3)
+    h = gpu_build(v, t[:0], layout)
+    prim, tuv = gpu_trace(h, rays)
+    assert (prim == -1).all() and np.isinf(tuv[:, 0]).all()
+    # zero rays and one ray
+    v, t = W.soup_scene(64, seed=9)
+    h = gpu_build(v, t, layout)
+    empty = h.trace(dev(rays[:0]))
+    assert empty.shape == (0, 4)
+    ref = oracle_ref(orc, v, t, rays[:1])
+    prim, tuv = gpu_trace(h, rays[:1])
+    assert prim[0] == ref[0][0]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_duplicates_degenerates_and_axis_rays(orc, layout):
+    rng = np.random.default_rng(77)
+    v, t = W.soup_scene(300, seed=77)
+    # exact duplicates (ties: lowest id wins), zero-area and collinear triangles
+    v = np.concatenate([v, v[:90], np.repeat(v[90:120:3], 3, axis=0),
+                        np.stack([v[120], v[120] + 0.01, v[120] + 0.02])]).astype(np.float32)
+    t = np.arange(v.shape[0], dtype=np.int32).reshape(-1, 3)
+    # rays along the axes (zero direction components) through the scene
+    o = rng.uniform(0, 1, (3000, 3))
+    d = np.zeros((3000, 3))
+    axis = rng.integers(0, 3, 3000)
+    d[np.arange(3000), axis] = rng.choice([-1.0, 1.0], 3000)
+    # every other ray starts outside the unit cube on its own axis
+    k = np.arange(0, 3000, 2)
+    o[k, axis[k]] = np.where(d[k, axis[k]] > 0, -0.5, 1.5)
+    rays = np.concatenate([W.make_rays(o, d), W.uniform_rays(2000, 78)])
+    ref = oracle_ref(orc, v, t, rays)
+    prim, tuv = gpu_trace(gpu_build(v, t, layout), rays)
+    check_closest(orc, v, t, rays, prim, tuv, ref)
+    # exact duplicates tie at equal t: the lower id is reported, on both sides
+    assert not ((ref[0] >= 300) & (ref[0] < 330)).any()
+    tie = (ref[2] == ref[0] + 300) & (ref[3] == ref[1][:, 0])
+    assert tie.sum() > 20
+    assert np.array_equal(prim[tie], ref[0][tie])
+
+
+def _sample(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, size=min(k, n), replace=False))
+
+
+@pytest.fixture(scope="module")
+def terrain_full(orc):
+    w = W.terrain_workload()
+    v, t = w["verts"], w["tris"]
+    bvh = orc.OracleBVH(v, t)
+    return w, bvh
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_terrain_full_size_sampled(orc, terrain_full, layout):
+    """Full 2.1 M-triangle terrain, all 2,073,600 camera rays traced in one
+    launch, then the bounce rays of those hits; a 4,096-ray sample of each
+    set is checked against the oracle."""
+    w, bvh = terrain_full
+    v, t = w["verts"], w["tris"]
+    h = gpu_build(v, t, layout)
+    prim, tuv = gpu_trace(h, w["rays"])
+    s = _sample(len(prim), 4096, 1)
+    ref = bvh.trace(w["rays"][s], orc.TOP2)
+    check_closest(orc, v, t, w["rays"][s], prim[s], tuv[s], ref)
+    assert (prim >= 0).all()
+    # bounce rays from the oracle's hits of the sample, traced on both sides
+    bounce, _ = W.bounce_rays(w["rays"][s], ref[0], ref[1][:, 0], v, t, seed=1001)
+    refb = bvh.trace(bounce, orc.TOP2)
+    pb, tb = gpu_trace(h, bounce)
+    check_closest(orc, v, t, bounce, pb, tb, refb)
+
+
+@pytest.fixture(scope="module")
+def spheres_full(orc):
+    w = W.spheres_workload()
+    bvh = orc.OracleBVH(w["verts"], w["tris"])
+    return w, bvh
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_spheres_full_size_sampled(orc, spheres_full, layout):
+    """Full 4.05 M-triangle scene, all 2^23 rays in one launch (closest and
+    any-hit); a 4,096-ray sample of each is checked against the oracle."""
+    w, bvh = spheres_full
+    v, t = w["verts"], w["tris"]
+    h = gpu_build(v, t, layout)
+    prim, tuv = gpu_trace(h, w["rays"])
+    s = _sample(len(prim), 4096, 2)
+    ref = bvh.trace(w["rays"][s], orc.TOP2)
+    check_closest(orc, v, t, w["rays"][s], prim[s], tuv[s], ref)
+    pa, ta = gpu_trace(h, w["shadow"], mode=1)
+    sh = w["shadow"][s]
+    pc, tc, _, _ = bvh.trace(sh, orc.TOP2)
+    graded = (pc < 0) | (np.abs(tc[:, 0] - sh[:, 7]) > 1e-5 * sh[:, 7])
+    assert np.array_equal((pa[s] >= 0)[graded], (pc >= 0)[graded])
