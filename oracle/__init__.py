@@ -74,7 +74,7 @@ def _declare(L):
     L.orc_max_threads.restype = ctypes.c_int
     L.orc_tuv_f64.argtypes = [_P, _P, _P, _P, _I64, _P]
     L.orc_tuv_f64.restype = None
-    L.orc_grad_f64.argtypes = [_P, _P, _P, _P, _P, _I64, _P, _P, _P]
+    L.orc_grad_f64.argtypes = [_P, _P, _P, _P, _P, _I64, _P, _P, _P, _P]
     L.orc_grad_f64.restype = None
 
 
@@ -187,9 +187,11 @@ def tuv_f64(verts, tris, rays, prims):
     return out
 
 
-def grad_f64(verts, tris, rays, prims, grad_hits):
+def grad_f64(verts, tris, rays, prims, grad_hits, tuv_at=None):
     """Closed-form FP64 gradient at fixed primitives.
 
+    tuv_at: optional [n,3] hit parameters at which to evaluate it (the
+    oracle's own FP32 forward result); by default they are solved in FP64.
     Returns (grad_verts[V,3] f64, grad_rays[n,6] f64, tuv[n,3] f64)."""
     verts = _c(verts, np.float32)
     tris = _c(tris, np.int32)
@@ -200,8 +202,12 @@ def grad_f64(verts, tris, rays, prims, grad_hits):
     gv = np.zeros((verts.shape[0], 3), np.float64)
     gr = np.empty((n, 6), np.float64)
     tuv = np.empty((n, 3), np.float64)
+    at = None
+    if tuv_at is not None:
+        at = _c(tuv_at, np.float32)
+        assert at.shape == (n, 3)
     lib().orc_grad_f64(_ptr(verts), _ptr(tris), _ptr(rays), _ptr(prims), _ptr(grad_hits),
-                       n, _ptr(gv), _ptr(gr), _ptr(tuv))
+                       n, _ptr(gv), _ptr(gr), _ptr(tuv), _ptr(at) if at is not None else None)
     return gv, gr, tuv
 
 

@@ -472,10 +472,15 @@ void orc_tuv_f64(const double *verts, const int32_t *tris, const double *rays,
 
 /* Gradient of L = sum_i g_i . (t_i, u_i, v_i) at fixed prims.
  * grad_verts (nverts*3) is accumulated (+=), grad_rays (n*6: dL/do, dL/dd) is
- * overwritten, tuv (n*3) receives the FP64 hit parameters. */
+ * overwritten, tuv (n*3) receives the hit parameters used.  lam depends only
+ * on d and the triangle; the hit parameters enter through the weights
+ * (1-u-v, u, v) and dL/dd = -t lam.  With tuv_at == NULL they are solved in
+ * FP64; otherwise they are taken from tuv_at (n*3, e.g. the FP32 forward's
+ * own hit), so the gradient is evaluated at that forward result. */
 void orc_grad_f64(const float *verts, const int32_t *tris, const float *rays,
                   const int32_t *prims, const float *grad_hits, int64_t n,
-                  double *grad_verts, double *grad_rays, double *tuv) {
+                  double *grad_verts, double *grad_rays, double *tuv,
+                  const float *tuv_at) {
     for (int64_t i = 0; i < n; i++) {
         double *gr = grad_rays + 6 * i;
         for (int k = 0; k < 6; k++) gr[k] = 0.0;
@@ -489,6 +494,7 @@ void orc_grad_f64(const float *verts, const int32_t *tris, const float *rays,
         d3 o = d3_load(ry), d = d3_load(ry + 4);
         double t, u, v;
         if (!tuv_f64(o, d, p0, p1, p2, &t, &u, &v)) continue;
+        if (tuv_at) { t = tuv_at[3 * i]; u = tuv_at[3 * i + 1]; v = tuv_at[3 * i + 2]; }
         tuv[3 * i] = t; tuv[3 * i + 1] = u; tuv[3 * i + 2] = v;
         /* J^T lam = g: rows of J^T are a = d, b = p0-p1, c = p0-p2.
          * lam = (g_t (b x c) + g_u (c x a) + g_v (a x b)) / (a . (b x c)). */

@@ -42,7 +42,8 @@ def fma32(q, s, o):
     q = np.asarray(q, np.float64)
     s = np.asarray(s, np.float32).astype(np.float64)
     o = np.asarray(o, np.float32).astype(np.float64)
-    q, s, o = np.broadcast_arrays(q, s, o)
+    shape = np.broadcast(q, s, o).shape
+    q, s, o = (np.atleast_1d(x) for x in np.broadcast_arrays(q, s, o))
     y = q * s + o
     f = y.astype(np.float32)
     lo = np.nextafter(f, np.float32(-np.inf)).astype(np.float64)
@@ -54,7 +55,7 @@ def fma32(q, s, o):
         for idx in zip(*np.nonzero(amb)):
             exact = Fraction(float(q[idx])) * Fraction(float(s[idx])) + Fraction(float(o[idx]))
             f[idx] = _round_f32(exact)
-    return f
+    return f.reshape(shape)
 
 
 def _round_f32(x):

@@ -224,7 +224,16 @@ def test_terrain_full_size_sampled(orc, terrain_full, layout):
     s = _sample(len(prim), 4096, 1)
     ref = bvh.trace(w["rays"][s], orc.TOP2)
     check_closest(orc, v, t, w["rays"][s], prim[s], tuv[s], ref)
-    assert (prim >= 0).all()
+    # FP32 Moller-Trumbore is not watertight: a ray through a shared grid
+    # vertex or edge can pass between the triangles.  Such misses are rare
+    # and the oracle must miss them too.
+    miss = np.nonzero(prim < 0)[0]
+    assert len(miss) < 1e-4 * len(prim)
+    if len(miss):
+        pm, _ = bvh.trace(w["rays"][miss])
+        assert (pm < 0).all()
+    s = s[prim[s] >= 0]
+    ref = tuple(x[np.isin(_sample(len(prim), 4096, 1), s)] for x in ref)
     # bounce rays from the oracle's hits of the sample, traced on both sides
     bounce, _ = W.bounce_rays(w["rays"][s], ref[0], ref[1][:, 0], v, t, seed=1001)
     refb = bvh.trace(bounce, orc.TOP2)

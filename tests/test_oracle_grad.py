@@ -109,3 +109,22 @@ def test_misses_contribute_nothing(orc, hits):
     assert np.isnan(tuv64[::2]).all()
     gv_odd, _, _ = orc.grad_f64(verts, tris, rays[1::2], prim[1::2], wts[1::2])
     np.testing.assert_allclose(gv, gv_odd, rtol=1e-12, atol=1e-15)
+
+
+def test_gradient_at_given_hit_parameters(orc, hits):
+    verts, tris, rays, prim, tuv, wts = hits
+    gv, gr, tuv64 = orc.grad_f64(verts, tris, rays, prim, wts)
+    # evaluated at the FP64 parameters rounded to FP32: lam is unchanged, the
+    # weights and -t lam move by at most the rounding of (t, u, v)
+    gv2, gr2, tuv2 = orc.grad_f64(verts, tris, rays, prim, wts, tuv_at=tuv64.astype(np.float32))
+    np.testing.assert_array_equal(tuv2, tuv64.astype(np.float32).astype(np.float64))
+    np.testing.assert_array_equal(gr2[:, 0:3], gr[:, 0:3])
+    np.testing.assert_allclose(gr2[:, 3:6], gr[:, 3:6], rtol=1e-6)
+    # weights move by float32 rounding (< 2^-23 absolute); sums may cancel
+    np.testing.assert_allclose(gv2, gv, rtol=0, atol=1e-6 * np.abs(gv).max())
+    # and at the FP32 forward's own hit: the same lam, weights from that hit
+    gv3, gr3, tuv3 = orc.grad_f64(verts, tris, rays, prim, wts, tuv_at=tuv)
+    np.testing.assert_array_equal(tuv3, tuv.astype(np.float64))
+    np.testing.assert_array_equal(gr3[:, 0:3], gr[:, 0:3])
+    # dL/dd = -t lam with lam = -dL/do
+    np.testing.assert_allclose(gr3[:, 3:6], tuv[:, 0:1].astype(np.float64) * gr[:, 0:3], rtol=1e-12)
