@@ -1,0 +1,305 @@
+"""Benchmark: closest-hit BVH traversal on one MI355X.
+
+Workload: the procedural terrain (1024 x 1024 cells = 2,097,152 triangles,
+heights from 6-octave value noise, amplitude 0.2), 1920 x 1080 coherent
+camera rays plus one cosine-distributed diffuse bounce ray per hit
+(incoherent).  Inputs are generated on the host, uploaded once and stay
+resident in HBM; the bounce rays are made from the GPU's own camera hits
+before timing starts.
+
+One step = one pass of the hot path over that input: build the BVH on the
+GPU (bounds, Morton codes, radix sort, hierarchy, refit, collapse, packing
+into the node layout) and trace the camera rays and the bounce rays.
+`value` = rays traced per step / step time, in Mrays/s.
+
+Also reported: per-layout trace-only throughput and algorithmic bytes per
+ray (from the counting kernel), the roofline of the traversal kernel
+(timed with HIP events on the launch stream), the differentiable workload's
+forward and forward+backward throughput, and the CPU oracle timed on the
+host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--layout L]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+RAY_BYTES, HIT_BYTES = 32, 16
+LEAF_TRI_BYTES = {"compact": 48, "indexed": 4 + 12 + 36}  # record, or id + index + 3 verts
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--layout", default="bvh8_q8")
+    ap.add_argument("--leaf-mode", default="compact")
+    ap.add_argument("--leaf-size", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip per-layout table and fwd+bwd")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(counts, layout_bytes, leaf_mode):
+    """Per-ray bytes the method must move: ray + hit + node records fetched +
+    triangles tested (from the counting kernel)."""
+    nodes = counts[:, 0].astype(np.float64)
+    tris = counts[:, 1].astype(np.float64)
+    return RAY_BYTES + HIT_BYTES + nodes * layout_bytes + tris * LEAF_TRI_BYTES[leaf_mode]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); rays shard across GPUs "
+              "without communication, so the one-GPU number is the per-GPU share.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2511_15028_amd import bvh, workloads as W
+
+    bvh.lib()  # fails loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.time()
+    w = W.terrain_workload()
+    verts = torch.from_numpy(w["verts"]).to(dev)
+    tris = torch.from_numpy(w["tris"]).to(dev)
+    prim_rays = torch.from_numpy(w["rays"]).to(dev)
+    log(f"generated terrain: {w['tris'].shape[0]} tris, {w['rays'].shape[0]} camera rays "
+        f"({time.time() - t0:.1f}s)")
+
+    # bounce rays from the GPU's own camera hits (untimed setup)
+    h0 = bvh.build(verts, tris, args.layout, args.leaf_size, args.leaf_mode)
+    hits0 = h0.trace(prim_rays)
+    torch.cuda.synchronize()
+    hh = hits0.cpu().numpy()
+    prim0 = hh[:, 0].view(np.int32)
+    bounce_np, _ = W.bounce_rays(w["rays"], prim0, hh[:, 1], w["verts"], w["tris"], seed=1001)
+    bounce_rays = torch.from_numpy(bounce_np).to(dev)
+    h0.close()
+    n_rays = prim_rays.shape[0] + bounce_rays.shape[0]
+    log(f"bounce rays: {bounce_rays.shape[0]}")
+
+    hits_p = torch.empty((prim_rays.shape[0], 4), dtype=torch.float32, device=dev)
+    hits_b = torch.empty((bounce_rays.shape[0], 4), dtype=torch.float32, device=dev)
+
+    def step(ev=None):
+        h = bvh.build(verts, tris, args.layout, args.leaf_size, args.leaf_mode)
+        if ev is not None:
+            ev[0].record(stream)
+        h.trace(prim_rays, hits=hits_p)
+        if ev is not None:
+            ev[1].record(stream)
+            ev[2].record(stream)
+        h.trace(bounce_rays, hits=hits_b)
+        if ev is not None:
+            ev[3].record(stream)
+        return h
+
+    for _ in range(args.warmup):
+        step().close()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    handles = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        handles.append(step(events[k]))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    for h in handles:
+        h.close()
+    ms_step = 1000.0 * t_total / args.steps
+    dur_p = np.array([e[0].elapsed_time(e[1]) for e in events])
+    dur_b = np.array([e[2].elapsed_time(e[3]) for e in events])
+    value = n_rays / (t_total / args.steps) / 1e6
+
+    # measurement-only passes (outside the timed region)
+    h = bvh.build(verts, tris, args.layout, args.leaf_size, args.leaf_mode)
+    st = h.stats()
+    _, cnt_p = h.trace_counts(prim_rays)
+    _, cnt_b = h.trace_counts(bounce_rays)
+    torch.cuda.synchronize()
+    bytes_p = algorithmic_bytes(cnt_p.cpu().numpy(), st["node_bytes"], args.leaf_mode)
+    bytes_b = algorithmic_bytes(cnt_b.cpu().numpy(), st["node_bytes"], args.leaf_mode)
+    # dominant kernel: the traversal kernel; two launches per step (camera, bounce)
+    launch_bytes = bytes_p.sum() + bytes_b.sum()
+    launch_s = (dur_p.mean() + dur_b.mean()) / 1000.0
+    achieved = launch_bytes / launch_s / 1e9
+    trace_mrays = n_rays / launch_s / 1e6
+    build_ms = ms_step - (dur_p.mean() + dur_b.mean())
+    h.close()
+
+    out = {
+        "metric": "Mrays/s closest-hit per layout, % HBM roofline; batched & fwd+bwd vs plain",
+        "value": round(value, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "terrain 1024x1024 cells (2,097,152 tris), 1920x1080 camera rays + 1 "
+                        "diffuse bounce per hit; step = GPU BVH build + trace of both ray sets",
+            "layout": args.layout, "leaf_mode": args.leaf_mode, "leaf_size": args.leaf_size,
+            "rays_per_step": int(n_rays), "camera_rays": int(prim_rays.shape[0]),
+            "bounce_rays": int(bounce_rays.shape[0]),
+        },
+        "trace_mrays_s": round(trace_mrays, 2),
+        "trace_ms": {"camera": round(float(dur_p.mean()), 4), "bounce": round(float(dur_b.mean()), 4)},
+        "build_ms": round(build_ms, 3),
+        "bytes_per_ray": {"camera": round(float(bytes_p.mean()), 1),
+                          "bounce": round(float(bytes_b.mean()), 1)},
+        "bvh": {"nodes": st["n_nodes"], "node_bytes": st["node_bytes"],
+                "nodes_mb": round(st["nodes_buffer_bytes"] / 1e6, 2),
+                "leaf_mb": round(st["leaf_buffer_bytes"] / 1e6, 2), "depth": st["depth"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"trace ({args.layout}, {args.leaf_mode})"},
+    }
+
+    if not args.no_extras:
+        out["per_layout"] = per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
+        out["fwd_bwd"] = fwd_bwd(torch, bvh, W)
+
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = 2 * n * 4
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, W)
+
+    print(json.dumps(out), flush=True)
+
+
+def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
+    """Trace-only Mrays/s and algorithmic bytes per ray for every layout and
+    leaf mode (median of 5 launches per ray set, events on the stream)."""
+    stream = torch.cuda.current_stream()
+    res = {}
+    n = prim_rays.shape[0] + bounce_rays.shape[0]
+    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16"):
+        for leaf_mode in ("compact", "indexed"):
+            h = bvh.build(verts, tris, layout, args.leaf_size, leaf_mode)
+            st = h.stats()
+            times = []
+            for _ in range(6):
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                e[0].record(stream)
+                h.trace(prim_rays)
+                h.trace(bounce_rays)
+                e[1].record(stream)
+                torch.cuda.synchronize()
+                times.append(e[0].elapsed_time(e[1]))
+            t_ms = float(np.median(times[1:]))
+            _, cp = h.trace_counts(prim_rays)
+            _, cb = h.trace_counts(bounce_rays)
+            torch.cuda.synchronize()
+            by = np.concatenate([algorithmic_bytes(cp.cpu().numpy(), st["node_bytes"], leaf_mode),
+                                 algorithmic_bytes(cb.cpu().numpy(), st["node_bytes"], leaf_mode)])
+            gbs = by.sum() / (t_ms / 1000.0) / 1e9
+            res[f"{layout}/{leaf_mode}"] = {
+                "trace_mrays_s": round(n / (t_ms / 1000.0) / 1e6, 1),
+                "bytes_per_ray": round(float(by.mean()), 1),
+                "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                "bvh_mb": round((st["nodes_buffer_bytes"] + st["leaf_buffer_bytes"]
+                                 + st["extra_bytes"]) / 1e6, 1),
+            }
+            h.close()
+            log(f"layout {layout}/{leaf_mode}: {res[f'{layout}/{leaf_mode}']}")
+    return res
+
+
+def fwd_bwd(torch, bvh, W):
+    """Differentiable workload: icosphere level 7 (327,680 tris), 1,048,576
+    rays; forward-only vs forward + backward throughput (BVH prebuilt)."""
+    w = W.diff_workload()
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(w["verts"]).to(dev)
+    t = torch.from_numpy(w["tris"]).to(dev)
+    r = torch.from_numpy(w["rays"]).to(dev)
+    g = torch.from_numpy(w["weights"]).to(dev)
+    h = bvh.build(v, t, "bvh8_q8")
+    hits = torch.empty((r.shape[0], 4), dtype=torch.float32, device=dev)
+    gv = torch.zeros_like(v)
+    gr = torch.empty((r.shape[0], 6), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run(bwd):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        h.trace(r, hits=hits)
+        if bwd:
+            gv.zero_()
+            bvh.lib().bvh_trace_backward(v.data_ptr(), v.shape[0], t.data_ptr(), t.shape[0],
+                                         r.data_ptr(), r.shape[0], hits.data_ptr(), g.data_ptr(),
+                                         gv.data_ptr(), gr.data_ptr(), stream.cuda_stream)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1])
+
+    for _ in range(2):
+        run(False), run(True)
+    f = float(np.median([run(False) for _ in range(7)]))
+    fb = float(np.median([run(True) for _ in range(7)]))
+    h.close()
+    n = r.shape[0]
+    return {"workload": "icosphere level 7 (327,680 tris), 1,048,576 rays from 64 cameras",
+            "fwd_mrays_s": round(n / (f / 1000) / 1e6, 1),
+            "fwd_bwd_mrays_s": round(n / (fb / 1000) / 1e6, 1),
+            "fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4)}
+
+
+def cpu_baseline(w, W):
+    """The CPU oracle (median-split BVH, scalar stack traversal, OpenMP
+    dynamic,64 over rays) on the same terrain: all camera rays, then the
+    bounce rays made from the oracle's own hits.  Build time excluded."""
+    import oracle
+    b = oracle.OracleBVH(w["verts"], w["tris"])
+    cores = oracle.max_threads()
+    rays = w["rays"]
+    t0 = time.perf_counter()
+    p, tuv = b.trace(rays)
+    t1 = time.perf_counter()
+    bounce, _ = W.bounce_rays(rays, p, tuv[:, 0], w["verts"], w["tris"], seed=1001)
+    t2 = time.perf_counter()
+    b.trace(bounce)
+    t3 = time.perf_counter()
+    secs = (t1 - t0) + (t3 - t2)
+    n = rays.shape[0] + bounce.shape[0]
+    return {"value": round(n / secs / 1e6, 3), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {rays.shape[0]} camera rays + {bounce.shape[0]} bounce rays of the "
+                      f"terrain workload, traversal only ({secs:.2f} s wall on {cores} threads)"}
+
+
+if __name__ == "__main__":
+    main()

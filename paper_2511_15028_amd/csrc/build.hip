@@ -389,31 +389,86 @@ __global__ __launch_bounds__(kBlock) void k_karras(const uint64_t *keys, int n, 
 }
 
 // ---------------------------------------------------------------------------
-// a5: bottom-up box refit.  Each leaf walks towards the root; the second
-// child to arrive at a node (agent-scope acquire/release counter) forms the
-// union of both child boxes and continues.
+// a5: node boxes.  Every node of the hierarchy covers a contiguous range of
+// the sorted primitives, so its box is the union of the primitive boxes in
+// that range: a range query, answered without any inter-thread
+// synchronisation.  Sorted primitive boxes are grouped in blocks of kRangeBlock;
+// a sparse table holds the union of 2^k consecutive blocks, so a range is
+// its partial blocks (read directly) plus at most two overlapping table
+// entries (min/max are idempotent).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_refit(const Box *pbox, const uint32_t *perm, int n,
-                                                  const int32_t *ileft, const int32_t *iright,
-                                                  const int32_t *parent, uint32_t *flags,
-                                                  Box *nbox) {
+constexpr int kRangeBlock = 64;
+
+__device__ inline Box box_union(const Box &a, const Box &b) {
+    Box u;
+    u.lo = make_float4(fminf(a.lo.x, b.lo.x), fminf(a.lo.y, b.lo.y), fminf(a.lo.z, b.lo.z), 0.0f);
+    u.hi = make_float4(fmaxf(a.hi.x, b.hi.x), fmaxf(a.hi.y, b.hi.y), fmaxf(a.hi.z, b.hi.z), 0.0f);
+    return u;
+}
+
+__device__ inline Box box_empty() {
+    Box e;
+    e.lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    e.hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    return e;
+}
+
+// Leaf boxes in sorted order (node ids n-1 .. 2n-2) and, one wave per block
+// of kRangeBlock, the block unions (sparse-table level 0).
+__global__ __launch_bounds__(kBlock) void k_leaf_boxes(const Box *pbox, const uint32_t *perm, int n,
+                                                       Box *nbox, Box *table) {
     const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    int x = (n - 1) + j;
-    nbox[x] = pbox[perm[j]];
-    for (int guard = 0; x != 0 && guard < 4 * 64 + 64; guard++) {
-        const int p = parent[x];
-        if (p < 0 || p >= n - 1) return;  // malformed hierarchy: stop rather than fault
-        const uint32_t old =
-            __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;
-        const Box a = nbox[ileft[p]], b = nbox[iright[p]];
-        Box u;
-        u.lo = make_float4(fminf(a.lo.x, b.lo.x), fminf(a.lo.y, b.lo.y), fminf(a.lo.z, b.lo.z), 0.0f);
-        u.hi = make_float4(fmaxf(a.hi.x, b.hi.x), fmaxf(a.hi.y, b.hi.y), fmaxf(a.hi.z, b.hi.z), 0.0f);
-        nbox[p] = u;
-        x = p;
+    Box b = box_empty();
+    if (j < n) {
+        b = pbox[perm[j]];
+        nbox[(n - 1) + j] = b;
     }
+    float v[6] = {b.lo.x, b.lo.y, b.lo.z, b.hi.x, b.hi.y, b.hi.z};
+#pragma unroll
+    for (int k = 0; k < 6; k++) v[k] = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
+    const int blk = j / kRangeBlock;
+    if ((threadIdx.x & (kWave - 1)) == 0 && blk * kRangeBlock < n) {
+        Box u;
+        u.lo = make_float4(v[0], v[1], v[2], 0.0f);
+        u.hi = make_float4(v[3], v[4], v[5], 0.0f);
+        table[blk] = u;
+    }
+}
+
+// Sparse-table level k from level k-1: T_k[i] = T_{k-1}[i] u T_{k-1}[i + 2^(k-1)].
+__global__ __launch_bounds__(kBlock) void k_table_level(const Box *prev, Box *cur, int nblocks,
+                                                        int half) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i + 2 * half > nblocks) return;
+    cur[i] = box_union(prev[i], prev[i + half]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirst,
+                                                           const uint32_t *icount, int n,
+                                                           const Box *table, int nblocks,
+                                                           Box *nbox) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n - 1) return;
+    const Box *leaf = nbox + (n - 1);
+    const int a = (int)ifirst[i], b = a + (int)icount[i] - 1;
+    if (a < 0 || b >= n || b < a) return;  // malformed range: leave the box unset
+    const int ba = a / kRangeBlock, bb = b / kRangeBlock;
+    Box u = box_empty();
+    if (ba == bb) {
+        for (int j = a; j <= b; j++) u = box_union(u, leaf[j]);
+    } else {
+        const int ea = (ba + 1) * kRangeBlock, sb = bb * kRangeBlock;
+        for (int j = a; j < ea; j++) u = box_union(u, leaf[j]);
+        for (int j = sb; j <= b; j++) u = box_union(u, leaf[j]);
+        const int lo = ba + 1, hi = bb - 1;  // whole blocks in between
+        if (lo <= hi) {
+            const int len = hi - lo + 1;
+            const int k = 31 - __clz(len);
+            const Box *lvl = table + (size_t)k * nblocks;
+            u = box_union(u, box_union(lvl[lo], lvl[hi - (1 << k) + 1]));
+        }
+    }
+    nbox[i] = u;
 }
 
 // ---------------------------------------------------------------------------
@@ -733,25 +788,55 @@ __global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, con
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Build temporaries come from the device's stream-ordered memory pool
+// (hipMallocAsync / hipFreeAsync on the build stream); the pool keeps freed
+// blocks, so repeated builds do not return to the driver.
 struct DeviceTemps {
+    hipStream_t stream;
     std::vector<void *> ptrs;
+    explicit DeviceTemps(hipStream_t s) : stream(s) {}
     ~DeviceTemps() {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : ptrs) (void)hipFreeAsync(p, stream);
     }
     template <typename T>
     int32_t alloc(T **out, size_t count) {
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMallocAsync(&p, bytes, stream);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            return set_error(BVH_ENOMEM, "hipMalloc(%zu bytes) failed: %s",
-                             std::max<size_t>(count, 1) * sizeof(T), hipGetErrorString(e));
+            return set_error(BVH_ENOMEM, "hipMallocAsync(%zu bytes) failed: %s", bytes,
+                             hipGetErrorString(e));
         }
         ptrs.push_back(p);
         *out = static_cast<T *>(p);
         return BVH_OK;
     }
 };
+
+// Keeps freed pool memory cached in the device's default pool.
+int32_t retain_pool_memory(int dev) {
+    static bool done[64] = {};
+    if (dev < 0 || dev >= 64 || done[dev]) return BVH_OK;
+    hipMemPool_t pool;
+    BVH_HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t threshold = UINT64_MAX;
+    BVH_HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold));
+    done[dev] = true;
+    return BVH_OK;
+}
+
+// Small pinned host staging area for device-to-host readbacks (one per thread).
+template <typename T>
+T *pinned_scratch() {
+    static thread_local void *buf = nullptr;
+    if (!buf && hipHostMalloc(&buf, 256, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        buf = nullptr;
+    }
+    static_assert(sizeof(T) <= 256, "pinned scratch too small");
+    return static_cast<T *>(buf);
+}
 
 int32_t check_launch(const char *what) {
     hipError_t e = hipGetLastError();
@@ -791,9 +876,11 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, BuildInfo *in
             tv, base, count, cap, fr_node[cur], fr_aux[cur], cand, noff, wnodes, fr_node[cur ^ 1],
             fr_aux[cur ^ 1], info);
         BVH_TRY(check_launch("wide packing"));
-        uint32_t next = 0;
-        BVH_HIP_TRY(hipMemcpyAsync(&next, &info->next_count, sizeof(next), hipMemcpyDeviceToHost, s));
+        uint32_t *pin = pinned_scratch<uint32_t>();
+        if (!pin) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
+        BVH_HIP_TRY(hipMemcpyAsync(pin, &info->next_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         BVH_HIP_TRY(hipStreamSynchronize(s));
+        const uint32_t next = *pin;
         base += count;
         if (base + next > cap) return set_error(BVH_EHIP, "wide packing overflow");
         count = next;
@@ -811,12 +898,13 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
                    bvh_handle_s *h, hipStream_t s) {
     const int n = (int)n_tris;
     const int L = h->leaf_size;
-    DeviceTemps tmp;
+    BVH_TRY(retain_pool_memory(h->device));
+    DeviceTemps tmp(s);
     Box *pbox, *nbox;
     float *partial;
     BuildInfo *info;
     uint64_t *keys[2];
-    uint32_t *vals[2], *hist, *tile, *ifirst, *icount, *flags, *mark;
+    uint32_t *vals[2], *hist, *tile, *ifirst, *icount, *mark;
     int32_t *ileft, *iright, *parent;
     uint8_t *iaxis;
     const uint32_t nb = grid_for(n);
@@ -837,13 +925,11 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     BVH_TRY(tmp.alloc(&ifirst, n - 1));
     BVH_TRY(tmp.alloc(&icount, n - 1));
     BVH_TRY(tmp.alloc(&iaxis, n - 1));
-    BVH_TRY(tmp.alloc(&flags, n - 1));
     BVH_TRY(tmp.alloc(&parent, 2 * (size_t)n - 1));
     BVH_TRY(tmp.alloc(&nbox, 2 * (size_t)n - 1));
     BVH_TRY(tmp.alloc(&mark, n));
 
     BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
-    BVH_HIP_TRY(hipMemsetAsync(flags, 0, sizeof(uint32_t) * std::max(n - 1, 1), s));
     BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
     BVH_HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), s));
 
@@ -867,16 +953,33 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     if (n > 1)
         k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
                                                     iaxis, parent);
-    k_refit<<<nb, kBlock, 0, s>>>(pbox, perm, n, ileft, iright, parent, flags, nbox);
-    BVH_TRY(check_launch("hierarchy/refit"));
+    {
+        const int nblocks = (n + kRangeBlock - 1) / kRangeBlock;
+        int levels = 1;
+        while ((1 << levels) <= nblocks) levels++;
+        Box *table;
+        BVH_TRY(tmp.alloc(&table, (size_t)levels * nblocks));
+        k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table);
+        for (int k = 1; k < levels; k++) {
+            const int half = 1 << (k - 1);
+            k_table_level<<<grid_for(nblocks), kBlock, 0, s>>>(
+                table + (size_t)(k - 1) * nblocks, table + (size_t)k * nblocks, nblocks, half);
+        }
+        if (n > 1)
+            k_internal_boxes<<<grid_for(n - 1), kBlock, 0, s>>>(ifirst, icount, n, table, nblocks, nbox);
+    }
+    BVH_TRY(check_launch("hierarchy/boxes"));
     // a6
     TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox};
     k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
     scan_u32(mark, mark, n, tile, &info->n_leaves, s);
     BVH_TRY(check_launch("collapse"));
     BuildInfo hi;
-    BVH_HIP_TRY(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, s));
+    BuildInfo *pin = pinned_scratch<BuildInfo>();
+    if (!pin) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
+    BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     BVH_HIP_TRY(hipStreamSynchronize(s));
+    hi = *pin;
     if (hi.err & 1u) return set_error(BVH_EINVAL, "bvh_build: a vertex index is outside [0, n_verts)");
     for (int a = 0; a < 3; a++) {
         h->scene_lo[a] = hi.slo[a];
@@ -914,8 +1017,9 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
                                    hipMemcpyDeviceToDevice, s));
     }
     BVH_TRY(check_launch("leaf packing"));
-    BVH_HIP_TRY(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, s));
+    BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     BVH_HIP_TRY(hipStreamSynchronize(s));
+    hi = *pin;
     if (hi.err & 4u) return set_error(BVH_EHIP, "bvh_build: internal error (malformed hierarchy)");
     if (hi.err & 2u)
         return set_error(BVH_EUNSUPPORTED, "bvh_build: non-finite box extent (coordinates too large?)");
