@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-layout table and fwd+bwd")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
-                    help="run a plain device copy of this many MiB (counter calibration)")
+                    help="run an elementwise kernel over this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -185,15 +185,17 @@ def main():
     if not args.no_extras:
         out["per_layout"] = per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
         out["fwd_bwd"] = fwd_bwd(torch, bvh, W)
+        del verts, tris, prim_rays, bounce_rays, hits_p, hits_b
+        out["batched"] = batched(torch, bvh, W)
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)  # one elementwise kernel: reads n*4 B, writes n*4 B
         torch.cuda.synchronize()
-        out["copy_calib_bytes"] = 2 * n * 4
+        out["copy_calib_bytes"] = {"read": n * 4, "write": n * 4}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, W)
@@ -277,6 +279,71 @@ def fwd_bwd(torch, bvh, W):
             "fwd_mrays_s": round(n / (f / 1000) / 1e6, 1),
             "fwd_bwd_mrays_s": round(n / (fb / 1000) / 1e6, 1),
             "fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4)}
+
+
+def batched(torch, bvh, W):
+    """256 scenes of uneven size (1 K-500 K triangles, 1 K-1 M rays each):
+    one graph launch of the per-variant persistent kernels vs 256 plain
+    bvh_trace launches on one stream (same tuned BVHs), and vs plain launches
+    with one fixed layout.  BVH builds and tuning are excluded."""
+    t0 = time.time()
+    w = W.batch_workload()
+    log(f"batch workload: {len(w['scenes'])} scenes, {int(w['n_tris'].sum())} tris, "
+        f"{w['rays'].shape[0]} rays ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    scenes = [(torch.from_numpy(v).to(dev), torch.from_numpy(t).to(dev)) for v, t in w["scenes"]]
+    rays = torch.from_numpy(w["rays"]).to(dev)
+    off = w["offsets"]
+    n = rays.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = bvh.Batch(scenes, probe=rays, probe_offsets=off)
+    create_s = time.perf_counter() - t0
+    infos = [b.info(i) for i in range(len(scenes))]
+    handles = [b.handle(i) for i in range(len(scenes))]
+
+    def timed(fn, reps=5):
+        ts = []
+        for _ in range(reps + 1):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record(stream)
+            fn()
+            e[1].record(stream)
+            torch.cuda.synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+        return float(np.median(ts[1:]))
+
+    hits_b = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    hits_p = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    t_batch = timed(lambda: b.trace(rays, off, hits=hits_b))
+
+    def plain(hs, out):
+        for i, h in enumerate(hs):
+            if off[i + 1] > off[i]:
+                h.trace(rays[off[i]:off[i + 1]], hits=out[off[i]:off[i + 1]])
+
+    t_plain = timed(lambda: plain(handles, hits_p))
+    same = bool(torch.equal(hits_b.view(torch.int32), hits_p.view(torch.int32)))
+    fixed = [bvh.build(v, t, "bvh8_q8") for v, t in scenes]
+    t_fixed = timed(lambda: plain(fixed, hits_p))
+    for h in fixed:
+        h.close()
+    layouts = {}
+    for inf in infos:
+        k = f"{['aabb2', 'bvh4', 'bvh8_q8', 'bvh8_q16'][inf['layout']]}/lds{inf['stack_lds']}"
+        layouts[k] = layouts.get(k, 0) + 1
+    b.close()
+    return {"workload": f"{len(scenes)} scenes, {int(w['n_tris'].sum())} tris, {n} rays "
+                        "(log-uniform 1K-500K tris, 1K-1M incoherent rays per scene)",
+            "batched_mrays_s": round(n / (t_batch / 1000) / 1e6, 1),
+            "plain_tuned_mrays_s": round(n / (t_plain / 1000) / 1e6, 1),
+            "plain_bvh8_q8_mrays_s": round(n / (t_fixed / 1000) / 1e6, 1),
+            "speedup_vs_plain_tuned": round(t_plain / t_batch, 3),
+            "speedup_vs_plain_fixed": round(t_fixed / t_batch, 3),
+            "batched_ms": round(t_batch, 3), "plain_tuned_ms": round(t_plain, 3),
+            "plain_fixed_ms": round(t_fixed, 3), "hits_equal_plain": same,
+            "create_and_tune_s": round(create_s, 2), "chosen": layouts}
 
 
 def cpu_baseline(w, W):

@@ -83,7 +83,9 @@ typedef struct bvh_hit {
 typedef struct bvh_build_opts {
     int32_t leaf_size;   /* max triangles per leaf, 1..16 (default 4) */
     int32_t leaf_mode;   /* BVH_LEAF_COMPACT (default) or BVH_LEAF_INDEXED */
-    int32_t reserved[6]; /* must be zero */
+    int32_t stack_lds;   /* traversal stack entries kept in LDS per ray: 8, 16 (default) or 32;
+                            deeper entries spill to per-lane scratch.  Results do not depend on it. */
+    int32_t reserved[5]; /* must be zero */
 } bvh_build_opts;
 
 typedef struct bvh_stats {
@@ -98,6 +100,8 @@ typedef struct bvh_stats {
     int32_t depth;             /* nodes on the longest root-to-leaf path */
     int32_t max_stack;         /* worst-case traversal stack entries */
     float scene_lo[3], scene_hi[3];
+    int32_t stack_lds;         /* LDS stack entries per ray of the trace kernels */
+    int32_t pad;
 } bvh_stats;
 
 /* Compacted leaf triangle (BVH_LEAF_COMPACT), 48 B, in leaf order. */
@@ -263,6 +267,81 @@ int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const int32_t *t
                            const bvh_ray *rays, int64_t n, const bvh_hit *hits,
                            const float *grad_hits, float *grad_verts, float *grad_rays,
                            void *stream);
+
+/* ---- batched tracing ------------------------------------------------------ */
+/*
+ * Many scenes with uneven triangle and ray counts traced by one graph launch.
+ * The paper leaves execution scheduling to future work (Sec. 1) and shows that
+ * the best layout depends on scene and ray distribution (Sec. 6.2.1); here
+ * each scene's layout (and with it the tree arity) and LDS stack depth are
+ * chosen by timing candidates on probe rays, and all scenes' rays are drained
+ * from per-variant work queues by persistent kernels captured in one hipGraph.
+ */
+typedef struct bvh_scene_desc {
+    const float *verts;   /* device, n_verts x 3 float */
+    int64_t n_verts;
+    const int32_t *tris;  /* device, n_tris x 3 int32 */
+    int64_t n_tris;
+    int32_t layout;       /* BVH_LAYOUT_* to fix it, or -1 to let the tuner choose */
+    int32_t stack_lds;    /* 8, 16 or 32 to fix it, or 0 to let the tuner choose */
+    int32_t reserved[2];  /* must be zero */
+} bvh_scene_desc;
+
+typedef struct bvh_tune_opts {
+    int32_t probe_rays;           /* probe rays per scene and candidate (0: 16384) */
+    int32_t leaf_size;            /* 1..16 (0: 4); leaves are compacted */
+    const bvh_ray *probe;         /* device, optional probe rays of all scenes, concatenated */
+    const int64_t *probe_offsets; /* host, n_scenes + 1 offsets into probe; required with it */
+    int32_t reserved[4];          /* must be zero */
+} bvh_tune_opts;
+
+typedef struct bvh_batch_scene_info {
+    int32_t layout;           /* chosen layout */
+    int32_t stack_lds;        /* chosen LDS stack entries */
+    int32_t candidates;       /* candidates timed (1 when nothing was left to choose) */
+    float probe_ns_per_ray;   /* chosen candidate's time per probe ray (0 if not timed) */
+    int64_t n_nodes;
+    int64_t bvh_bytes;        /* nodes + leaf triangles */
+} bvh_batch_scene_info;
+
+typedef struct bvh_batch_s *bvh_batch_t;
+
+/*
+ * Builds a BVH per scene and tunes it.  Probe rays: opts->probe when given,
+ * otherwise generated on the device (origins uniform in the scene box,
+ * directions uniform on the sphere, a fixed integer-hash sequence).
+ *   scenes  host array of n_scenes descriptors (device mesh pointers, not
+ *           retained).  opts may be NULL.
+ * Errors: as bvh_build per scene, plus EINVAL for n_scenes < 1, a bad layout
+ * or stack value, nonzero reserved fields, or probe without probe_offsets.
+ * Synchronises `stream`.
+ */
+int32_t bvh_batch_create(const bvh_scene_desc *scenes, int32_t n_scenes, const bvh_tune_opts *opts,
+                         void *stream, bvh_batch_t *out);
+
+/* The tuner's choice for one scene.  out: host. */
+int32_t bvh_batch_get_scene_info(bvh_batch_t b, int32_t scene, bvh_batch_scene_info *out);
+
+/* The scene's BVH handle (owned by the batch; valid until bvh_batch_destroy),
+ * usable with bvh_trace. */
+int32_t bvh_batch_scene_handle(bvh_batch_t b, int32_t scene, bvh_handle_t *out);
+
+/*
+ * Closest hit for every scene's rays: rays[ray_offsets[s] .. ray_offsets[s+1])
+ * are traced against scene s and their hits written to the same positions
+ * of `hits`.  Results equal bvh_trace of each scene's handle.
+ *   rays, hits   device;  ray_offsets  host, n_scenes + 1 non-decreasing
+ * The first call for a given (rays, hits, ray_offsets) builds and
+ * instantiates a hipGraph (one small kernel that resets the work-queue
+ * counters, then one persistent kernel per layout/stack variant, in
+ * parallel branches); later calls with the same arguments replay it.  Calls
+ * on one batch must not overlap in time (they share the queue counters).
+ */
+int32_t bvh_batch_trace(bvh_batch_t b, const bvh_ray *rays, const int64_t *ray_offsets,
+                        bvh_hit *hits, void *stream);
+
+/* Frees the batch, its graph and every scene's BVH (synchronises the device). */
+int32_t bvh_batch_destroy(bvh_batch_t b);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ class BVHError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("stack_lds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("nodes_buffer_bytes", ctypes.c_int64), ("leaf_buffer_bytes", ctypes.c_int64),
                 ("extra_bytes", ctypes.c_int64), ("depth", ctypes.c_int32),
                 ("max_stack", ctypes.c_int32), ("scene_lo", ctypes.c_float * 3),
-                ("scene_hi", ctypes.c_float * 3)]
+                ("scene_hi", ctypes.c_float * 3), ("stack_lds", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -58,6 +59,21 @@ _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
 _lib = None
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("verts", _P), ("n_verts", _I64), ("tris", _P), ("n_tris", _I64),
+                ("layout", _I32), ("stack_lds", _I32), ("reserved", _I32 * 2)]
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("probe_rays", _I32), ("leaf_size", _I32), ("probe", _P),
+                ("probe_offsets", ctypes.POINTER(_I64)), ("reserved", _I32 * 4)]
+
+
+class SceneInfo(ctypes.Structure):
+    _fields_ = [("layout", _I32), ("stack_lds", _I32), ("candidates", _I32),
+                ("probe_ns_per_ray", ctypes.c_float), ("n_nodes", _I64), ("bvh_bytes", _I64)]
 
 
 def lib() -> ctypes.CDLL:
@@ -86,6 +102,17 @@ def lib() -> ctypes.CDLL:
         L.bvh_trace_counts.restype = _I32
         L.bvh_trace_backward.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P, _P]
         L.bvh_trace_backward.restype = _I32
+        L.bvh_batch_create.argtypes = [ctypes.POINTER(SceneDesc), _I32, ctypes.POINTER(TuneOpts),
+                                       _P, ctypes.POINTER(_P)]
+        L.bvh_batch_create.restype = _I32
+        L.bvh_batch_get_scene_info.argtypes = [_P, _I32, ctypes.POINTER(SceneInfo)]
+        L.bvh_batch_get_scene_info.restype = _I32
+        L.bvh_batch_scene_handle.argtypes = [_P, _I32, ctypes.POINTER(_P)]
+        L.bvh_batch_scene_handle.restype = _I32
+        L.bvh_batch_trace.argtypes = [_P, _P, ctypes.POINTER(_I64), _P, _P]
+        L.bvh_batch_trace.restype = _I32
+        L.bvh_batch_destroy.argtypes = [_P]
+        L.bvh_batch_destroy.restype = _I32
         _lib = L
     return _lib
 
@@ -118,17 +145,19 @@ def _layout_id(layout) -> int:
 
 
 class BVH:
-    """A built BVH (owns the library handle).  Build with :func:`build`."""
+    """A built BVH.  Build with :func:`build`; a BVH taken from a
+    :class:`Batch` is borrowed (the batch owns it)."""
 
-    def __init__(self, handle: int, layout: int, leaf_mode: int):
+    def __init__(self, handle: int, layout: int, leaf_mode: int, owned: bool = True):
         self._h = handle
         self.layout = layout
         self.leaf_mode = leaf_mode
+        self._owned = owned
 
     def close(self):
-        if self._h:
+        if self._h and self._owned:
             lib().bvh_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -176,13 +205,13 @@ class BVH:
 
 
 def build(verts: torch.Tensor, tris: torch.Tensor, layout="bvh8_q8", leaf_size: int = 4,
-          leaf_mode="compact", stream=None) -> BVH:
+          leaf_mode="compact", stream=None, stack_lds: int = 0) -> BVH:
     """verts [V,3] float32 device, tris [N,3] int32 device."""
     _dev(verts, torch.float32, 3, "verts")
     _dev(tris, torch.int32, 3, "tris")
     lm = LEAF_MODES[leaf_mode] if isinstance(leaf_mode, str) else int(leaf_mode)
     lid = _layout_id(layout)
-    opts = BuildOpts(leaf_size, lm)
+    opts = BuildOpts(leaf_size, lm, stack_lds)
     h = _P()
     _check(lib().bvh_build(verts.data_ptr(), verts.shape[0], tris.data_ptr(), tris.shape[0], lid,
                            ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
@@ -240,3 +269,78 @@ class BVHTrace(torch.autograd.Function):
             return None, None, None, None, None, None
         gv, gr = trace_backward(verts, tris, rays, hits, grad_tuv.contiguous().float())
         return gv, None, gr[:, 0:3], gr[:, 3:6], None, None
+
+
+class Batch:
+    """Many scenes traced by one graph launch (bvh_batch_*).
+
+    scenes: list of (verts [V,3] f32, tris [N,3] i32) device tensors.
+    layout / stack_lds: None lets the tuner choose per scene; a value (or a
+    per-scene list) fixes it.  probe / probe_offsets: optional device rays and
+    host offsets for the tuner."""
+
+    def __init__(self, scenes, layout=None, stack_lds=None, probe=None, probe_offsets=None,
+                 probe_rays: int = 0, leaf_size: int = 4, stream=None):
+        n = len(scenes)
+        descs = (SceneDesc * n)()
+        lay = layout if isinstance(layout, (list, tuple)) else [layout] * n
+        sls = stack_lds if isinstance(stack_lds, (list, tuple)) else [stack_lds] * n
+        for i, (v, t) in enumerate(scenes):
+            _dev(v, torch.float32, 3, "verts")
+            _dev(t, torch.int32, 3, "tris")
+            descs[i].verts = v.data_ptr()
+            descs[i].n_verts = v.shape[0]
+            descs[i].tris = t.data_ptr()
+            descs[i].n_tris = t.shape[0]
+            descs[i].layout = -1 if lay[i] is None else _layout_id(lay[i])
+            descs[i].stack_lds = 0 if sls[i] is None else int(sls[i])
+        opts = TuneOpts(probe_rays, leaf_size)
+        self._probe_off = None
+        if probe is not None:
+            _dev(probe, torch.float32, 8, "probe")
+            self._probe_off = (_I64 * (n + 1))(*[int(x) for x in probe_offsets])
+            opts.probe = probe.data_ptr()
+            opts.probe_offsets = self._probe_off
+        b = _P()
+        _check(lib().bvh_batch_create(descs, n, ctypes.byref(opts), _stream(stream), ctypes.byref(b)))
+        self._b = b.value
+        self.n_scenes = n
+        self._off = None
+
+    def close(self):
+        if self._b:
+            lib().bvh_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, i: int) -> dict:
+        s = SceneInfo()
+        _check(lib().bvh_batch_get_scene_info(self._b, i, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def handle(self, i: int) -> BVH:
+        h = _P()
+        _check(lib().bvh_batch_scene_handle(self._b, i, ctypes.byref(h)))
+        inf = self.info(i)
+        return BVH(h.value, inf["layout"], LEAF_COMPACT, owned=False)
+
+    def trace(self, rays: torch.Tensor, offsets, hits: torch.Tensor = None, stream=None):
+        """rays [n,8] device; offsets: n_scenes + 1 ray offsets (host ints)."""
+        _dev(rays, torch.float32, 8, "rays")
+        if hits is None:
+            hits = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device)
+        _dev(hits, torch.float32, 4, "hits")
+        off = [int(x) for x in offsets]
+        if len(off) != self.n_scenes + 1:
+            raise ValueError("offsets must have n_scenes + 1 entries")
+        if off[-1] > rays.shape[0] or off[-1] > hits.shape[0]:
+            raise ValueError("offsets exceed the ray or hit buffer")
+        self._off = (_I64 * (self.n_scenes + 1))(*off)
+        _check(lib().bvh_batch_trace(self._b, rays.data_ptr(), self._off, hits.data_ptr(),
+                                     _stream(stream)))
+        return hits

@@ -79,6 +79,7 @@ extern "C" int32_t bvh_get_stats(bvh_handle_t h, bvh_stats *out) {
         out->scene_lo[a] = h->scene_lo[a];
         out->scene_hi[a] = h->scene_hi[a];
     }
+    out->stack_lds = h->stack_lds;
     return BVH_OK;
 }
 

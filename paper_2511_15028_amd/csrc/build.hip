@@ -1036,6 +1036,41 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
 
 using namespace bvhlib;
 
+namespace bvhlib {
+
+int32_t build_handle(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                     int32_t layout, int32_t leaf_size, int32_t leaf_mode, int32_t stack_lds,
+                     hipStream_t s, bvh_handle_s **out) {
+    *out = nullptr;
+    BVH_TRY(require_device());
+    int dev = 0;
+    BVH_HIP_TRY(hipGetDevice(&dev));
+    bvh_handle_s *h = new bvh_handle_s;
+    h->device = dev;
+    h->layout = layout;
+    h->leaf_mode = leaf_mode;
+    h->leaf_size = leaf_size;
+    h->stack_lds = stack_lds;
+    h->arity = layout_arity(layout);
+    h->n_tris = n_tris;
+    h->n_verts = n_verts;
+    h->node_bytes = node_record_bytes(layout);
+    if (n_tris == 0) {
+        *out = h;
+        return BVH_OK;
+    }
+    int32_t rc = build_impl(verts, n_verts, tris, n_tris, h, s);
+    if (rc != BVH_OK) {
+        std::string msg = bvh_last_error();
+        bvh_destroy(h);
+        return set_error(rc, "%s", msg.c_str());
+    }
+    *out = h;
+    return BVH_OK;
+}
+
+}  // namespace bvhlib
+
 extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t *tris,
                              int64_t n_tris, int32_t layout, const bvh_build_opts *opts,
                              void *stream, bvh_handle_t *out) {
@@ -1046,42 +1081,23 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
     if (n_tris > 0 && n_verts == 0) return set_error(BVH_EINVAL, "bvh_build: triangles without vertices");
     if (layout < 0 || layout >= BVH_NUM_LAYOUTS)
         return set_error(BVH_EINVAL, "bvh_build: unknown layout %d", layout);
-    int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT;
+    int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT, stack_lds = 16;
     if (opts) {
-        for (int k = 0; k < 6; k++)
+        for (int k = 0; k < 5; k++)
             if (opts->reserved[k] != 0) return set_error(BVH_EINVAL, "bvh_build: reserved option set");
         if (opts->leaf_size != 0) leaf_size = opts->leaf_size;
         if (opts->leaf_mode != 0) leaf_mode = opts->leaf_mode;
+        if (opts->stack_lds != 0) stack_lds = opts->stack_lds;
     }
     if (leaf_size < 1 || leaf_size > kMaxLeafSize)
         return set_error(BVH_EINVAL, "bvh_build: leaf_size %d outside 1..%d", leaf_size, kMaxLeafSize);
     if (leaf_mode != BVH_LEAF_COMPACT && leaf_mode != BVH_LEAF_INDEXED)
         return set_error(BVH_EINVAL, "bvh_build: unknown leaf mode %d", leaf_mode);
+    if (stack_lds != 8 && stack_lds != 16 && stack_lds != 32)
+        return set_error(BVH_EINVAL, "bvh_build: stack_lds %d is not 8, 16 or 32", stack_lds);
     if (n_tris > kMaxTris)
         return set_error(BVH_EUNSUPPORTED, "bvh_build: %lld triangles exceed %lld",
                          (long long)n_tris, (long long)kMaxTris);
-    BVH_TRY(require_device());
-    int dev = 0;
-    BVH_HIP_TRY(hipGetDevice(&dev));
-    bvh_handle_s *h = new bvh_handle_s;
-    h->device = dev;
-    h->layout = layout;
-    h->leaf_mode = leaf_mode;
-    h->leaf_size = leaf_size;
-    h->arity = layout_arity(layout);
-    h->n_tris = n_tris;
-    h->n_verts = n_verts;
-    h->node_bytes = node_record_bytes(layout);
-    if (n_tris == 0) {
-        *out = h;
-        return BVH_OK;
-    }
-    int32_t rc = build_impl(verts, n_verts, tris, n_tris, h, static_cast<hipStream_t>(stream));
-    if (rc != BVH_OK) {
-        std::string msg = bvh_last_error();
-        bvh_destroy(h);
-        return set_error(rc, "%s", msg.c_str());
-    }
-    *out = h;
-    return BVH_OK;
+    return build_handle(verts, n_verts, tris, n_tris, layout, leaf_size, leaf_mode, stack_lds,
+                        static_cast<hipStream_t>(stream), out);
 }

@@ -35,16 +35,16 @@ int32_t set_error(int32_t code, const char *fmt, ...);
 // Fails with ENODEV when no HIP device is present.
 int32_t require_device();
 
+
+
 // ---------------------------------------------------------------------------
 // Limits shared by build and trace
 // ---------------------------------------------------------------------------
 constexpr int kMaxLeafSize = 16;
 constexpr int64_t kMaxTris = (int64_t(1) << 27) - 1;   // leaf ref has 27 offset bits
-// Traversal stack: kStackLds entries per lane in LDS, then a private
-// overflow area of kStackOvf entries.
-constexpr int kStackLds = 16;
-constexpr int kStackOvf = 240;
-constexpr int kStackMax = kStackLds + kStackOvf;
+// Traversal stack: the newest 8, 16 or 32 entries per lane live in LDS, the
+// rest in a private overflow area; kStackMax entries in all.
+constexpr int kStackMax = 256;
 
 // ---------------------------------------------------------------------------
 // Handle
@@ -56,6 +56,7 @@ struct bvh_handle_s {
     int32_t layout = 0;
     int32_t leaf_mode = 0;
     int32_t leaf_size = 4;
+    int32_t stack_lds = 16;
     int32_t arity = 2;
     int64_t n_tris = 0;
     int64_t n_verts = 0;
@@ -91,6 +92,18 @@ inline int32_t layout_arity(int32_t layout) {
         default: return 8;
     }
 }
+
+// EINVAL unless the calling thread's current device is the handle's device.
+int32_t check_handle_device(const bvh_handle_s *h, const char *who);
+
+// Builds one BVH (bvh_build after argument checks); used by the batch path.
+int32_t build_handle(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                     int32_t layout, int32_t leaf_size, int32_t leaf_mode, int32_t stack_lds,
+                     hipStream_t s, bvh_handle_s **out);
+
+// bvh_trace without argument checks (closest or any hit, no counters).
+int32_t trace_launch(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits,
+                     int32_t mode, hipStream_t s);
 
 static_assert(sizeof(bvh_ray) == 32, "bvh_ray");
 static_assert(sizeof(bvh_hit) == 16, "bvh_hit");

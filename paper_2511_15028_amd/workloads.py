@@ -407,3 +407,69 @@ def diff_workload(seed=1004, level=7, n_cams=64, res=128):
     rays = sphere_cameras_rays(n_cams, res)
     w = _rng(seed, 9).uniform(-1.0, 1.0, (rays.shape[0], 3)).astype(np.float32)
     return dict(name=f"ico{level}", verts=verts, tris=tris, rays=rays, weights=w)
+
+
+def sphere_cluster_exact(n_tris, seed, quota=SPHERE_LEVEL_QUOTA, tris_per_sphere=7717):
+    """A sphere cluster of exactly n_tris triangles: ceil(n_tris / 7717)
+    icospheres (7717 = the mean triangles per sphere of the 512-sphere scene),
+    levels by radius rank with the same proportions as that scene's quota,
+    the largest spheres' levels lowered until the count fits, slivers for the
+    remainder."""
+    rng = _rng(seed, 0)
+    k = max(1, int(math.ceil(n_tris / tris_per_sphere)))
+    centers = rng.uniform(0.0, 1.0, (k, 3))
+    radii = np.exp(rng.uniform(math.log(0.005), math.log(0.2), k))
+    total_q = sum(c for _, c in quota)
+    bounds = np.cumsum([c for _, c in quota])
+    order = np.argsort(radii, kind="stable")
+    levels = np.empty(k, np.int64)
+    for r, s in enumerate(order):
+        pos = (r + 0.5) / k * total_q
+        levels[s] = quota[int(np.searchsorted(bounds, pos))][0]
+    count = lambda: int(sum(20 * 4 ** int(l) for l in levels))
+    for s in order[::-1]:                 # largest first
+        while count() > n_tris and levels[s] > 0:
+            levels[s] -= 1
+    vs, fs, base = [], [], 0
+    if count() <= n_tris:
+        for s in range(k):
+            v, f = icosphere(int(levels[s]))
+            vs.append(centers[s] + radii[s] * v)
+            fs.append(f + base)
+            base += v.shape[0]
+        n_sl = n_tris - count()
+    else:                                 # fewer than 20 triangles: slivers only
+        n_sl = n_tris
+    if n_sl > 0:
+        sl = _slivers(rng, n_sl)
+        vs.append(sl)
+        fs.append(base + np.arange(sl.shape[0], dtype=np.int64).reshape(-1, 3))
+    verts = np.concatenate(vs, axis=0).astype(np.float32)
+    tris = np.concatenate(fs, axis=0).astype(np.int32)
+    assert tris.shape[0] == n_tris
+    return verts, tris
+
+
+def batch_workload(seed=1003, n_scenes=256, tri_range=(1e3, 5e5), ray_range=(1e3, 1e6)):
+    """Scenes of uneven size for batched tracing: triangle counts log-uniform
+    in tri_range (even scenes: soups as in the soup workload; odd scenes:
+    sphere clusters with slivers), each with a log-uniform number of
+    incoherent rays (origins U[0,1]^3, uniform directions).  Returns a dict
+    with per-scene (verts, tris), the concatenated rays and the ray offsets."""
+    rng = _rng(seed, 0)
+    lt = np.log(np.asarray(tri_range, np.float64))
+    lr = np.log(np.asarray(ray_range, np.float64))
+    n_tris = np.round(np.exp(rng.uniform(lt[0], lt[1], n_scenes))).astype(np.int64)
+    n_rays = np.round(np.exp(rng.uniform(lr[0], lr[1], n_scenes))).astype(np.int64)
+    scenes, rays = [], []
+    for i in range(n_scenes):
+        s = seed * 1000 + i
+        if i % 2 == 0:
+            scenes.append(soup_scene(int(n_tris[i]), seed=s))
+        else:
+            scenes.append(sphere_cluster_exact(int(n_tris[i]), seed=s))
+        rays.append(uniform_rays(int(n_rays[i]), seed=s, tag=2))
+    offsets = np.zeros(n_scenes + 1, np.int64)
+    offsets[1:] = np.cumsum(n_rays)
+    return dict(name=f"batch-{n_scenes}", scenes=scenes, rays=np.concatenate(rays),
+                offsets=offsets, n_tris=n_tris, n_rays=n_rays)

@@ -59,6 +59,8 @@ def test_build_argument_validation(L):
     res = bvh.BuildOpts(4, 0)
     res.reserved[2] = 1
     assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(res), None, ctypes.byref(h)) == bvh.EINVAL
+    res = bvh.BuildOpts(4, 0, 12)
+    assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(res), None, ctypes.byref(h)) == bvh.EINVAL
     assert L.bvh_build(fake, 3, fake, 1 << 27, 0, None, None, ctypes.byref(h)) == bvh.EUNSUPPORTED
 
 
@@ -73,3 +75,50 @@ def test_trace_and_backward_argument_validation(L):
     assert L.bvh_get_stats(None, None) == bvh.EINVAL
     assert L.bvh_read_buffer(None, 0, None, 0, None) == bvh.EINVAL
     assert L.bvh_destroy(None) == bvh.OK
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors in bvh.py have the sizes and field offsets of the C
+    structs in bvh.h (checked by compiling the header with gcc)."""
+    import subprocess
+    from paper_2511_15028_amd import bvh
+    pairs = {"bvh_build_opts": bvh.BuildOpts, "bvh_stats": bvh.Stats,
+             "bvh_scene_desc": bvh.SceneDesc, "bvh_tune_opts": bvh.TuneOpts,
+             "bvh_batch_scene_info": bvh.SceneInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bvh.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append('printf("bvh_ray %zu\\nbvh_hit %zu\\nbvh_tri %zu\\n", sizeof(bvh_ray), sizeof(bvh_hit), sizeof(bvh_tri));')
+    lines.append("return 0; }")
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True,
+                                                               text=True, check=True).stdout.split("\n") if line)
+    for cname, py in pairs.items():
+        assert int(out[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+    assert (out["bvh_ray"], out["bvh_hit"], out["bvh_tri"]) == ("32", "16", "48")
+
+
+def test_batch_argument_validation(L):
+    from paper_2511_15028_amd import bvh
+    b = ctypes.c_void_p(7)
+    descs = (bvh.SceneDesc * 2)()
+    assert L.bvh_batch_create(descs, 0, None, None, ctypes.byref(b)) == bvh.EINVAL
+    assert b.value is None
+    descs[0].layout = 9
+    assert L.bvh_batch_create(descs, 2, None, None, ctypes.byref(b)) == bvh.EINVAL
+    descs[0].layout = -1
+    descs[1].stack_lds = 12
+    assert L.bvh_batch_create(descs, 2, None, None, ctypes.byref(b)) == bvh.EINVAL
+    descs[1].stack_lds = 0
+    descs[1].n_tris = 5  # no mesh pointers
+    assert L.bvh_batch_create(descs, 2, None, None, ctypes.byref(b)) == bvh.EINVAL
+    assert L.bvh_batch_trace(None, None, None, None, None) == bvh.EINVAL
+    assert L.bvh_batch_destroy(None) == bvh.OK
