@@ -83,8 +83,10 @@ typedef struct bvh_hit {
 typedef struct bvh_build_opts {
     int32_t leaf_size;   /* max triangles per leaf, 1..16 (default 4) */
     int32_t leaf_mode;   /* BVH_LEAF_COMPACT (default) or BVH_LEAF_INDEXED */
-    int32_t stack_lds;   /* traversal stack entries kept in LDS per ray: 8, 16 (default) or 32;
-                            deeper entries spill to per-lane scratch.  Results do not depend on it. */
+    int32_t stack_lds;   /* traversal stack entries kept in LDS per ray: 8, 16 or 32 (default:
+                            32 for AABB2, 16 for the wide layouts).  A ray that needs more is
+                            re-traced by a fallback pass with a deep stack in global memory.
+                            Results do not depend on it. */
     int32_t reserved[5]; /* must be zero */
 } bvh_build_opts;
 

@@ -42,14 +42,16 @@ __device__ inline uint32_t find_scene(const uint32_t *tile_off, uint32_t n, uint
 
 // Persistent kernel: each wave takes 64-ray tiles from the group's queue
 // until it is empty.  Every wave reaches the exit (no wave ever waits on
-// another), so the grid always drains.
+// another), so the grid always drains.  Rays that overflow the LDS stack go
+// to the group's fallback list.
 template <int Layout, int SL>
 __global__ __launch_bounds__(kTraceBlock) void k_batch_trace(const BatchScene *scenes,
                                                              const uint32_t *tile_off,
                                                              uint32_t n_scenes,
                                                              uint32_t total_tiles,
                                                              uint32_t *counter,
-                                                             const bvh_ray *rays, bvh_hit *hits) {
+                                                             const bvh_ray *rays, bvh_hit *hits,
+                                                             Fallback fb) {
     __shared__ uint32_t s_ref[SL * kTraceBlock];
     __shared__ float s_t[(Layout == BVH_LAYOUT_AABB2 ? 1 : SL) * kTraceBlock];
     const int lane = threadIdx.x & 63;
@@ -66,21 +68,73 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_trace(const BatchScene *s
             const Ray r = load_ray(rays, i);
             const LeafData ld{sc.leaf, nullptr, nullptr, sc.n_tris};
             uint32_t nf = 0, nt = 0;
+            bool incomplete = false;
             Best b;
-            if (Layout == BVH_LAYOUT_AABB2)
-                b = trace_aabb2<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST, SL>(
-                    static_cast<const bvh_node_aabb2 *>(sc.nodes), sc.n_nodes, ld, r, s_ref, nf, nt);
-            else if (Layout == BVH_LAYOUT_BVH4)
-                b = trace_wide<DecodeBVH4, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST, SL>(
-                    sc.nodes, sc.n_nodes, ld, r, s_ref, s_t, nf, nt);
-            else if (Layout == BVH_LAYOUT_BVH8_Q8)
-                b = trace_wide<DecodeBVH8Q8, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST, SL>(
-                    sc.nodes, sc.n_nodes, ld, r, s_ref, s_t, nf, nt);
-            else
-                b = trace_wide<DecodeBVH8Q16, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST, SL>(
-                    sc.nodes, sc.n_nodes, ld, r, s_ref, s_t, nf, nt);
-            store_hit(hits, i, b);
+            if (Layout == BVH_LAYOUT_AABB2) {
+                LdsStack<false, SL> st(s_ref, nullptr);
+                b = trace_aabb2<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                    static_cast<const bvh_node_aabb2 *>(sc.nodes), sc.n_nodes, ld, r, st, nf, nt,
+                    incomplete);
+            } else {
+                LdsStack<true, SL> st(s_ref, s_t);
+                if (Layout == BVH_LAYOUT_BVH4)
+                    b = trace_wide<DecodeBVH4, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                        sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
+                else if (Layout == BVH_LAYOUT_BVH8_Q8)
+                    b = trace_wide<DecodeBVH8Q8, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                        sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
+                else
+                    b = trace_wide<DecodeBVH8Q16, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                        sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
+            }
+            if (incomplete) fallback_append(fb, (uint32_t)i);
+            else store_hit(hits, i, b);
         }
+    }
+}
+
+// The group's fallback: re-trace listed rays with a deep global stack; the
+// scene of a ray is found from the scenes' ray ranges (disjoint, increasing).
+template <int Layout>
+__global__ __launch_bounds__(kTraceBlock) void k_batch_fallback(const BatchScene *scenes,
+                                                                uint32_t n_scenes,
+                                                                const bvh_ray *rays, bvh_hit *hits,
+                                                                Fallback fb) {
+    const uint32_t lane = blockIdx.x * kTraceBlock + threadIdx.x;
+    const uint32_t total = *fb.count;
+    for (uint32_t k = lane; k < total; k += kFallbackLanes) {
+        const uint32_t i = fb.list[k];
+        uint32_t lo = 0, hi = n_scenes;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (scenes[mid].ray_begin <= i) lo = mid;
+            else hi = mid;
+        }
+        const BatchScene sc = scenes[lo];
+        const Ray r = load_ray(rays, i);
+        const LeafData ld{sc.leaf, nullptr, nullptr, sc.n_tris};
+        uint32_t nf = 0, nt = 0;
+        bool incomplete = false;
+        Best b;
+        if (Layout == BVH_LAYOUT_AABB2) {
+            GlobalStack<false> st(fb.stack_ref + (size_t)lane * kStackMax, nullptr);
+            b = trace_aabb2<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                static_cast<const bvh_node_aabb2 *>(sc.nodes), sc.n_nodes, ld, r, st, nf, nt,
+                incomplete);
+        } else {
+            GlobalStack<true> st(fb.stack_ref + (size_t)lane * kStackMax,
+                                 fb.stack_t + (size_t)lane * kStackMax);
+            if (Layout == BVH_LAYOUT_BVH4)
+                b = trace_wide<DecodeBVH4, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                    sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
+            else if (Layout == BVH_LAYOUT_BVH8_Q8)
+                b = trace_wide<DecodeBVH8Q8, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                    sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
+            else
+                b = trace_wide<DecodeBVH8Q16, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                    sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
+        }
+        store_hit(hits, i, b);
     }
 }
 
@@ -126,7 +180,17 @@ __global__ void k_probe_rays(bvh_ray *out, uint32_t n, float lx, float ly, float
 }
 
 using KernelFn = void (*)(const BatchScene *, const uint32_t *, uint32_t, uint32_t, uint32_t *,
-                          const bvh_ray *, bvh_hit *);
+                          const bvh_ray *, bvh_hit *, Fallback);
+using FallbackFn = void (*)(const BatchScene *, uint32_t, const bvh_ray *, bvh_hit *, Fallback);
+
+FallbackFn fallback_for(int layout) {
+    switch (layout) {
+        case BVH_LAYOUT_AABB2: return &k_batch_fallback<BVH_LAYOUT_AABB2>;
+        case BVH_LAYOUT_BVH4: return &k_batch_fallback<BVH_LAYOUT_BVH4>;
+        case BVH_LAYOUT_BVH8_Q8: return &k_batch_fallback<BVH_LAYOUT_BVH8_Q8>;
+        default: return &k_batch_fallback<BVH_LAYOUT_BVH8_Q16>;
+    }
+}
 
 template <int Layout>
 KernelFn kernel_for_sl(int sl) {
@@ -207,19 +271,15 @@ int32_t create_impl(const bvh_scene_desc *scenes, int32_t n_scenes, const bvh_tu
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int32_t rc = BVH_OK;
     auto cleanup = [&]() {
-        if (gen) (void)hipFreeAsync(gen, s);
-        if (hits) (void)hipFreeAsync(hits, s);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
     if (max_probe > 0) {
-        if (hipMallocAsync((void **)&hits, (size_t)max_probe * sizeof(bvh_hit), s) != hipSuccess ||
-            (!(opts && opts->probe) &&
-             hipMallocAsync((void **)&gen, (size_t)max_probe * sizeof(bvh_ray), s) != hipSuccess)) {
-            (void)hipGetLastError();
-            cleanup();
-            return set_error(BVH_ENOMEM, "bvh_batch_create: probe buffers");
-        }
+        Arena arena;
+        arena.request(&hits, (size_t)max_probe);
+        if (!(opts && opts->probe)) arena.request(&gen, (size_t)max_probe);
+        rc = arena.bind(s, kAreaTune);
+        if (rc != BVH_OK) return rc;
     }
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         cleanup();
@@ -336,17 +396,19 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
     }
     int n_cu = 0;
     BVH_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+    // counters[g]: work queue of group g; counters[ngroups + g]: its fallback count
+    const int ngroups = (int)groups.size();
     uint32_t *counters = nullptr;
-    BVH_TRY(upload(b, std::vector<uint32_t>(std::max<size_t>(groups.size(), 1), 0u), &counters));
+    BVH_TRY(upload(b, std::vector<uint32_t>(std::max<size_t>(2 * groups.size(), 1), 0u), &counters));
     BVH_HIP_TRY(hipGraphCreate(&b->graph, 0));
     hipGraphNode_t reset;
     {
-        int ngroups = (int)groups.size();
-        void *args[] = {&counters, &ngroups};
+        int nctr = 2 * ngroups;
+        void *args[] = {&counters, &nctr};
         hipKernelNodeParams p{};
         p.func = reinterpret_cast<void *>(&k_reset_counters);
-        p.gridDim = dim3(1);
-        p.blockDim = dim3(64);
+        p.gridDim = dim3((unsigned)((2 * ngroups + 255) / 256 + 1));
+        p.blockDim = dim3(256);
         p.sharedMemBytes = 0;
         p.kernelParams = args;
         p.extra = nullptr;
@@ -384,7 +446,15 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
         uint32_t *ctr = counters + g;
         const bvh_ray *r = rays;
         bvh_hit *hh = hits;
-        void *args[] = {&d_sc, &d_toff, &nsc, (void *)&total, &ctr, &r, &hh};
+        // fallback work area of this group (list sized for all its rays)
+        uint64_t group_rays = 0;
+        for (const BatchScene &x : sc) group_rays += x.ray_count;
+        void *ws = nullptr;
+        BVH_HIP_TRY(hipMalloc(&ws, fallback_bytes(group_rays)));
+        b->g_mem.push_back(ws);
+        Fallback fb = fallback_view(ws, group_rays);
+        fb.count = counters + ngroups + g;
+        void *args[] = {&d_sc, &d_toff, &nsc, (void *)&total, &ctr, &r, &hh, &fb};
         hipKernelNodeParams p{};
         p.func = reinterpret_cast<void *>(fn);
         p.gridDim = dim3(grid);
@@ -394,6 +464,16 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
         p.extra = nullptr;
         hipGraphNode_t node;
         BVH_HIP_TRY(hipGraphAddKernelNode(&node, b->graph, &reset, 1, &p));
+        void *fargs[] = {&d_sc, &nsc, &r, &hh, &fb};
+        hipKernelNodeParams q{};
+        q.func = reinterpret_cast<void *>(fallback_for(kv.first.first));
+        q.gridDim = dim3(kFallbackBlocks);
+        q.blockDim = dim3(kTraceBlock);
+        q.sharedMemBytes = 0;
+        q.kernelParams = fargs;
+        q.extra = nullptr;
+        hipGraphNode_t fnode;
+        BVH_HIP_TRY(hipGraphAddKernelNode(&fnode, b->graph, &node, 1, &q));
         g++;
     }
     BVH_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -479,6 +559,8 @@ extern "C" int32_t bvh_batch_trace(bvh_batch_t b, const bvh_ray *rays, const int
     if (ray_offsets[n] > ray_offsets[0] && (!rays || !hits))
         return set_error(BVH_EINVAL, "bvh_batch_trace: null ray or hit buffer");
     if (ray_offsets[n] == ray_offsets[0]) return BVH_OK;
+    if (ray_offsets[n] > (int64_t)0xFFFFFFFFll)
+        return set_error(BVH_EUNSUPPORTED, "bvh_batch_trace: more than 2^32 - 1 rays");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
         return set_error(BVH_EINVAL, "bvh_batch_trace: batch belongs to another device");

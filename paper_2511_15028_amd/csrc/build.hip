@@ -788,44 +788,6 @@ __global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, con
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-// Build temporaries come from the device's stream-ordered memory pool
-// (hipMallocAsync / hipFreeAsync on the build stream); the pool keeps freed
-// blocks, so repeated builds do not return to the driver.
-struct DeviceTemps {
-    hipStream_t stream;
-    std::vector<void *> ptrs;
-    explicit DeviceTemps(hipStream_t s) : stream(s) {}
-    ~DeviceTemps() {
-        for (void *p : ptrs) (void)hipFreeAsync(p, stream);
-    }
-    template <typename T>
-    int32_t alloc(T **out, size_t count) {
-        void *p = nullptr;
-        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-        hipError_t e = hipMallocAsync(&p, bytes, stream);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return set_error(BVH_ENOMEM, "hipMallocAsync(%zu bytes) failed: %s", bytes,
-                             hipGetErrorString(e));
-        }
-        ptrs.push_back(p);
-        *out = static_cast<T *>(p);
-        return BVH_OK;
-    }
-};
-
-// Keeps freed pool memory cached in the device's default pool.
-int32_t retain_pool_memory(int dev) {
-    static bool done[64] = {};
-    if (dev < 0 || dev >= 64 || done[dev]) return BVH_OK;
-    hipMemPool_t pool;
-    BVH_HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
-    uint64_t threshold = UINT64_MAX;
-    BVH_HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold));
-    done[dev] = true;
-    return BVH_OK;
-}
-
 // Small pinned host staging area for device-to-host readbacks (one per thread).
 template <typename T>
 T *pinned_scratch() {
@@ -846,22 +808,24 @@ int32_t check_launch(const char *what) {
 
 template <int Layout>
 int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, BuildInfo *info_host,
-                  bvh_handle_s *h, DeviceTemps &tmp, hipStream_t s) {
+                  bvh_handle_s *h, hipStream_t s) {
     constexpr int K = WideOut<Layout>::K;
     const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
     void *wnodes;
     int32_t *fr_node[2], *cand;
     uint32_t *fr_aux[2], *noff, *tile;
     uint8_t *raw;
-    BVH_TRY(tmp.alloc(&raw, (size_t)cap * h->node_bytes));
+    Arena arena;
+    arena.request(&raw, (size_t)cap * h->node_bytes);
+    arena.request(&fr_node[0], cap);
+    arena.request(&fr_node[1], cap);
+    arena.request(&fr_aux[0], cap);
+    arena.request(&fr_aux[1], cap);
+    arena.request(&cand, (size_t)cap * K);
+    arena.request(&noff, cap);
+    arena.request(&tile, (cap + kScanTile - 1) / kScanTile + 1);
+    BVH_TRY(arena.bind(s, kAreaBuildWide));
     wnodes = raw;
-    BVH_TRY(tmp.alloc(&fr_node[0], cap));
-    BVH_TRY(tmp.alloc(&fr_node[1], cap));
-    BVH_TRY(tmp.alloc(&fr_aux[0], cap));
-    BVH_TRY(tmp.alloc(&fr_aux[1], cap));
-    BVH_TRY(tmp.alloc(&cand, (size_t)cap * K));
-    BVH_TRY(tmp.alloc(&noff, cap));
-    BVH_TRY(tmp.alloc(&tile, (cap + kScanTile - 1) / kScanTile + 1));
     const int32_t root = 0;
     const uint32_t zero = 0;
     BVH_HIP_TRY(hipMemcpyAsync(fr_node[0], &root, sizeof(root), hipMemcpyHostToDevice, s));
@@ -898,8 +862,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
                    bvh_handle_s *h, hipStream_t s) {
     const int n = (int)n_tris;
     const int L = h->leaf_size;
-    BVH_TRY(retain_pool_memory(h->device));
-    DeviceTemps tmp(s);
+
     Box *pbox, *nbox;
     float *partial;
     BuildInfo *info;
@@ -911,23 +874,30 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     const uint32_t nsort = (uint32_t)((n + kSortTile - 1) / kSortTile);
     const uint32_t nhist = nsort * kRadix;
     const uint32_t max_scan = std::max<uint32_t>(nhist, (uint32_t)n);
-    BVH_TRY(tmp.alloc(&pbox, n));
-    BVH_TRY(tmp.alloc(&partial, (size_t)nb * 12));
-    BVH_TRY(tmp.alloc(&info, 1));
-    BVH_TRY(tmp.alloc(&keys[0], n));
-    BVH_TRY(tmp.alloc(&keys[1], n));
-    BVH_TRY(tmp.alloc(&vals[0], n));
-    BVH_TRY(tmp.alloc(&vals[1], n));
-    BVH_TRY(tmp.alloc(&hist, nhist));
-    BVH_TRY(tmp.alloc(&tile, (max_scan + kScanTile - 1) / kScanTile + 1));
-    BVH_TRY(tmp.alloc(&ileft, n - 1));
-    BVH_TRY(tmp.alloc(&iright, n - 1));
-    BVH_TRY(tmp.alloc(&ifirst, n - 1));
-    BVH_TRY(tmp.alloc(&icount, n - 1));
-    BVH_TRY(tmp.alloc(&iaxis, n - 1));
-    BVH_TRY(tmp.alloc(&parent, 2 * (size_t)n - 1));
-    BVH_TRY(tmp.alloc(&nbox, 2 * (size_t)n - 1));
-    BVH_TRY(tmp.alloc(&mark, n));
+    const int nblocks = (n + kRangeBlock - 1) / kRangeBlock;
+    int levels = 1;
+    while ((1 << levels) <= nblocks) levels++;
+    Box *table;
+    Arena arena;
+    arena.request(&pbox, n);
+    arena.request(&partial, (size_t)nb * 12);
+    arena.request(&info, 1);
+    arena.request(&keys[0], n);
+    arena.request(&keys[1], n);
+    arena.request(&vals[0], n);
+    arena.request(&vals[1], n);
+    arena.request(&hist, nhist);
+    arena.request(&tile, (max_scan + kScanTile - 1) / kScanTile + 1);
+    arena.request(&ileft, n - 1);
+    arena.request(&iright, n - 1);
+    arena.request(&ifirst, n - 1);
+    arena.request(&icount, n - 1);
+    arena.request(&iaxis, n - 1);
+    arena.request(&parent, 2 * (size_t)n - 1);
+    arena.request(&nbox, 2 * (size_t)n - 1);
+    arena.request(&mark, n);
+    arena.request(&table, (size_t)levels * nblocks);
+    BVH_TRY(arena.bind(s, kAreaBuild));
 
     BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
     BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
@@ -954,11 +924,6 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
                                                     iaxis, parent);
     {
-        const int nblocks = (n + kRangeBlock - 1) / kRangeBlock;
-        int levels = 1;
-        while ((1 << levels) <= nblocks) levels++;
-        Box *table;
-        BVH_TRY(tmp.alloc(&table, (size_t)levels * nblocks));
         k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table);
         for (int k = 1; k < levels; k++) {
             const int half = 1 << (k - 1);
@@ -995,11 +960,11 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
             tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
         BVH_TRY(check_launch("aabb2 packing"));
     } else if (h->layout == BVH_LAYOUT_BVH4) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, &hi, h, tmp, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, &hi, h, s));
     } else if (h->layout == BVH_LAYOUT_BVH8_Q8) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, &hi, h, tmp, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, &hi, h, s));
     } else {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, &hi, h, tmp, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, &hi, h, s));
     }
 
     // leaf data
@@ -1081,7 +1046,10 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
     if (n_tris > 0 && n_verts == 0) return set_error(BVH_EINVAL, "bvh_build: triangles without vertices");
     if (layout < 0 || layout >= BVH_NUM_LAYOUTS)
         return set_error(BVH_EINVAL, "bvh_build: unknown layout %d", layout);
-    int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT, stack_lds = 16;
+    // LDS stack default: binary trees push one entry per level (32 entries of
+    // 4 B); wide trees push up to arity-1 entries of 8 B (16 entries)
+    int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT;
+    int32_t stack_lds = layout == BVH_LAYOUT_AABB2 ? 32 : 16;
     if (opts) {
         for (int k = 0; k < 5; k++)
             if (opts->reserved[k] != 0) return set_error(BVH_EINVAL, "bvh_build: reserved option set");

@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
+#include <vector>
 
 #include "bvh.h"
 
@@ -42,8 +44,9 @@ int32_t require_device();
 // ---------------------------------------------------------------------------
 constexpr int kMaxLeafSize = 16;
 constexpr int64_t kMaxTris = (int64_t(1) << 27) - 1;   // leaf ref has 27 offset bits
-// Traversal stack: the newest 8, 16 or 32 entries per lane live in LDS, the
-// rest in a private overflow area; kStackMax entries in all.
+// Traversal stack bound: the fast pass keeps 8, 16 or 32 entries per lane in
+// LDS; rays that need more are re-traced with a deep stack of kStackMax
+// entries, so a tree's worst-case stack need must not exceed it.
 constexpr int kStackMax = 256;
 
 // ---------------------------------------------------------------------------
@@ -104,6 +107,41 @@ int32_t build_handle(const float *verts, int64_t n_verts, const int32_t *tris, i
 // bvh_trace without argument checks (closest or any hit, no counters).
 int32_t trace_launch(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits,
                      int32_t mode, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Device work areas (workspace.hip): grow-only, one per (device, stream,
+// purpose), kept until the process ends.  Callers that use one stream from
+// several host threads must serialise those calls themselves.
+// ---------------------------------------------------------------------------
+enum AreaPurpose { kAreaBuild = 0, kAreaBuildWide = 1, kAreaTrace = 2, kAreaTune = 3 };
+int32_t stream_workspace(hipStream_t s, int purpose, size_t bytes, void **out);
+
+// Carves several device buffers out of one work area: request() them all,
+// then bind() once.
+class Arena {
+  public:
+    template <typename T>
+    void request(T **slot, size_t count) {
+        reqs_.push_back(Req{reinterpret_cast<void **>(slot), total_});
+        total_ += (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~size_t(255);
+    }
+    int32_t bind(hipStream_t s, int purpose) {
+        void *base = nullptr;
+        int32_t rc = stream_workspace(s, purpose, total_, &base);
+        if (rc != 0) return rc;
+        for (const Req &r : reqs_) *r.slot = static_cast<char *>(base) + r.offset;
+        return 0;
+    }
+    size_t bytes() const { return total_; }
+
+  private:
+    struct Req {
+        void **slot;
+        size_t offset;
+    };
+    std::vector<Req> reqs_;
+    size_t total_ = 0;
+};
 
 static_assert(sizeof(bvh_ray) == 32, "bvh_ray");
 static_assert(sizeof(bvh_hit) == 16, "bvh_hit");

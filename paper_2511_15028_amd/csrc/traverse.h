@@ -162,42 +162,52 @@ __device__ inline bool test_leaf(const LeafData &ld, const Ray &r, uint32_t firs
 }
 
 // ---------------------------------------------------------------------------
-// Per-lane traversal stack: the newest SL entries live in LDS (one column per
-// lane, so lanes never share a bank), older entries spill to a private
-// overflow array.  The build guarantees at most kStackMax entries.
+// Traversal stacks.  The fast path keeps SL entries per lane in LDS (one
+// column per lane, so lanes never share a bank) and has no overflow area: a
+// push beyond SL fails, the ray stops and is re-traced by the fallback pass,
+// which keeps a deep stack (kStackMax entries, the build's bound) in a
+// global-memory workspace.  No private (scratch) memory is used.
 // ---------------------------------------------------------------------------
 template <bool WithT, int SL>
-struct LaneStack {
-    static constexpr int kOvf = kStackMax - SL;
+struct LdsStack {
     uint32_t *lds_ref;  // [SL][kTraceBlock]
     float *lds_t;
-    uint32_t ovf_ref[kOvf];
-    float ovf_t[WithT ? kOvf : 1];
     uint32_t sp = 0;
-
-    __device__ void push(uint32_t ref, float t) {
-        const uint32_t slot = (sp % SL) * kTraceBlock + threadIdx.x;
-        if (sp >= (uint32_t)SL) {
-            const uint32_t o = sp - SL;
-            if (o >= (uint32_t)kOvf) return;  // unreachable for trees the build accepts
-            ovf_ref[o] = lds_ref[slot];
-            if (WithT) ovf_t[o] = lds_t[slot];
-        }
+    __device__ LdsStack(uint32_t *r, float *t) : lds_ref(r), lds_t(t) {}
+    __device__ bool push(uint32_t ref, float t) {
+        if (sp >= (uint32_t)SL) return false;
+        const uint32_t slot = sp * kTraceBlock + threadIdx.x;
         lds_ref[slot] = ref;
         if (WithT) lds_t[slot] = t;
         sp++;
+        return true;
     }
     __device__ uint32_t pop(float &t) {
         sp--;
-        const uint32_t slot = (sp % SL) * kTraceBlock + threadIdx.x;
-        const uint32_t ref = lds_ref[slot];
+        const uint32_t slot = sp * kTraceBlock + threadIdx.x;
         t = WithT ? lds_t[slot] : 0.0f;
-        if (sp >= (uint32_t)SL) {
-            const uint32_t o = sp - SL;
-            lds_ref[slot] = ovf_ref[o];
-            if (WithT) lds_t[slot] = ovf_t[o];
-        }
-        return ref;
+        return lds_ref[slot];
+    }
+};
+
+// Deep stack of one lane in global memory: ref[kStackMax], t[kStackMax].
+template <bool WithT>
+struct GlobalStack {
+    uint32_t *ref;
+    float *tt;
+    uint32_t sp = 0;
+    __device__ GlobalStack(uint32_t *r, float *t) : ref(r), tt(t) {}
+    __device__ bool push(uint32_t r, float t) {
+        if (sp >= (uint32_t)kStackMax) return false;  // the build bounds the depth by kStackMax
+        ref[sp] = r;
+        if (WithT) tt[sp] = t;
+        sp++;
+        return true;
+    }
+    __device__ uint32_t pop(float &t) {
+        sp--;
+        t = WithT ? tt[sp] : 0.0f;
+        return ref[sp];
     }
 };
 
@@ -216,13 +226,11 @@ __device__ inline void store_hit(bvh_hit *hits, uint64_t i, const Best &b) {
 // box against the current best, descend near child first (split axis and
 // ray direction sign), push the far child.  s_ref: [SL][kTraceBlock] LDS.
 // ---------------------------------------------------------------------------
-template <int LeafMode, int Mode, int SL>
+template <int LeafMode, int Mode, class Stack>
 __device__ inline Best trace_aabb2(const bvh_node_aabb2 *nodes, int64_t n_nodes, const LeafData &ld,
-                                   const Ray &r, uint32_t *s_ref, uint32_t &nfetch, uint32_t &ntri) {
+                                   const Ray &r, Stack &st, uint32_t &nfetch, uint32_t &ntri,
+                                   bool &incomplete) {
     Best best{INFINITY, 0.0f, 0.0f, 0xFFFFFFFFu};
-    LaneStack<false, SL> st;
-    st.lds_ref = s_ref;
-    st.lds_t = nullptr;
     uint32_t node = 0;
     bool active = n_nodes > 0;
     while (active) {
@@ -241,7 +249,10 @@ __device__ inline Best trace_aabb2(const bvh_node_aabb2 *nodes, int64_t n_nodes,
                 const uint32_t axis = (meta >> 16) & 3u;
                 const bool neg = axis == 0 ? r.nx : (axis == 1 ? r.ny : r.nz);
                 const uint32_t left = node + 1, right = node + off;
-                st.push(neg ? left : right, 0.0f);
+                if (!st.push(neg ? left : right, 0.0f)) {
+                    incomplete = true;
+                    break;
+                }
                 node = neg ? right : left;
                 continue;
             }
@@ -374,15 +385,12 @@ __device__ inline void sort_children(float *t, uint32_t *r) {
 // ones near-first, continue with the nearest and push the rest with their
 // entry distances; popped entries are re-culled against the current best.
 // s_ref, s_t: [SL][kTraceBlock] LDS.
-template <class Dec, int LeafMode, int Mode, int SL>
+template <class Dec, int LeafMode, int Mode, class Stack>
 __device__ inline Best trace_wide(const void *nodes, int64_t n_nodes, const LeafData &ld,
-                                  const Ray &r, uint32_t *s_ref, float *s_t, uint32_t &nfetch,
-                                  uint32_t &ntri) {
+                                  const Ray &r, Stack &st, uint32_t &nfetch, uint32_t &ntri,
+                                  bool &incomplete) {
     constexpr int K = Dec::K;
     Best best{INFINITY, 0.0f, 0.0f, 0xFFFFFFFFu};
-    LaneStack<true, SL> st;
-    st.lds_ref = s_ref;
-    st.lds_t = s_t;
     uint32_t cur = n_nodes > 0 ? ref_interior(0) : kRefEmpty;
     while (cur != kRefEmpty) {
         const float tcur = (Mode == BVH_TRACE_ANY) ? r.tmax : fminf(best.t, r.tmax);
@@ -393,9 +401,14 @@ __device__ inline Best trace_wide(const void *nodes, int64_t n_nodes, const Leaf
             Dec::test(nodes, cur >> 1, r, tcur, tn, ref);
             nfetch++;
             sort_children<K>(tn, ref);
+            bool ok = true;
 #pragma unroll
             for (int c = K - 1; c >= 1; c--)
-                if (tn[c] != INFINITY) st.push(ref[c], tn[c]);
+                if (tn[c] != INFINITY) ok = st.push(ref[c], tn[c]) && ok;
+            if (!ok) {
+                incomplete = true;
+                break;
+            }
             if (tn[0] != INFINITY) {
                 cur = ref[0];
                 continue;
@@ -417,6 +430,37 @@ __device__ inline Best trace_wide(const void *nodes, int64_t n_nodes, const Leaf
         }
     }
     return best;
+}
+
+// Work area of the fallback pass: a counter and list of rays that
+// overflowed the LDS stack, and one deep stack per fallback lane.
+constexpr int kFallbackBlocks = 128;
+constexpr int kFallbackLanes = kFallbackBlocks * kTraceBlock;
+struct Fallback {
+    uint32_t *count;     // rays appended by the fast pass
+    uint32_t *list;      // ray indices (capacity: rays of the launch)
+    uint32_t *stack_ref; // [kFallbackLanes][kStackMax]
+    float *stack_t;      // [kFallbackLanes][kStackMax]
+};
+
+inline size_t fallback_bytes(uint64_t n_rays) {
+    return 256 + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 8;
+}
+
+// Carves the work area out of one allocation of fallback_bytes(n_rays).
+inline Fallback fallback_view(void *base, uint64_t n_rays) {
+    char *p = static_cast<char *>(base);
+    Fallback f;
+    f.count = reinterpret_cast<uint32_t *>(p);
+    f.list = reinterpret_cast<uint32_t *>(p + 256);
+    f.stack_ref = reinterpret_cast<uint32_t *>(p + 256 + n_rays * 4);
+    f.stack_t = reinterpret_cast<float *>(p + 256 + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 4);
+    return f;
+}
+
+__device__ inline void fallback_append(const Fallback &fb, uint32_t ray) {
+    const uint32_t k = atomicAdd(fb.count, 1u);
+    fb.list[k] = ray;
 }
 
 }  // namespace bvhlib

@@ -264,3 +264,26 @@ def test_spheres_full_size_sampled(orc, spheres_full, layout):
     pc, tc, _, _ = bvh.trace(sh, orc.TOP2)
     graded = (pc < 0) | (np.abs(tc[:, 0] - sh[:, 7]) > 1e-5 * sh[:, 7])
     assert np.array_equal((pa[s] >= 0)[graded], (pc >= 0)[graded])
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_stack_depths_agree_and_fallback_is_exact(orc, layout):
+    """With an 8-entry LDS stack many rays overflow and are finished by the
+    deep-stack fallback pass; hits must be identical for 8, 16 and 32
+    entries and match the oracle (closest and any-hit)."""
+    w = _small_spheres()
+    v, t = w["verts"], w["tris"]
+    res = {}
+    for sl in (8, 16, 32):
+        h = B().build(dev(v), dev(t), layout, 4, "compact", stack_lds=sl)
+        assert h.stats()["stack_lds"] == sl
+        hits = h.trace(dev(w["rays"]))
+        anyh = h.trace(dev(w["shadow"]), 1)
+        torch.cuda.synchronize()
+        res[sl] = (hits.cpu().numpy(), anyh.cpu().numpy())
+    for sl in (16, 32):
+        assert np.array_equal(res[sl][0].view(np.uint32), res[8][0].view(np.uint32))
+        assert np.array_equal(res[sl][1][:, 0] >= 0, res[8][1][:, 0] >= 0)
+    hh = res[8][0]
+    ref = orc.OracleBVH(v, t).trace(w["rays"], orc.TOP2)
+    check_closest(orc, v, t, w["rays"], hh[:, 0].view(np.int32), hh[:, 1:4], ref)
