@@ -227,17 +227,21 @@ __global__ __launch_bounds__(kBlock) void k_bounds_final(const float *partial, u
 }
 
 // ---------------------------------------------------------------------------
-// a2: 63-bit Morton codes (21 bits per axis) of the box centres
+// a2: Morton codes of the box centres, `bits` bits per axis (at most 21).
+// The builder uses ceil(log2(n)/3) + 4 bits: about 2^12 grid cells per
+// triangle, so equal codes are rare, and the radix sort only sorts 3*bits
+// bits (five 8-bit passes for two million triangles instead of eight).
 // ---------------------------------------------------------------------------
-__device__ inline uint32_t quant21(float x, float lo, float inv_ext) {
-    float u = (x - lo) * inv_ext * 2097152.0f;
-    u = fminf(fmaxf(u, 0.0f), 2097151.0f);
+__device__ inline uint32_t quantize_axis_bits(float x, float lo, float inv_ext, int bits) {
+    const float cells = (float)(1u << bits);
+    float u = (x - lo) * inv_ext * cells;
+    u = fminf(fmaxf(u, 0.0f), cells - 1.0f);
     return (uint32_t)u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_morton(const Box *pbox, uint32_t n,
-                                                   const BuildInfo *info, uint64_t *keys,
-                                                   uint32_t *vals) {
+                                                   const BuildInfo *info, int bits,
+                                                   uint64_t *keys, uint32_t *vals) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     Box b = pbox[i];
@@ -247,17 +251,23 @@ __global__ __launch_bounds__(kBlock) void k_morton(const Box *pbox, uint32_t n,
     for (int a = 0; a < 3; a++) {
         float ext = info->chi[a] - info->clo[a];
         float inv = ext > 0.0f ? 1.0f / ext : 0.0f;
-        q[a] = quant21(c[a], info->clo[a], inv);
+        q[a] = quantize_axis_bits(c[a], info->clo[a], inv, bits);
     }
-    // bit b of x, y, z goes to key bit 3b+2, 3b+1, 3b
+    // bit k of x, y, z goes to key bit 3k+2, 3k+1, 3k
     uint64_t key = 0;
-    for (int bit = 0; bit < 21; bit++) {
+    for (int bit = 0; bit < bits; bit++) {
         key |= (uint64_t)((q[0] >> bit) & 1u) << (3 * bit + 2);
         key |= (uint64_t)((q[1] >> bit) & 1u) << (3 * bit + 1);
         key |= (uint64_t)((q[2] >> bit) & 1u) << (3 * bit);
     }
     keys[i] = key;
     vals[i] = i;
+}
+
+inline int morton_bits(int n) {
+    int lg = 0;
+    while ((1ll << lg) < (long long)std::max(n, 2)) lg++;
+    return std::min(21, std::max(4, (lg + 2) / 3 + 4));
 }
 
 // ---------------------------------------------------------------------------
@@ -414,25 +424,47 @@ __device__ inline Box box_empty() {
 }
 
 // Leaf boxes in sorted order (node ids n-1 .. 2n-2) and, one wave per block
-// of kRangeBlock, the block unions (sparse-table level 0).
+// of kRangeBlock: the block union (sparse-table level 0) and the in-block
+// prefix and suffix unions (inclusive wave scans).
+__device__ inline void wave_scan_box(float *v, bool reverse) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const float t = reverse ? __shfl_down(v[k], o, kWave) : __shfl_up(v[k], o, kWave);
+            const bool take = reverse ? (lane + o < kWave) : (lane >= o);
+            if (take) v[k] = k < 3 ? fminf(v[k], t) : fmaxf(v[k], t);
+        }
+    }
+}
+
+__device__ inline Box box_of(const float *v) {
+    Box u;
+    u.lo = make_float4(v[0], v[1], v[2], 0.0f);
+    u.hi = make_float4(v[3], v[4], v[5], 0.0f);
+    return u;
+}
+
 __global__ __launch_bounds__(kBlock) void k_leaf_boxes(const Box *pbox, const uint32_t *perm, int n,
-                                                       Box *nbox, Box *table) {
+                                                       Box *nbox, Box *table, Box *pre, Box *suf) {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     Box b = box_empty();
     if (j < n) {
         b = pbox[perm[j]];
         nbox[(n - 1) + j] = b;
     }
-    float v[6] = {b.lo.x, b.lo.y, b.lo.z, b.hi.x, b.hi.y, b.hi.z};
-#pragma unroll
-    for (int k = 0; k < 6; k++) v[k] = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
-    const int blk = j / kRangeBlock;
-    if ((threadIdx.x & (kWave - 1)) == 0 && blk * kRangeBlock < n) {
-        Box u;
-        u.lo = make_float4(v[0], v[1], v[2], 0.0f);
-        u.hi = make_float4(v[3], v[4], v[5], 0.0f);
-        table[blk] = u;
+    const float v0[6] = {b.lo.x, b.lo.y, b.lo.z, b.hi.x, b.hi.y, b.hi.z};
+    float p[6], q[6];
+    for (int k = 0; k < 6; k++) p[k] = q[k] = v0[k];
+    wave_scan_box(p, false);
+    wave_scan_box(q, true);
+    if (j < n) {
+        pre[j] = box_of(p);
+        suf[j] = box_of(q);
     }
+    const int blk = j / kRangeBlock;
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1 && blk * kRangeBlock < n) table[blk] = box_of(p);
 }
 
 // Sparse-table level k from level k-1: T_k[i] = T_{k-1}[i] u T_{k-1}[i + 2^(k-1)].
@@ -446,7 +478,8 @@ __global__ __launch_bounds__(kBlock) void k_table_level(const Box *prev, Box *cu
 __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirst,
                                                            const uint32_t *icount, int n,
                                                            const Box *table, int nblocks,
-                                                           Box *nbox) {
+                                                           const Box *pre, const Box *suf,
+                                                           Box *nbox, float *area) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n - 1) return;
     const Box *leaf = nbox + (n - 1);
@@ -455,12 +488,16 @@ __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirs
     const int ba = a / kRangeBlock, bb = b / kRangeBlock;
     Box u = box_empty();
     if (ba == bb) {
-        for (int j = a; j <= b; j++) u = box_union(u, leaf[j]);
+        int j = a;
+        for (; j + 3 <= b; j += 4) {
+            const Box x0 = leaf[j], x1 = leaf[j + 1], x2 = leaf[j + 2], x3 = leaf[j + 3];
+            u = box_union(u, box_union(box_union(x0, x1), box_union(x2, x3)));
+        }
+        for (; j <= b; j++) u = box_union(u, leaf[j]);
     } else {
-        const int ea = (ba + 1) * kRangeBlock, sb = bb * kRangeBlock;
-        for (int j = a; j < ea; j++) u = box_union(u, leaf[j]);
-        for (int j = sb; j <= b; j++) u = box_union(u, leaf[j]);
-        const int lo = ba + 1, hi = bb - 1;  // whole blocks in between
+        // suffix of a's block, prefix of b's block, whole blocks in between
+        u = box_union(suf[a], pre[b]);
+        const int lo = ba + 1, hi = bb - 1;
         if (lo <= hi) {
             const int len = hi - lo + 1;
             const int k = 31 - __clz(len);
@@ -469,6 +506,8 @@ __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirs
         }
     }
     nbox[i] = u;
+    const float dx = u.hi.x - u.lo.x, dy = u.hi.y - u.lo.y, dz = u.hi.z - u.lo.z;
+    area[i] = dx * dy + dy * dz + dz * dx;
 }
 
 // ---------------------------------------------------------------------------
@@ -483,6 +522,7 @@ struct TreeView {
     const uint32_t *ifirst, *icount;
     const uint8_t *iaxis;
     const Box *nbox;
+    const float *area;     // surface-area measure of internal nodes
     __device__ bool is_prim(int x) const { return x >= n - 1; }
     __device__ uint32_t count(int x) const { return is_prim(x) ? 1u : icount[x]; }
     __device__ uint32_t first(int x) const { return is_prim(x) ? (uint32_t)(x - (n - 1)) : ifirst[x]; }
@@ -553,19 +593,13 @@ __global__ __launch_bounds__(kBlock) void k_emit_aabb2(TreeView tv, const uint32
 // Pass A forms the lists and counts interior children; an exclusive scan
 // places them; pass B writes the node and the next frontier.
 // ---------------------------------------------------------------------------
-__device__ inline float surface_area(const Box &b) {
-    const float dx = b.hi.x - b.lo.x, dy = b.hi.y - b.lo.y, dz = b.hi.z - b.lo.z;
-    return dx * dy + dy * dz + dz * dx;
-}
-
+// Greedy opening of one wide node (binary node x): returns the number of
+// interior candidates and writes K candidate ids (-1 for unused slots).
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_wide_open(TreeView tv, uint32_t count,
-                                                      const int32_t *fr_node, int32_t *cand,
-                                                      uint32_t *ninterior) {
-    const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= count) return;
-    const int x = fr_node[f];
+__device__ inline uint32_t wide_open_item(const TreeView &tv, int x, int32_t *cand_out) {
     int c[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) c[k] = -1;
     int nc;
     if (tv.is_leaf(x)) {  // only for a root that is a single leaf
         c[0] = x;
@@ -577,31 +611,54 @@ __global__ __launch_bounds__(kBlock) void k_wide_open(TreeView tv, uint32_t coun
         while (nc < K) {
             int best = -1;
             float best_a = -1.0f;
-            for (int k = 0; k < nc; k++) {
-                if (tv.is_leaf(c[k])) continue;
-                const float a = surface_area(tv.nbox[c[k]]);
-                if (a > best_a) { best_a = a; best = k; }
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                if (k >= nc || tv.is_leaf(c[k])) continue;
+                const float a = tv.area[c[k]];
+                if (a > best_a) {
+                    best_a = a;
+                    best = k;
+                }
             }
             if (best < 0) break;
-            const int y = c[best];
-            for (int k = nc; k > best + 1; k--) c[k] = c[k - 1];
-            c[best] = tv.ileft[y];
-            c[best + 1] = tv.iright[y];
+            // replace c[best] by its two children, keeping left-to-right order
+            int y = -1;
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                if (k == best) y = c[k];
+            const int yl = tv.ileft[y], yr = tv.iright[y];
+#pragma unroll
+            for (int k = K - 1; k >= 1; k--)
+                if (k > best + 1 && k <= nc) c[k] = c[k - 1];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                if (k == best) c[k] = yl;
+                if (k == best + 1) c[k] = yr;
+            }
             nc++;
         }
     }
     uint32_t ni = 0;
+#pragma unroll
     for (int k = 0; k < K; k++) {
-        const int v = k < nc ? c[k] : -1;
-        cand[(size_t)f * K + k] = v;
-        if (v >= 0 && !tv.is_leaf(v)) ni++;
+        cand_out[k] = c[k];
+        if (c[k] >= 0 && !tv.is_leaf(c[k])) ni++;
     }
-    ninterior[f] = ni;
+    return ni;
 }
 
-// Quantisation of one axis of up to K child intervals to QMAX steps of the
-// parent interval [plo, phi].  Returns the scale; q values are chosen so that
-// fmaf(qlo, s, plo) <= clo and fmaf(qhi, s, plo) >= chi exactly.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_wide_open(TreeView tv, uint32_t count,
+                                                      const int32_t *fr_node, int32_t *cand,
+                                                      uint32_t *ninterior) {
+    const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= count) return;
+    ninterior[f] = wide_open_item<K>(tv, fr_node[f], cand + (size_t)f * K);
+}
+
+// Quantisation of one axis of K child intervals (the first nc valid) to QMAX
+// steps of the parent interval [plo, phi].  Returns the scale; q values are
+// the tightest with fmaf(qlo, s, plo) <= clo and fmaf(qhi, s, plo) >= chi.
 template <int K, int QMAX>
 __device__ inline float quantize_axis(float plo, float phi, const float *clo, const float *chi,
                                       int nc, uint32_t *qlo, uint32_t *qhi, uint32_t *err) {
@@ -613,6 +670,7 @@ __device__ inline float quantize_axis(float plo, float phi, const float *clo, co
         s = ext / (float)QMAX;
         for (int g = 0; g < 64 && fmaf((float)QMAX, s, plo) < phi; g++) s = nextafterf(s, INFINITY);
     }
+#pragma unroll
     for (int k = 0; k < K; k++) {
         uint32_t a = QMAX, b = 0;  // empty slot: lo above hi
         if (k < nc) {
@@ -638,6 +696,12 @@ __device__ inline float quantize_axis(float plo, float phi, const float *clo, co
     return s;
 }
 
+__device__ inline float box_comp(const Box &b, int c) {
+    return c == 0 ? b.lo.x : c == 1 ? b.lo.y : c == 2 ? b.lo.z : c == 3 ? b.hi.x : c == 4 ? b.hi.y : b.hi.z;
+}
+
+// Node writers: the record is written straight to global memory, field by
+// field, so no node-sized array lives in private memory.
 template <int Layout>
 struct WideOut;
 
@@ -648,48 +712,60 @@ struct WideOut<BVH_LAYOUT_BVH4> {
                                  const uint32_t *ref, int nc, uint32_t *err) {
         (void)pb;
         (void)err;
-        bvh_node_bvh4 nd;
+        bvh_node_bvh4 *nd = static_cast<bvh_node_bvh4 *>(nodes) + w;
+#pragma unroll
         for (int k = 0; k < K; k++) {
             const bool v = k < nc;
-            nd.lo_x[k] = v ? cb[k].lo.x : INFINITY;
-            nd.lo_y[k] = v ? cb[k].lo.y : INFINITY;
-            nd.lo_z[k] = v ? cb[k].lo.z : INFINITY;
-            nd.hi_x[k] = v ? cb[k].hi.x : -INFINITY;
-            nd.hi_y[k] = v ? cb[k].hi.y : -INFINITY;
-            nd.hi_z[k] = v ? cb[k].hi.z : -INFINITY;
-            nd.child[k] = v ? ref[k] : kRefEmpty;
+            nd->lo_x[k] = v ? cb[k].lo.x : INFINITY;
+            nd->lo_y[k] = v ? cb[k].lo.y : INFINITY;
+            nd->lo_z[k] = v ? cb[k].lo.z : INFINITY;
+            nd->hi_x[k] = v ? cb[k].hi.x : -INFINITY;
+            nd->hi_y[k] = v ? cb[k].hi.y : -INFINITY;
+            nd->hi_z[k] = v ? cb[k].hi.z : -INFINITY;
+            nd->child[k] = v ? ref[k] : kRefEmpty;
         }
-        nd.nchild = (uint32_t)nc;
-        nd.pad[0] = nd.pad[1] = nd.pad[2] = 0;
-        static_cast<bvh_node_bvh4 *>(nodes)[w] = nd;
+        nd->nchild = (uint32_t)nc;
+        nd->pad[0] = nd->pad[1] = nd->pad[2] = 0;
     }
 };
 
+// Packs q values of one plane row (8 children) into 32-bit words.
+template <typename QT>
+__device__ inline void store_row(QT *row, const uint32_t *q) {
+    if (sizeof(QT) == 1) {
+        uint32_t *w = reinterpret_cast<uint32_t *>(row);
+        w[0] = q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24);
+        w[1] = q[4] | (q[5] << 8) | (q[6] << 16) | (q[7] << 24);
+    } else {
+        uint32_t *w = reinterpret_cast<uint32_t *>(row);
+#pragma unroll
+        for (int k = 0; k < 4; k++) w[k] = q[2 * k] | (q[2 * k + 1] << 16);
+    }
+}
+
 template <typename NodeT, int QMAX, typename QT>
-__device__ inline void write_quantized(NodeT &nd, const Box &pb, const Box *cb, const uint32_t *ref,
+__device__ inline void write_quantized(NodeT *nd, const Box &pb, const Box *cb, const uint32_t *ref,
                                        int nc, uint32_t *err) {
     constexpr int K = 8;
-    float clo[K], chi[K];
-    uint32_t qlo[K], qhi[K];
-    const float plo[3] = {pb.lo.x, pb.lo.y, pb.lo.z}, phi[3] = {pb.hi.x, pb.hi.y, pb.hi.z};
-    QT *dst_lo[3] = {nd.qlo_x, nd.qlo_y, nd.qlo_z};
-    QT *dst_hi[3] = {nd.qhi_x, nd.qhi_y, nd.qhi_z};
+#pragma unroll
     for (int a = 0; a < 3; a++) {
+        float clo[K], chi[K];
+        uint32_t qlo[K], qhi[K];
+#pragma unroll
         for (int k = 0; k < K; k++) {
-            const bool v = k < nc;
-            clo[k] = v ? (a == 0 ? cb[k].lo.x : a == 1 ? cb[k].lo.y : cb[k].lo.z) : 0.0f;
-            chi[k] = v ? (a == 0 ? cb[k].hi.x : a == 1 ? cb[k].hi.y : cb[k].hi.z) : 0.0f;
+            clo[k] = k < nc ? box_comp(cb[k], a) : 0.0f;
+            chi[k] = k < nc ? box_comp(cb[k], a + 3) : 0.0f;
         }
-        const float s = quantize_axis<K, QMAX>(plo[a], phi[a], clo, chi, nc, qlo, qhi, err);
-        nd.origin[a] = plo[a];
-        nd.scale[a] = s;
-        for (int k = 0; k < K; k++) {
-            dst_lo[a][k] = (QT)qlo[k];
-            dst_hi[a][k] = (QT)qhi[k];
-        }
+        const float plo = box_comp(pb, a), phi = box_comp(pb, a + 3);
+        const float s = quantize_axis<K, QMAX>(plo, phi, clo, chi, nc, qlo, qhi, err);
+        nd->origin[a] = plo;
+        nd->scale[a] = s;
+        store_row<QT>(a == 0 ? nd->qlo_x : a == 1 ? nd->qlo_y : nd->qlo_z, qlo);
+        store_row<QT>(a == 0 ? nd->qhi_x : a == 1 ? nd->qhi_y : nd->qhi_z, qhi);
     }
-    for (int k = 0; k < K; k++) nd.child[k] = k < nc ? ref[k] : kRefEmpty;
-    nd.nchild = (uint32_t)nc;
+#pragma unroll
+    for (int k = 0; k < K; k++) nd->child[k] = k < nc ? ref[k] : kRefEmpty;
+    nd->nchild = (uint32_t)nc;
 }
 
 template <>
@@ -697,10 +773,10 @@ struct WideOut<BVH_LAYOUT_BVH8_Q8> {
     static constexpr int K = 8;
     __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
-        bvh_node_bvh8_q8 nd;
+        bvh_node_bvh8_q8 *nd = static_cast<bvh_node_bvh8_q8 *>(nodes) + w;
         write_quantized<bvh_node_bvh8_q8, 255, uint8_t>(nd, pb, cb, ref, nc, err);
-        for (int k = 0; k < 5; k++) nd.pad[k] = 0;
-        static_cast<bvh_node_bvh8_q8 *>(nodes)[w] = nd;
+#pragma unroll
+        for (int k = 0; k < 5; k++) nd->pad[k] = 0;
     }
 };
 
@@ -709,12 +785,58 @@ struct WideOut<BVH_LAYOUT_BVH8_Q16> {
     static constexpr int K = 8;
     __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
-        bvh_node_bvh8_q16 nd;
+        bvh_node_bvh8_q16 *nd = static_cast<bvh_node_bvh8_q16 *>(nodes) + w;
         write_quantized<bvh_node_bvh8_q16, 65535, uint16_t>(nd, pb, cb, ref, nc, err);
-        nd.pad = 0;
-        static_cast<bvh_node_bvh8_q16 *>(nodes)[w] = nd;
+        nd->pad = 0;
     }
 };
+
+// Writes wide node base+f from its candidate list and appends its interior
+// children to the next frontier at noff_f, noff_f+1, ...
+template <int Layout>
+__device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_t count,
+                                      uint32_t cap, uint32_t f, int x, uint32_t aux,
+                                      const int32_t *cand_f, uint32_t noff_f, void *nodes,
+                                      int32_t *next_node, uint32_t *next_aux, BuildInfo *info) {
+    constexpr int K = WideOut<Layout>::K;
+    if (base + f >= cap) {
+        atomicOr(&info->err, 4u);
+        return;
+    }
+    Box cb[K];
+    uint32_t ref[K];
+    int nc = 0;
+    uint32_t r = 0;
+    const uint32_t next_base = base + count;
+    const uint32_t depth = (aux >> 16) + 1;
+    uint32_t stack_need = aux & 0xFFFFu;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int c = cand_f[k];  // valid candidates are the first nc slots
+        ref[k] = kRefEmpty;
+        cb[k] = box_empty();
+        if (c < 0) continue;
+        nc++;
+        cb[k] = tv.nbox[c];
+        if (tv.is_leaf(c)) {
+            ref[k] = ref_leaf(tv.first(c), tv.count(c));
+        } else {
+            const uint32_t pos = noff_f + r;
+            if (pos >= cap || next_base + pos >= cap) {
+                atomicOr(&info->err, 4u);
+                return;
+            }
+            ref[k] = ref_interior(next_base + pos);
+            next_node[pos] = c;
+            r++;
+        }
+    }
+    stack_need += (uint32_t)(nc - 1);
+    for (uint32_t k = 0; k < r; k++) next_aux[noff_f + k] = (stack_need & 0xFFFFu) | (depth << 16);
+    WideOut<Layout>::write(nodes, base + f, tv.nbox[x], cb, ref, nc, &info->err);
+    atomicMax(&info->max_stack, stack_need);
+    atomicMax(&info->max_depth, depth + 1);  // + the leaf level below
+}
 
 template <int Layout>
 __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base, uint32_t count,
@@ -726,41 +848,56 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base
     constexpr int K = WideOut<Layout>::K;
     const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
     if (f >= count) return;
-    if (base + f >= cap || noff[f] + K > cap + K) {
-        atomicOr(&info->err, 4u);
-        return;
-    }
-    const int x = fr_node[f];
-    const uint32_t aux = fr_aux[f];  // bits 0..15 stack need so far, 16..31 depth
-    Box cb[K];
-    uint32_t ref[K];
-    int nc = 0;
-    uint32_t r = 0;
-    const uint32_t next_base = base + count;
-    for (int k = 0; k < K; k++) {
-        const int c = cand[(size_t)f * K + k];
-        if (c < 0) continue;
-        cb[nc] = tv.nbox[c];
-        if (tv.is_leaf(c)) {
-            ref[nc] = ref_leaf(tv.first(c), tv.count(c));
-        } else {
-            const uint32_t pos = noff[f] + r;
-            if (pos >= cap || next_base + pos >= cap) {
-                atomicOr(&info->err, 4u);
-                return;
-            }
-            ref[nc] = ref_interior(next_base + pos);
-            next_node[pos] = c;
-            r++;
+    wide_emit_item<Layout>(tv, base, count, cap, f, fr_node[f], fr_aux[f], cand + (size_t)f * K,
+                           noff[f], nodes, next_node, next_aux, info);
+}
+
+// The top levels, while the frontier is small, in one workgroup: open, scan
+// and emit per level with block barriers instead of kernel launches and host
+// round trips.  Leaves (base, count, frontier buffer) for the multi-block
+// levels in state[0..2].
+constexpr uint32_t kTopMaxFrontier = 2048;
+
+template <int Layout>
+__global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, int32_t *fr_node0,
+                                                     int32_t *fr_node1, uint32_t *fr_aux0,
+                                                     uint32_t *fr_aux1, int32_t *cand,
+                                                     uint32_t *noff, void *nodes, BuildInfo *info,
+                                                     uint32_t *state) {
+    constexpr int K = WideOut<Layout>::K;
+    __shared__ uint32_t wsum[kBlock / kWave];
+    uint32_t base = 0, count = 1;
+    int cur = 0;
+    for (int level = 0; level < 64 && count > 0 && count <= kTopMaxFrontier; level++) {
+        int32_t *frn = cur ? fr_node1 : fr_node0;
+        uint32_t *fra = cur ? fr_aux1 : fr_aux0;
+        for (uint32_t f = threadIdx.x; f < count; f += kBlock)
+            noff[f] = wide_open_item<K>(tv, frn[f], cand + (size_t)f * K);
+        __syncthreads();
+        uint32_t carry = 0;
+        for (uint32_t c = 0; c < count; c += kBlock) {
+            const uint32_t f = c + threadIdx.x;
+            const uint32_t v = f < count ? noff[f] : 0u;
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan(v, &tot, wsum);
+            if (f < count) noff[f] = carry + ex;
+            carry += tot;
         }
-        nc++;
+        __syncthreads();
+        for (uint32_t f = threadIdx.x; f < count; f += kBlock)
+            wide_emit_item<Layout>(tv, base, count, cap, f, frn[f], fra[f], cand + (size_t)f * K,
+                                   noff[f], nodes, cur ? fr_node0 : fr_node1, cur ? fr_aux0 : fr_aux1,
+                                   info);
+        __syncthreads();
+        base += count;
+        count = carry;
+        cur ^= 1;
     }
-    const uint32_t stack_need = (aux & 0xFFFFu) + (uint32_t)(nc - 1);
-    const uint32_t depth = (aux >> 16) + 1;
-    for (uint32_t k = 0; k < r; k++) next_aux[noff[f] + k] = (stack_need & 0xFFFFu) | (depth << 16);
-    WideOut<Layout>::write(nodes, base + f, tv.nbox[x], cb, ref, nc, &info->err);
-    atomicMax(&info->max_stack, stack_need);
-    atomicMax(&info->max_depth, depth + 1);  // + the leaf level below
+    if (threadIdx.x == 0) {
+        state[0] = base;
+        state[1] = count;
+        state[2] = (uint32_t)cur;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -807,16 +944,14 @@ int32_t check_launch(const char *what) {
 }
 
 template <int Layout>
-int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, BuildInfo *info_host,
-                  bvh_handle_s *h, hipStream_t s) {
+int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s *h, hipStream_t s) {
     constexpr int K = WideOut<Layout>::K;
     const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
-    void *wnodes;
     int32_t *fr_node[2], *cand;
-    uint32_t *fr_aux[2], *noff, *tile;
-    uint8_t *raw;
+    uint32_t *fr_aux[2], *noff, *tile, *state;
+    uint8_t *wnodes;
     Arena arena;
-    arena.request(&raw, (size_t)cap * h->node_bytes);
+    arena.request(&wnodes, (size_t)cap * h->node_bytes);
     arena.request(&fr_node[0], cap);
     arena.request(&fr_node[1], cap);
     arena.request(&fr_aux[0], cap);
@@ -824,14 +959,23 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, BuildInfo *in
     arena.request(&cand, (size_t)cap * K);
     arena.request(&noff, cap);
     arena.request(&tile, (cap + kScanTile - 1) / kScanTile + 1);
+    arena.request(&state, 4);
     BVH_TRY(arena.bind(s, kAreaBuildWide));
-    wnodes = raw;
-    const int32_t root = 0;
-    const uint32_t zero = 0;
-    BVH_HIP_TRY(hipMemcpyAsync(fr_node[0], &root, sizeof(root), hipMemcpyHostToDevice, s));
-    BVH_HIP_TRY(hipMemcpyAsync(fr_aux[0], &zero, sizeof(zero), hipMemcpyHostToDevice, s));
-    uint32_t base = 0, count = 1;
-    int cur = 0;
+    uint32_t *pin = pinned_scratch<uint32_t>();
+    if (!pin) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
+    // frontier = {root} with zero stack need and depth
+    pin[0] = 0;
+    pin[1] = 0;
+    BVH_HIP_TRY(hipMemcpyAsync(fr_node[0], &pin[0], sizeof(int32_t), hipMemcpyHostToDevice, s));
+    BVH_HIP_TRY(hipMemcpyAsync(fr_aux[0], &pin[1], sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    k_wide_top<Layout><<<1, kBlock, 0, s>>>(tv, cap, fr_node[0], fr_node[1], fr_aux[0], fr_aux[1],
+                                           cand, noff, wnodes, info, state);
+    BVH_TRY(check_launch("wide packing (top levels)"));
+    BVH_HIP_TRY(hipMemcpyAsync(pin, state, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    BVH_HIP_TRY(hipStreamSynchronize(s));
+    uint32_t base = pin[0], count = pin[1];
+    int cur = (int)pin[2];
+    if (base + count > cap) return set_error(BVH_EHIP, "wide packing overflow");
     for (int level = 0; count > 0; level++) {
         if (level > 4096) return set_error(BVH_EHIP, "wide packing did not terminate");
         k_wide_open<K><<<grid_for(count), kBlock, 0, s>>>(tv, count, fr_node[cur], cand, noff);
@@ -840,8 +984,6 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, BuildInfo *in
             tv, base, count, cap, fr_node[cur], fr_aux[cur], cand, noff, wnodes, fr_node[cur ^ 1],
             fr_aux[cur ^ 1], info);
         BVH_TRY(check_launch("wide packing"));
-        uint32_t *pin = pinned_scratch<uint32_t>();
-        if (!pin) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
         BVH_HIP_TRY(hipMemcpyAsync(pin, &info->next_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         BVH_HIP_TRY(hipStreamSynchronize(s));
         const uint32_t next = *pin;
@@ -854,7 +996,6 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, BuildInfo *in
     BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)base * h->node_bytes));
     BVH_HIP_TRY(hipMemcpyAsync(h->nodes, wnodes, (size_t)base * h->node_bytes,
                                hipMemcpyDeviceToDevice, s));
-    (void)info_host;
     return BVH_OK;
 }
 
@@ -877,7 +1018,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     const int nblocks = (n + kRangeBlock - 1) / kRangeBlock;
     int levels = 1;
     while ((1 << levels) <= nblocks) levels++;
-    Box *table;
+    Box *table, *pre, *suf;
+    float *area;
     Arena arena;
     arena.request(&pbox, n);
     arena.request(&partial, (size_t)nb * 12);
@@ -897,6 +1039,9 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     arena.request(&nbox, 2 * (size_t)n - 1);
     arena.request(&mark, n);
     arena.request(&table, (size_t)levels * nblocks);
+    arena.request(&pre, n);
+    arena.request(&suf, n);
+    arena.request(&area, n - 1);
     BVH_TRY(arena.bind(s, kAreaBuild));
 
     BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
@@ -906,11 +1051,12 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // a1, a2
     k_prim_bounds<<<nb, kBlock, 0, s>>>(verts, n_verts, tris, n, pbox, partial, info);
     k_bounds_final<<<1, kBlock, 0, s>>>(partial, nb, info);
-    k_morton<<<nb, kBlock, 0, s>>>(pbox, n, info, keys[0], vals[0]);
+    const int mbits = morton_bits(n);
+    k_morton<<<nb, kBlock, 0, s>>>(pbox, n, info, mbits, keys[0], vals[0]);
     BVH_TRY(check_launch("bounds/morton"));
     // a3: 8 passes of 8 bits
     int cur = 0;
-    for (int shift = 0; shift < 64; shift += 8) {
+    for (int shift = 0; shift < 3 * mbits; shift += 8) {
         k_radix_hist<<<nsort, kBlock, 0, s>>>(keys[cur], n, shift, hist, nsort);
         scan_u32(hist, hist, nhist, tile, nullptr, s);
         k_radix_scatter<<<nsort, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1],
@@ -924,18 +1070,19 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
                                                     iaxis, parent);
     {
-        k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table);
+        k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table, pre, suf);
         for (int k = 1; k < levels; k++) {
             const int half = 1 << (k - 1);
             k_table_level<<<grid_for(nblocks), kBlock, 0, s>>>(
                 table + (size_t)(k - 1) * nblocks, table + (size_t)k * nblocks, nblocks, half);
         }
         if (n > 1)
-            k_internal_boxes<<<grid_for(n - 1), kBlock, 0, s>>>(ifirst, icount, n, table, nblocks, nbox);
+            k_internal_boxes<<<grid_for(n - 1), kBlock, 0, s>>>(ifirst, icount, n, table, nblocks,
+                                                                pre, suf, nbox, area);
     }
     BVH_TRY(check_launch("hierarchy/boxes"));
     // a6
-    TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox};
+    TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox, area};
     k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
     scan_u32(mark, mark, n, tile, &info->n_leaves, s);
     BVH_TRY(check_launch("collapse"));
@@ -960,11 +1107,11 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
             tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
         BVH_TRY(check_launch("aabb2 packing"));
     } else if (h->layout == BVH_LAYOUT_BVH4) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, &hi, h, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, h, s));
     } else if (h->layout == BVH_LAYOUT_BVH8_Q8) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, &hi, h, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, h, s));
     } else {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, &hi, h, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, h, s));
     }
 
     // leaf data
