@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--layout", default="bvh8_q8")
+    ap.add_argument("--layout", default="bvh4")
     ap.add_argument("--leaf-mode", default="compact")
     ap.add_argument("--leaf-size", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -63,6 +63,41 @@ def algorithmic_bytes(counts, layout_bytes, leaf_mode):
     nodes = counts[:, 0].astype(np.float64)
     tris = counts[:, 1].astype(np.float64)
     return RAY_BYTES + HIT_BYTES + nodes * layout_bytes + tris * LEAF_TRI_BYTES[leaf_mode]
+
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "trace_kernel_counters.txt")
+TRAVERSAL_SOURCES = [os.path.join(ROOT, "paper_2511_15028_amd", "csrc", f)
+                     for f in ("traverse.h", "trace.hip")]
+
+
+def traversal_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAVERSAL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(args):
+    """HBM bytes per traversal launch pair (camera + bounce) from the committed
+    rocprofv3 counter summary, scaled by its calibration factors; None when the
+    summary is missing, was taken for another configuration, or the traversal
+    sources changed since."""
+    try:
+        kv = {}
+        with open(COUNTERS_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_digest") != traversal_source_digest():
+            return None
+        if kv.get("layout") != args.layout or kv.get("leaf_mode") != args.leaf_mode:
+            return None
+        return int(float(kv["hbm_bytes_per_step_launches"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -178,7 +213,8 @@ def main():
                 "nodes_mb": round(st["nodes_buffer_bytes"] / 1e6, 2),
                 "leaf_mb": round(st["leaf_buffer_bytes"] / 1e6, 2), "depth": st["depth"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args),
                      "kernel": f"trace ({args.layout}, {args.leaf_mode})"},
     }
 
