@@ -222,6 +222,7 @@ def main():
         out["per_layout"] = per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
         out["fwd_bwd"] = fwd_bwd(torch, bvh, W)
         del verts, tris, prim_rays, bounce_rays, hits_p, hits_b
+        out["spheres"] = spheres(torch, bvh, W, args)
         out["batched"] = batched(torch, bvh, W)
 
     if args.copy_calib_mib > 0:
@@ -239,41 +240,74 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
-    """Trace-only Mrays/s and algorithmic bytes per ray for every layout and
-    leaf mode (median of 5 launches per ray set, events on the stream)."""
+def time_trace(torch, h, rays, mode=0, reps=5):
+    """Median event time (ms) of `reps` trace calls after one warm-up call."""
     stream = torch.cuda.current_stream()
+    hits = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device)
+    times = []
+    for _ in range(reps + 1):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        h.trace(rays, mode=mode, hits=hits)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        times.append(e[0].elapsed_time(e[1]))
+    return float(np.median(times[1:]))
+
+
+def layout_row(torch, h, leaf_mode, ray_sets):
+    """Per ray set: Mrays/s, algorithmic bytes per ray and roofline fraction."""
+    st = h.stats()
+    row = {"bvh_mb": round((st["nodes_buffer_bytes"] + st["leaf_buffer_bytes"]
+                            + st["extra_bytes"]) / 1e6, 1)}
+    for name, rays, mode in ray_sets:
+        t_ms = time_trace(torch, h, rays, mode)
+        _, c = h.trace_counts(rays, mode=mode)
+        torch.cuda.synchronize()
+        by = algorithmic_bytes(c.cpu().numpy(), st["node_bytes"], leaf_mode)
+        gbs = by.sum() / (t_ms / 1000.0) / 1e9
+        row[name] = {"mrays_s": round(rays.shape[0] / (t_ms / 1000.0) / 1e6, 1),
+                     "ms": round(t_ms, 4), "bytes_per_ray": round(float(by.mean()), 1),
+                     "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return row
+
+
+def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
+    """Terrain: trace-only Mrays/s, algorithmic bytes per ray and roofline
+    fraction for every layout and leaf mode, camera (coherent) and bounce
+    (incoherent) rays separately (median of 5 launches, events on the stream)."""
     res = {}
-    n = prim_rays.shape[0] + bounce_rays.shape[0]
     for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16"):
         for leaf_mode in ("compact", "indexed"):
             h = bvh.build(verts, tris, layout, args.leaf_size, leaf_mode)
-            st = h.stats()
-            times = []
-            for _ in range(6):
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-                e[0].record(stream)
-                h.trace(prim_rays)
-                h.trace(bounce_rays)
-                e[1].record(stream)
-                torch.cuda.synchronize()
-                times.append(e[0].elapsed_time(e[1]))
-            t_ms = float(np.median(times[1:]))
-            _, cp = h.trace_counts(prim_rays)
-            _, cb = h.trace_counts(bounce_rays)
-            torch.cuda.synchronize()
-            by = np.concatenate([algorithmic_bytes(cp.cpu().numpy(), st["node_bytes"], leaf_mode),
-                                 algorithmic_bytes(cb.cpu().numpy(), st["node_bytes"], leaf_mode)])
-            gbs = by.sum() / (t_ms / 1000.0) / 1e9
-            res[f"{layout}/{leaf_mode}"] = {
-                "trace_mrays_s": round(n / (t_ms / 1000.0) / 1e6, 1),
-                "bytes_per_ray": round(float(by.mean()), 1),
-                "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "bvh_mb": round((st["nodes_buffer_bytes"] + st["leaf_buffer_bytes"]
-                                 + st["extra_bytes"]) / 1e6, 1),
-            }
+            res[f"{layout}/{leaf_mode}"] = layout_row(
+                torch, h, leaf_mode, [("camera", prim_rays, bvh.TRACE_CLOSEST),
+                                      ("bounce", bounce_rays, bvh.TRACE_CLOSEST)])
             h.close()
-            log(f"layout {layout}/{leaf_mode}: {res[f'{layout}/{leaf_mode}']}")
+            log(f"terrain {layout}/{leaf_mode}: {res[f'{layout}/{leaf_mode}']}")
+    return res
+
+
+def spheres(torch, bvh, W, args):
+    """Non-uniform density scene: 512 icospheres (levels 2-6 by radius rank)
+    plus 100,000 slivers, 4,051,040 tris; 2^23 incoherent closest-hit rays
+    and 2^23 any-hit shadow rays, per layout (compacted leaves)."""
+    t0 = time.time()
+    w = W.spheres_workload()
+    dev = torch.device("cuda:0")
+    verts = torch.from_numpy(w["verts"]).to(dev)
+    tris = torch.from_numpy(w["tris"]).to(dev)
+    rays = torch.from_numpy(w["rays"]).to(dev)
+    shadow = torch.from_numpy(w["shadow"]).to(dev)
+    log(f"spheres workload: {w['tris'].shape[0]} tris ({time.time() - t0:.1f}s)")
+    res = {"workload": f"{len(w['tris'])} tris (512 spheres + 100K slivers), {rays.shape[0]} "
+                       "uniform closest-hit rays + as many shadow rays (any hit)"}
+    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16"):
+        h = bvh.build(verts, tris, layout, args.leaf_size, "compact")
+        res[layout] = layout_row(torch, h, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
+                                                       ("shadow_any", shadow, bvh.TRACE_ANY)])
+        h.close()
+        log(f"spheres {layout}: {res[layout]}")
     return res
 
 

@@ -106,9 +106,12 @@ typedef struct bvh_stats {
     int32_t pad;
 } bvh_stats;
 
-/* Compacted leaf triangle (BVH_LEAF_COMPACT), 48 B, in leaf order. */
+/* Compacted leaf triangle (BVH_LEAF_COMPACT), 48 B, in leaf order: the
+ * first vertex and the two edges of the Moller-Trumbore test of App. G,
+ * e1 = p0 - p1 and e2 = p2 - p0, each component rounded to f32 exactly as
+ * the test rounds it (so p1 and p2 are not stored). */
 typedef struct bvh_tri {
-    float p0[3], p1[3], p2[3];
+    float p0[3], e1[3], e2[3];
     int32_t prim_id; /* index of the triangle in the caller's `tris` */
     int32_t pad[2];
 } bvh_tri;
@@ -202,8 +205,9 @@ int32_t bvh_version(void);
  * Errors: EINVAL for null pointers with a nonzero count, negative counts,
  * an unknown layout or leaf mode, leaf_size outside 1..16, nonzero reserved
  * fields, or (detected on the device, reported before returning) a vertex
- * index outside [0, n_verts); EUNSUPPORTED for n_tris >= 2^27 or a tree whose
- * traversal stack would exceed the kernel's limit; ENOMEM; EHIP; ENODEV.
+ * index outside [0, n_verts); EUNSUPPORTED for n_tris >= 2^27, a tree whose
+ * traversal stack would exceed the kernel's limit, or a wide layout whose
+ * node buffer would reach 4 GiB; ENOMEM; EHIP; ENODEV.
  * n_tris = 0 gives a valid empty handle whose traces all miss.
  * Synchronises `stream` before returning.  verts and tris are not retained.
  */

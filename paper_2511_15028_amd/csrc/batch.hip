@@ -26,6 +26,7 @@ struct BatchScene {
     uint64_t ray_begin;
     uint32_t n_tris;
     uint32_t ray_count;
+    float coord_max;
 };
 
 // Largest s in [0, n) with tile_off[s] <= tile (tile_off has n + 1 entries,
@@ -65,28 +66,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_trace(const BatchScene *s
         const uint32_t local = (tile - tile_off[s]) * kTile + lane;
         if (local < sc.ray_count) {
             const uint64_t i = sc.ray_begin + local;
-            const Ray r = load_ray(rays, i);
-            const LeafData ld{sc.leaf, nullptr, nullptr, sc.n_tris};
+            const Ray r = load_ray(rays, i, sc.coord_max);
+            const LeafData ld{sc.leaf, nullptr, nullptr, sc.n_tris, sc.coord_max};
             uint32_t nf = 0, nt = 0;
             bool incomplete = false;
-            Best b;
-            if (Layout == BVH_LAYOUT_AABB2) {
-                LdsStack<false, SL> st(s_ref, nullptr);
-                b = trace_aabb2<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                    static_cast<const bvh_node_aabb2 *>(sc.nodes), sc.n_nodes, ld, r, st, nf, nt,
-                    incomplete);
-            } else {
-                LdsStack<true, SL> st(s_ref, s_t);
-                if (Layout == BVH_LAYOUT_BVH4)
-                    b = trace_wide<DecodeBVH4, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                        sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
-                else if (Layout == BVH_LAYOUT_BVH8_Q8)
-                    b = trace_wide<DecodeBVH8Q8, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                        sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
-                else
-                    b = trace_wide<DecodeBVH8Q16, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                        sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
-            }
+            LdsStack<TracerFor<Layout>::type::kWithT, SL> st(s_ref, s_t);
+            const Best b = trace_ray<Layout, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+                sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
             if (incomplete) fallback_append(fb, (uint32_t)i);
             else store_hit(hits, i, b);
         }
@@ -111,29 +97,14 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_fallback(const BatchScene
             else hi = mid;
         }
         const BatchScene sc = scenes[lo];
-        const Ray r = load_ray(rays, i);
-        const LeafData ld{sc.leaf, nullptr, nullptr, sc.n_tris};
+        const Ray r = load_ray(rays, i, sc.coord_max);
+        const LeafData ld{sc.leaf, nullptr, nullptr, sc.n_tris, sc.coord_max};
         uint32_t nf = 0, nt = 0;
         bool incomplete = false;
-        Best b;
-        if (Layout == BVH_LAYOUT_AABB2) {
-            GlobalStack<false> st(fb.stack_ref + (size_t)lane * kStackMax, nullptr);
-            b = trace_aabb2<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                static_cast<const bvh_node_aabb2 *>(sc.nodes), sc.n_nodes, ld, r, st, nf, nt,
-                incomplete);
-        } else {
-            GlobalStack<true> st(fb.stack_ref + (size_t)lane * kStackMax,
-                                 fb.stack_t + (size_t)lane * kStackMax);
-            if (Layout == BVH_LAYOUT_BVH4)
-                b = trace_wide<DecodeBVH4, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                    sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
-            else if (Layout == BVH_LAYOUT_BVH8_Q8)
-                b = trace_wide<DecodeBVH8Q8, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                    sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
-            else
-                b = trace_wide<DecodeBVH8Q16, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                    sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
-        }
+        GlobalStack<TracerFor<Layout>::type::kWithT> st(fb.stack_ref + (size_t)lane * kStackMax,
+                                                        fb.stack_t + (size_t)lane * kStackMax);
+        const Best b = trace_ray<Layout, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
+            sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
         store_hit(hits, i, b);
     }
 }
@@ -423,7 +394,7 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
             const int64_t cnt = offsets[i + 1] - offsets[i];
             if (cnt > 0xFFFFFFFFll) return set_error(BVH_EUNSUPPORTED, "bvh_batch_trace: scene ray count");
             sc.push_back(BatchScene{h->nodes, h->n_nodes, h->leaf, (uint64_t)offsets[i],
-                                    (uint32_t)h->n_tris, (uint32_t)cnt});
+                                    (uint32_t)h->n_tris, (uint32_t)cnt, h->coord_max()});
             const uint64_t tiles = ((uint64_t)cnt + kTile - 1) / kTile;
             if (toff.back() + tiles > 0xFFFFFFFFull)
                 return set_error(BVH_EUNSUPPORTED, "bvh_batch_trace: too many rays");

@@ -909,13 +909,14 @@ __global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, con
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     const uint32_t t = perm[j];
+    const float *p0 = verts + 3 * (size_t)tris[3 * (size_t)t];
+    const float *p1 = verts + 3 * (size_t)tris[3 * (size_t)t + 1];
+    const float *p2 = verts + 3 * (size_t)tris[3 * (size_t)t + 2];
     bvh_tri r;
-    for (int k = 0; k < 3; k++) {
-        const float *p = verts + 3 * (size_t)tris[3 * (size_t)t + k];
-        float *dst = k == 0 ? r.p0 : (k == 1 ? r.p1 : r.p2);
-        dst[0] = p[0];
-        dst[1] = p[1];
-        dst[2] = p[2];
+    for (int a = 0; a < 3; a++) {
+        r.p0[a] = p0[a];
+        r.e1[a] = p0[a] - p1[a];  // the f32 edges of the intersection test
+        r.e2[a] = p2[a] - p0[a];
     }
     r.prim_id = (int32_t)t;
     r.pad[0] = r.pad[1] = 0;
@@ -993,6 +994,11 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
         cur ^= 1;
     }
     h->n_nodes = base;
+    // the wide traversal kernels address node fields with 32-bit byte offsets
+    if ((uint64_t)base * (uint64_t)h->node_bytes >= (1ull << 32))
+        return set_error(BVH_EUNSUPPORTED,
+                         "bvh_build: wide node buffer of %llu bytes exceeds 4 GiB (raise leaf_size)",
+                         (unsigned long long)base * (unsigned long long)h->node_bytes);
     BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)base * h->node_bytes));
     BVH_HIP_TRY(hipMemcpyAsync(h->nodes, wnodes, (size_t)base * h->node_bytes,
                                hipMemcpyDeviceToDevice, s));

@@ -74,6 +74,20 @@ struct bvh_handle_s {
     void *leaf = nullptr;        // bvh_tri[n_tris] or int32 prim id[n_tris]
     float *verts = nullptr;      // INDEXED: own copy of the vertices
     int32_t *tris = nullptr;     // INDEXED: own copy of the triangle indices
+
+    // Largest coordinate magnitude of the scene box (+inf for an empty or
+    // non-finite scene): decides which slab-distance form the kernels use.
+    float coord_max() const {
+        float m = 0.0f;
+        for (int a = 0; a < 3; a++) {
+            const float l = scene_lo[a] < 0 ? -scene_lo[a] : scene_lo[a];
+            const float u = scene_hi[a] < 0 ? -scene_hi[a] : scene_hi[a];
+            m = l > m ? l : m;
+            m = u > m ? u : m;
+            if (!(scene_lo[a] <= scene_hi[a])) return __builtin_inff();
+        }
+        return n_tris > 0 ? m : __builtin_inff();
+    }
 };
 
 namespace bvhlib {

@@ -1,26 +1,33 @@
 // Per-scene closest-hit / any-hit traversal kernels (one ray per lane) and
 // the bvh_trace / bvh_trace_counts entry points.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "traverse.h"
 
 namespace bvhlib {
 namespace {
 
-// Fast pass: one ray per lane, LDS stack of SL entries.  A ray whose stack
-// would overflow is appended to the fallback list instead of writing a hit.
-template <int LeafMode, int Mode, bool Count, int SL>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_aabb2(const bvh_node_aabb2 *nodes,
-                                                             int64_t n_nodes, LeafData ld,
-                                                             const bvh_ray *rays, uint64_t n,
-                                                             bvh_hit *hits, uint32_t *counts,
-                                                             Fallback fb) {
+// One ray per lane, LDS stack of SL entries.  A ray whose stack would
+// overflow is appended to the fallback list instead of writing a hit.
+template <int Layout, int LeafMode, int Mode, bool Count, int SL>
+__global__ __launch_bounds__(kTraceBlock) void k_trace(const void *nodes, int64_t n_nodes,
+                                                       LeafData ld, const bvh_ray *rays,
+                                                       uint64_t n, bvh_hit *hits,
+                                                       uint32_t *counts, Fallback fb) {
+    using Tr = typename TracerFor<Layout>::type;
     __shared__ uint32_t s_ref[SL * kTraceBlock];
+    __shared__ float s_t[(Tr::kWithT ? SL : 1) * kTraceBlock];
     const uint64_t i = (uint64_t)blockIdx.x * kTraceBlock + threadIdx.x;
     if (i >= n) return;
-    const Ray r = load_ray(rays, i);
+    const Ray r = load_ray(rays, i, ld.coord_max);
     uint32_t nfetch = 0, ntri = 0;
     bool incomplete = false;
-    LdsStack<false, SL> st(s_ref, nullptr);
-    const Best best = trace_aabb2<LeafMode, Mode>(nodes, n_nodes, ld, r, st, nfetch, ntri, incomplete);
+    LdsStack<Tr::kWithT, SL> st(s_ref, s_t);
+    const Best best =
+        trace_ray<Layout, LeafMode, Mode>(nodes, n_nodes, ld, r, st, nfetch, ntri, incomplete);
     if (incomplete) {
         fallback_append(fb, (uint32_t)i);
         return;
@@ -32,29 +39,111 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_aabb2(const bvh_node_aabb
     }
 }
 
-template <class Dec, int LeafMode, int Mode, bool Count, int SL>
-__global__ __launch_bounds__(kTraceBlock) void k_trace_wide(const void *nodes, int64_t n_nodes,
-                                                            LeafData ld, const bvh_ray *rays,
-                                                            uint64_t n, bvh_hit *hits,
-                                                            uint32_t *counts, Fallback fb) {
+// Persistent kernel: the grid holds as many blocks as fit on the GPU at
+// once, and every lane traces ray after ray.  A lane whose ray ends is
+// refilled from its wave's pool of claimed rays once enough lanes of the
+// wave are idle (a wave claims 64 consecutive rays per atomic), so the
+// wave's lanes stay busy on long rays instead of idling until the slowest
+// ray of a fixed group ends.  Each lane's stack is a ring in LDS over a spill
+// area in global memory that the lane owns for the launch; rays that outgrow
+// both go to the fallback pass.  Every wave leaves the loop once the queue is
+// drained and its lanes are idle, so the grid always drains.
+constexpr uint32_t kNoRay = 0xFFFFFFFFu;
+constexpr uint32_t kRefillLanes = 16;  // idle lanes of a wave that trigger a refill
+constexpr uint32_t kClaim = 64;        // rays claimed from the queue per atomic
+
+template <int Layout, int LeafMode, int Mode, bool Count, int SL>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes, int64_t n_nodes,
+                                                               LeafData ld, const bvh_ray *rays,
+                                                               uint64_t n, bvh_hit *hits,
+                                                               uint32_t *counts, Fallback fb,
+                                                               SpillArea sa) {
+    using Tr = typename TracerFor<Layout>::type;
     __shared__ uint32_t s_ref[SL * kTraceBlock];
-    __shared__ float s_t[SL * kTraceBlock];
-    const uint64_t i = (uint64_t)blockIdx.x * kTraceBlock + threadIdx.x;
-    if (i >= n) return;
-    const Ray r = load_ray(rays, i);
+    __shared__ float s_t[(Tr::kWithT ? SL : 1) * kTraceBlock];
+    const uint32_t lane = threadIdx.x & 63u;
+    SpillStack<Tr::kWithT, SL> st(s_ref, s_t, sa);
+    uint32_t ray = kNoRay;
+    Ray r{};
+    typename Tr::Prep prep{};
+    typename Tr::State ts = Tr::start(0);
     uint32_t nfetch = 0, ntri = 0;
     bool incomplete = false;
-    LdsStack<true, SL> st(s_ref, s_t);
-    const Best best =
-        trace_wide<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, st, nfetch, ntri, incomplete);
-    if (incomplete) {
-        fallback_append(fb, (uint32_t)i);
-        return;
-    }
-    store_hit(hits, i, best);
-    if (Count) {
-        counts[2 * i] = nfetch;
-        counts[2 * i + 1] = ntri;
+    // wave-uniform: the wave's pool of claimed rays [pool, pool_end), and
+    // whether the queue is exhausted
+    uint64_t pool = 0, pool_end = 0;
+    bool drained = false;
+    for (;;) {
+        const uint64_t idle = __builtin_amdgcn_ballot_w64(ray == kNoRay);
+        const uint32_t nidle = (uint32_t)__builtin_popcountll(idle);
+        if (nidle >= kRefillLanes && !(drained && pool == pool_end)) {
+            const uint32_t avail = (uint32_t)(pool_end - pool);
+            uint64_t fresh = 0;  // start of a newly claimed range
+            if (avail < nidle && !drained) {
+                const uint32_t leader = (uint32_t)__builtin_ctzll(idle);
+                uint32_t lo = 0, hi = 0;
+                if (lane == leader) {
+                    const unsigned long long b = atomicAdd(fb.queue, (unsigned long long)kClaim);
+                    lo = (uint32_t)b;
+                    hi = (uint32_t)(b >> 32);
+                }
+                fresh = ((uint64_t)__builtin_amdgcn_readlane(hi, leader) << 32) |
+                        __builtin_amdgcn_readlane(lo, leader);
+                if (fresh >= n) drained = true;
+            }
+            const uint32_t fresh_n =
+                (avail < nidle && fresh < n) ? (uint32_t)min((uint64_t)kClaim, n - fresh) : 0u;
+            if (ray == kNoRay) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                uint64_t my = kNoRay;
+                if (rank < avail) my = pool + rank;
+                else if (rank - avail < fresh_n) my = fresh + (rank - avail);
+                if (my != kNoRay) {
+                    ray = (uint32_t)my;
+                    r = load_ray(rays, my, ld.coord_max);
+                    prep = Tr::prep(r);
+                    ts = Tr::start(n_nodes);
+                    st.reset();
+                    nfetch = ntri = 0;
+                    incomplete = false;
+                }
+            }
+            // advance the pool past what was handed out
+            if (avail >= nidle) {
+                pool += nidle;
+            } else if (fresh_n > 0) {
+                pool = fresh + min(nidle - avail, fresh_n);
+                pool_end = fresh + fresh_n;
+            } else {
+                pool = pool_end;
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(ray != kNoRay) == 0) {
+            if (drained && pool == pool_end) break;
+            continue;
+        }
+        if (ray != kNoRay) {
+            const bool fast = wave_fast(r);
+            if (wave_coherent(r))
+                Tr::template round<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
+                                                   nfetch, ntri, incomplete);
+            else
+                Tr::template step<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
+                                                  nfetch, ntri, incomplete);
+            if (Tr::done(ts)) {
+                if (incomplete) {
+                    fallback_append(fb, ray);
+                } else {
+                    store_hit(hits, ray, ts.best);
+                    if (Count) {
+                        counts[2 * (size_t)ray] = nfetch;
+                        counts[2 * (size_t)ray + 1] = ntri;
+                    }
+                }
+                ray = kNoRay;
+            }
+        }
     }
 }
 
@@ -66,31 +155,18 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_fallback(const void *node
                                                                 LeafData ld, const bvh_ray *rays,
                                                                 bvh_hit *hits, uint32_t *counts,
                                                                 Fallback fb) {
+    using Tr = typename TracerFor<Layout>::type;
     const uint32_t lane = blockIdx.x * kTraceBlock + threadIdx.x;
     const uint32_t total = *fb.count;
     for (uint32_t k = lane; k < total; k += kFallbackLanes) {
         const uint32_t i = fb.list[k];
-        const Ray r = load_ray(rays, i);
+        const Ray r = load_ray(rays, i, ld.coord_max);
         uint32_t nfetch = 0, ntri = 0;
         bool incomplete = false;
-        Best best;
-        if (Layout == BVH_LAYOUT_AABB2) {
-            GlobalStack<false> st(fb.stack_ref + (size_t)lane * kStackMax, nullptr);
-            best = trace_aabb2<LeafMode, Mode>(static_cast<const bvh_node_aabb2 *>(nodes), n_nodes,
-                                               ld, r, st, nfetch, ntri, incomplete);
-        } else {
-            GlobalStack<true> st(fb.stack_ref + (size_t)lane * kStackMax,
-                                 fb.stack_t + (size_t)lane * kStackMax);
-            if (Layout == BVH_LAYOUT_BVH4)
-                best = trace_wide<DecodeBVH4, LeafMode, Mode>(nodes, n_nodes, ld, r, st, nfetch,
-                                                             ntri, incomplete);
-            else if (Layout == BVH_LAYOUT_BVH8_Q8)
-                best = trace_wide<DecodeBVH8Q8, LeafMode, Mode>(nodes, n_nodes, ld, r, st, nfetch,
-                                                               ntri, incomplete);
-            else
-                best = trace_wide<DecodeBVH8Q16, LeafMode, Mode>(nodes, n_nodes, ld, r, st, nfetch,
-                                                                ntri, incomplete);
-        }
+        GlobalStack<Tr::kWithT> st(fb.stack_ref + (size_t)lane * kStackMax,
+                                   fb.stack_t + (size_t)lane * kStackMax);
+        const Best best =
+            trace_ray<Layout, LeafMode, Mode>(nodes, n_nodes, ld, r, st, nfetch, ntri, incomplete);
         store_hit(hits, i, best);
         if (Count) {
             counts[2 * (size_t)i] = nfetch;
@@ -99,56 +175,113 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_fallback(const void *node
     }
 }
 
+// Spill entries per lane of a persistent launch (beyond the LDS ring).
+constexpr uint32_t kSpillCap = 64;
+
+// Resident blocks of a kernel on the current device (cached per kernel).
+template <typename K>
+int32_t resident_blocks(K kernel, unsigned &blocks) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, unsigned> cache;
+    int dev = 0;
+    BVH_HIP_TRY(hipGetDevice(&dev));
+    const auto key = std::make_pair(reinterpret_cast<const void *>(kernel), dev);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            blocks = it->second;
+            return BVH_OK;
+        }
+    }
+    int per_cu = 0, n_cu = 0;
+    BVH_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTraceBlock, 0));
+    BVH_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    blocks = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(n_cu > 0 ? n_cu : 1);
+    std::lock_guard<std::mutex> lock(mu);
+    cache[key] = blocks;
+    return BVH_OK;
+}
+
+// Work area of one launch: the fallback header, list and deep stacks, then
+// (persistent launches) the per-lane spill area.
+struct TraceArea {
+    Fallback fb;
+    SpillArea sa;
+};
+
+int32_t trace_area(hipStream_t s, uint64_t n, uint32_t lanes, TraceArea &ta) {
+    const size_t fb_bytes = (fallback_bytes(n) + 255) & ~(size_t)255;
+    const size_t sp_bytes = (size_t)lanes * kSpillCap * 8;
+    void *ws = nullptr;
+    BVH_TRY(stream_workspace(s, kAreaTrace, fb_bytes + sp_bytes, &ws));
+    ta.fb = fallback_view(ws, n);
+    char *sp = static_cast<char *>(ws) + fb_bytes;
+    ta.sa.ref = reinterpret_cast<uint32_t *>(sp);
+    ta.sa.t = reinterpret_cast<float *>(sp + (size_t)lanes * kSpillCap * 4);
+    ta.sa.lanes = lanes;
+    ta.sa.cap = kSpillCap;
+    BVH_HIP_TRY(hipMemsetAsync(ta.fb.count, 0, kFallbackHeaderBytes, s));
+    return BVH_OK;
+}
+
+constexpr bool kPersistent = true;
+
+template <int Layout, int LeafMode, int Mode, bool Count, int SL>
+int32_t launch_layout(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *rays, uint64_t n,
+                      bvh_hit *hits, uint32_t *counts, hipStream_t s) {
+    const uint64_t need = (n + kTraceBlock - 1) / kTraceBlock;
+    TraceArea ta;
+    if (kPersistent) {
+        auto kernel = k_trace_persist<Layout, LeafMode, Mode, Count, SL>;
+        unsigned resident = 0;
+        BVH_TRY(resident_blocks(kernel, resident));
+        const unsigned grid = (unsigned)std::min<uint64_t>(resident, need);
+        BVH_TRY(trace_area(s, n, grid * kTraceBlock, ta));
+        kernel<<<grid, kTraceBlock, 0, s>>>(h->nodes, h->n_nodes, ld, rays, n, hits, counts, ta.fb,
+                                            ta.sa);
+    } else {
+        BVH_TRY(trace_area(s, n, 0, ta));
+        k_trace<Layout, LeafMode, Mode, Count, SL><<<(unsigned)need, kTraceBlock, 0, s>>>(
+            h->nodes, h->n_nodes, ld, rays, n, hits, counts, ta.fb);
+    }
+    k_trace_fallback<Layout, LeafMode, Mode, Count><<<kFallbackBlocks, kTraceBlock, 0, s>>>(
+        h->nodes, h->n_nodes, ld, rays, hits, counts, ta.fb);
+    return BVH_OK;
+}
+
 template <int LeafMode, int Mode, bool Count, int SL>
-void launch_sl(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *rays, uint64_t n,
-               bvh_hit *hits, uint32_t *counts, const Fallback &fb, hipStream_t s) {
-    const unsigned grid = (unsigned)((n + kTraceBlock - 1) / kTraceBlock);
+int32_t launch_sl(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *rays, uint64_t n,
+                  bvh_hit *hits, uint32_t *counts, hipStream_t s) {
     switch (h->layout) {
         case BVH_LAYOUT_AABB2:
-            k_trace_aabb2<LeafMode, Mode, Count, SL><<<grid, kTraceBlock, 0, s>>>(
-                static_cast<const bvh_node_aabb2 *>(h->nodes), h->n_nodes, ld, rays, n, hits, counts, fb);
-            k_trace_fallback<BVH_LAYOUT_AABB2, LeafMode, Mode, Count>
-                <<<kFallbackBlocks, kTraceBlock, 0, s>>>(h->nodes, h->n_nodes, ld, rays, hits, counts, fb);
-            break;
+            return launch_layout<BVH_LAYOUT_AABB2, LeafMode, Mode, Count, SL>(h, ld, rays, n, hits,
+                                                                             counts, s);
         case BVH_LAYOUT_BVH4:
-            k_trace_wide<DecodeBVH4, LeafMode, Mode, Count, SL><<<grid, kTraceBlock, 0, s>>>(
-                h->nodes, h->n_nodes, ld, rays, n, hits, counts, fb);
-            k_trace_fallback<BVH_LAYOUT_BVH4, LeafMode, Mode, Count>
-                <<<kFallbackBlocks, kTraceBlock, 0, s>>>(h->nodes, h->n_nodes, ld, rays, hits, counts, fb);
-            break;
+            return launch_layout<BVH_LAYOUT_BVH4, LeafMode, Mode, Count, SL>(h, ld, rays, n, hits,
+                                                                            counts, s);
         case BVH_LAYOUT_BVH8_Q8:
-            k_trace_wide<DecodeBVH8Q8, LeafMode, Mode, Count, SL><<<grid, kTraceBlock, 0, s>>>(
-                h->nodes, h->n_nodes, ld, rays, n, hits, counts, fb);
-            k_trace_fallback<BVH_LAYOUT_BVH8_Q8, LeafMode, Mode, Count>
-                <<<kFallbackBlocks, kTraceBlock, 0, s>>>(h->nodes, h->n_nodes, ld, rays, hits, counts, fb);
-            break;
+            return launch_layout<BVH_LAYOUT_BVH8_Q8, LeafMode, Mode, Count, SL>(h, ld, rays, n,
+                                                                               hits, counts, s);
         default:
-            k_trace_wide<DecodeBVH8Q16, LeafMode, Mode, Count, SL><<<grid, kTraceBlock, 0, s>>>(
-                h->nodes, h->n_nodes, ld, rays, n, hits, counts, fb);
-            k_trace_fallback<BVH_LAYOUT_BVH8_Q16, LeafMode, Mode, Count>
-                <<<kFallbackBlocks, kTraceBlock, 0, s>>>(h->nodes, h->n_nodes, ld, rays, hits, counts, fb);
-            break;
+            return launch_layout<BVH_LAYOUT_BVH8_Q16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
+                                                                                hits, counts, s);
     }
 }
 
 template <int LeafMode, int Mode, bool Count>
 int32_t launch_mode(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits,
                     uint32_t *counts, hipStream_t s) {
-    const LeafData ld{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris};
-    // fallback work area of this stream (grow-only, reused across calls)
-    void *ws = nullptr;
-    BVH_TRY(stream_workspace(s, kAreaTrace, fallback_bytes(n), &ws));
-    const Fallback fb = fallback_view(ws, n);
-    hipError_t e = hipMemsetAsync(fb.count, 0, sizeof(uint32_t), s);
-    if (e == hipSuccess) {
-        if (h->stack_lds == 8)
-            launch_sl<LeafMode, Mode, Count, 8>(h, ld, rays, n, hits, counts, fb, s);
-        else if (h->stack_lds == 32)
-            launch_sl<LeafMode, Mode, Count, 32>(h, ld, rays, n, hits, counts, fb, s);
-        else
-            launch_sl<LeafMode, Mode, Count, 16>(h, ld, rays, n, hits, counts, fb, s);
-        e = hipGetLastError();
-    }
+    const LeafData ld{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris, h->coord_max()};
+    int32_t rc;
+    if (h->stack_lds == 8)
+        rc = launch_sl<LeafMode, Mode, Count, 8>(h, ld, rays, n, hits, counts, s);
+    else if (h->stack_lds == 32)
+        rc = launch_sl<LeafMode, Mode, Count, 32>(h, ld, rays, n, hits, counts, s);
+    else
+        rc = launch_sl<LeafMode, Mode, Count, 16>(h, ld, rays, n, hits, counts, s);
+    if (rc != BVH_OK) return rc;
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(BVH_EHIP, "bvh_trace: launch failed: %s", hipGetErrorString(e));
     return BVH_OK;
 }

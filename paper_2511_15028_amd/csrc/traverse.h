@@ -29,10 +29,28 @@ struct Ray {
     float dx, dy, dz;
     float rx, ry, rz;  // 1/d, IEEE (+-inf for +-0)
     float tmax;
+    float knx, kny, knz;  // -(o * rdir) rounded up / down, for the one-FMA slab
+    float kfx, kfy, kfz;  // distances (see slab_nf)
     bool nx, ny, nz;   // sign bits of d
+    bool fast;         // the one-FMA slab distances are valid for this ray
 };
 
-__device__ inline Ray load_ray(const bvh_ray *rays, uint64_t i) {
+// Scenes whose coordinates exceed this magnitude, and rays whose origin or
+// 1/d components lie outside [2^-60, 2^60] in magnitude, use the two-rounding
+// slab distances; everything else uses the one-FMA form.
+constexpr float kFastLimit = 1.152921504606846976e18f;  // 2^60
+
+// o * rdir moved outward by at least one ulp: the returned pair (lo, hi)
+// brackets the exact product.
+__device__ inline void bracket_product(float o, float rd, float &lo, float &hi) {
+    const float c = o * rd;
+    const float delta = fabsf(c) * 2.384185791015625e-07f + 2.350988701644575e-38f;  // 2^-22, 2^-125
+    lo = c - delta;
+    hi = c + delta;
+}
+
+// coord_max: largest coordinate magnitude of the scene (or +inf).
+__device__ inline Ray load_ray(const bvh_ray *rays, uint64_t i, float coord_max) {
     const float4 *p = reinterpret_cast<const float4 *>(rays + i);
     const float4 a = p[0], b = p[1];
     Ray r;
@@ -45,34 +63,86 @@ __device__ inline Ray load_ray(const bvh_ray *rays, uint64_t i) {
     r.nx = signbit(r.dx);
     r.ny = signbit(r.dy);
     r.nz = signbit(r.dz);
+    float lo, hi;
+    bracket_product(r.ox, r.rx, lo, hi);
+    r.knx = -hi; r.kfx = -lo;
+    bracket_product(r.oy, r.ry, lo, hi);
+    r.kny = -hi; r.kfy = -lo;
+    bracket_product(r.oz, r.rz, lo, hi);
+    r.knz = -hi; r.kfz = -lo;
+    const float rmax = fmaxf(fabsf(r.rx), fmaxf(fabsf(r.ry), fabsf(r.rz)));
+    const float rmin = fminf(fabsf(r.rx), fminf(fabsf(r.ry), fabsf(r.rz)));
+    const float omax = fmaxf(fabsf(r.ox), fmaxf(fabsf(r.oy), fabsf(r.oz)));
+    r.fast = rmax <= kFastLimit && rmin >= 1.0f / kFastLimit && omax <= kFastLimit &&
+             coord_max <= kFastLimit;  // false for NaN as well
     return r;
 }
 
-// Ray/box test of App. G (intersectsp_ray_aabb) with the node cull folded
-// in: the far end is clipped at tcur (the best hit so far, or tmax).
-// Returns the entry distance, or +inf when the box is culled.
-__device__ inline float slab(const Ray &r, float lox, float loy, float loz, float hix, float hiy,
-                             float hiz, float tcur) {
-    const float nx = r.nx ? hix : lox, fx = r.nx ? lox : hix;
-    const float ny = r.ny ? hiy : loy, fy = r.ny ? loy : hiy;
-    const float nz = r.nz ? hiz : loz, fz = r.nz ? loz : hiz;
-    const float tnx = (nx - r.ox) * r.rx, tfx = (fx - r.ox) * r.rx;
-    const float tny = (ny - r.oy) * r.ry, tfy = (fy - r.oy) * r.ry;
-    const float tnz = (nz - r.oz) * r.rz, tfz = (fz - r.oz) * r.rz;
+// True when every active lane's ray can use the one-FMA slab distances (a
+// wave-uniform value, so the choice costs one scalar branch).
+__device__ inline bool wave_fast(const Ray &r) {
+    return __builtin_amdgcn_ballot_w64(!r.fast) == 0;
+}
+
+// True when the active lanes' rays all point into the same octant (a cheap
+// wave-uniform coherence test: camera rays of neighbouring pixels pass it,
+// scattered secondary rays do not).
+__device__ inline bool wave_coherent(const Ray &r) {
+    const uint64_t nx = __builtin_amdgcn_ballot_w64(r.nx), ny = __builtin_amdgcn_ballot_w64(r.ny);
+    const uint64_t nz = __builtin_amdgcn_ballot_w64(r.nz), all = __builtin_amdgcn_ballot_w64(true);
+    return (nx == 0 || nx == all) && (ny == 0 || ny == all) && (nz == 0 || nz == all);
+}
+
+// Ray/box test of App. G (intersectsp_ray_aabb) on planes already ordered
+// by the ray: (nx, ny, nz) are the planes the ray enters through (the lower
+// plane of an axis where d >= +0, the upper where d <= -0), (fx, fy, fz) the
+// planes it leaves through.  The node cull is folded in: the far end is
+// clipped at tcur (the best hit so far, or tmax).  Returns the entry
+// distance, or +inf when the box is culled.
+//
+// Plane distances: the two-rounding form (plane - o) * rdir of App. G, or,
+// when Fast, one FMA plane * rdir - o * rdir with the product o * rdir
+// bracketed outward (entry planes subtract an upper bound, exit planes a
+// lower bound), so the computed entry distance never exceeds
+// (plane - o) * rdir by more than one rounding and the exit distance never
+// falls short of it by more than one rounding.  Either way the relative
+// error of each distance against the exact (plane - o) / d stays below the
+// far-distance widening, so no box that the ray meets before tcur is culled.
+template <bool Fast>
+__device__ inline float slab_nf(const Ray &r, float nx, float ny, float nz, float fx, float fy,
+                                float fz, float tcur) {
+    float tnx, tny, tnz, tfx, tfy, tfz;
+    if (Fast) {
+        tnx = fmaf(nx, r.rx, r.knx); tfx = fmaf(fx, r.rx, r.kfx);
+        tny = fmaf(ny, r.ry, r.kny); tfy = fmaf(fy, r.ry, r.kfy);
+        tnz = fmaf(nz, r.rz, r.knz); tfz = fmaf(fz, r.rz, r.kfz);
+    } else {
+        tnx = (nx - r.ox) * r.rx; tfx = (fx - r.ox) * r.rx;
+        tny = (ny - r.oy) * r.ry; tfy = (fy - r.oy) * r.ry;
+        tnz = (nz - r.oz) * r.rz; tfz = (fz - r.oz) * r.rz;
+    }
     const float t_near = fmaxf(0.0f, fmaxf(tnx, fmaxf(tny, tnz)));
     const float t_far = fminf(tcur, fminf(tfx, fminf(tfy, tfz)));
     return (t_near <= t_far * kFarScale) ? t_near : INFINITY;
 }
 
+// The same test on a box given as (lo, hi): the entry and exit planes are
+// chosen by the sign bit of each direction component.
+template <bool Fast>
+__device__ inline float slab(const Ray &r, float lox, float loy, float loz, float hix, float hiy,
+                             float hiz, float tcur) {
+    return slab_nf<Fast>(r, r.nx ? hix : lox, r.ny ? hiy : loy, r.nz ? hiz : loz,
+                         r.nx ? lox : hix, r.ny ? loy : hiy, r.nz ? loz : hiz, tcur);
+}
+
 // Moller-Trumbore of App. G (intersectsp_ray_tri_mt), operation for
-// operation: e1 = p0-p1, e2 = p2-p0, ng = e2 x e1, c = p0-o, r = c x d,
+// operation, given p0 and the edges e1 = p0-p1, e2 = p2-p0 (each rounded to
+// f32 exactly as the test computes them): ng = e2 x e1, c = p0-o, r = c x d,
 // D = ng.d, U/V/T sign-folded by D, edges inclusive, 0 < t <= tmax,
 // t, u, v = (T, U, V) * (1/|D|).  Built without FMA contraction.
-__device__ inline bool mt(const Ray &r, float p0x, float p0y, float p0z, float p1x, float p1y,
-                          float p1z, float p2x, float p2y, float p2z, float &t, float &u,
-                          float &v) {
-    const float e1x = p0x - p1x, e1y = p0y - p1y, e1z = p0z - p1z;
-    const float e2x = p2x - p0x, e2y = p2y - p0y, e2z = p2z - p0z;
+__device__ inline bool mt_edges(const Ray &r, float p0x, float p0y, float p0z, float e1x,
+                                float e1y, float e1z, float e2x, float e2y, float e2z, float &t,
+                                float &u, float &v) {
     const float ngx = e2y * e1z - e2z * e1y;
     const float ngy = e2z * e1x - e2x * e1z;
     const float ngz = e2x * e1y - e2y * e1x;
@@ -96,6 +166,14 @@ __device__ inline bool mt(const Ray &r, float p0x, float p0y, float p0z, float p
     return true;
 }
 
+// The same test from the three vertices.
+__device__ inline bool mt(const Ray &r, float p0x, float p0y, float p0z, float p1x, float p1y,
+                          float p1z, float p2x, float p2y, float p2z, float &t, float &u,
+                          float &v) {
+    return mt_edges(r, p0x, p0y, p0z, p0x - p1x, p0y - p1y, p0z - p1z, p2x - p0x, p2y - p0y,
+                    p2z - p0z, t, u, v);
+}
+
 struct Best {
     float t, u, v;
     uint32_t id;  // 0xFFFFFFFF = none (compares above every valid id)
@@ -111,35 +189,20 @@ __device__ inline void consider(Best &b, float t, float u, float v, uint32_t id)
     }
 }
 
-// Leaf storage: COMPACT reads 48-B triangle records in leaf order; INDEXED
-// reads a primitive id, its three vertex indices and three vertices.
+// Leaf storage: COMPACT reads 48-B records {p0, e1, e2, prim id} in leaf
+// order; INDEXED reads a primitive id, its three vertex indices and three
+// vertices.
 struct LeafData {
     const void *leaf;
     const float *verts;
     const int32_t *tris;
     uint32_t n_tris;
+    float coord_max;  // largest coordinate magnitude of the scene (selects the slab form)
 };
 
-template <int LeafMode>
-__device__ inline void fetch_tri(const LeafData &ld, uint32_t k, float *p, uint32_t &id) {
-    if (LeafMode == BVH_LEAF_COMPACT) {
-        const float4 *q = static_cast<const float4 *>(ld.leaf) + 3 * (size_t)k;
-        const float4 a = q[0], b = q[1], c = q[2];
-        p[0] = a.x; p[1] = a.y; p[2] = a.z;
-        p[3] = a.w; p[4] = b.x; p[5] = b.y;
-        p[6] = b.z; p[7] = b.w; p[8] = c.x;
-        id = __float_as_uint(c.y);
-    } else {
-        id = (uint32_t)static_cast<const int32_t *>(ld.leaf)[k];
-        const int32_t *tv = ld.tris + 3 * (size_t)id;
-        for (int j = 0; j < 3; j++) {
-            const float *vp = ld.verts + 3 * (size_t)tv[j];
-            p[3 * j] = vp[0];
-            p[3 * j + 1] = vp[1];
-            p[3 * j + 2] = vp[2];
-        }
-    }
-}
+// Compacted leaves: triangles are fetched in batches of kLeafBatch (all loads
+// issued before the first test, so their latencies overlap).
+constexpr uint32_t kLeafBatch = 4;
 
 // Tests triangles [first, first+n) of the leaf order.  Returns true when an
 // any-hit query is satisfied.
@@ -147,13 +210,47 @@ template <int LeafMode, int Mode>
 __device__ inline bool test_leaf(const LeafData &ld, const Ray &r, uint32_t first, uint32_t n,
                                  Best &best, uint32_t &ntri) {
     const uint32_t end = min(first + n, ld.n_tris);  // bounds guard; a valid tree never clips
+    if (LeafMode == BVH_LEAF_COMPACT) {
+        const float4 *base = static_cast<const float4 *>(ld.leaf);
+        for (uint32_t k0 = first; k0 < end; k0 += kLeafBatch) {
+            float4 qa[kLeafBatch], qb[kLeafBatch];
+            float2 qc[kLeafBatch];  // e2.z and the prim id (the record's padding is not read)
+#pragma unroll
+            for (uint32_t j = 0; j < kLeafBatch; j++) {
+                if (k0 + j < end) {
+                    const float4 *p = base + 3 * (size_t)(k0 + j);
+                    qa[j] = p[0];
+                    qb[j] = p[1];
+                    qc[j] = *reinterpret_cast<const float2 *>(p + 2);
+                }
+            }
+            bool found = false;
+#pragma unroll
+            for (uint32_t j = 0; j < kLeafBatch; j++) {
+                if (k0 + j < end && !found) {
+                    ntri++;
+                    float t, u, v;
+                    const float4 a = qa[j], b = qb[j];
+                    const float2 c = qc[j];
+                    if (mt_edges(r, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, t, u, v)) {
+                        consider(best, t, u, v, __float_as_uint(c.y));
+                        found = Mode == BVH_TRACE_ANY;
+                    }
+                }
+            }
+            if (found) return true;
+        }
+        return false;
+    }
     for (uint32_t k = first; k < end; k++) {
-        float p[9];
-        uint32_t id;
-        fetch_tri<LeafMode>(ld, k, p, id);
+        const uint32_t id = (uint32_t) static_cast<const int32_t *>(ld.leaf)[k];
+        const int32_t *tv = ld.tris + 3 * (size_t)id;
+        const float *a = ld.verts + 3 * (size_t)tv[0];
+        const float *b = ld.verts + 3 * (size_t)tv[1];
+        const float *c = ld.verts + 3 * (size_t)tv[2];
         ntri++;
         float t, u, v;
-        if (mt(r, p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], p[8], t, u, v)) {
+        if (mt(r, a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2], t, u, v)) {
             consider(best, t, u, v, id);
             if (Mode == BVH_TRACE_ANY) return true;
         }
@@ -211,6 +308,64 @@ struct GlobalStack {
     }
 };
 
+// Stack of one lane of a persistent kernel: a ring of SL entries in LDS
+// (one column per lane) over a spill area in global memory that belongs to
+// the lane for the whole launch.  When the ring is full, a push first moves
+// its oldest half to the spill area; when it is empty, a pop first brings the
+// newest spilled half back.  Entries [0, lo) live in the spill area, entries
+// [lo, sp) in the ring (entry e in slot e mod SL).  A push fails only when
+// the spill area (cap entries) is full.
+struct SpillArea {
+    uint32_t *ref;    // [cap][lanes]
+    float *t;         // [cap][lanes]
+    uint32_t lanes;   // lanes of the launch (the grid's threads)
+    uint32_t cap;     // spill entries per lane
+};
+
+template <bool WithT, int SL>
+struct SpillStack {
+    static_assert((SL & (SL - 1)) == 0 && SL >= 2, "ring size must be a power of two");
+    uint32_t *lds_ref;  // [SL][kTraceBlock]
+    float *lds_t;       // [SL][kTraceBlock] when WithT
+    SpillArea area;     // uniform across the launch
+    uint32_t sp = 0, lo = 0;
+    __device__ SpillStack(uint32_t *r, float *t, const SpillArea &a) : lds_ref(r), lds_t(t), area(a) {}
+    __device__ void reset() { sp = lo = 0; }
+    __device__ static uint32_t slot(uint32_t e) { return (e & (SL - 1)) * kTraceBlock + threadIdx.x; }
+    // this lane's column of the spill area: the lane's index in the grid
+    __device__ size_t spill_index(uint32_t e) const {
+        return (size_t)e * area.lanes + blockIdx.x * kTraceBlock + threadIdx.x;
+    }
+    __device__ bool push(uint32_t ref, float t) {
+        if (sp - lo == (uint32_t)SL) {
+            constexpr uint32_t H = SL / 2;
+            if (lo + H > area.cap) return false;
+            for (uint32_t e = lo; e < lo + H; e++) {
+                area.ref[spill_index(e)] = lds_ref[slot(e)];
+                if (WithT) area.t[spill_index(e)] = lds_t[slot(e)];
+            }
+            lo += H;
+        }
+        lds_ref[slot(sp)] = ref;
+        if (WithT) lds_t[slot(sp)] = t;
+        sp++;
+        return true;
+    }
+    __device__ uint32_t pop(float &t) {  // requires sp > 0
+        if (sp == lo) {
+            const uint32_t n = lo < (uint32_t)(SL / 2) ? lo : (uint32_t)(SL / 2);
+            for (uint32_t e = lo - n; e < lo; e++) {
+                lds_ref[slot(e)] = area.ref[spill_index(e)];
+                if (WithT) lds_t[slot(e)] = area.t[spill_index(e)];
+            }
+            lo -= n;
+        }
+        sp--;
+        t = WithT ? lds_t[slot(sp)] : 0.0f;
+        return lds_ref[slot(sp)];
+    }
+};
+
 __device__ inline void store_hit(bvh_hit *hits, uint64_t i, const Best &b) {
     int4 w;
     w.x = (b.id == 0xFFFFFFFFu) ? -1 : (int)b.id;
@@ -221,71 +376,139 @@ __device__ inline void store_hit(bvh_hit *hits, uint64_t i, const Best &b) {
 }
 
 
+// The best-hit bound that culls nodes: the best hit so far (closest-hit
+// queries) or tmax.
+template <int Mode>
+__device__ inline float best_bound(const Ray &r, const Best &b) {
+    return (Mode == BVH_TRACE_ANY) ? r.tmax : fminf(b.t, r.tmax);
+}
+
 // ---------------------------------------------------------------------------
-// Binary layout with the box in the node (AABB2): pop a node, test its own
-// box against the current best, descend near child first (split axis and
-// ray direction sign), push the far child.  s_ref: [SL][kTraceBlock] LDS.
+// Binary layout with the box in the node (AABB2): visit a node by testing its
+// own box against the current best; a leaf's triangles are then tested, an
+// interior node continues with the near child (split axis and ray direction
+// sign) and pushes the far child.
 // ---------------------------------------------------------------------------
-template <int LeafMode, int Mode, class Stack>
-__device__ inline Best trace_aabb2(const bvh_node_aabb2 *nodes, int64_t n_nodes, const LeafData &ld,
-                                   const Ray &r, Stack &st, uint32_t &nfetch, uint32_t &ntri,
-                                   bool &incomplete) {
-    Best best{INFINITY, 0.0f, 0.0f, 0xFFFFFFFFu};
-    uint32_t node = 0;
-    bool active = n_nodes > 0;
-    while (active) {
-        if (node >= (uint64_t)n_nodes) break;  // bounds guard; a valid tree never takes it
-        const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
-        const float4 a = np[0], b = np[1];
-        nfetch++;
-        const float tcur = (Mode == BVH_TRACE_ANY) ? r.tmax : fminf(best.t, r.tmax);
-        const float tn = slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tcur);
-        if (tn != INFINITY) {
-            const uint32_t off = __float_as_uint(b.z), meta = __float_as_uint(b.w);
-            const uint32_t np_ = meta & 0xFFFFu;
-            if (np_ > 0) {
-                if (test_leaf<LeafMode, Mode>(ld, r, off, np_, best, ntri)) break;
-            } else {
-                const uint32_t axis = (meta >> 16) & 3u;
-                const bool neg = axis == 0 ? r.nx : (axis == 1 ? r.ny : r.nz);
-                const uint32_t left = node + 1, right = node + off;
-                if (!st.push(neg ? left : right, 0.0f)) {
-                    incomplete = true;
-                    break;
-                }
-                node = neg ? right : left;
-                continue;
-            }
-        }
-        if (st.sp == 0) break;
-        float unused;
-        node = st.pop(unused);
+struct BinState {
+    Best best;
+    uint32_t node;  // next node to visit; kRefEmpty when no node is left
+    uint32_t leaf;  // leaf parked by the two-phase order (kRefEmpty: none)
+    uint32_t hold;  // a second leaf met while one is parked
+};
+
+__device__ inline BinState bin_start(int64_t n_nodes) {
+    BinState s;
+    s.best = Best{INFINITY, 0.0f, 0.0f, 0xFFFFFFFFu};
+    s.node = n_nodes > 0 ? 0u : kRefEmpty;
+    s.leaf = s.hold = kRefEmpty;
+    return s;
+}
+
+template <class Stack>
+__device__ inline uint32_t bin_pop(Stack &st) {
+    float unused;
+    return st.sp > 0 ? st.pop(unused) : kRefEmpty;
+}
+
+// Visits bs.node; returns the leaf reference when the node is a leaf whose
+// box the ray meets (kRefEmpty otherwise).  bs.node moves on to the next node.
+template <int Mode, class Stack>
+__device__ inline uint32_t bin_visit(const bvh_node_aabb2 *nodes, int64_t n_nodes, const Ray &r,
+                                     bool fast, Stack &st, BinState &bs, uint32_t &nfetch,
+                                     bool &incomplete) {
+    if (bs.node >= (uint64_t)n_nodes) {  // bounds guard; a valid tree never takes it
+        bs.node = bs.leaf = bs.hold = kRefEmpty;
+        return kRefEmpty;
     }
-    return best;
+    const float4 *np = reinterpret_cast<const float4 *>(nodes + bs.node);
+    const float4 a = np[0], b = np[1];
+    nfetch++;
+    const float tcur = best_bound<Mode>(r, bs.best);
+    const float tn = fast ? slab<true>(r, a.x, a.y, a.z, a.w, b.x, b.y, tcur)
+                          : slab<false>(r, a.x, a.y, a.z, a.w, b.x, b.y, tcur);
+    if (tn != INFINITY) {
+        const uint32_t off = __float_as_uint(b.z), meta = __float_as_uint(b.w);
+        const uint32_t cnt = meta & 0xFFFFu;
+        if (cnt > 0) {
+            bs.node = bin_pop(st);
+            return ref_leaf(off, cnt);
+        }
+        const uint32_t axis = (meta >> 16) & 3u;
+        const bool neg = axis == 0 ? r.nx : (axis == 1 ? r.ny : r.nz);
+        const uint32_t left = bs.node + 1, right = bs.node + off;
+        if (!st.push(neg ? left : right, 0.0f)) {
+            incomplete = true;
+            bs.node = bs.leaf = bs.hold = kRefEmpty;
+            return kRefEmpty;
+        }
+        bs.node = neg ? right : left;
+        return kRefEmpty;
+    }
+    bs.node = bin_pop(st);
+    return kRefEmpty;
+}
+
+// Tests the triangles of a leaf reference; a satisfied any-hit query ends
+// the ray.
+template <int LeafMode, int Mode>
+__device__ inline bool bin_test_leaf(const LeafData &ld, const Ray &r, uint32_t leaf,
+                                     BinState &bs, uint32_t &ntri) {
+    const uint32_t first = leaf >> 5, cnt = ((leaf >> 1) & 0xFu) + 1u;
+    if (test_leaf<LeafMode, Mode>(ld, r, first, cnt, bs.best, ntri)) {
+        bs.node = bs.leaf = bs.hold = kRefEmpty;
+        return true;
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------------------
 // Wide layouts: the node holds its children's boxes.  Decoders expose
 //   K                      arity
-//   test(node ptr, ray, tcur, tn[K], ref[K])
+//   Prep prep(ray)         per-ray constants (which plane arrays are near/far)
+//   test(node ptr, node, ray, prep, tcur, tn[K], ref[K])
 // writing the entry distance of every child the ray meets (+inf otherwise).
 // ---------------------------------------------------------------------------
+
+// BVH4: the near and far plane arrays of an axis are picked by address (the
+// sign of the direction component decides whether lo_a or hi_a is entered
+// first), so the per-child slab test needs no plane selects.
 struct DecodeBVH4 {
     static constexpr int K = 4;
-    __device__ static void test(const void *base, uint32_t node, const Ray &r, float tcur,
-                                float *tn, uint32_t *ref) {
-        const float4 *p = static_cast<const float4 *>(base) + 8 * (size_t)node;
-        const float4 lx = p[0], ly = p[1], lz = p[2], hx = p[3], hy = p[4], hz = p[5];
-        const uint4 ch = reinterpret_cast<const uint4 *>(p)[6];
-        const float lxs[4] = {lx.x, lx.y, lx.z, lx.w}, lys[4] = {ly.x, ly.y, ly.z, ly.w};
-        const float lzs[4] = {lz.x, lz.y, lz.z, lz.w}, hxs[4] = {hx.x, hx.y, hx.z, hx.w};
-        const float hys[4] = {hy.x, hy.y, hy.z, hy.w}, hzs[4] = {hz.x, hz.y, hz.z, hz.w};
-        const uint32_t chs[4] = {ch.x, ch.y, ch.z, ch.w};
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-            tn[c] = slab(r, lxs[c], lys[c], lzs[c], hxs[c], hys[c], hzs[c], tcur);
-            ref[c] = chs[c];
-        }
+    struct Prep {
+        // byte offsets of the entry-plane arrays in a node; the exit-plane
+        // array of an axis is the other one of the pair (lo_a, hi_a), at
+        // (lo_a + hi_a offsets) - entry offset
+        uint32_t nx, ny, nz;
+    };
+    __device__ static Prep prep(const Ray &r) {
+        Prep p;
+        p.nx = r.nx ? 48u : 0u;
+        p.ny = r.ny ? 64u : 16u;
+        p.nz = r.nz ? 80u : 32u;
+        return p;
+    }
+    template <bool Fast>
+    __device__ static void test(const void *base, uint32_t node, const Ray &r, const Prep &pp,
+                                float tcur, float *tn, uint32_t *ref) {
+        // 32-bit byte offsets from the buffer base (the builder keeps wide
+        // node buffers below 4 GiB), so each fetch is base + one offset
+        const char *b = static_cast<const char *>(base);
+        const uint32_t o = node * 128u;
+        const float4 nx = *reinterpret_cast<const float4 *>(b + (o + pp.nx));
+        const float4 ny = *reinterpret_cast<const float4 *>(b + (o + pp.ny));
+        const float4 nz = *reinterpret_cast<const float4 *>(b + (o + pp.nz));
+        const float4 fx = *reinterpret_cast<const float4 *>(b + ((o + 48u) - pp.nx));
+        const float4 fy = *reinterpret_cast<const float4 *>(b + ((o + 80u) - pp.ny));
+        const float4 fz = *reinterpret_cast<const float4 *>(b + ((o + 112u) - pp.nz));
+        const uint4 ch = *reinterpret_cast<const uint4 *>(b + (o + 96u));
+        tn[0] = slab_nf<Fast>(r, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, tcur);
+        tn[1] = slab_nf<Fast>(r, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, tcur);
+        tn[2] = slab_nf<Fast>(r, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, tcur);
+        tn[3] = slab_nf<Fast>(r, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, tcur);
+        ref[0] = ch.x;
+        ref[1] = ch.y;
+        ref[2] = ch.z;
+        ref[3] = ch.w;
     }
 };
 
@@ -297,10 +520,19 @@ __device__ inline uint32_t half_of(const uint32_t *w, int c) {
     return (w[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
 }
 
+// Quantised layouts: the near/far choice is made once per packed word (four
+// u8 or two u16 planes at a time) before dequantising.
+struct SignPrep {
+    bool nx, ny, nz;
+};
+
 struct DecodeBVH8Q8 {
     static constexpr int K = 8;
-    __device__ static void test(const void *base, uint32_t node, const Ray &r, float tcur,
-                                float *tn, uint32_t *ref) {
+    using Prep = SignPrep;
+    __device__ static Prep prep(const Ray &r) { return Prep{r.nx, r.ny, r.nz}; }
+    template <bool Fast>
+    __device__ static void test(const void *base, uint32_t node, const Ray &r, const Prep &,
+                                float tcur, float *tn, uint32_t *ref) {
         const uint4 *p = static_cast<const uint4 *>(base) + 8 * (size_t)node;
         uint32_t w[28];
 #pragma unroll
@@ -310,16 +542,27 @@ struct DecodeBVH8Q8 {
         }
         const float ox = __uint_as_float(w[0]), oy = __uint_as_float(w[1]), oz = __uint_as_float(w[2]);
         const float sx = __uint_as_float(w[3]), sy = __uint_as_float(w[4]), sz = __uint_as_float(w[5]);
+        // words: lo_x 6-7, lo_y 8-9, lo_z 10-11, hi_x 12-13, hi_y 14-15, hi_z 16-17
+        uint32_t n[6], f[6];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            n[k] = r.nx ? w[12 + k] : w[6 + k];
+            f[k] = r.nx ? w[6 + k] : w[12 + k];
+            n[2 + k] = r.ny ? w[14 + k] : w[8 + k];
+            f[2 + k] = r.ny ? w[8 + k] : w[14 + k];
+            n[4 + k] = r.nz ? w[16 + k] : w[10 + k];
+            f[4 + k] = r.nz ? w[10 + k] : w[16 + k];
+        }
 #pragma unroll
         for (int c = 0; c < 8; c++) {
-            const float lox = fmaf((float)byte_of(w[6], w[7], c), sx, ox);
-            const float loy = fmaf((float)byte_of(w[8], w[9], c), sy, oy);
-            const float loz = fmaf((float)byte_of(w[10], w[11], c), sz, oz);
-            const float hix = fmaf((float)byte_of(w[12], w[13], c), sx, ox);
-            const float hiy = fmaf((float)byte_of(w[14], w[15], c), sy, oy);
-            const float hiz = fmaf((float)byte_of(w[16], w[17], c), sz, oz);
+            const float nxp = fmaf((float)byte_of(n[0], n[1], c), sx, ox);
+            const float nyp = fmaf((float)byte_of(n[2], n[3], c), sy, oy);
+            const float nzp = fmaf((float)byte_of(n[4], n[5], c), sz, oz);
+            const float fxp = fmaf((float)byte_of(f[0], f[1], c), sx, ox);
+            const float fyp = fmaf((float)byte_of(f[2], f[3], c), sy, oy);
+            const float fzp = fmaf((float)byte_of(f[4], f[5], c), sz, oz);
             const bool valid = (uint32_t)c < w[26];
-            tn[c] = valid ? slab(r, lox, loy, loz, hix, hiy, hiz, tcur) : INFINITY;
+            tn[c] = valid ? slab_nf<Fast>(r, nxp, nyp, nzp, fxp, fyp, fzp, tcur) : INFINITY;
             ref[c] = w[18 + c];
         }
     }
@@ -327,8 +570,11 @@ struct DecodeBVH8Q8 {
 
 struct DecodeBVH8Q16 {
     static constexpr int K = 8;
-    __device__ static void test(const void *base, uint32_t node, const Ray &r, float tcur,
-                                float *tn, uint32_t *ref) {
+    using Prep = SignPrep;
+    __device__ static Prep prep(const Ray &r) { return Prep{r.nx, r.ny, r.nz}; }
+    template <bool Fast>
+    __device__ static void test(const void *base, uint32_t node, const Ray &r, const Prep &,
+                                float tcur, float *tn, uint32_t *ref) {
         const uint4 *p = static_cast<const uint4 *>(base) + 10 * (size_t)node;
         uint32_t w[40];
 #pragma unroll
@@ -338,16 +584,27 @@ struct DecodeBVH8Q16 {
         }
         const float ox = __uint_as_float(w[0]), oy = __uint_as_float(w[1]), oz = __uint_as_float(w[2]);
         const float sx = __uint_as_float(w[3]), sy = __uint_as_float(w[4]), sz = __uint_as_float(w[5]);
+        // words: lo_x 6-9, lo_y 10-13, lo_z 14-17, hi_x 18-21, hi_y 22-25, hi_z 26-29
+        uint32_t n[12], f[12];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            n[k] = r.nx ? w[18 + k] : w[6 + k];
+            f[k] = r.nx ? w[6 + k] : w[18 + k];
+            n[4 + k] = r.ny ? w[22 + k] : w[10 + k];
+            f[4 + k] = r.ny ? w[10 + k] : w[22 + k];
+            n[8 + k] = r.nz ? w[26 + k] : w[14 + k];
+            f[8 + k] = r.nz ? w[14 + k] : w[26 + k];
+        }
 #pragma unroll
         for (int c = 0; c < 8; c++) {
-            const float lox = fmaf((float)half_of(w + 6, c), sx, ox);
-            const float loy = fmaf((float)half_of(w + 10, c), sy, oy);
-            const float loz = fmaf((float)half_of(w + 14, c), sz, oz);
-            const float hix = fmaf((float)half_of(w + 18, c), sx, ox);
-            const float hiy = fmaf((float)half_of(w + 22, c), sy, oy);
-            const float hiz = fmaf((float)half_of(w + 26, c), sz, oz);
+            const float nxp = fmaf((float)half_of(n, c), sx, ox);
+            const float nyp = fmaf((float)half_of(n + 4, c), sy, oy);
+            const float nzp = fmaf((float)half_of(n + 8, c), sz, oz);
+            const float fxp = fmaf((float)half_of(f, c), sx, ox);
+            const float fyp = fmaf((float)half_of(f + 4, c), sy, oy);
+            const float fzp = fmaf((float)half_of(f + 8, c), sz, oz);
             const bool valid = (uint32_t)c < w[38];
-            tn[c] = valid ? slab(r, lox, loy, loz, hix, hiy, hiz, tcur) : INFINITY;
+            tn[c] = valid ? slab_nf<Fast>(r, nxp, nyp, nzp, fxp, fyp, fzp, tcur) : INFINITY;
             ref[c] = w[30 + c];
         }
     }
@@ -381,55 +638,264 @@ __device__ inline void sort_children(float *t, uint32_t *r) {
 }
 
 
-// Wide-node traversal: test all children of the current node, sort the hit
-// ones near-first, continue with the nearest and push the rest with their
-// entry distances; popped entries are re-culled against the current best.
-// s_ref, s_t: [SL][kTraceBlock] LDS.
-template <class Dec, int LeafMode, int Mode, class Stack>
-__device__ inline Best trace_wide(const void *nodes, int64_t n_nodes, const LeafData &ld,
-                                  const Ray &r, Stack &st, uint32_t &nfetch, uint32_t &ntri,
-                                  bool &incomplete) {
-    constexpr int K = Dec::K;
-    Best best{INFINITY, 0.0f, 0.0f, 0xFFFFFFFFu};
-    uint32_t cur = n_nodes > 0 ? ref_interior(0) : kRefEmpty;
-    while (cur != kRefEmpty) {
-        const float tcur = (Mode == BVH_TRACE_ANY) ? r.tmax : fminf(best.t, r.tmax);
-        if (cur & 1u) {
-            if ((cur >> 1) >= (uint64_t)n_nodes) break;  // bounds guard; never taken on a valid tree
-            float tn[K];
-            uint32_t ref[K];
-            Dec::test(nodes, cur >> 1, r, tcur, tn, ref);
-            nfetch++;
-            sort_children<K>(tn, ref);
-            bool ok = true;
-#pragma unroll
-            for (int c = K - 1; c >= 1; c--)
-                if (tn[c] != INFINITY) ok = st.push(ref[c], tn[c]) && ok;
-            if (!ok) {
-                incomplete = true;
-                break;
-            }
-            if (tn[0] != INFINITY) {
-                cur = ref[0];
-                continue;
-            }
-        } else {
-            const uint32_t first = cur >> 5, cnt = ((cur >> 1) & 0xFu) + 1u;
-            if (test_leaf<LeafMode, Mode>(ld, r, first, cnt, best, ntri)) break;
-        }
-        // pop the next entry that the current best has not culled
-        cur = kRefEmpty;
-        const float tb = (Mode == BVH_TRACE_ANY) ? r.tmax : fminf(best.t, r.tmax);
-        while (st.sp > 0) {
-            float t;
-            const uint32_t ref = st.pop(t);
-            if (t <= tb * kFarScale) {
-                cur = ref;
-                break;
-            }
+// Pops stack entries until one is not culled by tb (the current best hit or
+// tmax); returns kRefEmpty when the stack runs dry.
+template <class Stack>
+__device__ inline uint32_t pop_unculled(Stack &st, float tb, float &t_entry) {
+    while (st.sp > 0) {
+        float t;
+        const uint32_t ref = st.pop(t);
+        if (t <= tb * kFarScale) {
+            t_entry = t;
+            return ref;
         }
     }
-    return best;
+    return kRefEmpty;
+}
+
+// Traversal state of one ray in a wide BVH.
+struct WideState {
+    Best best;
+    uint32_t cur;    // entry to visit next; kRefEmpty once the ray is done
+    float cur_t;     // entry distance of cur
+    uint32_t leaf;   // leaf parked by the two-phase order (kRefEmpty: none)
+};
+
+__device__ inline WideState wide_start(int64_t n_nodes) {
+    WideState ws;
+    ws.best = Best{INFINITY, 0.0f, 0.0f, 0xFFFFFFFFu};
+    ws.cur = n_nodes > 0 ? ref_interior(0) : kRefEmpty;
+    ws.cur_t = 0.0f;
+    ws.leaf = kRefEmpty;
+    return ws;
+}
+
+// Visits the interior node ws.cur: tests all its children, sorts the hit ones
+// near-first, pushes all but the nearest with their entry distances and
+// continues with the nearest (or with the next unculled stack entry when no
+// child is hit).  A failed push (stack full) ends the ray as incomplete.
+template <class Dec, int Mode, class Stack>
+__device__ inline void wide_visit_interior(const void *nodes, int64_t n_nodes, const Ray &r,
+                                           const typename Dec::Prep &prep, bool fast, Stack &st,
+                                           WideState &ws, uint32_t &nfetch, bool &incomplete) {
+    constexpr int K = Dec::K;
+    const float tcur = best_bound<Mode>(r, ws.best);
+    if ((ws.cur >> 1) >= (uint64_t)n_nodes) {  // bounds guard; never taken on a valid tree
+        ws.cur = kRefEmpty;
+        ws.leaf = kRefEmpty;
+        return;
+    }
+    float tn[K];
+    uint32_t ref[K];
+    if (fast)
+        Dec::template test<true>(nodes, ws.cur >> 1, r, prep, tcur, tn, ref);
+    else
+        Dec::template test<false>(nodes, ws.cur >> 1, r, prep, tcur, tn, ref);
+    nfetch++;
+    sort_children<K>(tn, ref);
+    bool ok = true;
+#pragma unroll
+    for (int c = K - 1; c >= 1; c--)
+        if (tn[c] != INFINITY) ok = st.push(ref[c], tn[c]) && ok;
+    if (!ok) {
+        incomplete = true;
+        ws.cur = kRefEmpty;
+        ws.leaf = kRefEmpty;
+    } else if (tn[0] != INFINITY) {
+        ws.cur = ref[0];
+        ws.cur_t = tn[0];
+    } else {
+        ws.cur = pop_unculled(st, tcur, ws.cur_t);
+    }
+}
+
+// Tests the triangles of a leaf reference; an any-hit query that is
+// satisfied ends the ray.
+template <int LeafMode, int Mode>
+__device__ inline bool wide_test_leaf(const LeafData &ld, const Ray &r, uint32_t leaf,
+                                      WideState &ws, uint32_t &ntri) {
+    const uint32_t first = leaf >> 5, cnt = ((leaf >> 1) & 0xFu) + 1u;
+    if (test_leaf<LeafMode, Mode>(ld, r, first, cnt, ws.best, ntri)) {
+        ws.cur = kRefEmpty;
+        ws.leaf = kRefEmpty;
+        return true;
+    }
+    return false;
+}
+
+// One step of the single-loop order: visit ws.cur (interior node or leaf),
+// then take the next entry.  The best hit is updated as soon as a leaf is
+// tested, which culls the most.
+template <class Dec, int LeafMode, int Mode, class Stack>
+__device__ inline void wide_step_single(const void *nodes, int64_t n_nodes, const LeafData &ld,
+                                        const Ray &r, const typename Dec::Prep &prep, bool fast,
+                                        Stack &st, WideState &ws, uint32_t &nfetch,
+                                        uint32_t &ntri, bool &incomplete) {
+    if (ws.cur & 1u) {
+        wide_visit_interior<Dec, Mode>(nodes, n_nodes, r, prep, fast, st, ws, nfetch, incomplete);
+        return;
+    }
+    if (wide_test_leaf<LeafMode, Mode>(ld, r, ws.cur, ws, ntri)) return;
+    ws.cur = pop_unculled(st, best_bound<Mode>(r, ws.best), ws.cur_t);
+}
+
+// One round of the two-phase order (the while-while scheme of Aila and
+// Laine 2009, with speculative traversal), wave-wide, so that the lanes test
+// nodes together and triangles together instead of splitting every step
+// between the two:
+//   interior phase: lanes visit interior nodes; a lane that reaches a leaf
+//     parks it (one at a time) and keeps descending; the phase ends when
+//     every lane has a parked leaf or has no entry left;
+//   leaf phase: every lane with a parked leaf tests its triangles.
+// Every node that the current best does not cull is still visited, so the
+// result equals the single-loop order's.
+template <class Dec, int LeafMode, int Mode, class Stack>
+__device__ inline void wide_round_two_phase(const void *nodes, int64_t n_nodes,
+                                            const LeafData &ld, const Ray &r,
+                                            const typename Dec::Prep &prep, bool fast,
+                                            Stack &st, WideState &ws, uint32_t &nfetch,
+                                            uint32_t &ntri, bool &incomplete) {
+    for (;;) {
+        if (ws.cur != kRefEmpty && (ws.cur & 1u))
+            wide_visit_interior<Dec, Mode>(nodes, n_nodes, r, prep, fast, st, ws, nfetch,
+                                           incomplete);
+        if (ws.cur != kRefEmpty && !(ws.cur & 1u) && ws.leaf == kRefEmpty) {
+            ws.leaf = ws.cur;
+            ws.cur = pop_unculled(st, best_bound<Mode>(r, ws.best), ws.cur_t);
+        }
+        if (__builtin_amdgcn_ballot_w64(ws.leaf == kRefEmpty && ws.cur != kRefEmpty) == 0) break;
+    }
+    if (ws.leaf != kRefEmpty) {
+        const uint32_t leaf = ws.leaf;
+        ws.leaf = kRefEmpty;
+        if (wide_test_leaf<LeafMode, Mode>(ld, r, leaf, ws, ntri)) return;
+        // the entry taken before the leaf test may be culled by the new best
+        const float tb = best_bound<Mode>(r, ws.best);
+        if (ws.cur != kRefEmpty && !(ws.cur_t <= tb * kFarScale))
+            ws.cur = pop_unculled(st, tb, ws.cur_t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tracer policies: the per-layout state and steps behind one interface, so
+// the kernels (one ray per lane, persistent, fallback, batched) are written
+// once for all layouts.
+//   kWithT              stack entries carry entry distances (pop-time cull)
+//   Prep prep(ray)      per-ray layout constants
+//   State start(nodes)  initial state;  done(state);  best(state)
+//   step<LeafMode, Mode>(...)   one node or leaf of the single-loop order
+//   round<LeafMode, Mode>(...)  one round of the two-phase order (wave-wide)
+// ---------------------------------------------------------------------------
+template <class Dec>
+struct WideTracer {
+    static constexpr bool kWithT = true;
+    using State = WideState;
+    using Prep = typename Dec::Prep;
+    __device__ static Prep prep(const Ray &r) { return Dec::prep(r); }
+    __device__ static State start(int64_t n_nodes) { return wide_start(n_nodes); }
+    __device__ static bool done(const State &s) { return s.cur == kRefEmpty; }
+    template <int LeafMode, int Mode, class Stack>
+    __device__ static void step(const void *nodes, int64_t n_nodes, const LeafData &ld,
+                                const Ray &r, const Prep &prep, bool fast, Stack &st, State &s,
+                                uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
+        wide_step_single<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s, nfetch,
+                                              ntri, incomplete);
+    }
+    template <int LeafMode, int Mode, class Stack>
+    __device__ static void round(const void *nodes, int64_t n_nodes, const LeafData &ld,
+                                 const Ray &r, const Prep &prep, bool fast, Stack &st, State &s,
+                                 uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
+        wide_round_two_phase<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s,
+                                                  nfetch, ntri, incomplete);
+    }
+};
+
+struct BinTracer {
+    static constexpr bool kWithT = false;
+    using State = BinState;
+    struct Prep {};
+    __device__ static Prep prep(const Ray &) { return Prep{}; }
+    __device__ static State start(int64_t n_nodes) { return bin_start(n_nodes); }
+    __device__ static bool done(const State &s) {
+        return s.node == kRefEmpty && s.leaf == kRefEmpty && s.hold == kRefEmpty;
+    }
+    // single-loop order: visit a node and test a leaf as soon as it is met
+    template <int LeafMode, int Mode, class Stack>
+    __device__ static void step(const void *nodes, int64_t n_nodes, const LeafData &ld,
+                                const Ray &r, const Prep &, bool fast, Stack &st, State &s,
+                                uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
+        const uint32_t leaf = bin_visit<Mode>(static_cast<const bvh_node_aabb2 *>(nodes), n_nodes,
+                                              r, fast, st, s, nfetch, incomplete);
+        if (leaf != kRefEmpty) bin_test_leaf<LeafMode, Mode>(ld, r, leaf, s, ntri);
+    }
+    // two-phase order: lanes visit nodes and park the leaves they meet (one,
+    // plus one held while the first is parked, after which the lane waits);
+    // the phase ends when every lane has a parked leaf or no node left; then
+    // the parked leaves are tested together.
+    template <int LeafMode, int Mode, class Stack>
+    __device__ static void round(const void *nodes, int64_t n_nodes, const LeafData &ld,
+                                 const Ray &r, const Prep &, bool fast, Stack &st, State &s,
+                                 uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
+        for (;;) {
+            if (s.node != kRefEmpty && s.hold == kRefEmpty) {
+                const uint32_t leaf = bin_visit<Mode>(static_cast<const bvh_node_aabb2 *>(nodes),
+                                                      n_nodes, r, fast, st, s, nfetch, incomplete);
+                if (leaf != kRefEmpty) {
+                    if (s.leaf == kRefEmpty) s.leaf = leaf;
+                    else s.hold = leaf;
+                }
+            }
+            if (__builtin_amdgcn_ballot_w64(s.leaf == kRefEmpty && s.node != kRefEmpty) == 0) break;
+        }
+        if (s.leaf != kRefEmpty) {
+            const uint32_t leaf = s.leaf;
+            s.leaf = s.hold;
+            s.hold = kRefEmpty;
+            bin_test_leaf<LeafMode, Mode>(ld, r, leaf, s, ntri);
+        }
+    }
+};
+
+template <int Layout>
+struct TracerFor;
+template <>
+struct TracerFor<BVH_LAYOUT_AABB2> {
+    using type = BinTracer;
+};
+template <>
+struct TracerFor<BVH_LAYOUT_BVH4> {
+    using type = WideTracer<DecodeBVH4>;
+};
+template <>
+struct TracerFor<BVH_LAYOUT_BVH8_Q8> {
+    using type = WideTracer<DecodeBVH8Q8>;
+};
+template <>
+struct TracerFor<BVH_LAYOUT_BVH8_Q16> {
+    using type = WideTracer<DecodeBVH8Q16>;
+};
+
+// Whole-ray traversal: waves of coherent rays use the two-phase order (their
+// lanes reach nodes and leaves in step, so batching the phases pays); other
+// waves use the single-loop order, which updates the best hit earliest.
+template <int Layout, int LeafMode, int Mode, class Stack>
+__device__ inline Best trace_ray(const void *nodes, int64_t n_nodes, const LeafData &ld,
+                                 const Ray &r, Stack &st, uint32_t &nfetch, uint32_t &ntri,
+                                 bool &incomplete) {
+    using Tr = typename TracerFor<Layout>::type;
+    const typename Tr::Prep prep = Tr::prep(r);
+    const bool fast = wave_fast(r);
+    typename Tr::State s = Tr::start(n_nodes);
+    if (wave_coherent(r)) {
+        while (!Tr::done(s))
+            Tr::template round<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s, nfetch,
+                                               ntri, incomplete);
+    } else {
+        while (!Tr::done(s))
+            Tr::template step<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s, nfetch,
+                                              ntri, incomplete);
+    }
+    return s.best;
 }
 
 // Work area of the fallback pass: a counter and list of rays that
@@ -438,10 +904,14 @@ constexpr int kFallbackBlocks = 128;
 constexpr int kFallbackLanes = kFallbackBlocks * kTraceBlock;
 struct Fallback {
     uint32_t *count;     // rays appended by the fast pass
+    unsigned long long *queue;  // next unclaimed ray of a persistent launch
     uint32_t *list;      // ray indices (capacity: rays of the launch)
     uint32_t *stack_ref; // [kFallbackLanes][kStackMax]
     float *stack_t;      // [kFallbackLanes][kStackMax]
 };
+
+// Bytes of the header (counter and queue) that must be zero before a launch.
+constexpr size_t kFallbackHeaderBytes = 16;
 
 inline size_t fallback_bytes(uint64_t n_rays) {
     return 256 + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 8;
@@ -452,6 +922,7 @@ inline Fallback fallback_view(void *base, uint64_t n_rays) {
     char *p = static_cast<char *>(base);
     Fallback f;
     f.count = reinterpret_cast<uint32_t *>(p);
+    f.queue = reinterpret_cast<unsigned long long *>(p + 8);
     f.list = reinterpret_cast<uint32_t *>(p + 256);
     f.stack_ref = reinterpret_cast<uint32_t *>(p + 256 + n_rays * 4);
     f.stack_t = reinterpret_cast<float *>(p + 256 + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 4);

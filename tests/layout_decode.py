@@ -23,7 +23,7 @@ Q16_DT = np.dtype([("origin", "<f4", 3), ("scale", "<f4", 3),
                    ("qlo_x", "<u2", 8), ("qlo_y", "<u2", 8), ("qlo_z", "<u2", 8),
                    ("qhi_x", "<u2", 8), ("qhi_y", "<u2", 8), ("qhi_z", "<u2", 8),
                    ("child", "<u4", 8), ("nchild", "<u4"), ("pad", "<u4")])
-TRI_DT = np.dtype([("p0", "<f4", 3), ("p1", "<f4", 3), ("p2", "<f4", 3), ("prim", "<i4"),
+TRI_DT = np.dtype([("p0", "<f4", 3), ("e1", "<f4", 3), ("e2", "<f4", 3), ("prim", "<i4"),
                    ("pad", "<i4", 2)])
 assert AABB2_DT.itemsize == 32 and BVH4_DT.itemsize == 128
 assert Q8_DT.itemsize == 128 and Q16_DT.itemsize == 160 and TRI_DT.itemsize == 48

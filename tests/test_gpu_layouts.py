@@ -58,9 +58,11 @@ def test_round_trip(layout, leaf_mode, scene):
     if leaf_mode == "compact":
         tri = np.frombuffer(leaf_raw, dtype=LD.TRI_DT)
         order = tri["prim"]
-        pts = np.stack([tri["p0"], tri["p1"], tri["p2"]], axis=1)
-        # bit copies of the input triangles
-        assert np.array_equal(pts.view(np.uint32), v[t[order]].view(np.uint32))
+        pts = v[t[order]]
+        # p0 is a bit copy; the edges are the f32 differences p0 - p1, p2 - p0
+        assert np.array_equal(tri["p0"].view(np.uint32), pts[:, 0].view(np.uint32))
+        assert np.array_equal(tri["e1"].view(np.uint32), (pts[:, 0] - pts[:, 1]).view(np.uint32))
+        assert np.array_equal(tri["e2"].view(np.uint32), (pts[:, 2] - pts[:, 0]).view(np.uint32))
     else:
         order = np.frombuffer(leaf_raw, dtype=np.int32)
         pts = v[t[order]]
@@ -93,7 +95,7 @@ def test_quantised_boxes_are_tight(layout):
     h = _build(v, t, layout)
     nodes, leaves, _ = LD.walk(lid, h.read_buffer(bvh.BUF_NODES))
     order = np.frombuffer(h.read_buffer(bvh.BUF_LEAF), dtype=LD.TRI_DT)
-    pts = np.stack([order["p0"], order["p1"], order["p2"]], axis=1)
+    pts = v[t[order["prim"]]]
     qmax = 255 if lid == LD.BVH8_Q8 else 65535
     # exact child boxes of leaf children: compare with the q one step tighter
     checked = 0
