@@ -47,7 +47,8 @@ extern "C" {
 #define BVH_LAYOUT_BVH4 1     /* 4-wide, f32 child boxes in SoA, 128 B */
 #define BVH_LAYOUT_BVH8_Q8 2  /* 8-wide, u8 child boxes in the parent frame, 128 B */
 #define BVH_LAYOUT_BVH8_Q16 3 /* 8-wide, u16 child boxes in the parent frame, 160 B */
-#define BVH_NUM_LAYOUTS 4
+#define BVH_LAYOUT_PBRT_Q16 4 /* binary, own u16 box in the scene frame, 16 B */
+#define BVH_NUM_LAYOUTS 5
 
 /* Leaf storage. */
 #define BVH_LEAF_COMPACT 0 /* triangles copied into leaf order (bvh_tri records) */
@@ -81,7 +82,7 @@ typedef struct bvh_hit {
 
 /* Build options; a zero field selects the default. */
 typedef struct bvh_build_opts {
-    int32_t leaf_size;   /* max triangles per leaf, 1..16 (default 4) */
+    int32_t leaf_size;   /* max triangles per leaf, 1..16 (1..15 for PBRT_Q16; default 4) */
     int32_t leaf_mode;   /* BVH_LEAF_COMPACT (default) or BVH_LEAF_INDEXED */
     int32_t stack_lds;   /* traversal stack entries kept in LDS per ray: 8, 16 or 32 (default:
                             32 for AABB2, 16 for the wide layouts).  A ray that needs more is
@@ -104,6 +105,9 @@ typedef struct bvh_stats {
     float scene_lo[3], scene_hi[3];
     int32_t stack_lds;         /* LDS stack entries per ray of the trace kernels */
     int32_t pad;
+    /* PBRT_Q16: the scene frame of the quantised boxes (a plane value is
+     * fmaf((float)q, frame_scale[a], frame_origin[a])); zero otherwise. */
+    float frame_origin[3], frame_scale[3];
 } bvh_stats;
 
 /* Compacted leaf triangle (BVH_LEAF_COMPACT), 48 B, in leaf order: the
@@ -180,6 +184,24 @@ typedef struct bvh_node_bvh8_q16 {
     uint32_t pad;
 } bvh_node_bvh8_q16; /* 160 B */
 
+/*
+ * BVH_LAYOUT_PBRT_Q16 (the pbrt-q16 layout of Sec. 9.2.5 and App. D.3): the
+ * AABB2 tree in the same preorder, each node 16 B.  Its box is quantised to
+ * u16 in one frame for the whole scene (the root box split into 65535 steps
+ * per axis; bvh_stats.frame_*), conservatively as for the quantised wide
+ * layouts.  meta bits 0..3 = number of triangles (0 for an interior node),
+ * bits 4..31 = right-child offset (interior: right child = I + offset) or
+ * first leaf-order triangle (leaf).  The lowest bits of an interior node's
+ * lo[0] and lo[1] carry its split axis (axis = (lo[0] & 1) | (lo[1] & 1) << 1,
+ * 3 = unknown): the quantised lower plane is lowered by one step where needed
+ * to hold the bit, which keeps the box conservative; the traversal uses the
+ * axis only to pick the near child first.
+ */
+typedef struct bvh_node_pbrt_q16 {
+    uint16_t lo[3], hi[3];
+    uint32_t meta;
+} bvh_node_pbrt_q16; /* 16 B */
+
 typedef struct bvh_handle_s *bvh_handle_t;
 
 /* ---- calls -------------------------------------------------------------- */
@@ -203,7 +225,8 @@ int32_t bvh_version(void);
  *   opts    host, may be NULL for defaults
  *   out     host; receives the handle on success, NULL on failure
  * Errors: EINVAL for null pointers with a nonzero count, negative counts,
- * an unknown layout or leaf mode, leaf_size outside 1..16, nonzero reserved
+ * an unknown layout or leaf mode, leaf_size outside 1..16 (1..15 for
+ * PBRT_Q16), nonzero reserved
  * fields, or (detected on the device, reported before returning) a vertex
  * index outside [0, n_verts); EUNSUPPORTED for n_tris >= 2^27, a tree whose
  * traversal stack would exceed the kernel's limit, or a wide layout whose
@@ -278,7 +301,7 @@ int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const int32_t *t
 /*
  * Many scenes with uneven triangle and ray counts traced by one graph launch.
  * The paper leaves execution scheduling to future work (Sec. 1) and shows that
- * the best layout depends on scene and ray distribution (Sec. 6.2.1); here
+ * the best layout depends on scene and ray distribution (Sec. 9.2.2); here
  * each scene's layout (and with it the tree arity) and LDS stack depth are
  * chosen by timing candidates on probe rays, and all scenes' rays are drained
  * from per-variant work queues by persistent kernels captured in one hipGraph.
@@ -295,7 +318,8 @@ typedef struct bvh_scene_desc {
 
 typedef struct bvh_tune_opts {
     int32_t probe_rays;           /* probe rays per scene and candidate (0: 16384) */
-    int32_t leaf_size;            /* 1..16 (0: 4); leaves are compacted */
+    int32_t leaf_size;            /* 1..16 (0: 4); leaves are compacted; PBRT_Q16 is a
+                                     tuning candidate only for leaf_size <= 15 */
     const bvh_ray *probe;         /* device, optional probe rays of all scenes, concatenated */
     const int64_t *probe_offsets; /* host, n_scenes + 1 offsets into probe; required with it */
     int32_t reserved[4];          /* must be zero */

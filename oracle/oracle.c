@@ -16,8 +16,8 @@
  *                       ties broken by lowest primitive id.
  *   - orc_bvh_*         a median-split BVH (top-down, largest-extent axis,
  *                       leaves of at most 4 triangles, the construction
- *                       pattern of Sec. 6.3 "Collision Detection") with a
- *                       scalar 64-entry stack traversal (Sec. 6.1) in three
+ *                       pattern of Sec. 9.3.3 "Collision Detection") with a
+ *                       scalar 64-entry stack traversal (Sec. 9.1) in three
  *                       modes: closest, top-2 (runner-up tracking for the
  *                       ambiguity mask) and any-hit.
  *   - orc_grad_f64      closed-form FP64 gradient of L = sum(w_t t + w_u u +

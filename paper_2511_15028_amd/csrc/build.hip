@@ -586,6 +586,71 @@ __global__ __launch_bounds__(kBlock) void k_emit_aabb2(TreeView tv, const uint32
 }
 
 // ---------------------------------------------------------------------------
+// a7 (pbrt-q16): the AABB2 nodes re-encoded with u16 boxes in one frame for
+// the whole scene (App. D.3).  The plane value of q is fmaf(q, s, o); each
+// box gets the tightest q that still encloses it (as quantize_axis does for
+// the wide layouts), and an interior node's split axis goes into the lowest
+// bits of its lower x and y planes, lowering a plane by one step where the
+// bit differs (which keeps the box enclosing).
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t q16_lower(float x, float o, float s) {
+    if (s == 0.0f) return 0u;
+    float f = floorf((x - o) / s);
+    f = fminf(fmaxf(f, 0.0f), 65535.0f);
+    uint32_t a = (uint32_t)f;
+    while (a > 0 && fmaf((float)a, s, o) > x) a--;
+    while (a < 65535u && fmaf((float)(a + 1), s, o) <= x) a++;
+    return a;
+}
+__device__ inline uint32_t q16_upper(float x, float o, float s) {
+    if (s == 0.0f) return 0u;
+    float f = ceilf((x - o) / s);
+    f = fminf(fmaxf(f, 0.0f), 65535.0f);
+    uint32_t b = (uint32_t)f;
+    while (b < 65535u && fmaf((float)b, s, o) < x) b++;
+    while (b > 0 && fmaf((float)(b - 1), s, o) >= x) b--;
+    return b;
+}
+
+struct WorldFrame {
+    float o[3], s[3];
+};
+
+__global__ __launch_bounds__(kBlock) void k_pack_pbrt_q16(const bvh_node_aabb2 *in, uint32_t n_nodes,
+                                                          WorldFrame fr, bvh_node_pbrt_q16 *out,
+                                                          BuildInfo *info) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_nodes) return;
+    const bvh_node_aabb2 nd = in[i];
+    uint32_t lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = q16_lower(nd.lo[a], fr.o[a], fr.s[a]);
+        hi[a] = q16_upper(nd.hi[a], fr.o[a], fr.s[a]);
+        // a plane outside the frame (never for a valid build) is reported
+        if (fr.s[a] != 0.0f && (fmaf((float)lo[a], fr.s[a], fr.o[a]) > nd.lo[a] ||
+                                fmaf((float)hi[a], fr.s[a], fr.o[a]) < nd.hi[a]))
+            atomicOr(&info->err, 4u);
+    }
+    const uint32_t cnt = nd.meta & 0xFFFFu;
+    uint32_t meta;
+    if (cnt > 0) {
+        meta = cnt | (nd.offset << 4);
+    } else {
+        const uint32_t axis = (nd.meta >> 16) & 3u;
+        for (int k = 0; k < 2; k++) {
+            const uint32_t bit = (axis >> k) & 1u;
+            if ((lo[k] & 1u) != bit && lo[k] > 0) lo[k]--;
+        }
+        meta = nd.offset << 4;
+    }
+    bvh_node_pbrt_q16 q;
+    q.lo[0] = (uint16_t)lo[0]; q.lo[1] = (uint16_t)lo[1]; q.lo[2] = (uint16_t)lo[2];
+    q.hi[0] = (uint16_t)hi[0]; q.hi[1] = (uint16_t)hi[1]; q.hi[2] = (uint16_t)hi[2];
+    q.meta = meta;
+    out[i] = q;
+}
+
+// ---------------------------------------------------------------------------
 // a7 (wide): top-down, one frontier level per step.  Each frontier item is an
 // alive interior binary node that becomes a wide node: its child list starts
 // as its two children and repeatedly replaces the interior candidate of
@@ -938,6 +1003,25 @@ T *pinned_scratch() {
     return static_cast<T *>(buf);
 }
 
+// Scene frame of the pbrt-q16 layout: origin = scene box corner, scale = the
+// smallest step with fmaf(65535, s, o) >= scene hi (std::fmaf rounds like the
+// device's fmaf).  Non-finite extents give scale 0 (reported elsewhere).
+WorldFrame world_frame(const float *lo, const float *hi) {
+    WorldFrame fr;
+    for (int a = 0; a < 3; a++) {
+        fr.o[a] = lo[a];
+        const float ext = hi[a] - lo[a];
+        float sc = 0.0f;
+        if (ext > 0.0f && std::isfinite(ext)) {
+            sc = ext / 65535.0f;
+            for (int g = 0; g < 64 && std::fmaf(65535.0f, sc, lo[a]) < hi[a]; g++)
+                sc = std::nextafter(sc, INFINITY);
+        }
+        fr.s[a] = sc;
+    }
+    return fr;
+}
+
 int32_t check_launch(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(BVH_EHIP, "%s: launch failed: %s", what, hipGetErrorString(e));
@@ -1112,6 +1196,23 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(
             tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
         BVH_TRY(check_launch("aabb2 packing"));
+    } else if (h->layout == BVH_LAYOUT_PBRT_Q16) {
+        h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
+        WorldFrame fr = world_frame(hi.slo, hi.shi);
+        for (int a = 0; a < 3; a++) {
+            h->frame_origin[a] = fr.o[a];
+            h->frame_scale[a] = fr.s[a];
+        }
+        Arena ar;
+        bvh_node_aabb2 *tmp = nullptr;
+        ar.request(&tmp, (size_t)h->n_nodes);
+        BVH_TRY(ar.bind(s, kAreaBuildWide));
+        BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)h->n_nodes * sizeof(bvh_node_pbrt_q16)));
+        k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
+                                                                      (uint32_t)h->n_nodes, info);
+        k_pack_pbrt_q16<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
+            tmp, (uint32_t)h->n_nodes, fr, static_cast<bvh_node_pbrt_q16 *>(h->nodes), info);
+        BVH_TRY(check_launch("pbrt-q16 packing"));
     } else if (h->layout == BVH_LAYOUT_BVH4) {
         BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, h, s));
     } else if (h->layout == BVH_LAYOUT_BVH8_Q8) {
@@ -1202,7 +1303,7 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
     // LDS stack default: binary trees push one entry per level (32 entries of
     // 4 B); wide trees push up to arity-1 entries of 8 B (16 entries)
     int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT;
-    int32_t stack_lds = layout == BVH_LAYOUT_AABB2 ? 32 : 16;
+    int32_t stack_lds = (layout == BVH_LAYOUT_AABB2 || layout == BVH_LAYOUT_PBRT_Q16) ? 32 : 16;
     if (opts) {
         for (int k = 0; k < 5; k++)
             if (opts->reserved[k] != 0) return set_error(BVH_EINVAL, "bvh_build: reserved option set");
@@ -1210,8 +1311,9 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
         if (opts->leaf_mode != 0) leaf_mode = opts->leaf_mode;
         if (opts->stack_lds != 0) stack_lds = opts->stack_lds;
     }
-    if (leaf_size < 1 || leaf_size > kMaxLeafSize)
-        return set_error(BVH_EINVAL, "bvh_build: leaf_size %d outside 1..%d", leaf_size, kMaxLeafSize);
+    const int32_t max_leaf = layout == BVH_LAYOUT_PBRT_Q16 ? 15 : kMaxLeafSize;  // u4 count
+    if (leaf_size < 1 || leaf_size > max_leaf)
+        return set_error(BVH_EINVAL, "bvh_build: leaf_size %d outside 1..%d", leaf_size, max_leaf);
     if (leaf_mode != BVH_LEAF_COMPACT && leaf_mode != BVH_LEAF_INDEXED)
         return set_error(BVH_EINVAL, "bvh_build: unknown leaf mode %d", leaf_mode);
     if (stack_lds != 8 && stack_lds != 16 && stack_lds != 32)

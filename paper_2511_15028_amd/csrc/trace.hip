@@ -14,7 +14,7 @@ namespace {
 // overflow is appended to the fallback list instead of writing a hit.
 template <int Layout, int LeafMode, int Mode, bool Count, int SL>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(const void *nodes, int64_t n_nodes,
-                                                       LeafData ld, const bvh_ray *rays,
+                                                       SceneData ld, const bvh_ray *rays,
                                                        uint64_t n, bvh_hit *hits,
                                                        uint32_t *counts, Fallback fb) {
     using Tr = typename TracerFor<Layout>::type;
@@ -54,7 +54,7 @@ constexpr uint32_t kClaim = 64;        // rays claimed from the queue per atomic
 
 template <int Layout, int LeafMode, int Mode, bool Count, int SL>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes, int64_t n_nodes,
-                                                               LeafData ld, const bvh_ray *rays,
+                                                               SceneData ld, const bvh_ray *rays,
                                                                uint64_t n, bvh_hit *hits,
                                                                uint32_t *counts, Fallback fb,
                                                                SpillArea sa) {
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
 // exits at once when the list is empty.
 template <int Layout, int LeafMode, int Mode, bool Count>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_fallback(const void *nodes, int64_t n_nodes,
-                                                                LeafData ld, const bvh_ray *rays,
+                                                                SceneData ld, const bvh_ray *rays,
                                                                 bvh_hit *hits, uint32_t *counts,
                                                                 Fallback fb) {
     using Tr = typename TracerFor<Layout>::type;
@@ -228,7 +228,7 @@ int32_t trace_area(hipStream_t s, uint64_t n, uint32_t lanes, TraceArea &ta) {
 constexpr bool kPersistent = true;
 
 template <int Layout, int LeafMode, int Mode, bool Count, int SL>
-int32_t launch_layout(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *rays, uint64_t n,
+int32_t launch_layout(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *rays, uint64_t n,
                       bvh_hit *hits, uint32_t *counts, hipStream_t s) {
     const uint64_t need = (n + kTraceBlock - 1) / kTraceBlock;
     TraceArea ta;
@@ -251,7 +251,7 @@ int32_t launch_layout(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *
 }
 
 template <int LeafMode, int Mode, bool Count, int SL>
-int32_t launch_sl(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *rays, uint64_t n,
+int32_t launch_sl(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *rays, uint64_t n,
                   bvh_hit *hits, uint32_t *counts, hipStream_t s) {
     switch (h->layout) {
         case BVH_LAYOUT_AABB2:
@@ -263,6 +263,9 @@ int32_t launch_sl(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *rays
         case BVH_LAYOUT_BVH8_Q8:
             return launch_layout<BVH_LAYOUT_BVH8_Q8, LeafMode, Mode, Count, SL>(h, ld, rays, n,
                                                                                hits, counts, s);
+        case BVH_LAYOUT_PBRT_Q16:
+            return launch_layout<BVH_LAYOUT_PBRT_Q16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
+                                                                                hits, counts, s);
         default:
             return launch_layout<BVH_LAYOUT_BVH8_Q16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
                                                                                 hits, counts, s);
@@ -272,7 +275,9 @@ int32_t launch_sl(const bvh_handle_s *h, const LeafData &ld, const bvh_ray *rays
 template <int LeafMode, int Mode, bool Count>
 int32_t launch_mode(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits,
                     uint32_t *counts, hipStream_t s) {
-    const LeafData ld{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris, h->coord_max()};
+    const SceneData ld{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris, h->coord_max(),
+                       {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
+                       {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]}};
     int32_t rc;
     if (h->stack_lds == 8)
         rc = launch_sl<LeafMode, Mode, Count, 8>(h, ld, rays, n, hits, counts, s);

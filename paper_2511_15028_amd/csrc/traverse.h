@@ -189,15 +189,16 @@ __device__ inline void consider(Best &b, float t, float u, float v, uint32_t id)
     }
 }
 
-// Leaf storage: COMPACT reads 48-B records {p0, e1, e2, prim id} in leaf
-// order; INDEXED reads a primitive id, its three vertex indices and three
-// vertices.
-struct LeafData {
+// Per-scene data the kernels need besides the node buffer.  Leaf storage:
+// COMPACT reads 48-B records {p0, e1, e2, prim id} in leaf order; INDEXED
+// reads a primitive id, its three vertex indices and three vertices.
+struct SceneData {
     const void *leaf;
     const float *verts;
     const int32_t *tris;
     uint32_t n_tris;
     float coord_max;  // largest coordinate magnitude of the scene (selects the slab form)
+    float fo[3], fs[3];  // PBRT_Q16: plane value = fmaf(q, fs[a], fo[a])
 };
 
 // Compacted leaves: triangles are fetched in batches of kLeafBatch (all loads
@@ -207,7 +208,7 @@ constexpr uint32_t kLeafBatch = 4;
 // Tests triangles [first, first+n) of the leaf order.  Returns true when an
 // any-hit query is satisfied.
 template <int LeafMode, int Mode>
-__device__ inline bool test_leaf(const LeafData &ld, const Ray &r, uint32_t first, uint32_t n,
+__device__ inline bool test_leaf(const SceneData &ld, const Ray &r, uint32_t first, uint32_t n,
                                  Best &best, uint32_t &ntri) {
     const uint32_t end = min(first + n, ld.n_tris);  // bounds guard; a valid tree never clips
     if (LeafMode == BVH_LEAF_COMPACT) {
@@ -410,31 +411,64 @@ __device__ inline uint32_t bin_pop(Stack &st) {
     return st.sp > 0 ? st.pop(unused) : kRefEmpty;
 }
 
+// Binary node formats: load node i as its box, triangle count (0 for an
+// interior node), offset (right-child delta or first triangle) and split
+// axis (3 when unknown).
+struct BinAABB2 {
+    __device__ static void load(const void *nodes, uint32_t i, const SceneData &, float *lo,
+                                float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
+        const float4 *np = reinterpret_cast<const float4 *>(static_cast<const bvh_node_aabb2 *>(nodes) + i);
+        const float4 a = np[0], b = np[1];
+        lo[0] = a.x; lo[1] = a.y; lo[2] = a.z;
+        hi[0] = a.w; hi[1] = b.x; hi[2] = b.y;
+        off = __float_as_uint(b.z);
+        const uint32_t meta = __float_as_uint(b.w);
+        cnt = meta & 0xFFFFu;
+        axis = (meta >> 16) & 3u;
+    }
+};
+
+// pbrt-q16: one 16-B load; planes dequantised in the scene frame.
+struct BinPbrtQ16 {
+    __device__ static void load(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
+                                float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
+        const uint4 w = reinterpret_cast<const uint4 *>(nodes)[i];
+        const uint32_t q[6] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu,
+                               w.y >> 16,     w.z & 0xFFFFu, w.z >> 16};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmaf((float)q[a], sd.fs[a], sd.fo[a]);
+            hi[a] = fmaf((float)q[3 + a], sd.fs[a], sd.fo[a]);
+        }
+        cnt = w.w & 0xFu;
+        off = w.w >> 4;
+        axis = (q[0] & 1u) | ((q[1] & 1u) << 1);
+    }
+};
+
 // Visits bs.node; returns the leaf reference when the node is a leaf whose
 // box the ray meets (kRefEmpty otherwise).  bs.node moves on to the next node.
-template <int Mode, class Stack>
-__device__ inline uint32_t bin_visit(const bvh_node_aabb2 *nodes, int64_t n_nodes, const Ray &r,
-                                     bool fast, Stack &st, BinState &bs, uint32_t &nfetch,
-                                     bool &incomplete) {
+template <class Node, int Mode, class Stack>
+__device__ inline uint32_t bin_visit(const void *nodes, int64_t n_nodes, const SceneData &sd,
+                                     const Ray &r, bool fast, Stack &st, BinState &bs,
+                                     uint32_t &nfetch, bool &incomplete) {
     if (bs.node >= (uint64_t)n_nodes) {  // bounds guard; a valid tree never takes it
         bs.node = bs.leaf = bs.hold = kRefEmpty;
         return kRefEmpty;
     }
-    const float4 *np = reinterpret_cast<const float4 *>(nodes + bs.node);
-    const float4 a = np[0], b = np[1];
+    float lo[3], hi[3];
+    uint32_t cnt, off, axis;
+    Node::load(nodes, bs.node, sd, lo, hi, cnt, off, axis);
     nfetch++;
     const float tcur = best_bound<Mode>(r, bs.best);
-    const float tn = fast ? slab<true>(r, a.x, a.y, a.z, a.w, b.x, b.y, tcur)
-                          : slab<false>(r, a.x, a.y, a.z, a.w, b.x, b.y, tcur);
+    const float tn = fast ? slab<true>(r, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], tcur)
+                          : slab<false>(r, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], tcur);
     if (tn != INFINITY) {
-        const uint32_t off = __float_as_uint(b.z), meta = __float_as_uint(b.w);
-        const uint32_t cnt = meta & 0xFFFFu;
         if (cnt > 0) {
             bs.node = bin_pop(st);
             return ref_leaf(off, cnt);
         }
-        const uint32_t axis = (meta >> 16) & 3u;
-        const bool neg = axis == 0 ? r.nx : (axis == 1 ? r.ny : r.nz);
+        const bool neg = axis == 0 ? r.nx : (axis == 1 ? r.ny : (axis == 2 ? r.nz : false));
         const uint32_t left = bs.node + 1, right = bs.node + off;
         if (!st.push(neg ? left : right, 0.0f)) {
             incomplete = true;
@@ -451,7 +485,7 @@ __device__ inline uint32_t bin_visit(const bvh_node_aabb2 *nodes, int64_t n_node
 // Tests the triangles of a leaf reference; a satisfied any-hit query ends
 // the ray.
 template <int LeafMode, int Mode>
-__device__ inline bool bin_test_leaf(const LeafData &ld, const Ray &r, uint32_t leaf,
+__device__ inline bool bin_test_leaf(const SceneData &ld, const Ray &r, uint32_t leaf,
                                      BinState &bs, uint32_t &ntri) {
     const uint32_t first = leaf >> 5, cnt = ((leaf >> 1) & 0xFu) + 1u;
     if (test_leaf<LeafMode, Mode>(ld, r, first, cnt, bs.best, ntri)) {
@@ -712,7 +746,7 @@ __device__ inline void wide_visit_interior(const void *nodes, int64_t n_nodes, c
 // Tests the triangles of a leaf reference; an any-hit query that is
 // satisfied ends the ray.
 template <int LeafMode, int Mode>
-__device__ inline bool wide_test_leaf(const LeafData &ld, const Ray &r, uint32_t leaf,
+__device__ inline bool wide_test_leaf(const SceneData &ld, const Ray &r, uint32_t leaf,
                                       WideState &ws, uint32_t &ntri) {
     const uint32_t first = leaf >> 5, cnt = ((leaf >> 1) & 0xFu) + 1u;
     if (test_leaf<LeafMode, Mode>(ld, r, first, cnt, ws.best, ntri)) {
@@ -727,7 +761,7 @@ __device__ inline bool wide_test_leaf(const LeafData &ld, const Ray &r, uint32_t
 // then take the next entry.  The best hit is updated as soon as a leaf is
 // tested, which culls the most.
 template <class Dec, int LeafMode, int Mode, class Stack>
-__device__ inline void wide_step_single(const void *nodes, int64_t n_nodes, const LeafData &ld,
+__device__ inline void wide_step_single(const void *nodes, int64_t n_nodes, const SceneData &ld,
                                         const Ray &r, const typename Dec::Prep &prep, bool fast,
                                         Stack &st, WideState &ws, uint32_t &nfetch,
                                         uint32_t &ntri, bool &incomplete) {
@@ -751,7 +785,7 @@ __device__ inline void wide_step_single(const void *nodes, int64_t n_nodes, cons
 // result equals the single-loop order's.
 template <class Dec, int LeafMode, int Mode, class Stack>
 __device__ inline void wide_round_two_phase(const void *nodes, int64_t n_nodes,
-                                            const LeafData &ld, const Ray &r,
+                                            const SceneData &ld, const Ray &r,
                                             const typename Dec::Prep &prep, bool fast,
                                             Stack &st, WideState &ws, uint32_t &nfetch,
                                             uint32_t &ntri, bool &incomplete) {
@@ -795,14 +829,14 @@ struct WideTracer {
     __device__ static State start(int64_t n_nodes) { return wide_start(n_nodes); }
     __device__ static bool done(const State &s) { return s.cur == kRefEmpty; }
     template <int LeafMode, int Mode, class Stack>
-    __device__ static void step(const void *nodes, int64_t n_nodes, const LeafData &ld,
+    __device__ static void step(const void *nodes, int64_t n_nodes, const SceneData &ld,
                                 const Ray &r, const Prep &prep, bool fast, Stack &st, State &s,
                                 uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
         wide_step_single<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s, nfetch,
                                               ntri, incomplete);
     }
     template <int LeafMode, int Mode, class Stack>
-    __device__ static void round(const void *nodes, int64_t n_nodes, const LeafData &ld,
+    __device__ static void round(const void *nodes, int64_t n_nodes, const SceneData &ld,
                                  const Ray &r, const Prep &prep, bool fast, Stack &st, State &s,
                                  uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
         wide_round_two_phase<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s,
@@ -810,6 +844,7 @@ struct WideTracer {
     }
 };
 
+template <class Node>
 struct BinTracer {
     static constexpr bool kWithT = false;
     using State = BinState;
@@ -821,11 +856,11 @@ struct BinTracer {
     }
     // single-loop order: visit a node and test a leaf as soon as it is met
     template <int LeafMode, int Mode, class Stack>
-    __device__ static void step(const void *nodes, int64_t n_nodes, const LeafData &ld,
+    __device__ static void step(const void *nodes, int64_t n_nodes, const SceneData &ld,
                                 const Ray &r, const Prep &, bool fast, Stack &st, State &s,
                                 uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
-        const uint32_t leaf = bin_visit<Mode>(static_cast<const bvh_node_aabb2 *>(nodes), n_nodes,
-                                              r, fast, st, s, nfetch, incomplete);
+        const uint32_t leaf =
+            bin_visit<Node, Mode>(nodes, n_nodes, ld, r, fast, st, s, nfetch, incomplete);
         if (leaf != kRefEmpty) bin_test_leaf<LeafMode, Mode>(ld, r, leaf, s, ntri);
     }
     // two-phase order: lanes visit nodes and park the leaves they meet (one,
@@ -833,13 +868,13 @@ struct BinTracer {
     // the phase ends when every lane has a parked leaf or no node left; then
     // the parked leaves are tested together.
     template <int LeafMode, int Mode, class Stack>
-    __device__ static void round(const void *nodes, int64_t n_nodes, const LeafData &ld,
+    __device__ static void round(const void *nodes, int64_t n_nodes, const SceneData &ld,
                                  const Ray &r, const Prep &, bool fast, Stack &st, State &s,
                                  uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
         for (;;) {
             if (s.node != kRefEmpty && s.hold == kRefEmpty) {
-                const uint32_t leaf = bin_visit<Mode>(static_cast<const bvh_node_aabb2 *>(nodes),
-                                                      n_nodes, r, fast, st, s, nfetch, incomplete);
+                const uint32_t leaf =
+                    bin_visit<Node, Mode>(nodes, n_nodes, ld, r, fast, st, s, nfetch, incomplete);
                 if (leaf != kRefEmpty) {
                     if (s.leaf == kRefEmpty) s.leaf = leaf;
                     else s.hold = leaf;
@@ -860,7 +895,11 @@ template <int Layout>
 struct TracerFor;
 template <>
 struct TracerFor<BVH_LAYOUT_AABB2> {
-    using type = BinTracer;
+    using type = BinTracer<BinAABB2>;
+};
+template <>
+struct TracerFor<BVH_LAYOUT_PBRT_Q16> {
+    using type = BinTracer<BinPbrtQ16>;
 };
 template <>
 struct TracerFor<BVH_LAYOUT_BVH4> {
@@ -879,7 +918,7 @@ struct TracerFor<BVH_LAYOUT_BVH8_Q16> {
 // lanes reach nodes and leaves in step, so batching the phases pays); other
 // waves use the single-loop order, which updates the best hit earliest.
 template <int Layout, int LeafMode, int Mode, class Stack>
-__device__ inline Best trace_ray(const void *nodes, int64_t n_nodes, const LeafData &ld,
+__device__ inline Best trace_ray(const void *nodes, int64_t n_nodes, const SceneData &ld,
                                  const Ray &r, Stack &st, uint32_t &nfetch, uint32_t &ntri,
                                  bool &incomplete) {
     using Tr = typename TracerFor<Layout>::type;

@@ -16,7 +16,7 @@ Conventions
 The paper's own scenes (scanned and architectural meshes of 36 K to 28 M
 triangles) are not available; these procedural scenes stand in for them at
 the same scale and with the same two ray classes, coherent camera rays and
-incoherent secondary rays (Sec. 6.2.1).
+incoherent secondary rays (Sec. 9.2.1).
 """
 from __future__ import annotations
 

@@ -3,13 +3,13 @@
 Written from the header's format description only (it shares nothing with
 the HIP sources), so that a packed BVH can be decoded on the CPU and
 compared with the geometry: the round trip of Sec. B (dec(enc(t)) = t),
-with quantised boxes required to contain the exact ones (Sec. 6.1 footnote).
+with quantised boxes required to contain the exact ones (Sec. 9.1 footnote).
 """
 from __future__ import annotations
 
 import numpy as np
 
-AABB2, BVH4, BVH8_Q8, BVH8_Q16 = 0, 1, 2, 3
+AABB2, BVH4, BVH8_Q8, BVH8_Q16, PBRT_Q16 = 0, 1, 2, 3, 4
 
 AABB2_DT = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("offset", "<u4"), ("meta", "<u4")])
 BVH4_DT = np.dtype([("lo_x", "<f4", 4), ("lo_y", "<f4", 4), ("lo_z", "<f4", 4),
@@ -23,12 +23,14 @@ Q16_DT = np.dtype([("origin", "<f4", 3), ("scale", "<f4", 3),
                    ("qlo_x", "<u2", 8), ("qlo_y", "<u2", 8), ("qlo_z", "<u2", 8),
                    ("qhi_x", "<u2", 8), ("qhi_y", "<u2", 8), ("qhi_z", "<u2", 8),
                    ("child", "<u4", 8), ("nchild", "<u4"), ("pad", "<u4")])
+PQ16_DT = np.dtype([("lo", "<u2", 3), ("hi", "<u2", 3), ("meta", "<u4")])
 TRI_DT = np.dtype([("p0", "<f4", 3), ("e1", "<f4", 3), ("e2", "<f4", 3), ("prim", "<i4"),
                    ("pad", "<i4", 2)])
 assert AABB2_DT.itemsize == 32 and BVH4_DT.itemsize == 128
 assert Q8_DT.itemsize == 128 and Q16_DT.itemsize == 160 and TRI_DT.itemsize == 48
+assert PQ16_DT.itemsize == 16
 
-DTYPES = {AABB2: AABB2_DT, BVH4: BVH4_DT, BVH8_Q8: Q8_DT, BVH8_Q16: Q16_DT}
+DTYPES = {AABB2: AABB2_DT, BVH4: BVH4_DT, BVH8_Q8: Q8_DT, BVH8_Q16: Q16_DT, PBRT_Q16: PQ16_DT}
 
 
 def fma32(q, s, o):
@@ -92,14 +94,40 @@ def child_boxes(layout, rec):
     return np.stack(cols, axis=1)
 
 
-def walk(layout, nodes_bytes):
+def pbrt_q16_box(rec, frame):
+    """Decoded box (lo xyz, hi xyz) of one pbrt-q16 node in the scene frame
+    (frame = (origin[3], scale[3]))."""
+    o, s = (np.asarray(x, np.float32) for x in frame)
+    lo = fma32(rec["lo"].astype(np.float64), s, o)
+    hi = fma32(rec["hi"].astype(np.float64), s, o)
+    return np.concatenate([lo, hi]).astype(np.float32)
+
+
+def walk(layout, nodes_bytes, frame=None):
     """Decodes a packed tree.  Returns a list of leaves (first, n, box or None,
-    path boxes) and the count of visited nodes; raises on malformed records."""
+    path boxes) and the count of visited nodes; raises on malformed records.
+    frame: the scene frame of PBRT_Q16 (origin[3], scale[3])."""
     dt = DTYPES[layout]
     nodes = np.frombuffer(nodes_bytes, dtype=dt)
     leaves = []
     visited = np.zeros(len(nodes), np.int64)
     if len(nodes) == 0:
+        return nodes, leaves, visited
+    if layout == PBRT_Q16:
+        stack = [(0, [])]
+        while stack:
+            i, path = stack.pop()
+            visited[i] += 1
+            rec = nodes[i]
+            box = pbrt_q16_box(rec, frame)
+            meta = int(rec["meta"])
+            nprim, off = meta & 0xF, meta >> 4
+            if nprim > 0:
+                leaves.append((off, nprim, path + [box]))
+            else:
+                assert off >= 2
+                stack.append((i + 1, path + [box]))
+                stack.append((i + off, path + [box]))
         return nodes, leaves, visited
     if layout == AABB2:
         stack = [(0, [])]

@@ -18,7 +18,8 @@ from paper_2511_15028_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = {"aabb2": LD.AABB2, "bvh4": LD.BVH4, "bvh8_q8": LD.BVH8_Q8, "bvh8_q16": LD.BVH8_Q16}
+LAYOUTS = {"aabb2": LD.AABB2, "bvh4": LD.BVH4, "bvh8_q8": LD.BVH8_Q8, "bvh8_q16": LD.BVH8_Q16,
+           "pbrt_q16": LD.PBRT_Q16}
 
 
 def _build(v, t, layout, leaf_mode="compact", leaf_size=4):
@@ -51,7 +52,7 @@ def test_round_trip(layout, leaf_mode, scene):
     lid = LAYOUTS[layout]
     nodes_bytes = h.read_buffer(bvh.BUF_NODES)
     assert len(nodes_bytes) == st["n_nodes"] * st["node_bytes"]
-    nodes, leaves, visited = LD.walk(lid, nodes_bytes)
+    nodes, leaves, visited = LD.walk(lid, nodes_bytes, (st["frame_origin"], st["frame_scale"]))
     assert (visited == 1).all(), "every node reachable exactly once"
     assert len(leaves) == st["n_leaves"]
     leaf_raw = h.read_buffer(bvh.BUF_LEAF)
@@ -80,7 +81,7 @@ def test_round_trip(layout, leaf_mode, scene):
             assert np.array_equal(path[-1][0:3], lo) and np.array_equal(path[-1][3:6], hi)
     assert (covered == 1).all()
     assert st["max_stack"] >= 1 and st["depth"] >= 2
-    assert st["nodes_buffer_bytes"] == st["n_nodes"] * {0: 32, 1: 128, 2: 128, 3: 160}[lid]
+    assert st["nodes_buffer_bytes"] == st["n_nodes"] * {0: 32, 1: 128, 2: 128, 3: 160, 4: 16}[lid]
 
 
 @pytest.mark.parametrize("layout", list(LAYOUTS))
@@ -89,7 +90,7 @@ def test_quantised_boxes_are_tight(layout):
     step inward would cut into the child (checked on the decoded nodes)."""
     lid = LAYOUTS[layout]
     if lid not in (LD.BVH8_Q8, LD.BVH8_Q16):
-        pytest.skip("f32 layout")
+        pytest.skip("f32 layout, or the scene-frame layout (its own test)")
     from paper_2511_15028_amd import bvh
     v, t = SCENES["spheres"]
     h = _build(v, t, layout)
@@ -127,3 +128,52 @@ def test_build_is_deterministic(layout):
     a = _build(v, t, layout).read_buffer(bvh.BUF_NODES)
     b = _build(v, t, layout).read_buffer(bvh.BUF_NODES)
     assert a == b
+
+
+@pytest.mark.parametrize("scene", list(SCENES))
+def test_pbrt_q16_matches_aabb2(scene):
+    """pbrt-q16 is the AABB2 tree re-encoded (App. D.3): node i has the same
+    triangle count and offset, its dequantised box encloses the exact AABB2
+    box with the tightest q (an interior node's lower x / y plane may sit one
+    step lower to carry the split axis), and the axis bits decode to the
+    AABB2 split axis wherever that lowering was possible."""
+    from paper_2511_15028_amd import bvh
+    v, t = SCENES[scene]
+    ha = _build(v, t, "aabb2")
+    hq = _build(v, t, "pbrt_q16")
+    a = np.frombuffer(ha.read_buffer(bvh.BUF_NODES), dtype=LD.AABB2_DT)
+    q = np.frombuffer(hq.read_buffer(bvh.BUF_NODES), dtype=LD.PQ16_DT)
+    assert len(a) == len(q)
+    st = hq.stats()
+    o = np.asarray(st["frame_origin"], np.float32)
+    s = np.asarray(st["frame_scale"], np.float32)
+    assert np.array_equal(o, np.asarray(st["scene_lo"], np.float32))
+    # the frame covers the scene: 65535 steps reach the upper corner
+    hi_scene = np.asarray(st["scene_hi"], np.float32)
+    assert (LD.fma32(65535.0, s, o) >= hi_scene).all()
+    cnt_a = a["meta"] & 0xFFFF
+    cnt_q = q["meta"] & 0xF
+    assert np.array_equal(cnt_a, cnt_q)
+    assert np.array_equal(a["offset"], q["meta"] >> 4)
+    lo_d = LD.fma32(q["lo"].astype(np.float64), s, o)
+    hi_d = LD.fma32(q["hi"].astype(np.float64), s, o)
+    assert (lo_d <= a["lo"]).all() and (hi_d >= a["hi"]).all()
+    # tightness: one step tighter would cut into the box
+    interior = cnt_a == 0
+    for ax in range(3):
+        if s[ax] == 0:
+            continue
+        up = LD.fma32(q["lo"][:, ax].astype(np.float64) + 1, s[ax], o[ax])
+        slack = (interior & (ax < 2)).astype(np.int64)  # axis-bit lowering
+        tight_lo = (up > a["lo"][:, ax]) | (q["lo"][:, ax] == 65535)
+        up2 = LD.fma32(q["lo"][:, ax].astype(np.float64) + 2, s[ax], o[ax])
+        tight_lo2 = (up2 > a["lo"][:, ax]) | (q["lo"][:, ax] >= 65534)
+        assert np.where(slack == 1, tight_lo2, tight_lo).all()
+        dn = LD.fma32(q["hi"][:, ax].astype(np.float64) - 1, s[ax], o[ax])
+        assert ((dn < a["hi"][:, ax]) | (q["hi"][:, ax] == 0)).all()
+    axis_a = (a["meta"] >> 16) & 3
+    axis_q = (q["lo"][:, 0] & 1) | ((q["lo"][:, 1] & 1) << 1)
+    ok = axis_q == axis_a
+    # the bit could not be set only where the lower plane was already at q = 0
+    assert (ok | ~interior | (q["lo"][:, 0] == 0) | (q["lo"][:, 1] == 0)).all()
+    assert ok[interior].mean() > 0.9
