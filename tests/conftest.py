@@ -15,5 +15,9 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def orc():
     import oracle
+    # the planted-mistake test runs the oracle pins against a modified copy
+    override = os.environ.get("ORACLE_TEST_LIB")
+    if override:
+        oracle.LIB_PATH = override
     oracle.lib()
     return oracle

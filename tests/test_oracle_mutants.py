@@ -1,0 +1,81 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each mutant is a copy of oracle/oracle.c with one planted mistake (a dropped
+term, a wrong sign, a transposed operand, a swapped index, an off-by-one, an
+interval end flipped); it is built into a temporary library and the oracle pin
+tests (test_oracle_mt, test_oracle_closest, test_oracle_grad) are run against
+it in a child process.  Every mutant must make at least one pin fail, and the
+unmodified source must pass the same harness.  CPU only; the shipped oracle is
+never touched.
+"""
+import concurrent.futures
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+PINS = [os.path.join(HERE, f) for f in ("test_oracle_mt.py", "test_oracle_closest.py",
+                                         "test_oracle_grad.py")]
+
+MUTANTS = [
+    ("edge e2 reversed", "v3 e2 = v3_sub(p2, p0);", "v3 e2 = v3_sub(p0, p2);"),
+    ("cross x operands transposed", "r.x = a.y * b.z - a.z * b.y;", "r.x = a.z * b.y - a.y * b.z;"),
+    ("dot drops the z term", "return (a.x * b.x + a.y * b.y) + a.z * b.z;",
+     "return (a.x * b.x + a.y * b.y);"),
+    ("u and v swapped", "float U = u2f(f2u(v3_dot(r, e2)) ^ sgnD);\n    float V = u2f(f2u(v3_dot(r, e1)) ^ sgnD);",
+     "float U = u2f(f2u(v3_dot(r, e1)) ^ sgnD);\n    float V = u2f(f2u(v3_dot(r, e2)) ^ sgnD);"),
+    ("edges exclusive", "U + V <= absD", "U + V < absD"),
+    ("t = 0 accepted", "absD * 0.0f < T", "absD * 0.0f <= T"),
+    ("tmax exclusive", "T <= absD * tmax", "T < absD * tmax"),
+    ("sign of T not folded", "float T = u2f(f2u(v3_dot(ng, c)) ^ sgnD);", "float T = v3_dot(ng, c);"),
+    ("t scaled from U", "*t_out = T * inv;", "*t_out = U * inv;"),
+    ("ties to the highest id", "return ta < tb || (ta == tb && ia < ib);",
+     "return ta < tb || (ta == tb && ia > ib);"),
+    ("slab entry plane from the wrong side", "float nearp = neg[a] ? n->hi[a] : n->lo[a];",
+     "float nearp = neg[a] ? n->lo[a] : n->hi[a];"),
+    ("right child never visited", "            stack[sp++] = n->right;\n", ""),
+    ("last triangle of a leaf skipped", "k < n->first + n->count; k++", "k < n->first + n->count - 1; k++"),
+    ("gradient: dL/dd sign", "gr[3] = -t * lam.x;", "gr[3] = t * lam.x;"),
+    ("gradient: vertex weights of p1, p2 swapped", "double w[3] = { 1.0 - u - v, u, v };",
+     "double w[3] = { 1.0 - u - v, v, u };"),
+    ("gradient: Cramer column transposed", "ab = d3_cross(a, b);", "ab = d3_cross(b, a);"),
+]
+
+
+def _build(tmp, tag, text):
+    c = os.path.join(tmp, f"{tag}.c")
+    so = os.path.join(tmp, f"{tag}.so")
+    with open(c, "w") as fh:
+        fh.write(text)
+    sys.path.insert(0, ROOT)
+    import oracle
+    cmd = ["gcc", *oracle.CFLAGS, c, "-o", so, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return so
+
+
+def _run_pins(so):
+    env = dict(os.environ, ORACLE_TEST_LIB=so, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "-m", "not gpu", *PINS], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    return r.returncode, r.stdout[-2000:]
+
+
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    src = open(SRC).read()
+    jobs = [("original", src)]
+    for i, (name, old, new) in enumerate(MUTANTS):
+        assert src.count(old) == 1, f"mutation site not unique or missing: {name}"
+        jobs.append((f"m{i:02d}", src.replace(old, new)))
+    libs = {tag: _build(str(tmp_path), tag, text) for tag, text in jobs}
+    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+        res = dict(zip(libs, ex.map(_run_pins, libs.values())))
+    rc, out = res["original"]
+    assert rc == 0, "the unmodified oracle must pass its pins:\n" + out
+    survivors = [name for i, (name, _, _) in enumerate(MUTANTS) if res[f"m{i:02d}"][0] == 0]
+    assert not survivors, f"mistakes no pin catches: {survivors}"
