@@ -277,7 +277,7 @@ def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
     fraction for every layout and leaf mode, camera (coherent) and bounce
     (incoherent) rays separately (median of 5 launches, events on the stream)."""
     res = {}
-    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16"):
+    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq"):
         for leaf_mode in ("compact", "indexed"):
             h = bvh.build(verts, tris, layout, args.leaf_size, leaf_mode)
             res[f"{layout}/{leaf_mode}"] = layout_row(
@@ -302,7 +302,7 @@ def spheres(torch, bvh, W, args):
     log(f"spheres workload: {w['tris'].shape[0]} tris ({time.time() - t0:.1f}s)")
     res = {"workload": f"{len(w['tris'])} tris (512 spheres + 100K slivers), {rays.shape[0]} "
                        "uniform closest-hit rays + as many shadow rays (any hit)"}
-    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16"):
+    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq"):
         h = bvh.build(verts, tris, layout, args.leaf_size, "compact")
         res[layout] = layout_row(torch, h, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
                                                        ("shadow_any", shadow, bvh.TRACE_ANY)])

@@ -48,7 +48,8 @@ extern "C" {
 #define BVH_LAYOUT_BVH8_Q8 2  /* 8-wide, u8 child boxes in the parent frame, 128 B */
 #define BVH_LAYOUT_BVH8_Q16 3 /* 8-wide, u16 child boxes in the parent frame, 160 B */
 #define BVH_LAYOUT_PBRT_Q16 4 /* binary, own u16 box in the scene frame, 16 B */
-#define BVH_NUM_LAYOUTS 5
+#define BVH_LAYOUT_SG_EQ 5    /* binary, own 10-bit box in the scene frame, 12 B */
+#define BVH_NUM_LAYOUTS 6
 
 /* Leaf storage. */
 #define BVH_LEAF_COMPACT 0 /* triangles copied into leaf order (bvh_tri records) */
@@ -82,7 +83,8 @@ typedef struct bvh_hit {
 
 /* Build options; a zero field selects the default. */
 typedef struct bvh_build_opts {
-    int32_t leaf_size;   /* max triangles per leaf, 1..16 (1..15 for PBRT_Q16; default 4) */
+    int32_t leaf_size;   /* max triangles per leaf, 1..16 (1..15 for PBRT_Q16 and SG_EQ;
+                            default 4) */
     int32_t leaf_mode;   /* BVH_LEAF_COMPACT (default) or BVH_LEAF_INDEXED */
     int32_t stack_lds;   /* traversal stack entries kept in LDS per ray: 8, 16 or 32 (default:
                             32 for AABB2, 16 for the wide layouts).  A ray that needs more is
@@ -105,9 +107,12 @@ typedef struct bvh_stats {
     float scene_lo[3], scene_hi[3];
     int32_t stack_lds;         /* LDS stack entries per ray of the trace kernels */
     int32_t pad;
-    /* PBRT_Q16: the scene frame of the quantised boxes (a plane value is
-     * fmaf((float)q, frame_scale[a], frame_origin[a])); zero otherwise. */
-    float frame_origin[3], frame_scale[3];
+    /* PBRT_Q16 and SG_EQ: the scene frame of the quantised boxes (a lower
+     * plane value is fmaf((float)q, frame_scale[a], frame_origin[a]); an
+     * SG_EQ upper plane is fmaf(-(float)q, frame_scale[a], frame_top[a]));
+     * zero otherwise. */
+    float frame_origin[3], frame_scale[3], frame_top[3];
+    int32_t pad2;
 } bvh_stats;
 
 /* Compacted leaf triangle (BVH_LEAF_COMPACT), 48 B, in leaf order: the
@@ -202,6 +207,27 @@ typedef struct bvh_node_pbrt_q16 {
     uint32_t meta;
 } bvh_node_pbrt_q16; /* 16 B */
 
+/*
+ * BVH_LAYOUT_SG_EQ (the snapped-grid extent quantisation of App. D.1): the
+ * AABB2 tree in the same preorder, each node 12 B.  The scene box is split
+ * into 1023 steps of frame_scale per axis; a lower plane counts steps up from
+ * frame_origin, an upper plane counts steps down from frame_top:
+ *   lo[a] = fmaf((float)qlo_a, frame_scale[a], frame_origin[a])
+ *   hi[a] = fmaf(-(float)qhi_a, frame_scale[a], frame_top[a])
+ * with the tightest q whose plane still encloses the node's box (the builder
+ * checks this with the same fused multiply-add, so no directed rounding is
+ * needed at traversal time).  Packing:
+ *   qlo  = qlo_x << 20 | qlo_y << 10 | qlo_z | (nprims & 3) << 30
+ *   qhi  = qhi_x << 20 | qhi_y << 10 | qhi_z | (nprims >> 2) << 30
+ *   off  = bits 0..29: right-child offset (interior: right = I + off) or
+ *          first leaf-order triangle (leaf); bits 30..31: split axis of an
+ *          interior node (x, y, z = 0, 1, 2), used only for near-first order.
+ * nprims = 0 marks an interior node (1..15 triangles in a leaf).
+ */
+typedef struct bvh_node_sg_eq {
+    uint32_t qlo, qhi, off;
+} bvh_node_sg_eq; /* 12 B */
+
 typedef struct bvh_handle_s *bvh_handle_t;
 
 /* ---- calls -------------------------------------------------------------- */
@@ -226,7 +252,7 @@ int32_t bvh_version(void);
  *   out     host; receives the handle on success, NULL on failure
  * Errors: EINVAL for null pointers with a nonzero count, negative counts,
  * an unknown layout or leaf mode, leaf_size outside 1..16 (1..15 for
- * PBRT_Q16), nonzero reserved
+ * PBRT_Q16 and SG_EQ), nonzero reserved
  * fields, or (detected on the device, reported before returning) a vertex
  * index outside [0, n_verts); EUNSUPPORTED for n_tris >= 2^27, a tree whose
  * traversal stack would exceed the kernel's limit, or a wide layout whose
@@ -318,8 +344,8 @@ typedef struct bvh_scene_desc {
 
 typedef struct bvh_tune_opts {
     int32_t probe_rays;           /* probe rays per scene and candidate (0: 16384) */
-    int32_t leaf_size;            /* 1..16 (0: 4); leaves are compacted; PBRT_Q16 is a
-                                     tuning candidate only for leaf_size <= 15 */
+    int32_t leaf_size;            /* 1..16 (0: 4); leaves are compacted; PBRT_Q16 and
+                                     SG_EQ are tuning candidates only for leaf_size <= 15 */
     const bvh_ray *probe;         /* device, optional probe rays of all scenes, concatenated */
     const int64_t *probe_offsets; /* host, n_scenes + 1 offsets into probe; required with it */
     int32_t reserved[4];          /* must be zero */

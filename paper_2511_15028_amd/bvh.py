@@ -16,16 +16,16 @@ LIB_PATH = os.path.join(_PKG, "libbvh.so")
 
 # enums of bvh.h
 OK, EINVAL, ENOMEM, EHIP, ENODEV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-LAYOUT_AABB2, LAYOUT_BVH4, LAYOUT_BVH8_Q8, LAYOUT_BVH8_Q16, LAYOUT_PBRT_Q16 = 0, 1, 2, 3, 4
+LAYOUT_AABB2, LAYOUT_BVH4, LAYOUT_BVH8_Q8, LAYOUT_BVH8_Q16, LAYOUT_PBRT_Q16, LAYOUT_SG_EQ = range(6)
 LAYOUTS = {"aabb2": LAYOUT_AABB2, "bvh4": LAYOUT_BVH4, "bvh8_q8": LAYOUT_BVH8_Q8,
-           "bvh8_q16": LAYOUT_BVH8_Q16, "pbrt_q16": LAYOUT_PBRT_Q16}
+           "bvh8_q16": LAYOUT_BVH8_Q16, "pbrt_q16": LAYOUT_PBRT_Q16, "sg_eq": LAYOUT_SG_EQ}
 LAYOUT_NAMES = {v: k for k, v in LAYOUTS.items()}
 LEAF_COMPACT, LEAF_INDEXED = 0, 1
 LEAF_MODES = {"compact": LEAF_COMPACT, "indexed": LEAF_INDEXED}
 TRACE_CLOSEST, TRACE_ANY = 0, 1
 BUF_NODES, BUF_LEAF = 0, 1
 NODE_BYTES = {LAYOUT_AABB2: 32, LAYOUT_BVH4: 128, LAYOUT_BVH8_Q8: 128, LAYOUT_BVH8_Q16: 160,
-              LAYOUT_PBRT_Q16: 16}
+              LAYOUT_PBRT_Q16: 16, LAYOUT_SG_EQ: 12}
 
 
 class BVHError(RuntimeError):
@@ -49,11 +49,12 @@ class Stats(ctypes.Structure):
                 ("max_stack", ctypes.c_int32), ("scene_lo", ctypes.c_float * 3),
                 ("scene_hi", ctypes.c_float * 3), ("stack_lds", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("frame_origin", ctypes.c_float * 3),
-                ("frame_scale", ctypes.c_float * 3)]
+                ("frame_scale", ctypes.c_float * 3), ("frame_top", ctypes.c_float * 3),
+                ("pad2", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        for k in ("scene_lo", "scene_hi", "frame_origin", "frame_scale"):
+        for k in ("scene_lo", "scene_hi", "frame_origin", "frame_scale", "frame_top"):
             d[k] = list(getattr(self, k))
         return d
 

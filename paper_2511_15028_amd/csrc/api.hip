@@ -83,6 +83,7 @@ extern "C" int32_t bvh_get_stats(bvh_handle_t h, bvh_stats *out) {
     for (int a = 0; a < 3; a++) {
         out->frame_origin[a] = h->frame_origin[a];
         out->frame_scale[a] = h->frame_scale[a];
+        out->frame_top[a] = h->frame_top[a];
     }
     return BVH_OK;
 }

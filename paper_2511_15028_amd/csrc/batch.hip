@@ -27,7 +27,7 @@ struct BatchScene {
     uint32_t n_tris;
     uint32_t ray_count;
     float coord_max;
-    float fo[3], fs[3];  // PBRT_Q16 scene frame
+    float fo[3], fs[3], ft[3];  // PBRT_Q16 / SG_EQ scene frame
 };
 
 // Largest s in [0, n) with tile_off[s] <= tile (tile_off has n + 1 entries,
@@ -69,7 +69,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_trace(const BatchScene *s
             const uint64_t i = sc.ray_begin + local;
             const Ray r = load_ray(rays, i, sc.coord_max);
             const SceneData ld{sc.leaf, nullptr, nullptr, sc.n_tris, sc.coord_max,
-                               {sc.fo[0], sc.fo[1], sc.fo[2]}, {sc.fs[0], sc.fs[1], sc.fs[2]}};
+                               {sc.fo[0], sc.fo[1], sc.fo[2]}, {sc.fs[0], sc.fs[1], sc.fs[2]},
+                               {sc.ft[0], sc.ft[1], sc.ft[2]}};
             uint32_t nf = 0, nt = 0;
             bool incomplete = false;
             LdsStack<TracerFor<Layout>::type::kWithT, SL> st(s_ref, s_t);
@@ -101,7 +102,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_fallback(const BatchScene
         const BatchScene sc = scenes[lo];
         const Ray r = load_ray(rays, i, sc.coord_max);
         const SceneData ld{sc.leaf, nullptr, nullptr, sc.n_tris, sc.coord_max,
-                               {sc.fo[0], sc.fo[1], sc.fo[2]}, {sc.fs[0], sc.fs[1], sc.fs[2]}};
+                               {sc.fo[0], sc.fo[1], sc.fo[2]}, {sc.fs[0], sc.fs[1], sc.fs[2]},
+                               {sc.ft[0], sc.ft[1], sc.ft[2]}};
         uint32_t nf = 0, nt = 0;
         bool incomplete = false;
         GlobalStack<TracerFor<Layout>::type::kWithT> st(fb.stack_ref + (size_t)lane * kStackMax,
@@ -163,6 +165,7 @@ FallbackFn fallback_for(int layout) {
         case BVH_LAYOUT_BVH4: return &k_batch_fallback<BVH_LAYOUT_BVH4>;
         case BVH_LAYOUT_BVH8_Q8: return &k_batch_fallback<BVH_LAYOUT_BVH8_Q8>;
         case BVH_LAYOUT_PBRT_Q16: return &k_batch_fallback<BVH_LAYOUT_PBRT_Q16>;
+        case BVH_LAYOUT_SG_EQ: return &k_batch_fallback<BVH_LAYOUT_SG_EQ>;
         default: return &k_batch_fallback<BVH_LAYOUT_BVH8_Q16>;
     }
 }
@@ -180,6 +183,7 @@ KernelFn kernel_for(int layout, int sl) {
         case BVH_LAYOUT_BVH4: return kernel_for_sl<BVH_LAYOUT_BVH4>(sl);
         case BVH_LAYOUT_BVH8_Q8: return kernel_for_sl<BVH_LAYOUT_BVH8_Q8>(sl);
         case BVH_LAYOUT_PBRT_Q16: return kernel_for_sl<BVH_LAYOUT_PBRT_Q16>(sl);
+        case BVH_LAYOUT_SG_EQ: return kernel_for_sl<BVH_LAYOUT_SG_EQ>(sl);
         default: return kernel_for_sl<BVH_LAYOUT_BVH8_Q16>(sl);
     }
 }
@@ -269,7 +273,10 @@ int32_t create_impl(const bvh_scene_desc *scenes, int32_t n_scenes, const bvh_tu
         if (sd.layout >= 0) layouts.push_back(sd.layout);
         else {
             layouts = {BVH_LAYOUT_BVH8_Q8, BVH_LAYOUT_BVH4, BVH_LAYOUT_BVH8_Q16, BVH_LAYOUT_AABB2};
-            if (leaf_size <= 15) layouts.push_back(BVH_LAYOUT_PBRT_Q16);  // u4 leaf count
+            if (leaf_size <= 15) {  // u4 leaf count
+                layouts.push_back(BVH_LAYOUT_PBRT_Q16);
+                layouts.push_back(BVH_LAYOUT_SG_EQ);
+            }
         }
         if (sd.stack_lds > 0) sls.push_back(sd.stack_lds);
         else sls = {16, 8, 32};
@@ -404,7 +411,8 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
             sc.push_back(BatchScene{h->nodes, h->n_nodes, h->leaf, (uint64_t)offsets[i],
                                     (uint32_t)h->n_tris, (uint32_t)cnt, h->coord_max(),
                                     {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
-                                    {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]}});
+                                    {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]},
+                                    {h->frame_top[0], h->frame_top[1], h->frame_top[2]}});
             const uint64_t tiles = ((uint64_t)cnt + kTile - 1) / kTile;
             if (toff.back() + tiles > 0xFFFFFFFFull)
                 return set_error(BVH_EUNSUPPORTED, "bvh_batch_trace: too many rays");

@@ -613,8 +613,51 @@ __device__ inline uint32_t q16_upper(float x, float o, float s) {
 }
 
 struct WorldFrame {
-    float o[3], s[3];
+    float o[3], s[3], top[3];
 };
+
+// sg-eq (App. D.1): 10-bit steps up from the frame origin (lower planes) and
+// down from the frame top (upper planes), tightest enclosing q per plane.
+__device__ inline uint32_t q10_lower(float x, float o, float s) {
+    if (s == 0.0f) return 0u;
+    float f = floorf((x - o) / s);
+    f = fminf(fmaxf(f, 0.0f), 1023.0f);
+    uint32_t a = (uint32_t)f;
+    while (a > 0 && fmaf((float)a, s, o) > x) a--;
+    while (a < 1023u && fmaf((float)(a + 1), s, o) <= x) a++;
+    return a;
+}
+__device__ inline uint32_t q10_upper(float x, float top, float s) {
+    if (s == 0.0f) return 0u;
+    float f = floorf((top - x) / s);
+    f = fminf(fmaxf(f, 0.0f), 1023.0f);
+    uint32_t b = (uint32_t)f;
+    while (b > 0 && fmaf(-(float)b, s, top) < x) b--;
+    while (b < 1023u && fmaf(-(float)(b + 1), s, top) >= x) b++;
+    return b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_sg_eq(const bvh_node_aabb2 *in, uint32_t n_nodes,
+                                                       WorldFrame fr, bvh_node_sg_eq *out,
+                                                       BuildInfo *info) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_nodes) return;
+    const bvh_node_aabb2 nd = in[i];
+    uint32_t lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = q10_lower(nd.lo[a], fr.o[a], fr.s[a]);
+        hi[a] = q10_upper(nd.hi[a], fr.top[a], fr.s[a]);
+        if (fr.s[a] != 0.0f && (fmaf((float)lo[a], fr.s[a], fr.o[a]) > nd.lo[a] ||
+                                fmaf(-(float)hi[a], fr.s[a], fr.top[a]) < nd.hi[a]))
+            atomicOr(&info->err, 4u);
+    }
+    const uint32_t cnt = nd.meta & 0xFFFFu;
+    bvh_node_sg_eq q;
+    q.qlo = lo[0] << 20 | lo[1] << 10 | lo[2] | (cnt & 3u) << 30;
+    q.qhi = hi[0] << 20 | hi[1] << 10 | hi[2] | (cnt >> 2) << 30;
+    q.off = cnt > 0 ? nd.offset : (nd.offset | ((nd.meta >> 16) & 3u) << 30);
+    out[i] = q;
+}
 
 __global__ __launch_bounds__(kBlock) void k_pack_pbrt_q16(const bvh_node_aabb2 *in, uint32_t n_nodes,
                                                           WorldFrame fr, bvh_node_pbrt_q16 *out,
@@ -1003,18 +1046,22 @@ T *pinned_scratch() {
     return static_cast<T *>(buf);
 }
 
-// Scene frame of the pbrt-q16 layout: origin = scene box corner, scale = the
-// smallest step with fmaf(65535, s, o) >= scene hi (std::fmaf rounds like the
-// device's fmaf).  Non-finite extents give scale 0 (reported elsewhere).
-WorldFrame world_frame(const float *lo, const float *hi) {
+// Scene frame of the scene-frame quantised layouts: origin and top = scene box
+// corners, scale = the smallest step with fmaf(steps, s, o) >= top and
+// fmaf(-steps, s, top) <= o (std::fmaf rounds like the device's fmaf).
+// Non-finite extents give scale 0 (reported elsewhere).
+WorldFrame world_frame(const float *lo, const float *hi, float steps) {
     WorldFrame fr;
     for (int a = 0; a < 3; a++) {
         fr.o[a] = lo[a];
+        fr.top[a] = hi[a];
         const float ext = hi[a] - lo[a];
         float sc = 0.0f;
         if (ext > 0.0f && std::isfinite(ext)) {
-            sc = ext / 65535.0f;
-            for (int g = 0; g < 64 && std::fmaf(65535.0f, sc, lo[a]) < hi[a]; g++)
+            sc = ext / steps;
+            // full range both ways: up from lo reaches hi, down from hi reaches lo
+            for (int g = 0; g < 64 && (std::fmaf(steps, sc, lo[a]) < hi[a] ||
+                                       std::fmaf(-steps, sc, hi[a]) > lo[a]); g++)
                 sc = std::nextafter(sc, INFINITY);
         }
         fr.s[a] = sc;
@@ -1196,23 +1243,30 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(
             tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
         BVH_TRY(check_launch("aabb2 packing"));
-    } else if (h->layout == BVH_LAYOUT_PBRT_Q16) {
+    } else if (h->layout == BVH_LAYOUT_PBRT_Q16 || h->layout == BVH_LAYOUT_SG_EQ) {
+        // the AABB2 tree, re-encoded node by node in the scene frame
+        const bool pq = h->layout == BVH_LAYOUT_PBRT_Q16;
         h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
-        WorldFrame fr = world_frame(hi.slo, hi.shi);
+        const WorldFrame fr = world_frame(hi.slo, hi.shi, pq ? 65535.0f : 1023.0f);
         for (int a = 0; a < 3; a++) {
             h->frame_origin[a] = fr.o[a];
             h->frame_scale[a] = fr.s[a];
+            h->frame_top[a] = pq ? 0.0f : fr.top[a];
         }
         Arena ar;
         bvh_node_aabb2 *tmp = nullptr;
         ar.request(&tmp, (size_t)h->n_nodes);
         BVH_TRY(ar.bind(s, kAreaBuildWide));
-        BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)h->n_nodes * sizeof(bvh_node_pbrt_q16)));
+        BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)h->n_nodes * h->node_bytes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
                                                                       (uint32_t)h->n_nodes, info);
-        k_pack_pbrt_q16<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
-            tmp, (uint32_t)h->n_nodes, fr, static_cast<bvh_node_pbrt_q16 *>(h->nodes), info);
-        BVH_TRY(check_launch("pbrt-q16 packing"));
+        if (pq)
+            k_pack_pbrt_q16<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
+                tmp, (uint32_t)h->n_nodes, fr, static_cast<bvh_node_pbrt_q16 *>(h->nodes), info);
+        else
+            k_pack_sg_eq<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
+                tmp, (uint32_t)h->n_nodes, fr, static_cast<bvh_node_sg_eq *>(h->nodes), info);
+        BVH_TRY(check_launch("scene-frame packing"));
     } else if (h->layout == BVH_LAYOUT_BVH4) {
         BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, h, s));
     } else if (h->layout == BVH_LAYOUT_BVH8_Q8) {
@@ -1303,7 +1357,7 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
     // LDS stack default: binary trees push one entry per level (32 entries of
     // 4 B); wide trees push up to arity-1 entries of 8 B (16 entries)
     int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT;
-    int32_t stack_lds = (layout == BVH_LAYOUT_AABB2 || layout == BVH_LAYOUT_PBRT_Q16) ? 32 : 16;
+    int32_t stack_lds = layout_arity(layout) == 2 ? 32 : 16;
     if (opts) {
         for (int k = 0; k < 5; k++)
             if (opts->reserved[k] != 0) return set_error(BVH_EINVAL, "bvh_build: reserved option set");
@@ -1311,7 +1365,8 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
         if (opts->leaf_mode != 0) leaf_mode = opts->leaf_mode;
         if (opts->stack_lds != 0) stack_lds = opts->stack_lds;
     }
-    const int32_t max_leaf = layout == BVH_LAYOUT_PBRT_Q16 ? 15 : kMaxLeafSize;  // u4 count
+    const int32_t max_leaf =  // the scene-frame binary layouts store a u4 count
+        (layout == BVH_LAYOUT_PBRT_Q16 || layout == BVH_LAYOUT_SG_EQ) ? 15 : kMaxLeafSize;
     if (leaf_size < 1 || leaf_size > max_leaf)
         return set_error(BVH_EINVAL, "bvh_build: leaf_size %d outside 1..%d", leaf_size, max_leaf);
     if (leaf_mode != BVH_LEAF_COMPACT && leaf_mode != BVH_LEAF_INDEXED)

@@ -70,8 +70,9 @@ struct bvh_handle_s {
     int32_t max_stack = 0;
     float scene_lo[3] = {0, 0, 0};
     float scene_hi[3] = {0, 0, 0};
-    float frame_origin[3] = {0, 0, 0};  // PBRT_Q16: plane = fmaf(q, frame_scale, frame_origin)
+    float frame_origin[3] = {0, 0, 0};  // PBRT_Q16, SG_EQ: lo = fmaf(q, frame_scale, frame_origin)
     float frame_scale[3] = {0, 0, 0};
+    float frame_top[3] = {0, 0, 0};     // SG_EQ: hi = fmaf(-q, frame_scale, frame_top)
     void *nodes = nullptr;       // node records
     void *leaf = nullptr;        // bvh_tri[n_tris] or int32 prim id[n_tris]
     float *verts = nullptr;      // INDEXED: own copy of the vertices
@@ -101,6 +102,7 @@ inline int64_t node_record_bytes(int32_t layout) {
         case BVH_LAYOUT_BVH8_Q8: return sizeof(bvh_node_bvh8_q8);
         case BVH_LAYOUT_BVH8_Q16: return sizeof(bvh_node_bvh8_q16);
         case BVH_LAYOUT_PBRT_Q16: return sizeof(bvh_node_pbrt_q16);
+        case BVH_LAYOUT_SG_EQ: return sizeof(bvh_node_sg_eq);
         default: return 0;
     }
 }
@@ -109,6 +111,7 @@ inline int32_t layout_arity(int32_t layout) {
     switch (layout) {
         case BVH_LAYOUT_AABB2: return 2;
         case BVH_LAYOUT_PBRT_Q16: return 2;
+        case BVH_LAYOUT_SG_EQ: return 2;
         case BVH_LAYOUT_BVH4: return 4;
         default: return 8;
     }
@@ -166,6 +169,7 @@ static_assert(sizeof(bvh_hit) == 16, "bvh_hit");
 static_assert(sizeof(bvh_tri) == 48, "bvh_tri");
 static_assert(sizeof(bvh_node_aabb2) == 32, "aabb2 node");
 static_assert(sizeof(bvh_node_pbrt_q16) == 16, "pbrt-q16 node");
+static_assert(sizeof(bvh_node_sg_eq) == 12, "sg-eq node");
 static_assert(sizeof(bvh_node_bvh4) == 128, "bvh4 node");
 static_assert(sizeof(bvh_node_bvh8_q8) == 128, "bvh8 q8 node");
 static_assert(sizeof(bvh_node_bvh8_q16) == 160, "bvh8 q16 node");

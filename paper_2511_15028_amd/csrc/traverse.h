@@ -198,7 +198,8 @@ struct SceneData {
     const int32_t *tris;
     uint32_t n_tris;
     float coord_max;  // largest coordinate magnitude of the scene (selects the slab form)
-    float fo[3], fs[3];  // PBRT_Q16: plane value = fmaf(q, fs[a], fo[a])
+    float fo[3], fs[3];  // PBRT_Q16, SG_EQ: lower plane = fmaf(q, fs[a], fo[a])
+    float ft[3];         // SG_EQ: upper plane = fmaf(-q, fs[a], ft[a])
 };
 
 // Compacted leaves: triangles are fetched in batches of kLeafBatch (all loads
@@ -443,6 +444,26 @@ struct BinPbrtQ16 {
         cnt = w.w & 0xFu;
         off = w.w >> 4;
         axis = (q[0] & 1u) | ((q[1] & 1u) << 1);
+    }
+};
+
+// sg-eq: one 12-B load; 10-bit planes counted up from the frame origin
+// (lower) and down from the frame top (upper).
+struct BinSgEq {
+    __device__ static void load(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
+                                float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
+        const uint32_t *p = static_cast<const uint32_t *>(nodes) + 3 * (size_t)i;
+        const uint32_t ql = p[0], qh = p[1], w = p[2];
+        const uint32_t qlo[3] = {(ql >> 20) & 1023u, (ql >> 10) & 1023u, ql & 1023u};
+        const uint32_t qhi[3] = {(qh >> 20) & 1023u, (qh >> 10) & 1023u, qh & 1023u};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmaf((float)qlo[a], sd.fs[a], sd.fo[a]);
+            hi[a] = fmaf(-(float)qhi[a], sd.fs[a], sd.ft[a]);
+        }
+        cnt = (ql >> 30) | ((qh >> 30) << 2);
+        off = w & 0x3FFFFFFFu;
+        axis = cnt > 0 ? 3u : (w >> 30);
     }
 };
 
@@ -900,6 +921,10 @@ struct TracerFor<BVH_LAYOUT_AABB2> {
 template <>
 struct TracerFor<BVH_LAYOUT_PBRT_Q16> {
     using type = BinTracer<BinPbrtQ16>;
+};
+template <>
+struct TracerFor<BVH_LAYOUT_SG_EQ> {
+    using type = BinTracer<BinSgEq>;
 };
 template <>
 struct TracerFor<BVH_LAYOUT_BVH4> {

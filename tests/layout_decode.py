@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import numpy as np
 
-AABB2, BVH4, BVH8_Q8, BVH8_Q16, PBRT_Q16 = 0, 1, 2, 3, 4
+AABB2, BVH4, BVH8_Q8, BVH8_Q16, PBRT_Q16, SG_EQ = 0, 1, 2, 3, 4, 5
 
 AABB2_DT = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("offset", "<u4"), ("meta", "<u4")])
 BVH4_DT = np.dtype([("lo_x", "<f4", 4), ("lo_y", "<f4", 4), ("lo_z", "<f4", 4),
@@ -24,13 +24,15 @@ Q16_DT = np.dtype([("origin", "<f4", 3), ("scale", "<f4", 3),
                    ("qhi_x", "<u2", 8), ("qhi_y", "<u2", 8), ("qhi_z", "<u2", 8),
                    ("child", "<u4", 8), ("nchild", "<u4"), ("pad", "<u4")])
 PQ16_DT = np.dtype([("lo", "<u2", 3), ("hi", "<u2", 3), ("meta", "<u4")])
+SGEQ_DT = np.dtype([("qlo", "<u4"), ("qhi", "<u4"), ("off", "<u4")])
 TRI_DT = np.dtype([("p0", "<f4", 3), ("e1", "<f4", 3), ("e2", "<f4", 3), ("prim", "<i4"),
                    ("pad", "<i4", 2)])
 assert AABB2_DT.itemsize == 32 and BVH4_DT.itemsize == 128
 assert Q8_DT.itemsize == 128 and Q16_DT.itemsize == 160 and TRI_DT.itemsize == 48
-assert PQ16_DT.itemsize == 16
+assert PQ16_DT.itemsize == 16 and SGEQ_DT.itemsize == 12
 
-DTYPES = {AABB2: AABB2_DT, BVH4: BVH4_DT, BVH8_Q8: Q8_DT, BVH8_Q16: Q16_DT, PBRT_Q16: PQ16_DT}
+DTYPES = {AABB2: AABB2_DT, BVH4: BVH4_DT, BVH8_Q8: Q8_DT, BVH8_Q16: Q16_DT, PBRT_Q16: PQ16_DT,
+          SG_EQ: SGEQ_DT}
 
 
 def fma32(q, s, o):
@@ -96,10 +98,30 @@ def child_boxes(layout, rec):
 
 def pbrt_q16_box(rec, frame):
     """Decoded box (lo xyz, hi xyz) of one pbrt-q16 node in the scene frame
-    (frame = (origin[3], scale[3]))."""
-    o, s = (np.asarray(x, np.float32) for x in frame)
+    (frame = (origin[3], scale[3], ...))."""
+    o, s = (np.asarray(x, np.float32) for x in frame[:2])
     lo = fma32(rec["lo"].astype(np.float64), s, o)
     hi = fma32(rec["hi"].astype(np.float64), s, o)
+    return np.concatenate([lo, hi]).astype(np.float32)
+
+
+def sg_eq_fields(rec):
+    """(qlo[3], qhi[3], nprims, offset, axis) of sg-eq records (vectorised)."""
+    ql = np.asarray(rec["qlo"], np.uint64)
+    qh = np.asarray(rec["qhi"], np.uint64)
+    w = np.asarray(rec["off"], np.uint64)
+    qlo = np.stack([(ql >> 20) & 1023, (ql >> 10) & 1023, ql & 1023], axis=-1)
+    qhi = np.stack([(qh >> 20) & 1023, (qh >> 10) & 1023, qh & 1023], axis=-1)
+    nprim = (ql >> 30) | ((qh >> 30) << 2)
+    return qlo, qhi, nprim, w & 0x3FFFFFFF, w >> 30
+
+
+def sg_eq_box(rec, frame):
+    """Decoded box of one sg-eq node; frame = (origin, scale, top)."""
+    o, s, top = (np.asarray(x, np.float32) for x in frame)
+    qlo, qhi, _, _, _ = sg_eq_fields(rec)
+    lo = fma32(qlo.astype(np.float64), s, o)
+    hi = fma32(-qhi.astype(np.float64), s, top)
     return np.concatenate([lo, hi]).astype(np.float32)
 
 
@@ -113,15 +135,20 @@ def walk(layout, nodes_bytes, frame=None):
     visited = np.zeros(len(nodes), np.int64)
     if len(nodes) == 0:
         return nodes, leaves, visited
-    if layout == PBRT_Q16:
+    if layout in (PBRT_Q16, SG_EQ):
         stack = [(0, [])]
         while stack:
             i, path = stack.pop()
             visited[i] += 1
             rec = nodes[i]
-            box = pbrt_q16_box(rec, frame)
-            meta = int(rec["meta"])
-            nprim, off = meta & 0xF, meta >> 4
+            if layout == PBRT_Q16:
+                box = pbrt_q16_box(rec, frame)
+                meta = int(rec["meta"])
+                nprim, off = meta & 0xF, meta >> 4
+            else:
+                box = sg_eq_box(rec, frame)
+                _, _, nprim, off, _ = sg_eq_fields(rec)
+                nprim, off = int(nprim), int(off)
             if nprim > 0:
                 leaves.append((off, nprim, path + [box]))
             else:

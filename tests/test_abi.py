@@ -58,9 +58,10 @@ def test_build_argument_validation(L):
         assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(bad), None, ctypes.byref(h)) == bvh.EINVAL
     # the pbrt-q16 layout stores the triangle count in 4 bits
     sixteen = bvh.BuildOpts(16, 0)
-    assert L.bvh_build(fake, 3, fake, 1, bvh.LAYOUT_PBRT_Q16, ctypes.byref(sixteen), None,
-                       ctypes.byref(h)) == bvh.EINVAL
-    assert b"leaf_size" in L.bvh_last_error()
+    for lay in (bvh.LAYOUT_PBRT_Q16, bvh.LAYOUT_SG_EQ):
+        assert L.bvh_build(fake, 3, fake, 1, lay, ctypes.byref(sixteen), None,
+                           ctypes.byref(h)) == bvh.EINVAL
+        assert b"leaf_size" in L.bvh_last_error()
     res = bvh.BuildOpts(4, 0)
     res.reserved[2] = 1
     assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(res), None, ctypes.byref(h)) == bvh.EINVAL

@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 LAYOUTS = {"aabb2": LD.AABB2, "bvh4": LD.BVH4, "bvh8_q8": LD.BVH8_Q8, "bvh8_q16": LD.BVH8_Q16,
-           "pbrt_q16": LD.PBRT_Q16}
+           "pbrt_q16": LD.PBRT_Q16, "sg_eq": LD.SG_EQ}
 
 
 def _build(v, t, layout, leaf_mode="compact", leaf_size=4):
@@ -52,7 +52,8 @@ def test_round_trip(layout, leaf_mode, scene):
     lid = LAYOUTS[layout]
     nodes_bytes = h.read_buffer(bvh.BUF_NODES)
     assert len(nodes_bytes) == st["n_nodes"] * st["node_bytes"]
-    nodes, leaves, visited = LD.walk(lid, nodes_bytes, (st["frame_origin"], st["frame_scale"]))
+    nodes, leaves, visited = LD.walk(lid, nodes_bytes,
+                                     (st["frame_origin"], st["frame_scale"], st["frame_top"]))
     assert (visited == 1).all(), "every node reachable exactly once"
     assert len(leaves) == st["n_leaves"]
     leaf_raw = h.read_buffer(bvh.BUF_LEAF)
@@ -81,7 +82,7 @@ def test_round_trip(layout, leaf_mode, scene):
             assert np.array_equal(path[-1][0:3], lo) and np.array_equal(path[-1][3:6], hi)
     assert (covered == 1).all()
     assert st["max_stack"] >= 1 and st["depth"] >= 2
-    assert st["nodes_buffer_bytes"] == st["n_nodes"] * {0: 32, 1: 128, 2: 128, 3: 160, 4: 16}[lid]
+    assert st["nodes_buffer_bytes"] == st["n_nodes"] * {0: 32, 1: 128, 2: 128, 3: 160, 4: 16, 5: 12}[lid]
 
 
 @pytest.mark.parametrize("layout", list(LAYOUTS))
@@ -177,3 +178,41 @@ def test_pbrt_q16_matches_aabb2(scene):
     # the bit could not be set only where the lower plane was already at q = 0
     assert (ok | ~interior | (q["lo"][:, 0] == 0) | (q["lo"][:, 1] == 0)).all()
     assert ok[interior].mean() > 0.9
+
+
+@pytest.mark.parametrize("scene", list(SCENES))
+def test_sg_eq_matches_aabb2(scene):
+    """sg-eq is the AABB2 tree re-encoded (App. D.1) with 10-bit planes: node
+    i has the same triangle count, offset and split axis; lower planes count
+    steps up from the frame origin and upper planes steps down from the frame
+    top; every dequantised box encloses the exact AABB2 box with the tightest
+    q (no directed rounding: the builder checks the traversal's own fmaf)."""
+    from paper_2511_15028_amd import bvh
+    v, t = SCENES[scene]
+    a = np.frombuffer(_build(v, t, "aabb2").read_buffer(bvh.BUF_NODES), dtype=LD.AABB2_DT)
+    hq = _build(v, t, "sg_eq")
+    q = np.frombuffer(hq.read_buffer(bvh.BUF_NODES), dtype=LD.SGEQ_DT)
+    assert len(a) == len(q)
+    st = hq.stats()
+    o = np.asarray(st["frame_origin"], np.float32)
+    s = np.asarray(st["frame_scale"], np.float32)
+    top = np.asarray(st["frame_top"], np.float32)
+    assert np.array_equal(o, np.asarray(st["scene_lo"], np.float32))
+    assert np.array_equal(top, np.asarray(st["scene_hi"], np.float32))
+    assert (LD.fma32(1023.0, s, o) >= top).all() and (LD.fma32(-1023.0, s, top) <= o).all()
+    qlo, qhi, nprim, off, axis = LD.sg_eq_fields(q)
+    cnt_a = (a["meta"] & 0xFFFF).astype(np.uint64)
+    assert np.array_equal(nprim, cnt_a)
+    assert np.array_equal(off, a["offset"].astype(np.uint64))
+    interior = cnt_a == 0
+    assert np.array_equal(axis[interior], ((a["meta"] >> 16) & 3)[interior].astype(np.uint64))
+    for ax in range(3):
+        if s[ax] == 0:
+            continue
+        lo_d = LD.fma32(qlo[:, ax].astype(np.float64), s[ax], o[ax])
+        hi_d = LD.fma32(-qhi[:, ax].astype(np.float64), s[ax], top[ax])
+        assert (lo_d <= a["lo"][:, ax]).all() and (hi_d >= a["hi"][:, ax]).all()
+        up = LD.fma32(qlo[:, ax].astype(np.float64) + 1, s[ax], o[ax])
+        assert ((up > a["lo"][:, ax]) | (qlo[:, ax] == 1023)).all()
+        dn = LD.fma32(-(qhi[:, ax].astype(np.float64) + 1), s[ax], top[ax])
+        assert ((dn < a["hi"][:, ax]) | (qhi[:, ax] == 1023)).all()
