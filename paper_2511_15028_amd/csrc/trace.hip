@@ -44,7 +44,12 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(const void *nodes, int64_
 // refilled from its wave's pool of claimed rays once enough lanes of the
 // wave are idle (a wave claims 64 consecutive rays per atomic), so the
 // wave's lanes stay busy on long rays instead of idling until the slowest
-// ray of a fixed group ends.  Each lane's stack is a ring in LDS over a spill
+// ray of a fixed group ends.  A wave whose rays were coherent waits until
+// all its lanes are idle and then takes 64 consecutive rays, which keeps
+// neighbouring camera rays together (they end at nearly the same time).
+// The first three quarters of the rays are dealt to the waves round-robin in
+// 64-ray chunks (no atomics); the rest is claimed from a queue, which
+// balances the tail.  Each lane's stack is a ring in LDS over a spill
 // area in global memory that the lane owns for the launch; rays that outgrow
 // both go to the fallback pass.  Every wave leaves the loop once the queue is
 // drained and its lanes are idle, so the grid always drains.
@@ -73,22 +78,35 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
     // whether the queue is exhausted
     uint64_t pool = 0, pool_end = 0;
     bool drained = false;
+    const uint32_t waves = gridDim.x * (kTraceBlock / 64u);
+    const uint32_t wave =  // the same in every lane: keep it scalar
+        blockIdx.x * (kTraceBlock / 64u) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t static_rounds = (n * 3u / 4u) / ((uint64_t)waves * kClaim);
+    const uint64_t static_end = static_rounds * waves * kClaim;
+    uint64_t round = 0;  // static chunks taken by this wave
+    bool coherent = true;  // the wave's last rays all pointed into one octant
     for (;;) {
         const uint64_t idle = __builtin_amdgcn_ballot_w64(ray == kNoRay);
         const uint32_t nidle = (uint32_t)__builtin_popcountll(idle);
-        if (nidle >= kRefillLanes && !(drained && pool == pool_end)) {
+        const uint32_t need = coherent ? 64u : kRefillLanes;
+        if (nidle >= need && !(drained && pool == pool_end)) {
             const uint32_t avail = (uint32_t)(pool_end - pool);
             uint64_t fresh = 0;  // start of a newly claimed range
             if (avail < nidle && !drained) {
-                const uint32_t leader = (uint32_t)__builtin_ctzll(idle);
-                uint32_t lo = 0, hi = 0;
-                if (lane == leader) {
-                    const unsigned long long b = atomicAdd(fb.queue, (unsigned long long)kClaim);
-                    lo = (uint32_t)b;
-                    hi = (uint32_t)(b >> 32);
+                if (round < static_rounds) {
+                    fresh = (round * waves + wave) * kClaim;
+                    round++;
+                } else {
+                    const uint32_t leader = (uint32_t)__builtin_ctzll(idle);
+                    uint32_t lo = 0, hi = 0;
+                    if (lane == leader) {
+                        const unsigned long long b = atomicAdd(fb.queue, (unsigned long long)kClaim);
+                        lo = (uint32_t)b;
+                        hi = (uint32_t)(b >> 32);
+                    }
+                    fresh = static_end + (((uint64_t)__builtin_amdgcn_readlane(hi, leader) << 32) |
+                                          __builtin_amdgcn_readlane(lo, leader));
                 }
-                fresh = ((uint64_t)__builtin_amdgcn_readlane(hi, leader) << 32) |
-                        __builtin_amdgcn_readlane(lo, leader);
                 if (fresh >= n) drained = true;
             }
             const uint32_t fresh_n =
@@ -119,13 +137,16 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
                 pool = pool_end;
             }
         }
-        if (__builtin_amdgcn_ballot_w64(ray != kNoRay) == 0) {
+        const uint64_t busy = __builtin_amdgcn_ballot_w64(ray != kNoRay);
+        if (busy == 0) {
             if (drained && pool == pool_end) break;
             continue;
         }
+        // computed by every lane (converged), so the value stays wave-uniform
+        coherent = rays_share_octant(r, ray != kNoRay, busy);
         if (ray != kNoRay) {
             const bool fast = wave_fast(r);
-            if (wave_coherent(r))
+            if (coherent)
                 Tr::template round<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
                                                    nfetch, ntri, incomplete);
             else

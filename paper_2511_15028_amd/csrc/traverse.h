@@ -84,13 +84,21 @@ __device__ inline bool wave_fast(const Ray &r) {
     return __builtin_amdgcn_ballot_w64(!r.fast) == 0;
 }
 
+// True when the rays of the lanes in `mask` (those with `has` set) all point
+// into the same octant.  Called by every lane of the wave, so the result is
+// wave-uniform.
+__device__ inline bool rays_share_octant(const Ray &r, bool has, uint64_t mask) {
+    const uint64_t nx = __builtin_amdgcn_ballot_w64(has && r.nx);
+    const uint64_t ny = __builtin_amdgcn_ballot_w64(has && r.ny);
+    const uint64_t nz = __builtin_amdgcn_ballot_w64(has && r.nz);
+    return (nx == 0 || nx == mask) && (ny == 0 || ny == mask) && (nz == 0 || nz == mask);
+}
+
 // True when the active lanes' rays all point into the same octant (a cheap
 // wave-uniform coherence test: camera rays of neighbouring pixels pass it,
 // scattered secondary rays do not).
 __device__ inline bool wave_coherent(const Ray &r) {
-    const uint64_t nx = __builtin_amdgcn_ballot_w64(r.nx), ny = __builtin_amdgcn_ballot_w64(r.ny);
-    const uint64_t nz = __builtin_amdgcn_ballot_w64(r.nz), all = __builtin_amdgcn_ballot_w64(true);
-    return (nx == 0 || nx == all) && (ny == 0 || ny == all) && (nz == 0 || nz == all);
+    return rays_share_octant(r, true, __builtin_amdgcn_ballot_w64(true));
 }
 
 // Ray/box test of App. G (intersectsp_ray_aabb) on planes already ordered
@@ -875,11 +883,21 @@ struct BinTracer {
     __device__ static bool done(const State &s) {
         return s.node == kRefEmpty && s.leaf == kRefEmpty && s.hold == kRefEmpty;
     }
-    // single-loop order: visit a node and test a leaf as soon as it is met
+    // single-loop order: visit a node and test a leaf as soon as it is met.
+    // A persistent wave can switch orders between rounds, so a leaf still
+    // parked by the two-phase order is tested first.
     template <int LeafMode, int Mode, class Stack>
     __device__ static void step(const void *nodes, int64_t n_nodes, const SceneData &ld,
                                 const Ray &r, const Prep &, bool fast, Stack &st, State &s,
                                 uint32_t &nfetch, uint32_t &ntri, bool &incomplete) {
+        if (s.leaf != kRefEmpty) {
+            const uint32_t parked = s.leaf;
+            s.leaf = s.hold;
+            s.hold = kRefEmpty;
+            bin_test_leaf<LeafMode, Mode>(ld, r, parked, s, ntri);
+            return;
+        }
+        if (s.node == kRefEmpty) return;
         const uint32_t leaf =
             bin_visit<Node, Mode>(nodes, n_nodes, ld, r, fast, st, s, nfetch, incomplete);
         if (leaf != kRefEmpty) bin_test_leaf<LeafMode, Mode>(ld, r, leaf, s, ntri);

@@ -270,9 +270,10 @@ def test_spheres_full_size_sampled(orc, spheres_full, layout):
 
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_stack_depths_agree_and_fallback_is_exact(orc, layout):
-    """With an 8-entry LDS stack many rays overflow and are finished by the
-    deep-stack fallback pass; hits must be identical for 8, 16 and 32
-    entries and match the oracle (closest and any-hit)."""
+    """With an 8-entry LDS ring many rays spill to the per-lane global area
+    (rays beyond that would go to the deep-stack fallback pass); hits must be
+    identical for 8, 16 and 32 entries and match the oracle (closest and
+    any-hit)."""
     w = _small_spheres()
     v, t = w["verts"], w["tris"]
     res = {}
@@ -289,3 +290,27 @@ def test_stack_depths_agree_and_fallback_is_exact(orc, layout):
     hh = res[8][0]
     ref = orc.OracleBVH(v, t).trace(w["rays"], orc.TOP2)
     check_closest(orc, v, t, w["rays"], hh[:, 0].view(np.int32), hh[:, 1:4], ref)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_mixed_coherent_and_scattered_waves(orc, layout):
+    """Blocks of 64 camera rays alternate with blocks of 64 scattered rays, so
+    the lanes of a persistent wave hold coherent and scattered rays in turn as
+    they are refilled and the wave switches between the two traversal orders
+    mid-ray.  Every ray must still match the oracle."""
+    w = W.terrain_workload(cells=200, width=320, height=240)
+    v, t = w["verts"], w["tris"]
+    cam = w["rays"]
+    rnd = W.uniform_rays(len(cam), 17)
+    rnd[:, 0:3] = rnd[:, 0:3] * np.float32(0.9) + np.float32(0.05)
+    rnd[:, 2] += np.float32(0.3)  # above the terrain, scattered directions
+    blocks = []
+    for k in range(0, len(cam), 64):
+        blocks.append(cam[k:k + 64])
+        blocks.append(rnd[k:k + 64])
+    rays = np.ascontiguousarray(np.concatenate(blocks))
+    h = gpu_build(v, t, layout)
+    prim, tuv = gpu_trace(h, rays)
+    s_ = _sample(len(rays), 6000, 3)
+    ref = orc.OracleBVH(v, t).trace(rays[s_], orc.TOP2)
+    check_closest(orc, v, t, rays[s_], prim[s_], tuv[s_], ref)
