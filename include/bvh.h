@@ -329,8 +329,10 @@ int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const int32_t *t
  * The paper leaves execution scheduling to future work (Sec. 1) and shows that
  * the best layout depends on scene and ray distribution (Sec. 9.2.2); here
  * each scene's layout (and with it the tree arity) and LDS stack depth are
- * chosen by timing candidates on probe rays, and all scenes' rays are drained
- * from per-variant work queues by persistent kernels captured in one hipGraph.
+ * chosen by timing candidates on probe rays (every layout at the first stack
+ * depth, then the other depths on the winner), and all scenes' rays are
+ * drained from per-variant work queues by persistent kernels captured in one
+ * hipGraph (variants one after another, each on the whole GPU).
  */
 typedef struct bvh_scene_desc {
     const float *verts;   /* device, n_verts x 3 float */
@@ -343,7 +345,8 @@ typedef struct bvh_scene_desc {
 } bvh_scene_desc;
 
 typedef struct bvh_tune_opts {
-    int32_t probe_rays;           /* probe rays per scene and candidate (0: 16384) */
+    int32_t probe_rays;           /* probe rays per scene and candidate (0: 524288, enough
+                                     to fill the GPU) */
     int32_t leaf_size;            /* 1..16 (0: 4); leaves are compacted; PBRT_Q16 and
                                      SG_EQ are tuning candidates only for leaf_size <= 15 */
     const bvh_ray *probe;         /* device, optional probe rays of all scenes, concatenated */

@@ -42,10 +42,21 @@ __device__ inline uint32_t find_scene(const uint32_t *tile_off, uint32_t n, uint
     return lo;
 }
 
-// Persistent kernel: each wave takes 64-ray tiles from the group's queue
-// until it is empty.  Every wave reaches the exit (no wave ever waits on
-// another), so the grid always drains.  Rays that overflow the LDS stack go
-// to the group's fallback list.
+// Persistent kernel of one (layout, stack) group.  Waves take 64-ray tiles
+// from the group's queue.  A wave works on one scene at a time: lanes whose
+// ray ends are refilled from the wave's pool of claimed rays of that scene
+// once 16 lanes are idle (a further tile of the same scene extends the pool);
+// a claimed tile of another scene is held until every lane of the wave is
+// idle, and then the wave switches scenes.  Each lane's stack is a ring in
+// LDS over a spill area in global memory that the lane owns for the launch;
+// rays that outgrow both go to the group's fallback list.  Every wave leaves
+// the loop once the queue is drained and its lanes are idle (no wave ever
+// waits on another), so the grid always drains.
+constexpr uint32_t kNoRay = 0xFFFFFFFFu;
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+constexpr uint32_t kBatchRefill = 16;
+constexpr uint32_t kBatchSpillCap = 64;  // spill entries per lane beyond the LDS ring
+
 template <int Layout, int SL>
 __global__ __launch_bounds__(kTraceBlock) void k_batch_trace(const BatchScene *scenes,
                                                              const uint32_t *tile_off,
@@ -53,31 +64,97 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_trace(const BatchScene *s
                                                              uint32_t total_tiles,
                                                              uint32_t *counter,
                                                              const bvh_ray *rays, bvh_hit *hits,
-                                                             Fallback fb) {
+                                                             Fallback fb, SpillArea sa) {
+    using Tr = typename TracerFor<Layout>::type;
     __shared__ uint32_t s_ref[SL * kTraceBlock];
-    __shared__ float s_t[(TracerFor<Layout>::type::kWithT ? SL : 1) * kTraceBlock];
-    const int lane = threadIdx.x & 63;
+    __shared__ float s_t[(Tr::kWithT ? SL : 1) * kTraceBlock];
+    const uint32_t lane = threadIdx.x & 63u;
+    SpillStack<Tr::kWithT, SL> st(s_ref, s_t, sa);
+    // per lane
+    uint32_t ray = kNoRay;  // ray index within the launch's ray array
+    Ray r{};
+    typename Tr::Prep prep{};
+    typename Tr::State ts = Tr::start(0);
+    uint32_t nf = 0, nt = 0;
+    bool incomplete = false;
+    // wave-uniform
+    uint32_t scene = 0xFFFFFFFFu;  // scene of the wave's current rays
+    uint64_t pool = 0, pool_end = 0;
+    uint32_t pending = kNoTile;  // claimed tile of another scene
+    bool drained = false;
+    SceneData sd{};
+    const void *nodes = nullptr;
+    int64_t n_nodes = 0;
     for (;;) {
-        uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(counter, 1u);
-        tile = __shfl(tile, 0, 64);
-        if (tile >= total_tiles) break;
-        const uint32_t s = find_scene(tile_off, n_scenes, tile);
-        const BatchScene sc = scenes[s];
-        const uint32_t local = (tile - tile_off[s]) * kTile + lane;
-        if (local < sc.ray_count) {
-            const uint64_t i = sc.ray_begin + local;
-            const Ray r = load_ray(rays, i, sc.coord_max);
-            const SceneData ld{sc.leaf, nullptr, nullptr, sc.n_tris, sc.coord_max,
-                               {sc.fo[0], sc.fo[1], sc.fo[2]}, {sc.fs[0], sc.fs[1], sc.fs[2]},
-                               {sc.ft[0], sc.ft[1], sc.ft[2]}};
-            uint32_t nf = 0, nt = 0;
-            bool incomplete = false;
-            LdsStack<TracerFor<Layout>::type::kWithT, SL> st(s_ref, s_t);
-            const Best b = trace_ray<Layout, BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(
-                sc.nodes, sc.n_nodes, ld, r, st, nf, nt, incomplete);
-            if (incomplete) fallback_append(fb, (uint32_t)i);
-            else store_hit(hits, i, b);
+        const uint64_t idle = __builtin_amdgcn_ballot_w64(ray == kNoRay);
+        const uint32_t nidle = (uint32_t)__builtin_popcountll(idle);
+        if (nidle >= kBatchRefill) {
+            // claim a further tile when the pool cannot fill the idle lanes
+            if (pool_end - pool < nidle && pending == kNoTile && !drained) {
+                const uint32_t leader = (uint32_t)__builtin_ctzll(idle);
+                uint32_t t = 0;
+                if (lane == leader) t = atomicAdd(counter, 1u);
+                t = __builtin_amdgcn_readlane(t, leader);
+                if (t >= total_tiles) drained = true;
+                else pending = t;
+            }
+            // take the held tile once the pool is empty: at once for the same
+            // scene, after every lane is idle for another scene
+            if (pool == pool_end && pending != kNoTile) {
+                const uint32_t s2 = find_scene(tile_off, n_scenes, pending);
+                if (s2 == scene || nidle == 64u) {
+                    const BatchScene c = scenes[s2];
+                    if (s2 != scene) {
+                        scene = s2;
+                        nodes = c.nodes;
+                        n_nodes = c.n_nodes;
+                        sd = SceneData{c.leaf, nullptr, nullptr, c.n_tris, c.coord_max,
+                                       {c.fo[0], c.fo[1], c.fo[2]}, {c.fs[0], c.fs[1], c.fs[2]},
+                                       {c.ft[0], c.ft[1], c.ft[2]}};
+                    }
+                    const uint64_t lo = (uint64_t)(pending - tile_off[s2]) * kTile;
+                    pool = c.ray_begin + lo;
+                    pool_end = c.ray_begin + min((uint64_t)c.ray_count, lo + kTile);
+                    pending = kNoTile;
+                }
+            }
+            const uint32_t avail = (uint32_t)(pool_end - pool);
+            if (ray == kNoRay && avail > 0) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                if (rank < avail) {
+                    ray = (uint32_t)(pool + rank);
+                    r = load_ray(rays, ray, sd.coord_max);
+                    prep = Tr::prep(r);
+                    ts = Tr::start(n_nodes);
+                    st.reset();
+                    nf = nt = 0;
+                    incomplete = false;
+                }
+            }
+            pool += min(avail, nidle);
+        }
+        const uint64_t busy = __builtin_amdgcn_ballot_w64(ray != kNoRay);
+        if (busy == 0) {
+            if (drained && pending == kNoTile && pool == pool_end) break;
+            continue;
+        }
+        const bool coherent = rays_share_octant(r, ray != kNoRay, busy);
+        if (ray != kNoRay) {
+            const bool fast = wave_fast(r);
+            if (coherent)
+                Tr::template round<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(nodes, n_nodes, sd, r, prep,
+                                                                        fast, st, ts, nf, nt,
+                                                                        incomplete);
+            else
+                Tr::template step<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST>(nodes, n_nodes, sd, r, prep,
+                                                                       fast, st, ts, nf, nt,
+                                                                       incomplete);
+            if (Tr::done(ts)) {
+                if (incomplete) fallback_append(fb, ray);
+                else store_hit(hits, ray, ts.best);
+                ray = kNoRay;
+            }
         }
     }
 }
@@ -156,7 +233,7 @@ __global__ void k_probe_rays(bvh_ray *out, uint32_t n, float lx, float ly, float
 }
 
 using KernelFn = void (*)(const BatchScene *, const uint32_t *, uint32_t, uint32_t, uint32_t *,
-                          const bvh_ray *, bvh_hit *, Fallback);
+                          const bvh_ray *, bvh_hit *, Fallback, SpillArea);
 using FallbackFn = void (*)(const BatchScene *, uint32_t, const bvh_ray *, bvh_hit *, Fallback);
 
 FallbackFn fallback_for(int layout) {
@@ -238,7 +315,9 @@ int32_t time_trace(const bvh_handle_s *h, const bvh_ray *probe, uint64_t n, bvh_
 int32_t create_impl(const bvh_scene_desc *scenes, int32_t n_scenes, const bvh_tune_opts *opts,
                     hipStream_t s, bvh_batch_s *b) {
     const int32_t leaf_size = (opts && opts->leaf_size) ? opts->leaf_size : 4;
-    const int64_t probe_default = (opts && opts->probe_rays) ? opts->probe_rays : 16384;
+    // enough probe rays to fill the GPU, so that the timing sees the stack
+    // depth's effect on occupancy as the batched launch will
+    const int64_t probe_default = (opts && opts->probe_rays) ? opts->probe_rays : (1 << 19);
     int64_t max_probe = 0;
     for (int i = 0; i < n_scenes; i++) {
         int64_t np = probe_default;
@@ -290,14 +369,17 @@ int32_t create_impl(const bvh_scene_desc *scenes, int32_t n_scenes, const bvh_tu
         bvh_handle_s *best = nullptr;
         float best_ms = INFINITY;
         int ncand = 0;
+        // stage 1: every candidate layout at the first stack depth; stage 2:
+        // the other stack depths on the winning layout
+        const int sl0 = sls[0];
         for (int layout : (choose ? layouts : std::vector<int>{layouts[0]})) {
             bvh_handle_s *h = nullptr;
             rc = build_handle(sd.verts, sd.n_verts, sd.tris, sd.n_tris, layout, leaf_size,
-                              BVH_LEAF_COMPACT, sls[0], s, &h);
+                              BVH_LEAF_COMPACT, sl0, s, &h);
             if (rc != BVH_OK) break;
             if (!choose) {
                 best = h;
-                h->stack_lds = (sls.size() == 1) ? sls[0] : 16;
+                h->stack_lds = (sls.size() == 1) ? sl0 : 16;
                 break;
             }
             if (!probe) {
@@ -311,31 +393,35 @@ int32_t create_impl(const bvh_scene_desc *scenes, int32_t n_scenes, const bvh_tu
                     h->scene_hi[1], h->scene_hi[2], 0x5EEDu + (uint32_t)i);
                 probe = gen;
             }
-            bool keep = false;
-            int keep_sl = 16;
-            for (int sl : sls) {
-                h->stack_lds = sl;
-                float ms = 0.0f;
-                rc = time_trace(h, probe, (uint64_t)np, hits, s, e0, e1, &ms);
-                if (rc != BVH_OK) break;
-                ncand++;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    keep = true;
-                    keep_sl = sl;
-                }
-            }
+            float ms = 0.0f;
+            rc = time_trace(h, probe, (uint64_t)np, hits, s, e0, e1, &ms);
             if (rc != BVH_OK) {
                 bvh_destroy(h);
                 break;
             }
-            if (keep) {
+            ncand++;
+            if (ms < best_ms) {
+                best_ms = ms;
                 if (best) bvh_destroy(best);
                 best = h;
-                best->stack_lds = keep_sl;
             } else {
                 bvh_destroy(h);
             }
+        }
+        if (rc == BVH_OK && choose && best) {
+            int keep_sl = sl0;
+            for (size_t k = 1; k < sls.size(); k++) {
+                best->stack_lds = sls[k];
+                float ms = 0.0f;
+                rc = time_trace(best, probe, (uint64_t)np, hits, s, e0, e1, &ms);
+                if (rc != BVH_OK) break;
+                ncand++;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    keep_sl = sls[k];
+                }
+            }
+            best->stack_lds = keep_sl;
         }
         if (rc != BVH_OK) {
             if (best) bvh_destroy(best);
@@ -369,8 +455,9 @@ int32_t upload(bvh_batch_s *b, const std::vector<T> &v, T **out) {
 }
 
 // Builds and instantiates the graph for one argument set: a counter-reset
-// kernel, then one persistent kernel per (layout, stack) variant that depends
-// only on the reset (so variants run concurrently).
+// kernel, then per (layout, stack) variant its persistent kernel and its
+// fallback pass, the variants one after another (each fills the GPU, and
+// they share one per-lane stack spill area).
 int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, bvh_hit *hits) {
     b->drop_graph();
     const int n = (int)b->handles.size();
@@ -401,6 +488,9 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
         BVH_HIP_TRY(hipGraphAddKernelNode(&reset, b->graph, nullptr, 0, &p));
     }
     int g = 0;
+    hipGraphNode_t prev = reset;
+    void *spill = nullptr;
+    uint32_t spill_lanes = 0;
     for (auto &kv : groups) {
         std::vector<BatchScene> sc;
         std::vector<uint32_t> toff(1, 0);
@@ -428,22 +518,36 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
             &per_cu, reinterpret_cast<const void *>(fn), kTraceBlock, 0));
         const uint32_t total = toff.back();
         const uint32_t waves_per_block = kTraceBlock / 64;
-        uint32_t grid = std::max<uint32_t>(1, (uint32_t)std::max(per_cu, 1) * (uint32_t)n_cu);
-        grid = std::min<uint32_t>(grid, (total + waves_per_block - 1) / waves_per_block);
+        uint64_t group_rays = 0;
+        for (const BatchScene &x : sc) group_rays += x.ray_count;
+        // the groups run one after another, each on the whole GPU
+        const uint64_t resident = (uint64_t)std::max(per_cu, 1) * (uint64_t)n_cu;
+        uint32_t grid = (uint32_t)std::min<uint64_t>(resident, (total + waves_per_block - 1) / waves_per_block);
         grid = std::max<uint32_t>(grid, 1);
         uint32_t nsc = (uint32_t)sc.size();
         uint32_t *ctr = counters + g;
         const bvh_ray *r = rays;
         bvh_hit *hh = hits;
-        // fallback work area of this group (list sized for all its rays)
-        uint64_t group_rays = 0;
-        for (const BatchScene &x : sc) group_rays += x.ray_count;
+        // fallback work area of this group (list sized for all its rays),
+        // then the per-lane stack spill area of its grid
+        const uint32_t lanes = grid * kTraceBlock;
         void *ws = nullptr;
         BVH_HIP_TRY(hipMalloc(&ws, fallback_bytes(group_rays)));
         b->g_mem.push_back(ws);
         Fallback fb = fallback_view(ws, group_rays);
         fb.count = counters + ngroups + g;
-        void *args[] = {&d_sc, &d_toff, &nsc, (void *)&total, &ctr, &r, &hh, &fb};
+        if (lanes > spill_lanes) {  // the shared spill area, sized for the largest grid
+            spill_lanes = n_cu * 32u * 64u;  // every lane the GPU can hold
+            BVH_HIP_TRY(hipMalloc(&spill, (size_t)spill_lanes * kBatchSpillCap * 8));
+            b->g_mem.push_back(spill);
+        }
+        SpillArea sa;
+        sa.ref = static_cast<uint32_t *>(spill);
+        sa.t = reinterpret_cast<float *>(static_cast<char *>(spill) +
+                                         (size_t)spill_lanes * kBatchSpillCap * 4);
+        sa.lanes = lanes;
+        sa.cap = kBatchSpillCap;
+        void *args[] = {&d_sc, &d_toff, &nsc, (void *)&total, &ctr, &r, &hh, &fb, &sa};
         hipKernelNodeParams p{};
         p.func = reinterpret_cast<void *>(fn);
         p.gridDim = dim3(grid);
@@ -452,7 +556,7 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
         p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t node;
-        BVH_HIP_TRY(hipGraphAddKernelNode(&node, b->graph, &reset, 1, &p));
+        BVH_HIP_TRY(hipGraphAddKernelNode(&node, b->graph, &prev, 1, &p));
         void *fargs[] = {&d_sc, &nsc, &r, &hh, &fb};
         hipKernelNodeParams q{};
         q.func = reinterpret_cast<void *>(fallback_for(kv.first.first));
@@ -463,6 +567,7 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
         q.extra = nullptr;
         hipGraphNode_t fnode;
         BVH_HIP_TRY(hipGraphAddKernelNode(&fnode, b->graph, &node, 1, &q));
+        prev = fnode;
         g++;
     }
     BVH_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
