@@ -110,7 +110,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *tile_sums, uint
         if (i < ntiles) tile_sums[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
+    if (threadIdx.x == 0 && total_out) {
+        *total_out = carry;
+        __threadfence_system();  // the total may live in host memory the host polls
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_final(const uint32_t *in, uint32_t *out,
@@ -963,7 +966,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base
 // The top levels, while the frontier is small, in one workgroup: open, scan
 // and emit per level with block barriers instead of kernel launches and host
 // round trips.  Leaves (base, count, frontier buffer) for the multi-block
-// levels in state[0..2].
+// levels in state[0..2] (host-mapped words; state[2] last).
 constexpr uint32_t kTopMaxFrontier = 2048;
 
 template <int Layout>
@@ -974,6 +977,11 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
                                                      uint32_t *state) {
     constexpr int K = WideOut<Layout>::K;
     __shared__ uint32_t wsum[kBlock / kWave];
+    if (threadIdx.x == 0) {  // frontier = {root} with zero stack need and depth
+        fr_node0[0] = 0;
+        fr_aux0[0] = 0;
+    }
+    __syncthreads();
     uint32_t base = 0, count = 1;
     int cur = 0;
     for (int level = 0; level < 64 && count > 0 && count <= kTopMaxFrontier; level++) {
@@ -1002,9 +1010,13 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
         cur ^= 1;
     }
     if (threadIdx.x == 0) {
+        // state lives in host memory the host polls: state[2] is written
+        // last, after base and count are visible
         state[0] = base;
         state[1] = count;
+        __threadfence_system();
         state[2] = (uint32_t)cur;
+        __threadfence_system();
     }
 }
 
@@ -1034,6 +1046,49 @@ __global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, con
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Small host words that kernels write directly (pinned, coherent, mapped into
+// the device's address space), one set per host thread.  Polling them lets
+// the host learn a count as soon as the kernel that produces it has run,
+// while later kernels of the same level are still queued or running, instead
+// of waiting for the whole stream and a copy.
+constexpr uint32_t kPending = 0xFFFFFFFFu;
+
+uint32_t *host_words() {
+    static thread_local void *buf = nullptr;
+    if (!buf && hipHostMalloc(&buf, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        (void)hipGetLastError();
+        buf = nullptr;
+    }
+    return static_cast<uint32_t *>(buf);
+}
+
+// Waits until the kernel-written word p no longer holds kPending.  The wait
+// is bounded by the stream: if the stream has finished (or failed) and the
+// word is still pending, it reports an error instead of spinning on.
+int32_t wait_host_word(volatile uint32_t *p, hipStream_t s, uint32_t *out) {
+    for (uint64_t spin = 1;; spin++) {
+        const uint32_t v = *p;
+        if (v != kPending) {
+            *out = v;
+            return BVH_OK;
+        }
+        if ((spin & 255u) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                const uint32_t w = *p;
+                if (w != kPending) {
+                    *out = w;
+                    return BVH_OK;
+                }
+                return set_error(BVH_EHIP, "bvh_build: internal error (count not written)");
+            }
+            if (e != hipErrorNotReady) {
+                return set_error(BVH_EHIP, "bvh_build: %s", hipGetErrorString(e));
+            }
+        }
+    }
+}
+
 // Small pinned host staging area for device-to-host readbacks (one per thread).
 template <typename T>
 T *pinned_scratch() {
@@ -1080,7 +1135,7 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
     constexpr int K = WideOut<Layout>::K;
     const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
     int32_t *fr_node[2], *cand;
-    uint32_t *fr_aux[2], *noff, *tile, *state;
+    uint32_t *fr_aux[2], *noff, *tile;
     uint8_t *wnodes;
     Arena arena;
     arena.request(&wnodes, (size_t)cap * h->node_bytes);
@@ -1091,34 +1146,33 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
     arena.request(&cand, (size_t)cap * K);
     arena.request(&noff, cap);
     arena.request(&tile, (cap + kScanTile - 1) / kScanTile + 1);
-    arena.request(&state, 4);
     BVH_TRY(arena.bind(s, kAreaBuildWide));
-    uint32_t *pin = pinned_scratch<uint32_t>();
-    if (!pin) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
-    // frontier = {root} with zero stack need and depth
-    pin[0] = 0;
-    pin[1] = 0;
-    BVH_HIP_TRY(hipMemcpyAsync(fr_node[0], &pin[0], sizeof(int32_t), hipMemcpyHostToDevice, s));
-    BVH_HIP_TRY(hipMemcpyAsync(fr_aux[0], &pin[1], sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    uint32_t *hw = host_words();
+    if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
+    volatile uint32_t *vw = hw;
+    vw[0] = vw[1] = vw[2] = vw[3] = kPending;
     k_wide_top<Layout><<<1, kBlock, 0, s>>>(tv, cap, fr_node[0], fr_node[1], fr_aux[0], fr_aux[1],
-                                           cand, noff, wnodes, info, state);
+                                           cand, noff, wnodes, info, hw);
     BVH_TRY(check_launch("wide packing (top levels)"));
-    BVH_HIP_TRY(hipMemcpyAsync(pin, state, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    BVH_HIP_TRY(hipStreamSynchronize(s));
-    uint32_t base = pin[0], count = pin[1];
-    int cur = (int)pin[2];
+    uint32_t base = 0, count = 0, curw = 0;
+    BVH_TRY(wait_host_word(vw + 2, s, &curw));  // written last, after base and count
+    base = vw[0];
+    count = vw[1];
+    int cur = (int)curw;
     if (base + count > cap) return set_error(BVH_EHIP, "wide packing overflow");
     for (int level = 0; count > 0; level++) {
         if (level > 4096) return set_error(BVH_EHIP, "wide packing did not terminate");
+        vw[3] = kPending;
         k_wide_open<K><<<grid_for(count), kBlock, 0, s>>>(tv, count, fr_node[cur], cand, noff);
-        scan_u32(noff, noff, count, tile, &info->next_count, s);
+        scan_u32(noff, noff, count, tile, hw + 3, s);
         k_wide_emit<Layout><<<grid_for(count), kBlock, 0, s>>>(
             tv, base, count, cap, fr_node[cur], fr_aux[cur], cand, noff, wnodes, fr_node[cur ^ 1],
             fr_aux[cur ^ 1], info);
         BVH_TRY(check_launch("wide packing"));
-        BVH_HIP_TRY(hipMemcpyAsync(pin, &info->next_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        BVH_HIP_TRY(hipStreamSynchronize(s));
-        const uint32_t next = *pin;
+        // the next level's size is known once the scan's middle kernel has run;
+        // the next launches queue behind this level's emit
+        uint32_t next = 0;
+        BVH_TRY(wait_host_word(vw + 3, s, &next));
         base += count;
         if (base + next > cap) return set_error(BVH_EHIP, "wide packing overflow");
         count = next;
