@@ -76,6 +76,12 @@ def _declare(L):
     L.orc_tuv_f64.restype = None
     L.orc_grad_f64.argtypes = [_P, _P, _P, _P, _P, _I64, _P, _P, _P, _P]
     L.orc_grad_f64.restype = None
+    L.orc_point_tri_f64.argtypes = [_P, _P, _P, _P, _I64, _P]
+    L.orc_point_tri_f64.restype = None
+    L.orc_brute_closest_point.argtypes = [_P, _P, _I64, _P, _I64, _P, _P, _P, _P, ctypes.c_int]
+    L.orc_brute_closest_point.restype = None
+    L.orc_bvh_closest_point.argtypes = [_P, _P, _I64, _P, _P, _P, _P, ctypes.c_int]
+    L.orc_bvh_closest_point.restype = None
 
 
 def _c(a, dtype):
@@ -174,6 +180,20 @@ class OracleBVH:
             return prim, tuv, prim2, t2
         return prim, tuv
 
+    def closest_point(self, queries, nthreads: int = 0):
+        """Closest-point query through the BVH; same result as
+        brute_closest_point."""
+        queries = _c(queries, np.float32)
+        assert queries.ndim == 2 and queries.shape[1] == 4
+        n = queries.shape[0]
+        prim = np.empty(n, np.int32)
+        duv = np.empty((n, 3), np.float64)
+        top2 = np.empty((n, 2), np.int32)
+        d2top2 = np.empty((n, 2), np.float64)
+        lib().orc_bvh_closest_point(self._h, _ptr(queries), n, _ptr(prim), _ptr(duv),
+                                    _ptr(top2), _ptr(d2top2), nthreads)
+        return prim, duv, top2, d2top2
+
 
 def tuv_f64(verts, tris, rays, prims):
     """(t, u, v) in FP64 at fixed primitives; verts/rays are taken as float64."""
@@ -209,6 +229,37 @@ def grad_f64(verts, tris, rays, prims, grad_hits, tuv_at=None):
     lib().orc_grad_f64(_ptr(verts), _ptr(tris), _ptr(rays), _ptr(prims), _ptr(grad_hits),
                        n, _ptr(gv), _ptr(gr), _ptr(tuv), _ptr(at) if at is not None else None)
     return gv, gr, tuv
+
+
+def point_tri_f64(verts, tris, queries, prims):
+    """(d2, u, v) in FP64 of queries[i] (x, y, z, r2) against triangle
+    prims[i]; the nearest point is (1-u-v) p0 + u p1 + v p2.  prims < 0 give
+    (inf, 0, 0)."""
+    verts, tris = _c(verts, np.float32), _c(tris, np.int32)
+    queries, prims = _c(queries, np.float32), _c(prims, np.int32)
+    n = prims.shape[0]
+    out = np.empty((n, 3), np.float64)
+    lib().orc_point_tri_f64(_ptr(verts), _ptr(tris), _ptr(queries), _ptr(prims), n, _ptr(out))
+    return out
+
+
+def brute_closest_point(verts, tris, queries, nthreads: int = 0):
+    """Exhaustive closest-point query (App. G "Closest Point Query").
+
+    queries: [n,4] float32 (x, y, z, r2).  Returns (prim[n] int32, duv[n,3]
+    float64 = (d2, u, v), top2[n,2] int32, d2top2[n,2] float64): the nearest
+    triangle within r2 (else -1, inf, 0, 0) and, regardless of r2, the
+    nearest and runner-up triangles and their squared distances."""
+    verts, tris, queries = _c(verts, np.float32), _c(tris, np.int32), _c(queries, np.float32)
+    assert queries.ndim == 2 and queries.shape[1] == 4
+    n = queries.shape[0]
+    prim = np.empty(n, np.int32)
+    duv = np.empty((n, 3), np.float64)
+    top2 = np.empty((n, 2), np.int32)
+    d2top2 = np.empty((n, 2), np.float64)
+    lib().orc_brute_closest_point(_ptr(verts), _ptr(tris), tris.shape[0], _ptr(queries), n,
+                                  _ptr(prim), _ptr(duv), _ptr(top2), _ptr(d2top2), nthreads)
+    return prim, duv, top2, d2top2
 
 
 def max_threads() -> int:

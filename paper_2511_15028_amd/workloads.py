@@ -301,6 +301,20 @@ def uniform_rays(n, seed, tag=1):
     return make_rays(o, d)
 
 
+def box_points(n, lo, hi, seed, tag=5, r2=math.inf):
+    """Closest-point queries: points uniform in the box [lo, hi] (queries
+    sampled inside the scene's bounding volume, Sec. 9.3.2), packed as [n,4]
+    float32 records (x, y, z, r2) with squared search radius r2."""
+    rng = _rng(seed, tag)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    p = lo + (hi - lo) * rng.uniform(0.0, 1.0, (n, 3))
+    out = np.empty((n, 4), np.float32)
+    out[:, :3] = p
+    out[:, 3] = np.float32(r2)
+    return out
+
+
 def shadow_rays(n, seed, tag=1):
     """Same origins as uniform_rays(n, seed, tag); each aims at a target
     U[0,1]^3 with tmax = distance to the target (occlusion queries)."""

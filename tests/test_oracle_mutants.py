@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PINS = [os.path.join(HERE, f) for f in ("test_oracle_mt.py", "test_oracle_closest.py",
-                                         "test_oracle_grad.py")]
+                                         "test_oracle_grad.py", "test_oracle_closest_point.py")]
 
 MUTANTS = [
     ("edge e2 reversed", "v3 e2 = v3_sub(p2, p0);", "v3 e2 = v3_sub(p0, p2);"),
@@ -43,6 +43,24 @@ MUTANTS = [
     ("gradient: vertex weights of p1, p2 swapped", "double w[3] = { 1.0 - u - v, u, v };",
      "double w[3] = { 1.0 - u - v, v, u };"),
     ("gradient: Cramer column transposed", "ab = d3_cross(a, b);", "ab = d3_cross(b, a);"),
+    ("closest point: edge p1p2 never considered",
+     "    cp_consider(q, p0, e1, e2, 1.0 - s12, s12, &bd2, &bu, &bv);\n", ""),
+    ("closest point: normal-equation numerator transposed", "double s = (c * r1 - b * r2) / det",
+     "double s = (c * r2 - b * r1) / det"),
+    ("closest point: segment parameter not clamped at 1", "return s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);",
+     "return s < 0.0 ? 0.0 : s;"),
+    ("closest point: barycentrics swapped on edge p1p2", "cp_consider(q, p0, e1, e2, 1.0 - s12, s12,",
+     "cp_consider(q, p0, e1, e2, s12, 1.0 - s12,"),
+    ("closest point: stationary point kept outside the triangle", "if (s >= 0.0 && t >= 0.0 && s + t <= 1.0)",
+     "if (s >= 0.0 && t >= 0.0)"),
+    ("closest point: radius exclusive", "b->d1 <= (double)r2", "b->d1 < (double)r2"),
+    ("closest point: ties to the highest id", "return da < db || (da == db && ia < ib);",
+     "return da < db || (da == db && ia > ib);"),
+    ("closest point: BVH culls with the best instead of the runner-up",
+     "double bound = b.d2 + ldexp(b.d2, -30) + abs_margin;",
+     "double bound = b.d1 + ldexp(b.d1, -30) + abs_margin;"),
+    ("closest point: box gap below the box measured from the upper plane",
+     "if (qq[a] < nd->lo[a]) g = nd->lo[a] - qq[a];", "if (qq[a] < nd->lo[a]) g = nd->hi[a] - qq[a];"),
 ]
 
 
