@@ -323,6 +323,52 @@ int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const int32_t *t
                            const float *grad_hits, float *grad_verts, float *grad_rays,
                            void *stream);
 
+/* ---- closest-point query --------------------------------------------------- */
+/* A query point p with squared search radius r2 (inclusive; +inf means
+ * unbounded). */
+typedef struct bvh_point_query {
+    float p[3];
+    float r2;
+} bvh_point_query; /* 16 B */
+
+/* Nearest triangle of a query: its id, the squared distance d2 and the
+ * barycentrics of its nearest point, (1-u-v) p0 + u p1 + v p2.  None within
+ * r2 is {-1, +inf, 0, 0}. */
+typedef struct bvh_closest {
+    int32_t prim_id;
+    float d2, u, v;
+} bvh_closest; /* 16 B */
+
+/*
+ * Closest-point query on any layout (App. G "Closest Point Query"; the same
+ * layouts serve ray tracing and this query, Sec. 9.2.3 and 9.3.2): for each
+ * query the triangle at the smallest squared distance d2 <= r2 from p, ties
+ * to the lowest primitive id.  Children are visited nearest box first and
+ * boxes farther than the best triangle so far are skipped (box distances are
+ * computed conservatively, so the skip never loses a nearer triangle).  The
+ * point-triangle distance is Ericson's Voronoi-region method (Real-Time
+ * Collision Detection 5.1.5) in f32, the method of the paper's listing, on
+ * a = p0, ab = p1 - p0, ac = p2 - p0; d2, u, v are that computation's f32
+ * results.  A degenerate triangle is measured by its edges.
+ *   queries  device, n records;  out  device, n records (written)
+ * A query whose point has a non-finite coordinate, or whose r2 is negative
+ * or NaN, gets {-1, +inf, 0, 0}.
+ * Errors: EINVAL for a null handle, n < 0, null pointers with n > 0;
+ * EUNSUPPORTED for more than 2^32 - 1 queries.  Concurrent queries and
+ * traces on one handle are allowed.
+ */
+int32_t bvh_closest_point(bvh_handle_t h, const bvh_point_query *queries, int64_t n,
+                          bvh_closest *out, void *stream);
+
+/*
+ * bvh_closest_point plus per-query work counters, for measurement:
+ * counts[2i] = node records fetched, counts[2i+1] = triangles measured.
+ * Same results as bvh_closest_point.
+ *   counts  device, 2n uint32 (written)
+ */
+int32_t bvh_closest_point_counts(bvh_handle_t h, const bvh_point_query *queries, int64_t n,
+                                 bvh_closest *out, uint32_t *counts, void *stream);
+
 /* ---- batched tracing ------------------------------------------------------ */
 /*
  * Many scenes with uneven triangle and ray counts traced by one graph launch.

@@ -12,7 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libbvh.so")
-SOURCES = ["api.hip", "build.hip", "trace.hip", "backward.hip", "batch.hip", "workspace.hip"]
+SOURCES = ["api.hip", "build.hip", "trace.hip", "closest.hip", "backward.hip", "batch.hip",
+           "workspace.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 # -ffp-contract=off: the ray/triangle and ray/box tests must round every

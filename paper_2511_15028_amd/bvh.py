@@ -104,6 +104,10 @@ def lib() -> ctypes.CDLL:
         L.bvh_trace.restype = _I32
         L.bvh_trace_counts.argtypes = [_P, _P, _I64, _P, _I32, _P, _P]
         L.bvh_trace_counts.restype = _I32
+        L.bvh_closest_point.argtypes = [_P, _P, _I64, _P, _P]
+        L.bvh_closest_point.restype = _I32
+        L.bvh_closest_point_counts.argtypes = [_P, _P, _I64, _P, _P, _P]
+        L.bvh_closest_point_counts.restype = _I32
         L.bvh_trace_backward.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P, _P]
         L.bvh_trace_backward.restype = _I32
         L.bvh_batch_create.argtypes = [ctypes.POINTER(SceneDesc), _I32, ctypes.POINTER(TuneOpts),
@@ -206,6 +210,30 @@ class BVH:
         _check(lib().bvh_trace_counts(self._h, rays.data_ptr(), n, hits.data_ptr(), mode,
                                       counts.data_ptr(), _stream(stream)))
         return hits, counts
+
+    def closest_point(self, queries: torch.Tensor, out: torch.Tensor = None,
+                      stream=None) -> torch.Tensor:
+        """queries: [n,4] float32 device (x, y, z, r2).  Returns [n,4] float32
+        (prim id bits, d2, u, v); see :func:`prim_ids`."""
+        _dev(queries, torch.float32, 4, "queries")
+        n = queries.shape[0]
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=queries.device)
+        _dev(out, torch.float32, 4, "out")
+        _check(lib().bvh_closest_point(self._h, queries.data_ptr(), n, out.data_ptr(),
+                                       _stream(stream)))
+        return out
+
+    def closest_point_counts(self, queries: torch.Tensor, stream=None):
+        """Like closest_point, plus per-query (nodes fetched, triangles
+        measured) int32 [n,2]."""
+        _dev(queries, torch.float32, 4, "queries")
+        n = queries.shape[0]
+        out = torch.empty((n, 4), dtype=torch.float32, device=queries.device)
+        counts = torch.zeros((n, 2), dtype=torch.int32, device=queries.device)
+        _check(lib().bvh_closest_point_counts(self._h, queries.data_ptr(), n, out.data_ptr(),
+                                              counts.data_ptr(), _stream(stream)))
+        return out, counts
 
 
 def build(verts: torch.Tensor, tris: torch.Tensor, layout="bvh8_q8", leaf_size: int = 4,

@@ -42,10 +42,7 @@ extern "C" int32_t bvh_destroy(bvh_handle_t h) {
     bool have_prev = hipGetDevice(&prev) == hipSuccess;
     if (hipSetDevice(h->device) == hipSuccess) {
         (void)hipDeviceSynchronize();
-        if (h->nodes) (void)hipFree(h->nodes);
-        if (h->leaf) (void)hipFree(h->leaf);
-        if (h->verts) (void)hipFree(h->verts);
-        if (h->tris) (void)hipFree(h->tris);
+        if (h->block) (void)hipFree(h->block);
     }
     if (have_prev) (void)hipSetDevice(prev);
     delete h;

@@ -1130,6 +1130,27 @@ int32_t check_launch(const char *what) {
     return BVH_OK;
 }
 
+// One device allocation per handle, carved into the node records, the leaf
+// array and (indexed leaves) the copies of the vertices and triangle indices.
+int32_t alloc_handle_block(bvh_handle_s *h, int64_t n_nodes) {
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t n = (size_t)h->n_tris;
+    const bool compact = h->leaf_mode == BVH_LEAF_COMPACT;
+    const size_t b_nodes = up((size_t)n_nodes * (size_t)h->node_bytes);
+    const size_t b_leaf = up(n * (compact ? sizeof(bvh_tri) : sizeof(int32_t)));
+    const size_t b_verts = compact ? 0 : up((size_t)h->n_verts * 3 * sizeof(float));
+    const size_t b_tris = compact ? 0 : up(n * 3 * sizeof(int32_t));
+    BVH_HIP_TRY(hipMalloc(&h->block, b_nodes + b_leaf + b_verts + b_tris));
+    char *p = static_cast<char *>(h->block);
+    h->nodes = p;
+    h->leaf = p + b_nodes;
+    if (!compact) {
+        h->verts = reinterpret_cast<float *>(p + b_nodes + b_leaf);
+        h->tris = reinterpret_cast<int32_t *>(p + b_nodes + b_leaf + b_verts);
+    }
+    return BVH_OK;
+}
+
 template <int Layout>
 int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s *h, hipStream_t s) {
     constexpr int K = WideOut<Layout>::K;
@@ -1184,7 +1205,7 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
         return set_error(BVH_EUNSUPPORTED,
                          "bvh_build: wide node buffer of %llu bytes exceeds 4 GiB (raise leaf_size)",
                          (unsigned long long)base * (unsigned long long)h->node_bytes);
-    BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)base * h->node_bytes));
+    BVH_TRY(alloc_handle_block(h, base));
     BVH_HIP_TRY(hipMemcpyAsync(h->nodes, wnodes, (size_t)base * h->node_bytes,
                                hipMemcpyDeviceToDevice, s));
     return BVH_OK;
@@ -1293,7 +1314,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // a7
     if (h->layout == BVH_LAYOUT_AABB2) {
         h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
-        BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)h->n_nodes * sizeof(bvh_node_aabb2)));
+        BVH_TRY(alloc_handle_block(h, h->n_nodes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(
             tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
         BVH_TRY(check_launch("aabb2 packing"));
@@ -1311,7 +1332,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         bvh_node_aabb2 *tmp = nullptr;
         ar.request(&tmp, (size_t)h->n_nodes);
         BVH_TRY(ar.bind(s, kAreaBuildWide));
-        BVH_HIP_TRY(hipMalloc(&h->nodes, (size_t)h->n_nodes * h->node_bytes));
+        BVH_TRY(alloc_handle_block(h, h->n_nodes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
                                                                       (uint32_t)h->n_nodes, info);
         if (pq)
@@ -1331,12 +1352,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
 
     // leaf data
     if (h->leaf_mode == BVH_LEAF_COMPACT) {
-        BVH_HIP_TRY(hipMalloc(&h->leaf, (size_t)n * sizeof(bvh_tri)));
         k_leaf_compact<<<nb, kBlock, 0, s>>>(verts, tris, perm, n, static_cast<bvh_tri *>(h->leaf));
     } else {
-        BVH_HIP_TRY(hipMalloc(&h->leaf, (size_t)n * sizeof(int32_t)));
-        BVH_HIP_TRY(hipMalloc(&h->verts, (size_t)n_verts * 3 * sizeof(float)));
-        BVH_HIP_TRY(hipMalloc(&h->tris, (size_t)n * 3 * sizeof(int32_t)));
         BVH_HIP_TRY(hipMemcpyAsync(h->leaf, perm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         BVH_HIP_TRY(hipMemcpyAsync(h->verts, verts, (size_t)n_verts * 3 * sizeof(float),
                                    hipMemcpyDeviceToDevice, s));

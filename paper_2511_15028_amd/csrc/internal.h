@@ -73,6 +73,7 @@ struct bvh_handle_s {
     float frame_origin[3] = {0, 0, 0};  // PBRT_Q16, SG_EQ: lo = fmaf(q, frame_scale, frame_origin)
     float frame_scale[3] = {0, 0, 0};
     float frame_top[3] = {0, 0, 0};     // SG_EQ: hi = fmaf(-q, frame_scale, frame_top)
+    void *block = nullptr;       // the one device allocation the pointers below point into
     void *nodes = nullptr;       // node records
     void *leaf = nullptr;        // bvh_tri[n_tris] or int32 prim id[n_tris]
     float *verts = nullptr;      // INDEXED: own copy of the vertices
@@ -166,6 +167,8 @@ class Arena {
 
 static_assert(sizeof(bvh_ray) == 32, "bvh_ray");
 static_assert(sizeof(bvh_hit) == 16, "bvh_hit");
+static_assert(sizeof(bvh_point_query) == 16, "bvh_point_query");
+static_assert(sizeof(bvh_closest) == 16, "bvh_closest");
 static_assert(sizeof(bvh_tri) == 48, "bvh_tri");
 static_assert(sizeof(bvh_node_aabb2) == 32, "aabb2 node");
 static_assert(sizeof(bvh_node_pbrt_q16) == 16, "pbrt-q16 node");

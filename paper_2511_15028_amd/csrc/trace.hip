@@ -1,9 +1,6 @@
 // Per-scene closest-hit / any-hit traversal kernels (one ray per lane) and
 // the bvh_trace / bvh_trace_counts entry points.
 #include <algorithm>
-#include <map>
-#include <mutex>
-#include <utility>
 
 #include "traverse.h"
 
@@ -194,56 +191,6 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_fallback(const void *node
             counts[2 * (size_t)i + 1] = ntri;
         }
     }
-}
-
-// Spill entries per lane of a persistent launch (beyond the LDS ring).
-constexpr uint32_t kSpillCap = 64;
-
-// Resident blocks of a kernel on the current device (cached per kernel).
-template <typename K>
-int32_t resident_blocks(K kernel, unsigned &blocks) {
-    static std::mutex mu;
-    static std::map<std::pair<const void *, int>, unsigned> cache;
-    int dev = 0;
-    BVH_HIP_TRY(hipGetDevice(&dev));
-    const auto key = std::make_pair(reinterpret_cast<const void *>(kernel), dev);
-    {
-        std::lock_guard<std::mutex> lock(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) {
-            blocks = it->second;
-            return BVH_OK;
-        }
-    }
-    int per_cu = 0, n_cu = 0;
-    BVH_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTraceBlock, 0));
-    BVH_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    blocks = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(n_cu > 0 ? n_cu : 1);
-    std::lock_guard<std::mutex> lock(mu);
-    cache[key] = blocks;
-    return BVH_OK;
-}
-
-// Work area of one launch: the fallback header, list and deep stacks, then
-// (persistent launches) the per-lane spill area.
-struct TraceArea {
-    Fallback fb;
-    SpillArea sa;
-};
-
-int32_t trace_area(hipStream_t s, uint64_t n, uint32_t lanes, TraceArea &ta) {
-    const size_t fb_bytes = (fallback_bytes(n) + 255) & ~(size_t)255;
-    const size_t sp_bytes = (size_t)lanes * kSpillCap * 8;
-    void *ws = nullptr;
-    BVH_TRY(stream_workspace(s, kAreaTrace, fb_bytes + sp_bytes, &ws));
-    ta.fb = fallback_view(ws, n);
-    char *sp = static_cast<char *>(ws) + fb_bytes;
-    ta.sa.ref = reinterpret_cast<uint32_t *>(sp);
-    ta.sa.t = reinterpret_cast<float *>(sp + (size_t)lanes * kSpillCap * 4);
-    ta.sa.lanes = lanes;
-    ta.sa.cap = kSpillCap;
-    BVH_HIP_TRY(hipMemsetAsync(ta.fb.count, 0, kFallbackHeaderBytes, s));
-    return BVH_OK;
 }
 
 constexpr bool kPersistent = true;

@@ -8,6 +8,9 @@
 #pragma once
 
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "internal.h"
 
@@ -1014,6 +1017,59 @@ inline Fallback fallback_view(void *base, uint64_t n_rays) {
 __device__ inline void fallback_append(const Fallback &fb, uint32_t ray) {
     const uint32_t k = atomicAdd(fb.count, 1u);
     fb.list[k] = ray;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers of the persistent kernels.
+// ---------------------------------------------------------------------------
+// Spill entries per lane of a persistent launch (beyond the LDS ring).
+constexpr uint32_t kSpillCap = 64;
+
+// Resident blocks of a kernel on the current device (cached per kernel).
+template <typename K>
+inline int32_t resident_blocks(K kernel, unsigned &blocks) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, unsigned> cache;
+    int dev = 0;
+    BVH_HIP_TRY(hipGetDevice(&dev));
+    const auto key = std::make_pair(reinterpret_cast<const void *>(kernel), dev);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            blocks = it->second;
+            return BVH_OK;
+        }
+    }
+    int per_cu = 0, n_cu = 0;
+    BVH_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTraceBlock, 0));
+    BVH_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    blocks = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(n_cu > 0 ? n_cu : 1);
+    std::lock_guard<std::mutex> lock(mu);
+    cache[key] = blocks;
+    return BVH_OK;
+}
+
+// Work area of one launch: the fallback header, list and deep stacks, then
+// (persistent launches) the per-lane spill area.
+struct TraceArea {
+    Fallback fb;
+    SpillArea sa;
+};
+
+inline int32_t trace_area(hipStream_t s, uint64_t n, uint32_t lanes, TraceArea &ta) {
+    const size_t fb_bytes = (fallback_bytes(n) + 255) & ~(size_t)255;
+    const size_t sp_bytes = (size_t)lanes * kSpillCap * 8;
+    void *ws = nullptr;
+    BVH_TRY(stream_workspace(s, kAreaTrace, fb_bytes + sp_bytes, &ws));
+    ta.fb = fallback_view(ws, n);
+    char *sp = static_cast<char *>(ws) + fb_bytes;
+    ta.sa.ref = reinterpret_cast<uint32_t *>(sp);
+    ta.sa.t = reinterpret_cast<float *>(sp + (size_t)lanes * kSpillCap * 4);
+    ta.sa.lanes = lanes;
+    ta.sa.cap = kSpillCap;
+    BVH_HIP_TRY(hipMemsetAsync(ta.fb.count, 0, kFallbackHeaderBytes, s));
+    return BVH_OK;
 }
 
 }  // namespace bvhlib

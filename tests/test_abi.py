@@ -29,7 +29,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ("bvh_build", "bvh_trace", "bvh_trace_backward", "bvh_destroy", "bvh_get_stats",
-              "bvh_read_buffer", "bvh_trace_counts", "bvh_last_error", "bvh_version"):
+              "bvh_read_buffer", "bvh_trace_counts", "bvh_last_error", "bvh_version",
+              "bvh_closest_point", "bvh_closest_point_counts"):
         assert f in names
 
 
@@ -80,6 +81,11 @@ def test_trace_and_backward_argument_validation(L):
     assert L.bvh_trace_backward(None, 0, None, 0, None, 0, None, None, None, None, None) == bvh.OK
     assert L.bvh_get_stats(None, None) == bvh.EINVAL
     assert L.bvh_read_buffer(None, 0, None, 0, None) == bvh.EINVAL
+    assert L.bvh_closest_point(None, fake, 1, fake, None) == bvh.EINVAL
+    assert L.bvh_closest_point(fake, fake, -1, fake, None) == bvh.EINVAL
+    assert L.bvh_closest_point(fake, None, 1, fake, None) == bvh.EINVAL
+    assert L.bvh_closest_point(fake, fake, 1 << 32, fake, None) == bvh.EUNSUPPORTED
+    assert L.bvh_closest_point_counts(fake, fake, 1, fake, None, None) == bvh.EINVAL
     assert L.bvh_destroy(None) == bvh.OK
 
 
@@ -97,6 +103,7 @@ def test_struct_layouts_match_header(tmp_path):
         for f, _ in py._fields_:
             lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
     lines.append('printf("bvh_ray %zu\\nbvh_hit %zu\\nbvh_tri %zu\\n", sizeof(bvh_ray), sizeof(bvh_hit), sizeof(bvh_tri));')
+    lines.append('printf("bvh_point_query %zu\\nbvh_closest %zu\\n", sizeof(bvh_point_query), sizeof(bvh_closest));')
     lines.append("return 0; }")
     src = tmp_path / "sizes.c"
     src.write_text("\n".join(lines))
@@ -110,6 +117,7 @@ def test_struct_layouts_match_header(tmp_path):
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
     assert (out["bvh_ray"], out["bvh_hit"], out["bvh_tri"]) == ("32", "16", "48")
+    assert (out["bvh_point_query"], out["bvh_closest"]) == ("16", "16")
 
 
 def test_batch_argument_validation(L):
