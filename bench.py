@@ -14,9 +14,10 @@ into the node layout) and trace the camera rays and the bounce rays.
 
 Also reported: per-layout trace-only throughput and algorithmic bytes per
 ray (from the counting kernel), the roofline of the traversal kernel
-(timed with HIP events on the launch stream), the differentiable workload's
-forward and forward+backward throughput, and the CPU oracle timed on the
-host cores.
+(timed with HIP events on the launch stream), closest-point query
+throughput per layout on the terrain and sphere scenes, the differentiable
+workload's forward and forward+backward throughput, batched tracing, and
+the CPU oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--layout L]
 """
@@ -35,6 +36,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 RAY_BYTES, HIT_BYTES = 32, 16
+QUERY_BYTES, CLOSEST_BYTES = 16, 16  # bvh_point_query, bvh_closest
+LAYOUTS = ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq")
 LEAF_TRI_BYTES = {"compact": 48, "indexed": 4 + 12 + 36}  # record, or id + index + 3 verts
 
 
@@ -220,9 +223,11 @@ def main():
 
     if not args.no_extras:
         out["per_layout"] = per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
+        out["closest_point"] = {"terrain": closest_point_rows(torch, bvh, W, w["verts"], verts,
+                                                              w["tris"], tris, args, 1001)}
         out["fwd_bwd"] = fwd_bwd(torch, bvh, W)
         del verts, tris, prim_rays, bounce_rays, hits_p, hits_b
-        out["spheres"] = spheres(torch, bvh, W, args)
+        out["spheres"] = spheres(torch, bvh, W, args, out["closest_point"])
         out["batched"] = batched(torch, bvh, W)
 
     if args.copy_calib_mib > 0:
@@ -277,7 +282,7 @@ def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
     fraction for every layout and leaf mode, camera (coherent) and bounce
     (incoherent) rays separately (median of 5 launches, events on the stream)."""
     res = {}
-    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq"):
+    for layout in LAYOUTS:
         for leaf_mode in ("compact", "indexed"):
             h = bvh.build(verts, tris, layout, args.leaf_size, leaf_mode)
             res[f"{layout}/{leaf_mode}"] = layout_row(
@@ -288,10 +293,66 @@ def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
     return res
 
 
-def spheres(torch, bvh, W, args):
+def time_closest(torch, h, q, reps=5):
+    """Median event time (ms) of `reps` closest-point calls after a warm-up."""
+    stream = torch.cuda.current_stream()
+    out = torch.empty((q.shape[0], 4), dtype=torch.float32, device=q.device)
+    times = []
+    for _ in range(reps + 1):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        h.closest_point(q, out=out)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        times.append(e[0].elapsed_time(e[1]))
+    return float(np.median(times[1:]))
+
+
+def closest_point_rows(torch, bvh, W, verts_np, verts, tris_np, tris, args, seed):
+    """Closest-point queries: 2^20 points uniform in the scene's bounding box
+    (unbounded radius), per layout with compacted leaves: Mqueries/s,
+    node records and triangles per query (counting kernel), algorithmic
+    bytes per query (query + result + nodes x node size + triangles x 48 B)
+    and the fraction of the HBM peak; plus the CPU oracle on a sample."""
+    import oracle
+    lo, hi = verts_np.min(axis=0), verts_np.max(axis=0)
+    q_np = W.box_points(1 << 20, lo, hi, seed)
+    q = torch.from_numpy(q_np).to(verts.device)
+    res = {"queries": int(q.shape[0])}
+    for layout in LAYOUTS:
+        h = bvh.build(verts, tris, layout, args.leaf_size, "compact")
+        st = h.stats()
+        t_ms = time_closest(torch, h, q)
+        _, c = h.closest_point_counts(q)
+        torch.cuda.synchronize()
+        c = c.cpu().numpy().astype(np.float64)
+        by = QUERY_BYTES + CLOSEST_BYTES + c[:, 0] * st["node_bytes"] + c[:, 1] * LEAF_TRI_BYTES["compact"]
+        gbs = by.sum() / (t_ms / 1000.0) / 1e9
+        res[layout] = {"mqueries_s": round(q.shape[0] / (t_ms / 1000.0) / 1e6, 1),
+                       "ms": round(t_ms, 4), "nodes_per_query": round(float(c[:, 0].mean()), 1),
+                       "tris_per_query": round(float(c[:, 1].mean()), 1),
+                       "bytes_per_query": round(float(by.mean()), 1),
+                       "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        h.close()
+        log(f"closest point {layout}: {res[layout]}")
+    if not args.no_cpu_baseline:
+        b = oracle.OracleBVH(verts_np, tris_np)
+        sample = q_np[: 1 << 17]
+        t0 = time.perf_counter()
+        b.closest_point(sample)
+        secs = time.perf_counter() - t0
+        res["cpu_oracle"] = {"mqueries_s": round(len(sample) / secs / 1e6, 3),
+                             "cores": oracle.max_threads(),
+                             "sample": f"first {len(sample)} queries, FP64 median-split BVH search "
+                                       f"({secs:.2f} s wall)"}
+    return res
+
+
+def spheres(torch, bvh, W, args, cpq=None):
     """Non-uniform density scene: 512 icospheres (levels 2-6 by radius rank)
     plus 100,000 slivers, 4,051,040 tris; 2^23 incoherent closest-hit rays
-    and 2^23 any-hit shadow rays, per layout (compacted leaves)."""
+    and 2^23 any-hit shadow rays, per layout (compacted leaves).  With `cpq`
+    (a dict), the closest-point rows of this scene are added to it."""
     t0 = time.time()
     w = W.spheres_workload()
     dev = torch.device("cuda:0")
@@ -302,12 +363,16 @@ def spheres(torch, bvh, W, args):
     log(f"spheres workload: {w['tris'].shape[0]} tris ({time.time() - t0:.1f}s)")
     res = {"workload": f"{len(w['tris'])} tris (512 spheres + 100K slivers), {rays.shape[0]} "
                        "uniform closest-hit rays + as many shadow rays (any hit)"}
-    for layout in ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq"):
+    for layout in LAYOUTS:
         h = bvh.build(verts, tris, layout, args.leaf_size, "compact")
         res[layout] = layout_row(torch, h, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
                                                        ("shadow_any", shadow, bvh.TRACE_ANY)])
         h.close()
         log(f"spheres {layout}: {res[layout]}")
+    if cpq is not None:
+        del rays, shadow
+        cpq["spheres"] = closest_point_rows(torch, bvh, W, w["verts"], verts, w["tris"], tris,
+                                            args, 1002)
     return res
 
 

@@ -514,8 +514,7 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
         BVH_TRY(upload(b, toff, &d_toff));
         const KernelFn fn = kernel_for(kv.first.first, kv.first.second);
         int per_cu = 0;
-        BVH_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(fn), kTraceBlock, 0));
+        BVH_TRY(blocks_per_cu(reinterpret_cast<const void *>(fn), b->device, per_cu));
         const uint32_t total = toff.back();
         const uint32_t waves_per_block = kTraceBlock / 64;
         uint64_t group_rays = 0;

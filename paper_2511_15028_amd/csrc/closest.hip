@@ -113,12 +113,13 @@ __device__ inline float cp_tri(float apx, float apy, float apz, float abx, float
     const bool in_c = d6 >= 0.0f && d5 <= d6;
     const bool in_ac = vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f;
     const bool in_bc = va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f;
-    // the one division of the chosen region: s = num / den
+    // the one division of the chosen region, s = num / den, as num times the
+    // hardware reciprocal of den (within one ulp)
     float num = 1.0f, den = va + vb + vc;  // face: 1 / (va + vb + vc)
     if (in_bc) { num = d4 - d3; den = (d4 - d3) + (d5 - d6); }
     if (in_ac) { num = d2; den = d2 - d6; }
     if (in_ab) { num = d1; den = d1 - d3; }
-    const float s = num / den;
+    const float s = num * __builtin_amdgcn_rcpf(den);
     float uu = vb * s, vv = vc * s;  // face
     if (in_bc) { uu = 1.0f - s; vv = s; }
     if (in_ac) { uu = 0.0f; vv = s; }
@@ -632,13 +633,10 @@ int32_t launch_mode(const bvh_handle_s *h, const bvh_point_query *qs, uint64_t n
                        {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
                        {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]},
                        {h->frame_top[0], h->frame_top[1], h->frame_top[2]}};
-    int32_t rc;
-    if (h->stack_lds == 8)
-        rc = launch_sl<LeafMode, Count, 8>(h, ld, qs, n, out, counts, s);
-    else if (h->stack_lds == 32)
-        rc = launch_sl<LeafMode, Count, 32>(h, ld, qs, n, out, counts, s);
-    else
-        rc = launch_sl<LeafMode, Count, 16>(h, ld, qs, n, out, counts, s);
+    // every stack entry carries a distance, so the LDS ring holds at most 16
+    // entries per lane (32 would halve the resident waves)
+    const int32_t rc = h->stack_lds == 8 ? launch_sl<LeafMode, Count, 8>(h, ld, qs, n, out, counts, s)
+                                         : launch_sl<LeafMode, Count, 16>(h, ld, qs, n, out, counts, s);
     if (rc != BVH_OK) return rc;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -1025,6 +1025,27 @@ __device__ inline void fallback_append(const Fallback &fb, uint32_t ray) {
 // Spill entries per lane of a persistent launch (beyond the LDS ring).
 constexpr uint32_t kSpillCap = 64;
 
+// Workgroups of a kernel resident on one CU at once: the runtime's occupancy
+// figure, lowered so that the workgroups' static LDS stays strictly below the
+// CU's capacity.  With the LDS of the runtime's figure filling the CU exactly
+// (five 32 KiB workgroups in 160 KiB), a persistent grid of that size ran
+// about a quarter slower than one a workgroup per CU smaller, as if the last
+// workgroup of each CU started only once another had finished (the work
+// dealt to it in advance then ends late).
+inline int32_t blocks_per_cu(const void *kernel, int dev, int &per_cu) {
+    BVH_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTraceBlock, 0));
+    hipFuncAttributes attr;
+    BVH_HIP_TRY(hipFuncGetAttributes(&attr, kernel));
+    int lds_cu = 0;
+    BVH_HIP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+    if (attr.sharedSizeBytes > 0 && lds_cu > 0) {
+        const int cap = (int)((size_t)(lds_cu - 1) / attr.sharedSizeBytes);
+        per_cu = per_cu < cap ? per_cu : cap;
+    }
+    if (per_cu < 1) per_cu = 1;
+    return BVH_OK;
+}
+
 // Resident blocks of a kernel on the current device (cached per kernel).
 template <typename K>
 inline int32_t resident_blocks(K kernel, unsigned &blocks) {
@@ -1042,9 +1063,9 @@ inline int32_t resident_blocks(K kernel, unsigned &blocks) {
         }
     }
     int per_cu = 0, n_cu = 0;
-    BVH_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTraceBlock, 0));
+    BVH_TRY(blocks_per_cu(reinterpret_cast<const void *>(kernel), dev, per_cu));
     BVH_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    blocks = (unsigned)(per_cu > 0 ? per_cu : 1) * (unsigned)(n_cu > 0 ? n_cu : 1);
+    blocks = (unsigned)per_cu * (unsigned)(n_cu > 0 ? n_cu : 1);
     std::lock_guard<std::mutex> lock(mu);
     cache[key] = blocks;
     return BVH_OK;
