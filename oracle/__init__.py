@@ -82,6 +82,8 @@ def _declare(L):
     L.orc_brute_closest_point.restype = None
     L.orc_bvh_closest_point.argtypes = [_P, _P, _I64, _P, _P, _P, _P, ctypes.c_int]
     L.orc_bvh_closest_point.restype = None
+    L.orc_sah_build.argtypes = [_P, _P, _I64, _P, _P, _P]
+    L.orc_sah_build.restype = _I64
 
 
 def _c(a, dtype):
@@ -260,6 +262,37 @@ def brute_closest_point(verts, tris, queries, nthreads: int = 0):
     lib().orc_brute_closest_point(_ptr(verts), _ptr(tris), tris.shape[0], _ptr(queries), n,
                                   _ptr(prim), _ptr(duv), _ptr(top2), _ptr(d2top2), nthreads)
     return prim, duv, top2, d2top2
+
+
+def sah_build(verts, tris):
+    """Binned-SAH binary tree (32 bins; readings in oracle.c).  Returns
+    (perm[n] int32, nodes[2n-1,4] int64 = (first, count, axis, left count) in
+    preorder, boxes[2n-1,6] float32)."""
+    verts, tris = _c(verts, np.float32), _c(tris, np.int32)
+    n = tris.shape[0]
+    perm = np.empty(max(n, 1), np.int32)
+    nodes = np.empty((max(2 * n - 1, 1), 4), np.int64)
+    boxes = np.empty((max(2 * n - 1, 1), 6), np.float32)
+    m = lib().orc_sah_build(_ptr(verts), _ptr(tris), n, _ptr(perm), _ptr(nodes), _ptr(boxes))
+    return perm[:n], nodes[:m], boxes[:m]
+
+
+def collapse(nodes, leaf_size):
+    """Preorder nodes of the tree whose subtrees of at most leaf_size
+    primitives become leaves: rows (first, count, axis, left count, is_leaf)."""
+    out = []
+    i = 0
+    stack = [0]
+    while stack:
+        i = stack.pop()
+        first, count, axis, nl = (int(x) for x in nodes[i])
+        if count <= leaf_size:
+            out.append((first, count, axis, nl, 1, i))
+            continue
+        out.append((first, count, axis, nl, 0, i))
+        stack.append(i + 2 * nl)
+        stack.append(i + 1)
+    return out
 
 
 def max_threads() -> int:

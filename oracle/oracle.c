@@ -27,6 +27,8 @@
  *                       parameterisation: u weights p1, v weights p2).
  *   - orc_tuv_f64       the same (t,u,v) at a fixed primitive in FP64, for
  *                       finite differences.
+ *   - orc_sah_build     binned-SAH binary topology (32 bins, top-down,
+ *                       Sec. 9.2.1), node list in preorder.
  *   - orc_*closest_point  closest-point query (App. G "Closest Point
  *                       Query"): the nearest triangle to a point within a
  *                       squared radius, its squared distance and the
@@ -723,4 +725,151 @@ void orc_bvh_closest_point(void *h, const float *queries, int64_t n, int32_t *ou
         }
         cp_store(&b, qp[3], i, out_prim, out_duv, out_top2, out_d2top2);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Binned SAH topology (Sec. 9.2.1: trees built by top-down recursive        */
+/* partitioning into two, each split chosen by the surface area heuristic    */
+/* over 32 bins, after Wald 2007; the same construction as the closest-point */
+/* comparison of Sec. 9.3.2, which bins along each axis and sweeps for the  */
+/* cheapest partition).  Readings where the paper gives no detail:          */
+/*   - a primitive's box is the exact f32 box of its vertices and its       */
+/*     centroid c = 0.5 lo + 0.5 hi (f32);                                   */
+/*   - a node bins along each axis over the exact bounds [cl, ch] of its    */
+/*     primitives' centroids: an axis with ch - cl not positive and finite  */
+/*     is skipped; otherwise s = 32 / (ch - cl) and the bin of c is          */
+/*     min(31, trunc((c - cl) * s)), all in f32;                             */
+/*   - the split after bin k (k = 0..30) costs A(L) N(L) + A(R) N(R) in f32, */
+/*     A = dx dy + dy dz + dz dx of the union box of a side (half the        */
+/*     surface area; the constant factors of the heuristic do not move the  */
+/*     minimum), valid when both sides are non-empty; the cheapest valid     */
+/*     split wins, ties to the lower axis, then the lower k;                 */
+/*   - with no valid split (all centroids coincide) the first floor(N/2)     */
+/*     primitives in the current order go left (axis recorded as 0);         */
+/*   - partitions are stable (each side keeps the parent's order) and the    */
+/*     initial order is by primitive id;                                     */
+/*   - splitting continues down to single primitives: the layouts' leaves    */
+/*     are then the subtrees of at most leaf_size primitives.                */
+/* ------------------------------------------------------------------------ */
+#define SAH_BINS 32
+
+typedef struct { float lo[3], hi[3]; } fbox;
+
+static inline void fbox_empty(fbox *b) {
+    for (int a = 0; a < 3; a++) { b->lo[a] = INFINITY; b->hi[a] = -INFINITY; }
+}
+static inline void fbox_grow(fbox *b, const fbox *x) {
+    for (int a = 0; a < 3; a++) {
+        if (x->lo[a] < b->lo[a]) b->lo[a] = x->lo[a];
+        if (x->hi[a] > b->hi[a]) b->hi[a] = x->hi[a];
+    }
+}
+static inline float half_area(const fbox *b) {
+    float dx = b->hi[0] - b->lo[0], dy = b->hi[1] - b->lo[1], dz = b->hi[2] - b->lo[2];
+    return (dx * dy + dy * dz) + dz * dx;
+}
+
+typedef struct { int64_t first, count; int32_t node; } sah_task;
+
+/* Builds the full binary tree.  perm[n]: primitive ids in leaf order.
+ * nodes[4*i..]: (first, count, axis, left count) of node i in preorder
+ * (left subtree first); a single primitive has count 1, axis -1, left 0.
+ * boxes[6*i..]: node box (lo, hi).  Returns the node count 2n - 1. */
+int64_t orc_sah_build(const float *verts, const int32_t *tris, int64_t n, int32_t *perm,
+                      int64_t *nodes, float *boxes) {
+    if (n <= 0) return 0;
+    fbox *pb = (fbox *)malloc((size_t)n * sizeof(fbox));
+    float *cen = (float *)malloc((size_t)n * 3 * sizeof(float));
+    int32_t *tmp = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    unsigned char *side = (unsigned char *)malloc((size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        fbox_empty(&pb[i]);
+        for (int k = 0; k < 3; k++) {
+            const float *p = verts + 3 * (int64_t)tris[3 * i + k];
+            for (int a = 0; a < 3; a++) {
+                if (p[a] < pb[i].lo[a]) pb[i].lo[a] = p[a];
+                if (p[a] > pb[i].hi[a]) pb[i].hi[a] = p[a];
+            }
+        }
+        for (int a = 0; a < 3; a++) cen[3 * i + a] = 0.5f * pb[i].lo[a] + 0.5f * pb[i].hi[a];
+        perm[i] = (int32_t)i;
+    }
+    sah_task *stack = (sah_task *)malloc((size_t)(n + 1) * sizeof(sah_task));
+    int64_t sp = 0;
+    stack[sp++] = (sah_task){ 0, n, 0 };
+    while (sp > 0) {
+        sah_task t = stack[--sp];
+        int64_t *nd = nodes + 4 * (int64_t)t.node;
+        fbox box;
+        fbox_empty(&box);
+        for (int64_t i = t.first; i < t.first + t.count; i++) fbox_grow(&box, &pb[perm[i]]);
+        for (int a = 0; a < 3; a++) {
+            boxes[6 * (int64_t)t.node + a] = box.lo[a];
+            boxes[6 * (int64_t)t.node + 3 + a] = box.hi[a];
+        }
+        nd[0] = t.first; nd[1] = t.count;
+        if (t.count == 1) { nd[2] = -1; nd[3] = 0; continue; }
+        float cl[3] = { INFINITY, INFINITY, INFINITY }, ch[3] = { -INFINITY, -INFINITY, -INFINITY };
+        for (int64_t i = t.first; i < t.first + t.count; i++)
+            for (int a = 0; a < 3; a++) {
+                float c = cen[3 * (int64_t)perm[i] + a];
+                if (c < cl[a]) cl[a] = c;
+                if (c > ch[a]) ch[a] = c;
+            }
+        int best_axis = -1, best_k = -1;
+        float best_cost = INFINITY;
+        for (int a = 0; a < 3; a++) {
+            float ext = ch[a] - cl[a];
+            if (!(ext > 0.0f) || isinf(ext)) continue;
+            float scale = (float)SAH_BINS / ext;
+            int64_t cnt[SAH_BINS] = { 0 };
+            fbox bb[SAH_BINS];
+            for (int k = 0; k < SAH_BINS; k++) fbox_empty(&bb[k]);
+            for (int64_t i = t.first; i < t.first + t.count; i++) {
+                int32_t p = perm[i];
+                int b = (int)((cen[3 * (int64_t)p + a] - cl[a]) * scale);
+                if (b > SAH_BINS - 1) b = SAH_BINS - 1;
+                cnt[b]++;
+                fbox_grow(&bb[b], &pb[p]);
+            }
+            for (int k = 0; k < SAH_BINS - 1; k++) {
+                fbox l, r;
+                int64_t nl = 0, nr = 0;
+                fbox_empty(&l); fbox_empty(&r);
+                for (int j = 0; j <= k; j++) { fbox_grow(&l, &bb[j]); nl += cnt[j]; }
+                for (int j = k + 1; j < SAH_BINS; j++) { fbox_grow(&r, &bb[j]); nr += cnt[j]; }
+                if (nl == 0 || nr == 0) continue;
+                float cost = half_area(&l) * (float)nl + half_area(&r) * (float)nr;
+                if (cost < best_cost) { best_cost = cost; best_axis = a; best_k = k; }
+            }
+        }
+        int64_t nl = 0;
+        if (best_axis >= 0) {
+            float ext = ch[best_axis] - cl[best_axis];
+            float scale = (float)SAH_BINS / ext;
+            for (int64_t i = t.first; i < t.first + t.count; i++) {
+                int b = (int)((cen[3 * (int64_t)perm[i] + best_axis] - cl[best_axis]) * scale);
+                if (b > SAH_BINS - 1) b = SAH_BINS - 1;
+                side[i] = b <= best_k;
+                nl += side[i];
+            }
+        } else {
+            nl = t.count / 2;
+            for (int64_t i = t.first; i < t.first + t.count; i++) side[i] = (i - t.first) < nl;
+            best_axis = 0;
+        }
+        /* stable partition */
+        int64_t w = t.first;
+        for (int64_t i = t.first; i < t.first + t.count; i++) if (side[i]) tmp[w++] = perm[i];
+        for (int64_t i = t.first; i < t.first + t.count; i++) if (!side[i]) tmp[w++] = perm[i];
+        memcpy(perm + t.first, tmp + t.first, (size_t)t.count * sizeof(int32_t));
+        nd[2] = best_axis; nd[3] = nl;
+        /* preorder: the left child is the next node, the right child follows
+         * the left subtree (2 nl - 1 nodes) */
+        int32_t left = t.node + 1, right = t.node + (int32_t)(2 * nl);
+        stack[sp++] = (sah_task){ t.first + nl, t.count - nl, right };
+        stack[sp++] = (sah_task){ t.first, nl, left };
+    }
+    free(stack); free(side); free(tmp); free(cen); free(pb);
+    return 2 * n - 1;
 }

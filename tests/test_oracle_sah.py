@@ -1,0 +1,143 @@
+"""Pins for the oracle's binned-SAH topology (32 bins, top-down; the split
+rules are listed in oracle.c).
+
+Closed forms: identical, evenly spaced triangles along one axis give the
+perfectly balanced tree in coordinate order (the cost A(L) N(L) + A(R) N(R)
+is symmetric about the middle split and smallest there); two distant
+clusters are separated at the root; coincident triangles fall back to the
+index median; a scene symmetric in x and y splits on x first (ties to the
+lower axis); one far outlier lands alone in the last bin (ties to the lowest
+split position).  Invariants: a permutation, contiguous child ranges, boxes
+equal to the exact unions.  Quality: the SAH cost of the tree is below that
+of the median-split tree on random scenes.
+"""
+import numpy as np
+import pytest
+
+from paper_2511_15028_amd import workloads as W
+
+SMALL = np.array([[0, 0, 0], [0.1, 0, 0], [0, 0.1, 0.05]], np.float32)
+
+
+def _scene(offsets):
+    v = np.concatenate([SMALL + np.asarray(o, np.float32) for o in offsets]).astype(np.float32)
+    return v, np.arange(3 * len(offsets), dtype=np.int32).reshape(-1, 3)
+
+
+def _check_balanced(nodes, n):
+    for i, (first, count, axis, nl) in enumerate(nodes):
+        if count > 1:
+            assert nl == count // 2, (i, count, nl)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [32, 64])
+def test_evenly_spaced_line_gives_balanced_tree(orc, axis, n):
+    offs = np.zeros((n, 3))
+    offs[:, axis] = np.arange(n) * 2.0
+    v, t = _scene(offs)
+    perm, nodes, _ = orc.sah_build(v, t)
+    np.testing.assert_array_equal(perm, np.arange(n))
+    _check_balanced(nodes, n)
+    assert nodes[0, 2] == axis
+    assert len(nodes) == 2 * n - 1
+
+
+def test_distant_clusters_separate_at_the_root(orc):
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0, 1, (20, 3))
+    b = rng.uniform(0, 1, (5, 3)) + [100.0, 0, 0]
+    order = rng.permutation(25)
+    offs = np.concatenate([a, b])[order]
+    v, t = _scene(offs)
+    perm, nodes, _ = orc.sah_build(v, t)
+    in_a = order < 20
+    assert nodes[0, 2] == 0 and nodes[0, 3] == 20
+    assert in_a[perm[:20]].all() and not in_a[perm[20:]].any()
+    # stable: each side keeps the id order at the root split
+    left = perm[:20]
+    assert set(left) == set(np.nonzero(in_a)[0])
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 16])
+def test_coincident_triangles_fall_back_to_index_median(orc, n):
+    v, t = _scene(np.zeros((n, 3)))
+    perm, nodes, _ = orc.sah_build(v, t)
+    np.testing.assert_array_equal(perm, np.arange(n))
+    _check_balanced(nodes, n)
+    assert (nodes[nodes[:, 1] > 1, 2] == 0).all()
+
+
+def test_ties_go_to_the_lower_axis(orc):
+    v, t = _scene([(0, 0, 0), (10, 0, 0), (0, 10, 0), (10, 10, 0)])
+    perm, nodes, _ = orc.sah_build(v, t)
+    assert nodes[0, 2] == 0 and nodes[0, 3] == 2
+    np.testing.assert_array_equal(perm, [0, 2, 1, 3])
+    # preorder: the left child is node 1, the right child node 0 + 2 * 2
+    assert nodes[1, 2] == 1 and nodes[4, 2] == 1
+
+
+def test_outlier_alone_in_the_last_bin(orc):
+    rng = np.random.default_rng(4)
+    offs = np.concatenate([rng.uniform(0, 0.01, (9, 3)), [[1000.0, 0, 0]]])
+    v, t = _scene(offs)
+    perm, nodes, _ = orc.sah_build(v, t)
+    assert nodes[0, 2] == 0 and nodes[0, 3] == 9 and perm[9] == 9
+
+
+def _prim_boxes(v, t):
+    p = v[t]
+    return p.min(axis=1), p.max(axis=1)
+
+
+@pytest.mark.parametrize("scene", ["soup", "spheres", "terrain"])
+def test_structure_and_boxes(orc, scene):
+    if scene == "soup":
+        v, t = W.soup_scene(3000, seed=41)
+    elif scene == "spheres":
+        v, t = W.sphere_cluster_exact(4000, seed=42)
+    else:
+        w = W.terrain_workload(cells=40, width=4, height=4)
+        v, t = w["verts"], w["tris"]
+    n = t.shape[0]
+    perm, nodes, boxes = orc.sah_build(v, t)
+    assert len(nodes) == 2 * n - 1
+    np.testing.assert_array_equal(np.sort(perm), np.arange(n))
+    lo, hi = _prim_boxes(v, t)
+    for i, (first, count, axis, nl) in enumerate(nodes):
+        ids = perm[first:first + count]
+        np.testing.assert_array_equal(boxes[i, :3], lo[ids].min(axis=0))
+        np.testing.assert_array_equal(boxes[i, 3:], hi[ids].max(axis=0))
+        if count == 1:
+            assert axis == -1 and nl == 0
+            continue
+        assert 0 < nl < count and 0 <= axis < 3
+        lft, rgt = nodes[i + 1], nodes[i + 2 * nl]
+        assert (lft[0], lft[1]) == (first, nl)
+        assert (rgt[0], rgt[1]) == (first + nl, count - nl)
+
+
+def _half_area(b):
+    d = (b[..., 3:] - b[..., :3]).astype(np.float64)
+    return d[..., 0] * d[..., 1] + d[..., 1] * d[..., 2] + d[..., 2] * d[..., 0]
+
+
+@pytest.mark.parametrize("scene", ["soup", "spheres"])
+def test_sah_cost_below_median_split(orc, scene):
+    """Tree cost sum(A(interior)) + sum(A(leaf) N(leaf)) over A(root), with
+    leaves of at most 4 triangles: the binned-SAH tree beats the
+    median-split tree of the same scene."""
+    if scene == "soup":
+        v, t = W.soup_scene(4000, seed=43)
+    else:
+        v, t = W.sphere_cluster_exact(6000, seed=44)
+    perm, nodes, boxes = orc.sah_build(v, t)
+    rows = orc.collapse(nodes, 4)
+    ha = _half_area(boxes)
+    root = ha[0]
+    sah = sum(ha[r[5]] * (r[1] if r[4] else 1.0) for r in rows) / root
+    b = orc.OracleBVH(v, t)
+    mb, links, _ = b.export()
+    mha = _half_area(mb)
+    med = sum(mha[i] * (links[i, 3] if links[i, 0] < 0 else 1.0) for i in range(len(mb))) / mha[0]
+    assert sah < 0.95 * med, (sah, med)
