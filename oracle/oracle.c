@@ -832,14 +832,26 @@ int64_t orc_sah_build(const float *verts, const int32_t *tris, int64_t n, int32_
                 cnt[b]++;
                 fbox_grow(&bb[b], &pb[p]);
             }
+            /* suffix unions: right side of split k = bins k+1 .. 31 */
+            fbox rs[SAH_BINS];
+            int64_t rn[SAH_BINS];
+            fbox_empty(&rs[SAH_BINS - 1]);
+            fbox_grow(&rs[SAH_BINS - 1], &bb[SAH_BINS - 1]);
+            rn[SAH_BINS - 1] = cnt[SAH_BINS - 1];
+            for (int j = SAH_BINS - 2; j >= 0; j--) {
+                rs[j] = rs[j + 1];
+                fbox_grow(&rs[j], &bb[j]);
+                rn[j] = rn[j + 1] + cnt[j];
+            }
+            fbox l;
+            int64_t nl = 0;
+            fbox_empty(&l);
             for (int k = 0; k < SAH_BINS - 1; k++) {
-                fbox l, r;
-                int64_t nl = 0, nr = 0;
-                fbox_empty(&l); fbox_empty(&r);
-                for (int j = 0; j <= k; j++) { fbox_grow(&l, &bb[j]); nl += cnt[j]; }
-                for (int j = k + 1; j < SAH_BINS; j++) { fbox_grow(&r, &bb[j]); nr += cnt[j]; }
+                fbox_grow(&l, &bb[k]);
+                nl += cnt[k];
+                int64_t nr = rn[k + 1];
                 if (nl == 0 || nr == 0) continue;
-                float cost = half_area(&l) * (float)nl + half_area(&r) * (float)nr;
+                float cost = half_area(&l) * (float)nl + half_area(&rs[k + 1]) * (float)nr;
                 if (cost < best_cost) { best_cost = cost; best_axis = a; best_k = k; }
             }
         }

@@ -62,8 +62,8 @@ MUTANTS = [
      "double bound = b.d1 + ldexp(b.d1, -30) + abs_margin;"),
     ("closest point: box gap below the box measured from the upper plane",
      "if (qq[a] < nd->lo[a]) g = nd->lo[a] - qq[a];", "if (qq[a] < nd->lo[a]) g = nd->hi[a] - qq[a];"),
-    ("SAH: right side weighted by the left count", "half_area(&r) * (float)nr;",
-     "half_area(&r) * (float)nl;"),
+    ("SAH: right side weighted by the left count", "half_area(&rs[k + 1]) * (float)nr;",
+     "half_area(&rs[k + 1]) * (float)nl;"),
     ("SAH: ties to the higher split", "if (cost < best_cost) { best_cost = cost;",
      "if (cost <= best_cost) { best_cost = cost;"),
     ("SAH: partition not stable", "for (int64_t i = t.first; i < t.first + t.count; i++) if (!side[i]) tmp[w++] = perm[i];",
@@ -71,8 +71,7 @@ MUTANTS = [
     ("SAH: fallback rounds the left half up", "nl = t.count / 2;", "nl = (t.count + 1) / 2;"),
     ("SAH: right child one node early", "right = t.node + (int32_t)(2 * nl);",
      "right = t.node + (int32_t)(2 * nl) - 1;"),
-    ("SAH: left sweep misses its last bin", "for (int j = 0; j <= k; j++) { fbox_grow(&l, &bb[j]); nl += cnt[j]; }",
-     "for (int j = 0; j < k; j++) { fbox_grow(&l, &bb[j]); nl += cnt[j]; }"),
+    ("SAH: right side starts at the split bin", "int64_t nr = rn[k + 1];", "int64_t nr = rn[k];"),
     ("SAH: area drops a face pair", "return (dx * dy + dy * dz) + dz * dx;", "return dx * dy + dy * dz;"),
 ]
 

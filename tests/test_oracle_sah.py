@@ -141,3 +141,55 @@ def test_sah_cost_below_median_split(orc, scene):
     mha = _half_area(mb)
     med = sum(mha[i] * (links[i, 3] if links[i, 0] < 0 else 1.0) for i in range(len(mb))) / mha[0]
     assert sah < 0.95 * med, (sah, med)
+
+
+def _half_area64(lo, hi):
+    d = (hi - lo).astype(np.float64)
+    return d[0] * d[1] + d[1] * d[2] + d[2] * d[0]
+
+
+@pytest.mark.parametrize("seed", [51, 52, 53])
+def test_each_split_is_the_cheapest_binned_candidate(orc, seed):
+    """Brute force on small scenes: at every internal node, every candidate
+    partition (bins from the stated f32 binning rule, split after bin k on
+    each axis) is evaluated from the primitives themselves in float64; the
+    node's split must reach the minimum (within f32 rounding of the cost)."""
+    rng = np.random.default_rng(seed)
+    n = 150
+    v, t = W.soup_scene(n, seed=seed)
+    v = (v * rng.uniform(0.5, 2.0, 3)).astype(np.float32)
+    perm, nodes, _ = orc.sah_build(v, t)
+    lo, hi = _prim_boxes(v, t)
+    cen = (np.float32(0.5) * lo + np.float32(0.5) * hi).astype(np.float32)
+    checked = 0
+    for i, (first, count, axis, nl) in enumerate(nodes):
+        if count < 2:
+            continue
+        ids = perm[first:first + count]
+        c = cen[ids]
+        cl, ch = c.min(axis=0), c.max(axis=0)
+        best = np.inf
+        chosen = None
+        for a in range(3):
+            ext = np.float32(ch[a] - cl[a])
+            if not (ext > 0) or np.isinf(ext):
+                continue
+            scale = np.float32(np.float32(32.0) / ext)
+            b = np.minimum(31, ((c[:, a] - cl[a]).astype(np.float32) * scale).astype(np.float32).astype(np.int64))
+            for k in range(31):
+                left = b <= k
+                if left.all() or not left.any():
+                    continue
+                lids, rids = ids[left], ids[~left]
+                cost = (_half_area64(lo[lids].min(axis=0), hi[lids].max(axis=0)) * len(lids) +
+                        _half_area64(lo[rids].min(axis=0), hi[rids].max(axis=0)) * len(rids))
+                best = min(best, cost)
+                if set(ids[:nl]) == set(lids) and a == axis:
+                    chosen = cost
+        if np.isinf(best):
+            assert nl == count // 2   # no valid candidate: index median
+            continue
+        assert chosen is not None, (i, axis, nl)
+        assert chosen <= best * (1 + 1e-5), (i, chosen, best)
+        checked += 1
+    assert checked > 50
