@@ -59,6 +59,23 @@ extern "C" {
 #define BVH_TRACE_CLOSEST 0 /* nearest hit, ties to the lowest primitive id */
 #define BVH_TRACE_ANY 1     /* any hit with t <= tmax (occlusion) */
 
+/* Topology builders (bvh_build_opts.builder).  LBVH: Morton codes of the
+ * primitive-box centres, radix sort, Karras hierarchy (fast).  SAH: top-down
+ * binary splits chosen by the surface area heuristic over 32 bins per axis
+ * (Sec. 9.2.1; slower to build, fewer nodes visited per query).  SAH rules:
+ * a node bins its primitives' centres c = 0.5 lo + 0.5 hi along each axis
+ * over their exact bounds [cl, ch] (axes with ch - cl not positive and finite
+ * are skipped; bin = min(31, trunc((c - cl) * (32 / (ch - cl)))), f32); the
+ * split after bin k costs A(L) N(L) + A(R) N(R), A = dx dy + dy dz + dz dx of
+ * a side's box, both sides non-empty; the cheapest wins, ties to the lower
+ * axis and then the lower k; partitions are stable (initial order: primitive
+ * id); coincident centres split at the index median floor(N/2).  Splitting
+ * continues to single primitives; leaves are the subtrees of at most
+ * leaf_size primitives (as with LBVH).  A tree deeper than the traversal
+ * stack bound fails with EUNSUPPORTED. */
+#define BVH_BUILDER_LBVH 0
+#define BVH_BUILDER_SAH 1
+
 /* Buffers readable with bvh_read_buffer. */
 #define BVH_BUF_NODES 0
 #define BVH_BUF_LEAF 1 /* COMPACT: bvh_tri[n_tris]; INDEXED: int32 prim id[n_tris] */
@@ -90,7 +107,8 @@ typedef struct bvh_build_opts {
                             32 for AABB2, 16 for the wide layouts).  A ray that needs more is
                             re-traced by a fallback pass with a deep stack in global memory.
                             Results do not depend on it. */
-    int32_t reserved[5]; /* must be zero */
+    int32_t builder;     /* BVH_BUILDER_LBVH (default) or BVH_BUILDER_SAH */
+    int32_t reserved[4]; /* must be zero */
 } bvh_build_opts;
 
 typedef struct bvh_stats {
@@ -106,7 +124,7 @@ typedef struct bvh_stats {
     int32_t max_stack;         /* worst-case traversal stack entries */
     float scene_lo[3], scene_hi[3];
     int32_t stack_lds;         /* LDS stack entries per ray of the trace kernels */
-    int32_t pad;
+    int32_t builder;           /* BVH_BUILDER_LBVH or BVH_BUILDER_SAH */
     /* PBRT_Q16 and SG_EQ: the scene frame of the quantised boxes (a lower
      * plane value is fmaf((float)q, frame_scale[a], frame_origin[a]); an
      * SG_EQ upper plane is fmaf(-(float)q, frame_scale[a], frame_top[a]));

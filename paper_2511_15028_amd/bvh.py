@@ -36,7 +36,8 @@ class BVHError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("leaf_mode", ctypes.c_int32),
-                ("stack_lds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("stack_lds", ctypes.c_int32), ("builder", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -48,7 +49,7 @@ class Stats(ctypes.Structure):
                 ("extra_bytes", ctypes.c_int64), ("depth", ctypes.c_int32),
                 ("max_stack", ctypes.c_int32), ("scene_lo", ctypes.c_float * 3),
                 ("scene_hi", ctypes.c_float * 3), ("stack_lds", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("frame_origin", ctypes.c_float * 3),
+                ("builder", ctypes.c_int32), ("frame_origin", ctypes.c_float * 3),
                 ("frame_scale", ctypes.c_float * 3), ("frame_top", ctypes.c_float * 3),
                 ("pad2", ctypes.c_int32)]
 
@@ -236,14 +237,19 @@ class BVH:
         return out, counts
 
 
+BUILDERS = {"lbvh": 0, "sah": 1}
+
+
 def build(verts: torch.Tensor, tris: torch.Tensor, layout="bvh8_q8", leaf_size: int = 4,
-          leaf_mode="compact", stream=None, stack_lds: int = 0) -> BVH:
-    """verts [V,3] float32 device, tris [N,3] int32 device."""
+          leaf_mode="compact", stream=None, stack_lds: int = 0, builder="lbvh") -> BVH:
+    """verts [V,3] float32 device, tris [N,3] int32 device; builder "lbvh"
+    (Morton order, Karras hierarchy) or "sah" (binned SAH, 32 bins)."""
     _dev(verts, torch.float32, 3, "verts")
     _dev(tris, torch.int32, 3, "tris")
     lm = LEAF_MODES[leaf_mode] if isinstance(leaf_mode, str) else int(leaf_mode)
     lid = _layout_id(layout)
-    opts = BuildOpts(leaf_size, lm, stack_lds)
+    bid = BUILDERS[builder] if isinstance(builder, str) else int(builder)
+    opts = BuildOpts(leaf_size, lm, stack_lds, bid)
     h = _P()
     _check(lib().bvh_build(verts.data_ptr(), verts.shape[0], tris.data_ptr(), tris.shape[0], lid,
                            ctypes.byref(opts), _stream(stream), ctypes.byref(h)))

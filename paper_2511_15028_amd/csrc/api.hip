@@ -77,6 +77,7 @@ extern "C" int32_t bvh_get_stats(bvh_handle_t h, bvh_stats *out) {
         out->scene_hi[a] = h->scene_hi[a];
     }
     out->stack_lds = h->stack_lds;
+    out->builder = h->builder;
     for (int a = 0; a < 3; a++) {
         out->frame_origin[a] = h->frame_origin[a];
         out->frame_scale[a] = h->frame_scale[a];

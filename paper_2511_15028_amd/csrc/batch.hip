@@ -375,7 +375,7 @@ int32_t create_impl(const bvh_scene_desc *scenes, int32_t n_scenes, const bvh_tu
         for (int layout : (choose ? layouts : std::vector<int>{layouts[0]})) {
             bvh_handle_s *h = nullptr;
             rc = build_handle(sd.verts, sd.n_verts, sd.tris, sd.n_tris, layout, leaf_size,
-                              BVH_LEAF_COMPACT, sl0, s, &h);
+                              BVH_LEAF_COMPACT, sl0, BVH_BUILDER_LBVH, s, &h);
             if (rc != BVH_OK) break;
             if (!choose) {
                 best = h;

@@ -1211,6 +1211,657 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
     return BVH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// a4 alternative: binned-SAH topology (32 bins per axis; Sec. 9.2.1).  Top
+// down: a node bins its primitives' centroids along each axis over their
+// exact bounds, takes the cheapest split A(L) N(L) + A(R) N(R) (A = half
+// the surface area of a side's union box; ties to the lower axis, then the
+// lower split), and partitions stably; coincident centroids split at the
+// index median.  Splitting goes down to single primitives, and the result
+// is the same tree view the Karras hierarchy produces (internal nodes
+// 0 .. n-2, primitive at leaf position k is node n-1+k, ranges of the
+// permutation), so boxes, collapse and packing follow unchanged.
+//
+// Internal node ids: a node whose split falls between leaf positions m-1
+// and m gets id m-1 (unique), except that the root takes id 0 and the node
+// with natural id 0 takes the root's natural id.
+//
+// Large nodes (more than kSahSmall primitives) are processed level by level
+// with many blocks each: centroid bounds, binning into per-node global bins,
+// one wave per node for the sweep, then a stable partition by one global
+// scan.  Nodes of at most kSahSmall primitives are finished by one wave
+// each with the primitives held in the lanes.
+// ---------------------------------------------------------------------------
+constexpr int kSahBins = 32;
+constexpr uint32_t kSahSmall = 64;
+constexpr uint32_t kSahChunk = 2048;
+constexpr int kSahMaxLevels = kStackMax + 1;
+constexpr uint32_t kSahBinWords = 3 * kSahBins * 7;  // per node: count + ordered box per bin
+
+struct SahTask {
+    uint32_t first, count;
+    int32_t parent;  // id of the parent (-1: root)
+    uint32_t side;   // 0: left child of the parent, 1: right
+};
+
+struct SahSplit {
+    int32_t axis;  // split axis (0 for an index-median split)
+    int32_t k;     // last bin of the left side (-1: index median)
+    uint32_t nl;   // primitives on the left
+    uint32_t id;   // the node's id
+};
+
+// Floats as order-preserving ints, so min/max can use integer atomics.
+__device__ inline int f2o(float f) {
+    const int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__device__ inline float o2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
+
+__device__ inline float sah_centroid(const Box &b, int a) {
+    const float lo = a == 0 ? b.lo.x : (a == 1 ? b.lo.y : b.lo.z);
+    const float hi = a == 0 ? b.hi.x : (a == 1 ? b.hi.y : b.hi.z);
+    return 0.5f * lo + 0.5f * hi;
+}
+
+// Binning frame of one axis: valid when the centroid extent is positive and
+// finite; then bin(c) = min(31, trunc((c - lo) * scale)), scale = 32 / ext.
+struct SahFrame {
+    float lo[3], scale[3];
+    bool valid[3];
+};
+
+__device__ inline SahFrame sah_frame(const float *cl, const float *ch) {
+    SahFrame f;
+    for (int a = 0; a < 3; a++) {
+        const float ext = ch[a] - cl[a];
+        f.valid[a] = ext > 0.0f && !isinf(ext);
+        f.lo[a] = cl[a];
+        f.scale[a] = f.valid[a] ? __fdiv_rn((float)kSahBins, ext) : 0.0f;
+    }
+    return f;
+}
+
+__device__ inline int sah_bin(const SahFrame &f, int a, float c) {
+    const int b = (int)((c - f.lo[a]) * f.scale[a]);  // c >= lo: b >= 0 for finite input
+    return b < 0 ? 0 : (b < kSahBins - 1 ? b : kSahBins - 1);
+}
+
+__device__ inline float half_area3(float lx, float ly, float lz, float hx, float hy, float hz) {
+    const float dx = hx - lx, dy = hy - ly, dz = hz - lz;
+    return (dx * dy + dy * dz) + dz * dx;
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Cheapest split of one axis from its 32 bins (lane k of the wave holds bin
+// k: count and box as floats; empty bins hold an empty box).  Returns, in
+// every lane, the minimal cost and its split k (the lowest k on ties), or
+// +inf when no split leaves both sides non-empty.
+__device__ inline void sah_sweep(uint32_t cnt, float lx, float ly, float lz, float hx, float hy,
+                                 float hz, float &best_cost, int &best_k, uint32_t &best_nl) {
+    const int lane = threadIdx.x & (kWave - 1);
+    // inclusive prefix over lanes 0..k and suffix over lanes k..31
+    uint32_t pc = cnt, sc = cnt;
+    float p[6] = {lx, ly, lz, hx, hy, hz}, q[6] = {lx, ly, lz, hx, hy, hz};
+#pragma unroll
+    for (int o = 1; o < kSahBins; o <<= 1) {
+        const uint32_t tc = __shfl_up(pc, o, kWave);
+        const uint32_t uc = __shfl_down(sc, o, kWave);
+        float tp[6], tq[6];
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            tp[j] = __shfl_up(p[j], o, kWave);
+            tq[j] = __shfl_down(q[j], o, kWave);
+        }
+        if (lane >= o) {
+            pc += tc;
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                p[j] = fminf(p[j], tp[j]);
+                p[3 + j] = fmaxf(p[3 + j], tp[3 + j]);
+            }
+        }
+        if (lane + o < kSahBins) {
+            sc += uc;
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                q[j] = fminf(q[j], tq[j]);
+                q[3 + j] = fmaxf(q[3 + j], tq[3 + j]);
+            }
+        }
+    }
+    // right side of split k is the suffix starting at bin k + 1
+    const uint32_t rc = __shfl_down(sc, 1, kWave);
+    float r[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) r[j] = __shfl_down(q[j], 1, kWave);
+    float cost = INFINITY;
+    if (lane < kSahBins - 1 && pc > 0 && rc > 0)
+        cost = half_area3(p[0], p[1], p[2], p[3], p[4], p[5]) * (float)pc +
+               half_area3(r[0], r[1], r[2], r[3], r[4], r[5]) * (float)rc;
+    // minimum over the lanes, lowest k on ties
+    float c = cost;
+    int k = lane < kSahBins - 1 ? lane : kSahBins;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float oc = __shfl_xor(c, o, kWave);
+        const int ok = __shfl_xor(k, o, kWave);
+        if (oc < c || (oc == c && ok < k)) {
+            c = oc;
+            k = ok;
+        }
+    }
+    best_cost = c;
+    best_k = c < INFINITY ? k : -1;
+    best_nl = __shfl(pc, best_k < 0 ? 0 : best_k, kWave);
+}
+
+// Id of the node that splits at leaf position m (m-1 naturally; see above).
+__device__ inline uint32_t sah_node_id(uint32_t m, bool is_root, uint32_t root_nat) {
+    if (is_root) return 0u;
+    const uint32_t nat = m - 1u;
+    return nat == 0u ? root_nat : nat;
+}
+
+struct SahTree {
+    int32_t *ileft, *iright, *parent;
+    uint32_t *ifirst, *icount;
+    uint8_t *iaxis;
+    int n;
+};
+
+// Records node id (range, axis, parent link) and links its leaf children.
+__device__ inline void sah_write_node(const SahTree &tr, uint32_t id, uint32_t first,
+                                      uint32_t count, int axis, uint32_t nl, int32_t parent,
+                                      uint32_t side) {
+    tr.ifirst[id] = first;
+    tr.icount[id] = count;
+    tr.iaxis[id] = (uint8_t)axis;
+    tr.parent[id] = parent;
+    if (parent >= 0) (side ? tr.iright : tr.ileft)[parent] = (int32_t)id;
+    if (nl == 1) {
+        const int32_t leaf = tr.n - 1 + (int32_t)first;
+        tr.ileft[id] = leaf;
+        tr.parent[leaf] = (int32_t)id;
+    }
+    if (count - nl == 1) {
+        const int32_t leaf = tr.n - 1 + (int32_t)(first + nl);
+        tr.iright[id] = leaf;
+        tr.parent[leaf] = (int32_t)id;
+    }
+}
+
+// Per-level state of the large-node phase (device).
+struct SahLevel {
+    const SahTask *task;      // this level's nodes
+    const uint32_t *chunk;    // per chunk: task index
+    const uint32_t *cstart;   // per chunk: first position
+    int *cb;                  // per task: centroid bounds (ordered ints, lo xyz, hi xyz)
+    int *bins;                // per task: kSahBinWords
+    SahSplit *split;          // per task
+    uint32_t ntask;
+};
+
+__global__ __launch_bounds__(kBlock) void k_sah_clear(int *cb, int *bins, uint32_t ntask) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int inf = f2o(INFINITY), ninf = f2o(-INFINITY);
+    if (i < (uint64_t)ntask * 6) cb[i] = (i % 6) < 3 ? inf : ninf;
+    if (i < (uint64_t)ntask * kSahBinWords) {
+        const uint32_t w = (uint32_t)(i % 7);
+        bins[i] = w == 0 ? 0 : (w <= 3 ? inf : ninf);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sah_bounds(SahLevel lv, const uint32_t *ord,
+                                                       const Box *pbox) {
+    __shared__ float red[6][kBlock / kWave];
+    const uint32_t t = lv.chunk[blockIdx.x];
+    const SahTask tk = lv.task[t];
+    const uint32_t p0 = lv.cstart[blockIdx.x], p1 = min(p0 + kSahChunk, tk.first + tk.count);
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
+        const Box b = pbox[ord[p]];
+        for (int a = 0; a < 3; a++) {
+            const float c = sah_centroid(b, a);
+            v[a] = fminf(v[a], c);
+            v[3 + a] = fmaxf(v[3 + a], c);
+        }
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int j = 0; j < 6; j++) {
+        const float r = j < 3 ? wave_min(v[j]) : wave_max(v[j]);
+        if (lane == 0) red[j][w] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int j = threadIdx.x;
+        float r = red[j][0];
+        for (int k = 1; k < kBlock / kWave; k++) r = j < 3 ? fminf(r, red[j][k]) : fmaxf(r, red[j][k]);
+        if (j < 3) atomicMin(&lv.cb[6 * t + j], f2o(r));
+        else atomicMax(&lv.cb[6 * t + j], f2o(r));
+    }
+}
+
+__device__ inline SahFrame sah_task_frame(const int *cb) {
+    float cl[3], ch[3];
+    for (int a = 0; a < 3; a++) {
+        cl[a] = o2f(cb[a]);
+        ch[a] = o2f(cb[3 + a]);
+    }
+    return sah_frame(cl, ch);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sah_bin(SahLevel lv, const uint32_t *ord,
+                                                    const Box *pbox) {
+    __shared__ int sb[kSahBinWords];
+    const uint32_t t = lv.chunk[blockIdx.x];
+    const SahTask tk = lv.task[t];
+    const uint32_t p0 = lv.cstart[blockIdx.x], p1 = min(p0 + kSahChunk, tk.first + tk.count);
+    const int inf = f2o(INFINITY), ninf = f2o(-INFINITY);
+    for (uint32_t i = threadIdx.x; i < kSahBinWords; i += kBlock) {
+        const uint32_t w = i % 7;
+        sb[i] = w == 0 ? 0 : (w <= 3 ? inf : ninf);
+    }
+    __syncthreads();
+    const SahFrame f = sah_task_frame(lv.cb + 6 * t);
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
+        const Box b = pbox[ord[p]];
+        for (int a = 0; a < 3; a++) {
+            if (!f.valid[a]) continue;
+            int *bin = sb + (a * kSahBins + sah_bin(f, a, sah_centroid(b, a))) * 7;
+            atomicAdd(bin, 1);
+            atomicMin(bin + 1, f2o(b.lo.x));
+            atomicMin(bin + 2, f2o(b.lo.y));
+            atomicMin(bin + 3, f2o(b.lo.z));
+            atomicMax(bin + 4, f2o(b.hi.x));
+            atomicMax(bin + 5, f2o(b.hi.y));
+            atomicMax(bin + 6, f2o(b.hi.z));
+        }
+    }
+    __syncthreads();
+    int *gb = lv.bins + (size_t)t * kSahBinWords;
+    for (uint32_t i = threadIdx.x; i < kSahBinWords; i += kBlock) {
+        const uint32_t w = i % 7;
+        const int v = sb[i];
+        if (sb[i - w] == 0) continue;  // empty bin
+        if (w == 0) atomicAdd(gb + i, v);
+        else if (w <= 3) atomicMin(gb + i, v);
+        else atomicMax(gb + i, v);
+    }
+}
+
+// One wave per node: the sweep over the three axes, then the node's id and
+// record, and its children: single primitives are linked here, small ones
+// queued for the per-wave finisher, large ones queued (with their chunks)
+// for the next level.
+__global__ __launch_bounds__(kBlock) void k_sah_split(SahLevel lv, SahTree tr, uint32_t *root_nat,
+                                                      bool root_level, SahTask *next,
+                                                      uint32_t *next_chunk, uint32_t *next_cstart,
+                                                      uint32_t *counters, SahTask *small,
+                                                      uint32_t *small_count) {
+    const uint32_t t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (t >= lv.ntask) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const SahTask tk = lv.task[t];
+    const int *gb = lv.bins + (size_t)t * kSahBinWords;
+    const SahFrame f = sah_task_frame(lv.cb + 6 * t);
+    float best = INFINITY;
+    int axis = -1, bk = -1;
+    uint32_t nl = 0;
+    for (int a = 0; a < 3; a++) {
+        if (!f.valid[a]) continue;
+        const int *bin = gb + (a * kSahBins + (lane < kSahBins ? lane : 0)) * 7;
+        const bool in = lane < kSahBins;
+        const uint32_t c = in ? (uint32_t)bin[0] : 0u;
+        float cost;
+        int k;
+        uint32_t l;
+        sah_sweep(c, in ? o2f(bin[1]) : INFINITY, in ? o2f(bin[2]) : INFINITY,
+                  in ? o2f(bin[3]) : INFINITY, in ? o2f(bin[4]) : -INFINITY,
+                  in ? o2f(bin[5]) : -INFINITY, in ? o2f(bin[6]) : -INFINITY, cost, k, l);
+        if (cost < best) {
+            best = cost;
+            axis = a;
+            bk = k;
+            nl = l;
+        }
+    }
+    if (axis < 0) {
+        axis = 0;
+        bk = -1;
+        nl = tk.count / 2;
+    }
+    const uint32_t m = tk.first + nl;
+    if (root_level && lane == 0) *root_nat = m - 1;
+    const uint32_t rn = root_level ? m - 1 : *root_nat;
+    const uint32_t id = sah_node_id(m, tk.parent < 0, rn);
+    if (lane == 0) {
+        lv.split[t] = SahSplit{axis, bk, nl, id};
+        sah_write_node(tr, id, tk.first, tk.count, axis, nl, tk.parent, tk.side);
+        const uint32_t cf[2] = {tk.first, m}, cc[2] = {nl, tk.count - nl};
+        for (int s = 0; s < 2; s++) {
+            if (cc[s] < 2) continue;
+            const SahTask ch{cf[s], cc[s], (int32_t)id, (uint32_t)s};
+            if (cc[s] <= kSahSmall) {
+                small[atomicAdd(small_count, 1u)] = ch;
+            } else {
+                const uint32_t slot = atomicAdd(&counters[0], 1u);
+                next[slot] = ch;
+                const uint32_t nch = (cc[s] + kSahChunk - 1) / kSahChunk;
+                const uint32_t c0 = atomicAdd(&counters[1], nch);
+                for (uint32_t j = 0; j < nch; j++) {
+                    next_chunk[c0 + j] = slot;
+                    next_cstart[c0 + j] = cf[s] + j * kSahChunk;
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sah_flags(SahLevel lv, const uint32_t *ord,
+                                                      const Box *pbox, uint32_t *flags) {
+    const uint32_t t = lv.chunk[blockIdx.x];
+    const SahTask tk = lv.task[t];
+    const SahSplit sp = lv.split[t];
+    const uint32_t p0 = lv.cstart[blockIdx.x], p1 = min(p0 + kSahChunk, tk.first + tk.count);
+    const SahFrame f = sah_task_frame(lv.cb + 6 * t);
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
+        bool left;
+        if (sp.k < 0) left = p - tk.first < sp.nl;
+        else left = sah_bin(f, sp.axis, sah_centroid(pbox[ord[p]], sp.axis)) <= sp.k;
+        flags[p] = left ? 1u : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sah_scatter(SahLevel lv, const uint32_t *ord,
+                                                        const uint32_t *flags, const uint32_t *offs,
+                                                        uint32_t *ord_next, uint32_t *perm,
+                                                        uint32_t *err) {
+    const uint32_t t = lv.chunk[blockIdx.x];
+    const SahTask tk = lv.task[t];
+    const SahSplit sp = lv.split[t];
+    const uint32_t p0 = lv.cstart[blockIdx.x], p1 = min(p0 + kSahChunk, tk.first + tk.count);
+    const uint32_t base = offs[tk.first];
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
+        const uint32_t lrank = offs[p] - base;
+        const bool left = flags[p] != 0u;
+        const uint32_t dst = left ? tk.first + lrank : tk.first + sp.nl + (p - tk.first - lrank);
+        if (dst >= tk.first + tk.count || (left ? lrank >= sp.nl : false)) {
+            atomicOr(err, 1u);  // the flags disagree with the split's count
+            continue;
+        }
+        const uint32_t prim = ord[p];
+        ord_next[dst] = prim;
+        const uint32_t child = left ? sp.nl : tk.count - sp.nl;
+        if (child <= kSahSmall) perm[dst] = prim;
+    }
+}
+
+// Finishes nodes of at most kSahSmall primitives, one wave each, with the
+// primitives in the lanes (lane i holds position first + i of the node's
+// current order).  Subtrees are split in turn from a per-wave stack.
+__global__ __launch_bounds__(kBlock) void k_sah_small(const SahTask *small, uint32_t nsmall,
+                                                      const Box *pbox, uint32_t *perm, SahTree tr,
+                                                      const uint32_t *root_nat_p, uint32_t *err) {
+    constexpr int W = kBlock / kWave;
+    __shared__ int sbins[W][kSahBinWords];
+    __shared__ uint32_t sstack[W][kSahSmall][4];
+    __shared__ float sx[W][kSahSmall][7];  // exchange: prim id bits, box
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const uint32_t t = blockIdx.x * W + w;
+    if (t >= nsmall) return;
+    const SahTask tk = small[t];
+    const bool root_task = tk.parent < 0;
+    uint32_t root_nat = root_task ? 0u : *root_nat_p;
+    uint32_t prim = 0;
+    Box b;
+    b.lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    b.hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    if ((uint32_t)lane < tk.count) {
+        prim = perm[tk.first + lane];
+        b = pbox[prim];
+    }
+    int *bins = sbins[w];
+    uint32_t sp = 0;
+    sstack[w][0][0] = 0;
+    sstack[w][0][1] = tk.count;
+    sstack[w][0][2] = (uint32_t)tk.parent;
+    sstack[w][0][3] = tk.side;
+    sp = 1;
+    wave_sync();
+    while (sp > 0) {
+        sp--;
+        const uint32_t sf = sstack[w][sp][0], sc = sstack[w][sp][1];
+        const int32_t par = (int32_t)sstack[w][sp][2];
+        const uint32_t sd = sstack[w][sp][3];
+        wave_sync();
+        const bool act = (uint32_t)lane >= sf && (uint32_t)lane < sf + sc;
+        float cl[3], ch[3], c[3];
+        for (int a = 0; a < 3; a++) {
+            c[a] = sah_centroid(b, a);
+            cl[a] = wave_min(act ? c[a] : INFINITY);
+            ch[a] = wave_max(act ? c[a] : -INFINITY);
+        }
+        const SahFrame f = sah_frame(cl, ch);
+        float best = INFINITY;
+        int axis = -1, bk = -1;
+        uint32_t nl = 0;
+        for (int a = 0; a < 3; a++) {
+            if (!f.valid[a]) continue;
+            const int inf = f2o(INFINITY), ninf = f2o(-INFINITY);
+            if (lane < kSahBins) {
+                int *bin = bins + lane * 7;
+                bin[0] = 0;
+                bin[1] = bin[2] = bin[3] = inf;
+                bin[4] = bin[5] = bin[6] = ninf;
+            }
+            wave_sync();
+            if (act) {
+                int *bin = bins + sah_bin(f, a, c[a]) * 7;
+                atomicAdd(bin, 1);
+                atomicMin(bin + 1, f2o(b.lo.x));
+                atomicMin(bin + 2, f2o(b.lo.y));
+                atomicMin(bin + 3, f2o(b.lo.z));
+                atomicMax(bin + 4, f2o(b.hi.x));
+                atomicMax(bin + 5, f2o(b.hi.y));
+                atomicMax(bin + 6, f2o(b.hi.z));
+            }
+            wave_sync();
+            const bool in = lane < kSahBins;
+            const int *bin = bins + (in ? lane : 0) * 7;
+            float cost;
+            int k;
+            uint32_t l;
+            sah_sweep(in ? (uint32_t)bin[0] : 0u, in ? o2f(bin[1]) : INFINITY,
+                      in ? o2f(bin[2]) : INFINITY, in ? o2f(bin[3]) : INFINITY,
+                      in ? o2f(bin[4]) : -INFINITY, in ? o2f(bin[5]) : -INFINITY,
+                      in ? o2f(bin[6]) : -INFINITY, cost, k, l);
+            wave_sync();
+            if (cost < best) {
+                best = cost;
+                axis = a;
+                bk = k;
+                nl = l;
+            }
+        }
+        bool left;
+        if (axis < 0) {
+            axis = 0;
+            nl = sc / 2;
+            left = (uint32_t)lane - sf < nl;
+        } else {
+            left = sah_bin(f, axis, c[axis]) <= bk;
+        }
+        const uint32_t m = tk.first + sf + nl;
+        const bool is_root = root_task && par < 0;
+        if (is_root) root_nat = m - 1;
+        const uint32_t id = sah_node_id(m, is_root, root_nat);
+        if (lane == 0) sah_write_node(tr, id, tk.first + sf, sc, axis, nl, par, sd);
+        // stable partition of the active lanes
+        const uint64_t lmask = __builtin_amdgcn_ballot_w64(act && left);
+        const uint64_t rmask = __builtin_amdgcn_ballot_w64(act && !left);
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if ((uint32_t)__builtin_popcountll(lmask) != nl) {
+            if (lane == 0) atomicOr(err, 1u);  // the lanes disagree with the split's count
+            break;
+        }
+        if (act) {
+            const uint32_t dst = left ? sf + (uint32_t)__builtin_popcountll(lmask & below)
+                                      : sf + nl + (uint32_t)__builtin_popcountll(rmask & below);
+            float *x = sx[w][dst];
+            x[0] = __uint_as_float(prim);
+            x[1] = b.lo.x; x[2] = b.lo.y; x[3] = b.lo.z;
+            x[4] = b.hi.x; x[5] = b.hi.y; x[6] = b.hi.z;
+        }
+        wave_sync();
+        if (act) {
+            const float *x = sx[w][lane];
+            prim = __float_as_uint(x[0]);
+            b.lo = make_float4(x[1], x[2], x[3], 0.0f);
+            b.hi = make_float4(x[4], x[5], x[6], 0.0f);
+        }
+        wave_sync();
+        // children of two or more primitives go on the stack
+        if (lane == 0) {
+            if (sc - nl >= 2) {
+                sstack[w][sp][0] = sf + nl;
+                sstack[w][sp][1] = sc - nl;
+                sstack[w][sp][2] = id;
+                sstack[w][sp][3] = 1;
+                sp++;
+            }
+            if (nl >= 2) {
+                sstack[w][sp][0] = sf;
+                sstack[w][sp][1] = nl;
+                sstack[w][sp][2] = id;
+                sstack[w][sp][3] = 0;
+                sp++;
+            }
+        }
+        sp = (uint32_t)__shfl(sp, 0, kWave);
+        wave_sync();
+    }
+    if ((uint32_t)lane < tk.count) perm[tk.first + lane] = prim;
+}
+
+__global__ void k_sah_init(uint32_t *ord, uint32_t *perm, uint32_t n, SahTask *task,
+                           uint32_t *chunk, uint32_t *cstart, SahTask *small, uint32_t *nsmall) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        ord[i] = i;
+        perm[i] = i;
+    }
+    if (i == 0) {
+        const SahTask root{0u, n, -1, 0u};
+        if (n > kSahSmall) {
+            task[0] = root;
+        } else {
+            small[0] = root;
+            *nsmall = 1;
+        }
+    }
+    const uint32_t nch = (n + kSahChunk - 1) / kSahChunk;
+    if (n > kSahSmall && i < nch) {
+        chunk[i] = 0;
+        cstart[i] = i * kSahChunk;
+    }
+}
+
+__global__ void k_sah_publish(const uint32_t *src, uint32_t *dst, int k) {
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < k; i++) dst[i] = src[i];
+        __threadfence_system();
+    }
+}
+
+// Host side of the binned-SAH topology: fills perm and the tree arrays.
+int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, uint32_t *tile,
+                     hipStream_t s) {
+    if (n < 2) {
+        if (n == 1) BVH_HIP_TRY(hipMemsetAsync(perm, 0, sizeof(uint32_t), s));
+        return BVH_OK;
+    }
+    const uint32_t cap_task = n / (kSahSmall + 1) + 1;
+    const uint32_t cap_chunk = (n + kSahChunk - 1) / kSahChunk + cap_task;
+    uint32_t *ord[2], *flags, *offs, *chunk[2], *cstart[2], *counters, *small_count, *root_nat;
+    SahTask *task[2], *small;
+    SahSplit *split;
+    int *cb, *bins;
+    Arena ar;
+    ar.request(&ord[0], n);
+    ar.request(&ord[1], n);
+    ar.request(&flags, n);
+    ar.request(&offs, n);
+    ar.request(&task[0], cap_task);
+    ar.request(&task[1], cap_task);
+    ar.request(&chunk[0], cap_chunk);
+    ar.request(&chunk[1], cap_chunk);
+    ar.request(&cstart[0], cap_chunk);
+    ar.request(&cstart[1], cap_chunk);
+    ar.request(&split, cap_task);
+    ar.request(&cb, (size_t)cap_task * 6);
+    ar.request(&bins, (size_t)cap_task * kSahBinWords);
+    ar.request(&small, n / 2 + 1);
+    ar.request(&counters, 2 * kSahMaxLevels + 4);
+    BVH_TRY(ar.bind(s, kAreaSah));
+    small_count = counters + 2 * kSahMaxLevels;
+    root_nat = small_count + 1;
+    uint32_t *err = small_count + 2;
+    BVH_HIP_TRY(hipMemsetAsync(counters, 0, (2 * kSahMaxLevels + 4) * sizeof(uint32_t), s));
+    BVH_HIP_TRY(hipMemsetAsync(flags, 0, (size_t)n * sizeof(uint32_t), s));
+    k_sah_init<<<grid_for(n), kBlock, 0, s>>>(ord[0], perm, n, task[0], chunk[0], cstart[0], small,
+                                              small_count);
+    BVH_TRY(check_launch("sah init"));
+    uint32_t *hw = host_words();
+    if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
+    volatile uint32_t *vw = hw + 8;
+    uint32_t ntask = n > kSahSmall ? 1u : 0u;
+    uint32_t nchunk = (n + kSahChunk - 1) / kSahChunk;
+    int cur = 0;
+    for (int level = 0; ntask > 0; level++) {
+        if (level >= kSahMaxLevels)
+            return set_error(BVH_EUNSUPPORTED,
+                             "bvh_build: SAH tree deeper than the traversal stack bound %d", kStackMax);
+        SahLevel lv{task[cur], chunk[cur], cstart[cur], cb, bins, split, ntask};
+        k_sah_clear<<<grid_for((uint64_t)ntask * kSahBinWords), kBlock, 0, s>>>(cb, bins, ntask);
+        k_sah_bounds<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], pbox);
+        k_sah_bin<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], pbox);
+        k_sah_split<<<(ntask + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(
+            lv, tr, root_nat, level == 0, task[cur ^ 1], chunk[cur ^ 1], cstart[cur ^ 1],
+            counters + 2 * level, small, small_count);
+        k_sah_flags<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], pbox, flags);
+        scan_u32(flags, offs, n, tile, nullptr, s);
+        k_sah_scatter<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], flags, offs, ord[cur ^ 1], perm, err);
+        vw[0] = vw[1] = kPending;
+        k_sah_publish<<<1, 64, 0, s>>>(counters + 2 * level, hw + 8, 2);
+        BVH_TRY(check_launch("sah level"));
+        BVH_TRY(wait_host_word(vw, s, &ntask));
+        BVH_TRY(wait_host_word(vw + 1, s, &nchunk));
+        if (ntask > cap_task || nchunk > cap_chunk)
+            return set_error(BVH_EHIP, "bvh_build: internal error (SAH task overflow)");
+        cur ^= 1;
+    }
+    vw[2] = kPending;
+    k_sah_publish<<<1, 64, 0, s>>>(small_count, hw + 10, 1);
+    uint32_t nsmall = 0;
+    BVH_TRY(wait_host_word(vw + 2, s, &nsmall));
+    if (nsmall > n / 2 + 1) return set_error(BVH_EHIP, "bvh_build: internal error (SAH small overflow)");
+    if (nsmall > 0)
+        k_sah_small<<<(nsmall + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(
+            small, nsmall, pbox, perm, tr, root_nat, err);
+    vw[3] = kPending;
+    k_sah_publish<<<1, 64, 0, s>>>(err, hw + 11, 1);
+    BVH_TRY(check_launch("sah small nodes"));
+    uint32_t bad = 0;
+    BVH_TRY(wait_host_word(vw + 3, s, &bad));
+    if (bad) return set_error(BVH_EHIP, "bvh_build: internal error (SAH partition)");
+    return BVH_OK;
+}
+
 int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                    bvh_handle_s *h, hipStream_t s) {
     const int n = (int)n_tris;
@@ -1263,25 +1914,34 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // a1, a2
     k_prim_bounds<<<nb, kBlock, 0, s>>>(verts, n_verts, tris, n, pbox, partial, info);
     k_bounds_final<<<1, kBlock, 0, s>>>(partial, nb, info);
-    const int mbits = morton_bits(n);
-    k_morton<<<nb, kBlock, 0, s>>>(pbox, n, info, mbits, keys[0], vals[0]);
-    BVH_TRY(check_launch("bounds/morton"));
-    // a3: 8 passes of 8 bits
-    int cur = 0;
-    for (int shift = 0; shift < 3 * mbits; shift += 8) {
-        k_radix_hist<<<nsort, kBlock, 0, s>>>(keys[cur], n, shift, hist, nsort);
-        scan_u32(hist, hist, nhist, tile, nullptr, s);
-        k_radix_scatter<<<nsort, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1],
-                                                 n, shift, hist, nsort);
-        cur ^= 1;
+    const uint32_t *perm = nullptr;
+    if (h->builder == BVH_BUILDER_SAH) {
+        // a4 alternative: binned-SAH topology over the primitive boxes
+        BVH_TRY(check_launch("bounds"));
+        SahTree tr{ileft, iright, parent, ifirst, icount, iaxis, n};
+        BVH_TRY(sah_topology(pbox, (uint32_t)n, vals[0], tr, tile, s));
+        perm = vals[0];
+    } else {
+        const int mbits = morton_bits(n);
+        k_morton<<<nb, kBlock, 0, s>>>(pbox, n, info, mbits, keys[0], vals[0]);
+        BVH_TRY(check_launch("bounds/morton"));
+        // a3: 8 passes of 8 bits
+        int cur = 0;
+        for (int shift = 0; shift < 3 * mbits; shift += 8) {
+            k_radix_hist<<<nsort, kBlock, 0, s>>>(keys[cur], n, shift, hist, nsort);
+            scan_u32(hist, hist, nhist, tile, nullptr, s);
+            k_radix_scatter<<<nsort, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1],
+                                                     vals[cur ^ 1], n, shift, hist, nsort);
+            cur ^= 1;
+        }
+        BVH_TRY(check_launch("radix sort"));
+        perm = vals[cur];
+        // a4
+        if (n > 1)
+            k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
+                                                        iaxis, parent);
     }
-    BVH_TRY(check_launch("radix sort"));
-    const uint32_t *perm = vals[cur];
-    // a4, a5
-    if (n > 1)
-        k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
-                                                    iaxis, parent);
-    {
+    {  // a5
         k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table, pre, suf);
         for (int k = 1; k < levels; k++) {
             const int half = 1 << (k - 1);
@@ -1384,7 +2044,7 @@ namespace bvhlib {
 
 int32_t build_handle(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                      int32_t layout, int32_t leaf_size, int32_t leaf_mode, int32_t stack_lds,
-                     hipStream_t s, bvh_handle_s **out) {
+                     int32_t builder, hipStream_t s, bvh_handle_s **out) {
     *out = nullptr;
     BVH_TRY(require_device());
     int dev = 0;
@@ -1395,6 +2055,7 @@ int32_t build_handle(const float *verts, int64_t n_verts, const int32_t *tris, i
     h->leaf_mode = leaf_mode;
     h->leaf_size = leaf_size;
     h->stack_lds = stack_lds;
+    h->builder = builder;
     h->arity = layout_arity(layout);
     h->n_tris = n_tris;
     h->n_verts = n_verts;
@@ -1429,13 +2090,17 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
     // 4 B); wide trees push up to arity-1 entries of 8 B (16 entries)
     int32_t leaf_size = 4, leaf_mode = BVH_LEAF_COMPACT;
     int32_t stack_lds = layout_arity(layout) == 2 ? 32 : 16;
+    int32_t builder = BVH_BUILDER_LBVH;
     if (opts) {
-        for (int k = 0; k < 5; k++)
+        for (int k = 0; k < 4; k++)
             if (opts->reserved[k] != 0) return set_error(BVH_EINVAL, "bvh_build: reserved option set");
         if (opts->leaf_size != 0) leaf_size = opts->leaf_size;
         if (opts->leaf_mode != 0) leaf_mode = opts->leaf_mode;
         if (opts->stack_lds != 0) stack_lds = opts->stack_lds;
+        builder = opts->builder;
     }
+    if (builder != BVH_BUILDER_LBVH && builder != BVH_BUILDER_SAH)
+        return set_error(BVH_EINVAL, "bvh_build: unknown builder %d", builder);
     const int32_t max_leaf =  // the scene-frame binary layouts store a u4 count
         (layout == BVH_LAYOUT_PBRT_Q16 || layout == BVH_LAYOUT_SG_EQ) ? 15 : kMaxLeafSize;
     if (leaf_size < 1 || leaf_size > max_leaf)
@@ -1448,5 +2113,5 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
         return set_error(BVH_EUNSUPPORTED, "bvh_build: %lld triangles exceed %lld",
                          (long long)n_tris, (long long)kMaxTris);
     return build_handle(verts, n_verts, tris, n_tris, layout, leaf_size, leaf_mode, stack_lds,
-                        static_cast<hipStream_t>(stream), out);
+                        builder, static_cast<hipStream_t>(stream), out);
 }

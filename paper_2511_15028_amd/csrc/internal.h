@@ -60,6 +60,7 @@ struct bvh_handle_s {
     int32_t leaf_mode = 0;
     int32_t leaf_size = 4;
     int32_t stack_lds = 16;
+    int32_t builder = BVH_BUILDER_LBVH;
     int32_t arity = 2;
     int64_t n_tris = 0;
     int64_t n_verts = 0;
@@ -124,7 +125,7 @@ int32_t check_handle_device(const bvh_handle_s *h, const char *who);
 // Builds one BVH (bvh_build after argument checks); used by the batch path.
 int32_t build_handle(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                      int32_t layout, int32_t leaf_size, int32_t leaf_mode, int32_t stack_lds,
-                     hipStream_t s, bvh_handle_s **out);
+                     int32_t builder, hipStream_t s, bvh_handle_s **out);
 
 // bvh_trace without argument checks (closest or any hit, no counters).
 int32_t trace_launch(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits,
@@ -135,7 +136,7 @@ int32_t trace_launch(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh
 // purpose), kept until the process ends.  Callers that use one stream from
 // several host threads must serialise those calls themselves.
 // ---------------------------------------------------------------------------
-enum AreaPurpose { kAreaBuild = 0, kAreaBuildWide = 1, kAreaTrace = 2, kAreaTune = 3 };
+enum AreaPurpose { kAreaBuild = 0, kAreaBuildWide = 1, kAreaTrace = 2, kAreaTune = 3, kAreaSah = 4 };
 int32_t stream_workspace(hipStream_t s, int purpose, size_t bytes, void **out);
 
 // Carves several device buffers out of one work area: request() them all,
