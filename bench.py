@@ -223,6 +223,7 @@ def main():
 
     if not args.no_extras:
         out["per_layout"] = per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
+        out["sah"] = sah_rows(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
         out["closest_point"] = {"terrain": closest_point_rows(torch, bvh, W, w["verts"], verts,
                                                               w["tris"], tris, args, 1001)}
         out["fwd_bwd"] = fwd_bwd(torch, bvh, W)
@@ -319,8 +320,9 @@ def closest_point_rows(torch, bvh, W, verts_np, verts, tris_np, tris, args, seed
     q_np = W.box_points(1 << 20, lo, hi, seed)
     q = torch.from_numpy(q_np).to(verts.device)
     res = {"queries": int(q.shape[0])}
-    for layout in LAYOUTS:
-        h = bvh.build(verts, tris, layout, args.leaf_size, "compact")
+    for layout, builder in [(x, "lbvh") for x in LAYOUTS] + [("aabb2", "sah"), ("bvh4", "sah")]:
+        key = layout if builder == "lbvh" else f"{layout}/sah"
+        h = bvh.build(verts, tris, layout, args.leaf_size, "compact", builder=builder)
         st = h.stats()
         t_ms = time_closest(torch, h, q)
         _, c = h.closest_point_counts(q)
@@ -328,13 +330,13 @@ def closest_point_rows(torch, bvh, W, verts_np, verts, tris_np, tris, args, seed
         c = c.cpu().numpy().astype(np.float64)
         by = QUERY_BYTES + CLOSEST_BYTES + c[:, 0] * st["node_bytes"] + c[:, 1] * LEAF_TRI_BYTES["compact"]
         gbs = by.sum() / (t_ms / 1000.0) / 1e9
-        res[layout] = {"mqueries_s": round(q.shape[0] / (t_ms / 1000.0) / 1e6, 1),
+        res[key] = {"mqueries_s": round(q.shape[0] / (t_ms / 1000.0) / 1e6, 1),
                        "ms": round(t_ms, 4), "nodes_per_query": round(float(c[:, 0].mean()), 1),
                        "tris_per_query": round(float(c[:, 1].mean()), 1),
                        "bytes_per_query": round(float(by.mean()), 1),
                        "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
         h.close()
-        log(f"closest point {layout}: {res[layout]}")
+        log(f"closest point {key}: {res[key]}")
     if not args.no_cpu_baseline:
         b = oracle.OracleBVH(verts_np, tris_np)
         sample = q_np[: 1 << 17]
@@ -345,6 +347,40 @@ def closest_point_rows(torch, bvh, W, verts_np, verts, tris_np, tris, args, seed
                              "cores": oracle.max_threads(),
                              "sample": f"first {len(sample)} queries, FP64 median-split BVH search "
                                        f"({secs:.2f} s wall)"}
+    return res
+
+
+def timed_build(torch, bvh, verts, tris, layout, leaf_size, builder, reps=3):
+    """Median wall time (ms) of bvh_build, the stream drained before and after."""
+    ms = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = bvh.build(verts, tris, layout, leaf_size, "compact", builder=builder)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1000.0)
+        h.close()
+    return float(np.median(ms))
+
+
+def sah_rows(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
+    """Terrain: binned-SAH topology (32 bins) against LBVH per layout: build
+    time (median of 3 builds, wall clock) and the trace rows (camera and
+    bounce Mrays/s, algorithmic bytes per ray, roofline fraction)."""
+    res = {}
+    for layout in ("aabb2", "bvh4", "bvh8_q8", "pbrt_q16"):
+        row = {}
+        for builder in ("lbvh", "sah"):
+            build_ms = timed_build(torch, bvh, verts, tris, layout, args.leaf_size, builder)
+            h = bvh.build(verts, tris, layout, args.leaf_size, "compact", builder=builder)
+            r = layout_row(torch, h, "compact", [("camera", prim_rays, bvh.TRACE_CLOSEST),
+                                                 ("bounce", bounce_rays, bvh.TRACE_CLOSEST)])
+            r["build_ms"] = round(build_ms, 3)
+            r["depth"] = h.stats()["depth"]
+            h.close()
+            row[builder] = r
+        res[layout] = row
+        log(f"terrain sah vs lbvh {layout}: {row}")
     return res
 
 
@@ -369,6 +405,15 @@ def spheres(torch, bvh, W, args, cpq=None):
                                                        ("shadow_any", shadow, bvh.TRACE_ANY)])
         h.close()
         log(f"spheres {layout}: {res[layout]}")
+    for layout in ("aabb2", "bvh4"):
+        build_ms = timed_build(torch, bvh, verts, tris, layout, args.leaf_size, "sah")
+        h = bvh.build(verts, tris, layout, args.leaf_size, "compact", builder="sah")
+        r = layout_row(torch, h, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
+                                             ("shadow_any", shadow, bvh.TRACE_ANY)])
+        r["build_ms"] = round(build_ms, 3)
+        h.close()
+        res[f"{layout}/sah"] = r
+        log(f"spheres {layout}/sah: {r}")
     if cpq is not None:
         del rays, shadow
         cpq["spheres"] = closest_point_rows(torch, bvh, W, w["verts"], verts, w["tris"], tris,
