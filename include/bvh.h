@@ -49,7 +49,10 @@ extern "C" {
 #define BVH_LAYOUT_BVH8_Q16 3 /* 8-wide, u16 child boxes in the parent frame, 160 B */
 #define BVH_LAYOUT_PBRT_Q16 4 /* binary, own u16 box in the scene frame, 16 B */
 #define BVH_LAYOUT_SG_EQ 5    /* binary, own 10-bit box in the scene frame, 12 B */
-#define BVH_NUM_LAYOUTS 6
+#define BVH_LAYOUT_PBRT_SOAOS 6     /* AABB2 as a box array and a topology array, 24 + 8 B */
+#define BVH_LAYOUT_PBRT_Q16_SOAOS 7 /* PBRT_Q16 as a box array and a topology array, 12 + 4 B */
+#define BVH_LAYOUT_SG_EQ_A16 8      /* SG_EQ records padded to 16 B */
+#define BVH_NUM_LAYOUTS 9
 
 /* Leaf storage. */
 #define BVH_LEAF_COMPACT 0 /* triangles copied into leaf order (bvh_tri records) */
@@ -100,8 +103,8 @@ typedef struct bvh_hit {
 
 /* Build options; a zero field selects the default. */
 typedef struct bvh_build_opts {
-    int32_t leaf_size;   /* max triangles per leaf, 1..16 (1..15 for PBRT_Q16 and SG_EQ;
-                            default 4) */
+    int32_t leaf_size;   /* max triangles per leaf, 1..16 (1..15 for the PBRT_Q16 and SG_EQ
+                            layouts and their variants; default 4) */
     int32_t leaf_mode;   /* BVH_LEAF_COMPACT (default) or BVH_LEAF_INDEXED */
     int32_t stack_lds;   /* traversal stack entries kept in LDS per ray: 8, 16 or 32 (default:
                             32 for AABB2, 16 for the wide layouts).  A ray that needs more is
@@ -245,6 +248,39 @@ typedef struct bvh_node_pbrt_q16 {
 typedef struct bvh_node_sg_eq {
     uint32_t qlo, qhi, off;
 } bvh_node_sg_eq; /* 12 B */
+
+/*
+ * The "-soaos" and "-align16" variants of Table 1 (Sec. 9.1: a global
+ * memory transformation for locality, and 16-byte alignment), over the same
+ * preorder tree and the same field encodings:
+ *
+ * BVH_LAYOUT_PBRT_SOAOS: the AABB2 records split into two arrays of
+ *   n_nodes entries each, one after the other in the node buffer: first the
+ *   boxes (bvh_node_box_f32, 24 B), then the topology words
+ *   (bvh_node_topo, 8 B: AABB2's offset and meta).  The traversal fetches a
+ *   node's topology only when the ray meets its box.
+ * BVH_LAYOUT_PBRT_Q16_SOAOS: the PBRT_Q16 records split the same way: first
+ *   the u16 boxes (bvh_node_box_q16, 12 B, with the split axis in the lowest
+ *   bits of lo[0] and lo[1] as in PBRT_Q16), then the meta words (uint32_t:
+ *   count | offset << 4).
+ * BVH_LAYOUT_SG_EQ_A16: SG_EQ records followed by a zero word
+ *   (bvh_node_sg_eq_a16, 16 B), one aligned 16-byte fetch per node.
+ */
+typedef struct bvh_node_box_f32 {
+    float lo[3], hi[3];
+} bvh_node_box_f32; /* 24 B */
+
+typedef struct bvh_node_topo {
+    uint32_t offset, meta;
+} bvh_node_topo; /* 8 B */
+
+typedef struct bvh_node_box_q16 {
+    uint16_t lo[3], hi[3];
+} bvh_node_box_q16; /* 12 B */
+
+typedef struct bvh_node_sg_eq_a16 {
+    uint32_t qlo, qhi, off, pad;
+} bvh_node_sg_eq_a16; /* 16 B */
 
 typedef struct bvh_handle_s *bvh_handle_t;
 

@@ -28,6 +28,7 @@ struct BatchScene {
     uint32_t ray_count;
     float coord_max;
     float fo[3], fs[3], ft[3];  // PBRT_Q16 / SG_EQ scene frame
+    const void *topo;           // split layouts: the topology array
 };
 
 // Largest s in [0, n) with tile_off[s] <= tile (tile_off has n + 1 entries,
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_trace(const BatchScene *s
                         n_nodes = c.n_nodes;
                         sd = SceneData{c.leaf, nullptr, nullptr, c.n_tris, c.coord_max,
                                        {c.fo[0], c.fo[1], c.fo[2]}, {c.fs[0], c.fs[1], c.fs[2]},
-                                       {c.ft[0], c.ft[1], c.ft[2]}};
+                                       {c.ft[0], c.ft[1], c.ft[2]}, c.topo};
                     }
                     const uint64_t lo = (uint64_t)(pending - tile_off[s2]) * kTile;
                     pool = c.ray_begin + lo;
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_batch_fallback(const BatchScene
         const Ray r = load_ray(rays, i, sc.coord_max);
         const SceneData ld{sc.leaf, nullptr, nullptr, sc.n_tris, sc.coord_max,
                                {sc.fo[0], sc.fo[1], sc.fo[2]}, {sc.fs[0], sc.fs[1], sc.fs[2]},
-                               {sc.ft[0], sc.ft[1], sc.ft[2]}};
+                               {sc.ft[0], sc.ft[1], sc.ft[2]}, sc.topo};
         uint32_t nf = 0, nt = 0;
         bool incomplete = false;
         GlobalStack<TracerFor<Layout>::type::kWithT> st(fb.stack_ref + (size_t)lane * kStackMax,
@@ -243,6 +244,9 @@ FallbackFn fallback_for(int layout) {
         case BVH_LAYOUT_BVH8_Q8: return &k_batch_fallback<BVH_LAYOUT_BVH8_Q8>;
         case BVH_LAYOUT_PBRT_Q16: return &k_batch_fallback<BVH_LAYOUT_PBRT_Q16>;
         case BVH_LAYOUT_SG_EQ: return &k_batch_fallback<BVH_LAYOUT_SG_EQ>;
+        case BVH_LAYOUT_PBRT_SOAOS: return &k_batch_fallback<BVH_LAYOUT_PBRT_SOAOS>;
+        case BVH_LAYOUT_PBRT_Q16_SOAOS: return &k_batch_fallback<BVH_LAYOUT_PBRT_Q16_SOAOS>;
+        case BVH_LAYOUT_SG_EQ_A16: return &k_batch_fallback<BVH_LAYOUT_SG_EQ_A16>;
         default: return &k_batch_fallback<BVH_LAYOUT_BVH8_Q16>;
     }
 }
@@ -261,6 +265,9 @@ KernelFn kernel_for(int layout, int sl) {
         case BVH_LAYOUT_BVH8_Q8: return kernel_for_sl<BVH_LAYOUT_BVH8_Q8>(sl);
         case BVH_LAYOUT_PBRT_Q16: return kernel_for_sl<BVH_LAYOUT_PBRT_Q16>(sl);
         case BVH_LAYOUT_SG_EQ: return kernel_for_sl<BVH_LAYOUT_SG_EQ>(sl);
+        case BVH_LAYOUT_PBRT_SOAOS: return kernel_for_sl<BVH_LAYOUT_PBRT_SOAOS>(sl);
+        case BVH_LAYOUT_PBRT_Q16_SOAOS: return kernel_for_sl<BVH_LAYOUT_PBRT_Q16_SOAOS>(sl);
+        case BVH_LAYOUT_SG_EQ_A16: return kernel_for_sl<BVH_LAYOUT_SG_EQ_A16>(sl);
         default: return kernel_for_sl<BVH_LAYOUT_BVH8_Q16>(sl);
     }
 }
@@ -502,7 +509,8 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
                                     (uint32_t)h->n_tris, (uint32_t)cnt, h->coord_max(),
                                     {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
                                     {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]},
-                                    {h->frame_top[0], h->frame_top[1], h->frame_top[2]}});
+                                    {h->frame_top[0], h->frame_top[1], h->frame_top[2]},
+                                    topo_of(h->nodes, h->n_nodes, h->layout)});
             const uint64_t tiles = ((uint64_t)cnt + kTile - 1) / kTile;
             if (toff.back() + tiles > 0xFFFFFFFFull)
                 return set_error(BVH_EUNSUPPORTED, "bvh_batch_trace: too many rays");

@@ -640,9 +640,10 @@ __device__ inline uint32_t q10_upper(float x, float top, float s) {
     return b;
 }
 
+// A16: records padded with a zero word to 16 B (SG_EQ_A16).
+template <bool A16>
 __global__ __launch_bounds__(kBlock) void k_pack_sg_eq(const bvh_node_aabb2 *in, uint32_t n_nodes,
-                                                       WorldFrame fr, bvh_node_sg_eq *out,
-                                                       BuildInfo *info) {
+                                                       WorldFrame fr, void *out, BuildInfo *info) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n_nodes) return;
     const bvh_node_aabb2 nd = in[i];
@@ -659,12 +660,19 @@ __global__ __launch_bounds__(kBlock) void k_pack_sg_eq(const bvh_node_aabb2 *in,
     q.qlo = lo[0] << 20 | lo[1] << 10 | lo[2] | (cnt & 3u) << 30;
     q.qhi = hi[0] << 20 | hi[1] << 10 | hi[2] | (cnt >> 2) << 30;
     q.off = cnt > 0 ? nd.offset : (nd.offset | ((nd.meta >> 16) & 3u) << 30);
-    out[i] = q;
+    if (A16)
+        static_cast<bvh_node_sg_eq_a16 *>(out)[i] = bvh_node_sg_eq_a16{q.qlo, q.qhi, q.off, 0u};
+    else
+        static_cast<bvh_node_sg_eq *>(out)[i] = q;
 }
 
+// Split: boxes to out_box[i], meta words to out_meta[i] (PBRT_Q16_SOAOS);
+// otherwise whole records to out[i].
+template <bool Split>
 __global__ __launch_bounds__(kBlock) void k_pack_pbrt_q16(const bvh_node_aabb2 *in, uint32_t n_nodes,
                                                           WorldFrame fr, bvh_node_pbrt_q16 *out,
-                                                          BuildInfo *info) {
+                                                          bvh_node_box_q16 *out_box,
+                                                          uint32_t *out_meta, BuildInfo *info) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n_nodes) return;
     const bvh_node_aabb2 nd = in[i];
@@ -689,11 +697,34 @@ __global__ __launch_bounds__(kBlock) void k_pack_pbrt_q16(const bvh_node_aabb2 *
         }
         meta = nd.offset << 4;
     }
-    bvh_node_pbrt_q16 q;
-    q.lo[0] = (uint16_t)lo[0]; q.lo[1] = (uint16_t)lo[1]; q.lo[2] = (uint16_t)lo[2];
-    q.hi[0] = (uint16_t)hi[0]; q.hi[1] = (uint16_t)hi[1]; q.hi[2] = (uint16_t)hi[2];
-    q.meta = meta;
-    out[i] = q;
+    if (Split) {
+        bvh_node_box_q16 q;
+        q.lo[0] = (uint16_t)lo[0]; q.lo[1] = (uint16_t)lo[1]; q.lo[2] = (uint16_t)lo[2];
+        q.hi[0] = (uint16_t)hi[0]; q.hi[1] = (uint16_t)hi[1]; q.hi[2] = (uint16_t)hi[2];
+        out_box[i] = q;
+        out_meta[i] = meta;
+    } else {
+        bvh_node_pbrt_q16 q;
+        q.lo[0] = (uint16_t)lo[0]; q.lo[1] = (uint16_t)lo[1]; q.lo[2] = (uint16_t)lo[2];
+        q.hi[0] = (uint16_t)hi[0]; q.hi[1] = (uint16_t)hi[1]; q.hi[2] = (uint16_t)hi[2];
+        q.meta = meta;
+        out[i] = q;
+    }
+}
+
+// AABB2 records split into a box array and a topology array (PBRT_SOAOS).
+__global__ __launch_bounds__(kBlock) void k_split_aabb2(const bvh_node_aabb2 *in, uint32_t n_nodes,
+                                                        bvh_node_box_f32 *box, bvh_node_topo *topo) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_nodes) return;
+    const bvh_node_aabb2 nd = in[i];
+    bvh_node_box_f32 b;
+    for (int a = 0; a < 3; a++) {
+        b.lo[a] = nd.lo[a];
+        b.hi[a] = nd.hi[a];
+    }
+    box[i] = b;
+    topo[i] = bvh_node_topo{nd.offset, nd.meta};
 }
 
 // ---------------------------------------------------------------------------
@@ -1978,9 +2009,24 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(
             tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
         BVH_TRY(check_launch("aabb2 packing"));
-    } else if (h->layout == BVH_LAYOUT_PBRT_Q16 || h->layout == BVH_LAYOUT_SG_EQ) {
+    } else if (h->layout == BVH_LAYOUT_PBRT_SOAOS) {
+        // the AABB2 records, split into a box array and a topology array
+        h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
+        Arena ar;
+        bvh_node_aabb2 *tmp = nullptr;
+        ar.request(&tmp, (size_t)h->n_nodes);
+        BVH_TRY(ar.bind(s, kAreaBuildWide));
+        BVH_TRY(alloc_handle_block(h, h->n_nodes));
+        k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
+                                                                      (uint32_t)h->n_nodes, info);
+        k_split_aabb2<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
+            tmp, (uint32_t)h->n_nodes, static_cast<bvh_node_box_f32 *>(h->nodes),
+            const_cast<bvh_node_topo *>(static_cast<const bvh_node_topo *>(
+                topo_of(h->nodes, h->n_nodes, h->layout))));
+        BVH_TRY(check_launch("pbrt-soaos packing"));
+    } else if (layout_scene_frame(h->layout)) {
         // the AABB2 tree, re-encoded node by node in the scene frame
-        const bool pq = h->layout == BVH_LAYOUT_PBRT_Q16;
+        const bool pq = !layout_sg_eq(h->layout);
         h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
         const WorldFrame fr = world_frame(hi.slo, hi.shi, pq ? 65535.0f : 1023.0f);
         for (int a = 0; a < 3; a++) {
@@ -1995,12 +2041,20 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         BVH_TRY(alloc_handle_block(h, h->n_nodes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
                                                                       (uint32_t)h->n_nodes, info);
-        if (pq)
-            k_pack_pbrt_q16<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
-                tmp, (uint32_t)h->n_nodes, fr, static_cast<bvh_node_pbrt_q16 *>(h->nodes), info);
+        const unsigned g = grid_for((uint64_t)h->n_nodes);
+        const uint32_t nn = (uint32_t)h->n_nodes;
+        if (h->layout == BVH_LAYOUT_PBRT_Q16)
+            k_pack_pbrt_q16<false><<<g, kBlock, 0, s>>>(
+                tmp, nn, fr, static_cast<bvh_node_pbrt_q16 *>(h->nodes), nullptr, nullptr, info);
+        else if (h->layout == BVH_LAYOUT_PBRT_Q16_SOAOS)
+            k_pack_pbrt_q16<true><<<g, kBlock, 0, s>>>(
+                tmp, nn, fr, nullptr, static_cast<bvh_node_box_q16 *>(h->nodes),
+                static_cast<uint32_t *>(const_cast<void *>(topo_of(h->nodes, h->n_nodes, h->layout))),
+                info);
+        else if (h->layout == BVH_LAYOUT_SG_EQ)
+            k_pack_sg_eq<false><<<g, kBlock, 0, s>>>(tmp, nn, fr, h->nodes, info);
         else
-            k_pack_sg_eq<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
-                tmp, (uint32_t)h->n_nodes, fr, static_cast<bvh_node_sg_eq *>(h->nodes), info);
+            k_pack_sg_eq<true><<<g, kBlock, 0, s>>>(tmp, nn, fr, h->nodes, info);
         BVH_TRY(check_launch("scene-frame packing"));
     } else if (h->layout == BVH_LAYOUT_BVH4) {
         BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, h, s));
@@ -2102,7 +2156,7 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
     if (builder != BVH_BUILDER_LBVH && builder != BVH_BUILDER_SAH)
         return set_error(BVH_EINVAL, "bvh_build: unknown builder %d", builder);
     const int32_t max_leaf =  // the scene-frame binary layouts store a u4 count
-        (layout == BVH_LAYOUT_PBRT_Q16 || layout == BVH_LAYOUT_SG_EQ) ? 15 : kMaxLeafSize;
+        layout_scene_frame(layout) ? 15 : kMaxLeafSize;
     if (leaf_size < 1 || leaf_size > max_leaf)
         return set_error(BVH_EINVAL, "bvh_build: leaf_size %d outside 1..%d", leaf_size, max_leaf);
     if (leaf_mode != BVH_LEAF_COMPACT && leaf_mode != BVH_LEAF_INDEXED)

@@ -441,6 +441,9 @@ struct CpqFor;
 template <> struct CpqFor<BVH_LAYOUT_AABB2> { using type = CpqBin<BinAABB2>; };
 template <> struct CpqFor<BVH_LAYOUT_PBRT_Q16> { using type = CpqBin<BinPbrtQ16>; };
 template <> struct CpqFor<BVH_LAYOUT_SG_EQ> { using type = CpqBin<BinSgEq>; };
+template <> struct CpqFor<BVH_LAYOUT_PBRT_SOAOS> { using type = CpqBin<BinPbrtSoAoS>; };
+template <> struct CpqFor<BVH_LAYOUT_PBRT_Q16_SOAOS> { using type = CpqBin<BinPbrtQ16SoAoS>; };
+template <> struct CpqFor<BVH_LAYOUT_SG_EQ_A16> { using type = CpqBin<BinSgEqA16>; };
 template <> struct CpqFor<BVH_LAYOUT_BVH4> { using type = CpqWide<BVH_LAYOUT_BVH4>; };
 template <> struct CpqFor<BVH_LAYOUT_BVH8_Q8> { using type = CpqWide<BVH_LAYOUT_BVH8_Q8>; };
 template <> struct CpqFor<BVH_LAYOUT_BVH8_Q16> { using type = CpqWide<BVH_LAYOUT_BVH8_Q16>; };
@@ -621,6 +624,13 @@ int32_t launch_sl(const bvh_handle_s *h, const SceneData &ld, const bvh_point_qu
             return launch_layout<BVH_LAYOUT_PBRT_Q16, LeafMode, Count, SL>(h, ld, qs, n, out, counts, s);
         case BVH_LAYOUT_SG_EQ:
             return launch_layout<BVH_LAYOUT_SG_EQ, LeafMode, Count, SL>(h, ld, qs, n, out, counts, s);
+        case BVH_LAYOUT_PBRT_SOAOS:
+            return launch_layout<BVH_LAYOUT_PBRT_SOAOS, LeafMode, Count, SL>(h, ld, qs, n, out, counts, s);
+        case BVH_LAYOUT_PBRT_Q16_SOAOS:
+            return launch_layout<BVH_LAYOUT_PBRT_Q16_SOAOS, LeafMode, Count, SL>(h, ld, qs, n, out,
+                                                                                counts, s);
+        case BVH_LAYOUT_SG_EQ_A16:
+            return launch_layout<BVH_LAYOUT_SG_EQ_A16, LeafMode, Count, SL>(h, ld, qs, n, out, counts, s);
         default:
             return launch_layout<BVH_LAYOUT_BVH8_Q16, LeafMode, Count, SL>(h, ld, qs, n, out, counts, s);
     }
@@ -629,10 +639,7 @@ int32_t launch_sl(const bvh_handle_s *h, const SceneData &ld, const bvh_point_qu
 template <int LeafMode, bool Count>
 int32_t launch_mode(const bvh_handle_s *h, const bvh_point_query *qs, uint64_t n, bvh_closest *out,
                     uint32_t *counts, hipStream_t s) {
-    const SceneData ld{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris, h->coord_max(),
-                       {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
-                       {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]},
-                       {h->frame_top[0], h->frame_top[1], h->frame_top[2]}};
+    const SceneData ld = scene_data(h);
     // every stack entry carries a distance, so the LDS ring holds at most 16
     // entries per lane (32 would halve the resident waves)
     const int32_t rc = h->stack_lds == 8 ? launch_sl<LeafMode, Count, 8>(h, ld, qs, n, out, counts, s)

@@ -105,6 +105,9 @@ inline int64_t node_record_bytes(int32_t layout) {
         case BVH_LAYOUT_BVH8_Q16: return sizeof(bvh_node_bvh8_q16);
         case BVH_LAYOUT_PBRT_Q16: return sizeof(bvh_node_pbrt_q16);
         case BVH_LAYOUT_SG_EQ: return sizeof(bvh_node_sg_eq);
+        case BVH_LAYOUT_PBRT_SOAOS: return sizeof(bvh_node_box_f32) + sizeof(bvh_node_topo);
+        case BVH_LAYOUT_PBRT_Q16_SOAOS: return sizeof(bvh_node_box_q16) + sizeof(uint32_t);
+        case BVH_LAYOUT_SG_EQ_A16: return sizeof(bvh_node_sg_eq_a16);
         default: return 0;
     }
 }
@@ -114,6 +117,9 @@ inline int32_t layout_arity(int32_t layout) {
         case BVH_LAYOUT_AABB2: return 2;
         case BVH_LAYOUT_PBRT_Q16: return 2;
         case BVH_LAYOUT_SG_EQ: return 2;
+        case BVH_LAYOUT_PBRT_SOAOS: return 2;
+        case BVH_LAYOUT_PBRT_Q16_SOAOS: return 2;
+        case BVH_LAYOUT_SG_EQ_A16: return 2;
         case BVH_LAYOUT_BVH4: return 4;
         default: return 8;
     }
@@ -174,6 +180,33 @@ static_assert(sizeof(bvh_tri) == 48, "bvh_tri");
 static_assert(sizeof(bvh_node_aabb2) == 32, "aabb2 node");
 static_assert(sizeof(bvh_node_pbrt_q16) == 16, "pbrt-q16 node");
 static_assert(sizeof(bvh_node_sg_eq) == 12, "sg-eq node");
+static_assert(sizeof(bvh_node_box_f32) == 24 && sizeof(bvh_node_topo) == 8, "pbrt-soaos arrays");
+static_assert(sizeof(bvh_node_box_q16) == 12, "pbrt-q16-soaos boxes");
+static_assert(sizeof(bvh_node_sg_eq_a16) == 16, "sg-eq-align16 node");
+
+// Layouts whose node buffer is a box array followed by a topology array, and
+// the bytes of one box entry.
+inline bool layout_split(int32_t layout) {
+    return layout == BVH_LAYOUT_PBRT_SOAOS || layout == BVH_LAYOUT_PBRT_Q16_SOAOS;
+}
+inline int64_t split_box_bytes(int32_t layout) {
+    return layout == BVH_LAYOUT_PBRT_SOAOS ? (int64_t)sizeof(bvh_node_box_f32)
+                                           : (int64_t)sizeof(bvh_node_box_q16);
+}
+// The topology array of a split layout (after the n_nodes box entries).
+inline const void *topo_of(const void *nodes, int64_t n_nodes, int32_t layout) {
+    return layout_split(layout)
+               ? static_cast<const char *>(nodes) + split_box_bytes(layout) * n_nodes
+               : nullptr;
+}
+// Scene-frame quantised layouts (PBRT_Q16, SG_EQ and their variants).
+inline bool layout_scene_frame(int32_t layout) {
+    return layout == BVH_LAYOUT_PBRT_Q16 || layout == BVH_LAYOUT_SG_EQ ||
+           layout == BVH_LAYOUT_PBRT_Q16_SOAOS || layout == BVH_LAYOUT_SG_EQ_A16;
+}
+inline bool layout_sg_eq(int32_t layout) {
+    return layout == BVH_LAYOUT_SG_EQ || layout == BVH_LAYOUT_SG_EQ_A16;
+}
 static_assert(sizeof(bvh_node_bvh4) == 128, "bvh4 node");
 static_assert(sizeof(bvh_node_bvh8_q8) == 128, "bvh8 q8 node");
 static_assert(sizeof(bvh_node_bvh8_q16) == 160, "bvh8 q16 node");

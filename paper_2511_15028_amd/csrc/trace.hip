@@ -237,6 +237,15 @@ int32_t launch_sl(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *ray
         case BVH_LAYOUT_SG_EQ:
             return launch_layout<BVH_LAYOUT_SG_EQ, LeafMode, Mode, Count, SL>(h, ld, rays, n, hits,
                                                                              counts, s);
+        case BVH_LAYOUT_PBRT_SOAOS:
+            return launch_layout<BVH_LAYOUT_PBRT_SOAOS, LeafMode, Mode, Count, SL>(h, ld, rays, n,
+                                                                                  hits, counts, s);
+        case BVH_LAYOUT_PBRT_Q16_SOAOS:
+            return launch_layout<BVH_LAYOUT_PBRT_Q16_SOAOS, LeafMode, Mode, Count, SL>(
+                h, ld, rays, n, hits, counts, s);
+        case BVH_LAYOUT_SG_EQ_A16:
+            return launch_layout<BVH_LAYOUT_SG_EQ_A16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
+                                                                                 hits, counts, s);
         default:
             return launch_layout<BVH_LAYOUT_BVH8_Q16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
                                                                                 hits, counts, s);
@@ -246,10 +255,7 @@ int32_t launch_sl(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *ray
 template <int LeafMode, int Mode, bool Count>
 int32_t launch_mode(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits,
                     uint32_t *counts, hipStream_t s) {
-    const SceneData ld{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris, h->coord_max(),
-                       {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
-                       {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]},
-                       {h->frame_top[0], h->frame_top[1], h->frame_top[2]}};
+    const SceneData ld = scene_data(h);
     int32_t rc;
     if (h->stack_lds == 8)
         rc = launch_sl<LeafMode, Mode, Count, 8>(h, ld, rays, n, hits, counts, s);

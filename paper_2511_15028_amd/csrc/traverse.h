@@ -10,6 +10,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "internal.h"
@@ -211,6 +212,7 @@ struct SceneData {
     float coord_max;  // largest coordinate magnitude of the scene (selects the slab form)
     float fo[3], fs[3];  // PBRT_Q16, SG_EQ: lower plane = fmaf(q, fs[a], fo[a])
     float ft[3];         // SG_EQ: upper plane = fmaf(-q, fs[a], ft[a])
+    const void *topo;    // split layouts: the topology array after the boxes
 };
 
 // Compacted leaves: triangles are fetched in batches of kLeafBatch (all loads
@@ -427,6 +429,7 @@ __device__ inline uint32_t bin_pop(Stack &st) {
 // interior node), offset (right-child delta or first triangle) and split
 // axis (3 when unknown).
 struct BinAABB2 {
+    static constexpr bool kSplit = false;
     __device__ static void load(const void *nodes, uint32_t i, const SceneData &, float *lo,
                                 float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
         const float4 *np = reinterpret_cast<const float4 *>(static_cast<const bvh_node_aabb2 *>(nodes) + i);
@@ -442,6 +445,7 @@ struct BinAABB2 {
 
 // pbrt-q16: one 16-B load; planes dequantised in the scene frame.
 struct BinPbrtQ16 {
+    static constexpr bool kSplit = false;
     __device__ static void load(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
                                 float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
         const uint4 w = reinterpret_cast<const uint4 *>(nodes)[i];
@@ -461,6 +465,7 @@ struct BinPbrtQ16 {
 // sg-eq: one 12-B load; 10-bit planes counted up from the frame origin
 // (lower) and down from the frame top (upper).
 struct BinSgEq {
+    static constexpr bool kSplit = false;
     __device__ static void load(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
                                 float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
         const uint32_t *p = static_cast<const uint32_t *>(nodes) + 3 * (size_t)i;
@@ -478,6 +483,107 @@ struct BinSgEq {
     }
 };
 
+// Split layouts (box array, then topology array): load_box fetches only the
+// box, load_meta the topology word(s), so a node whose box the query misses
+// costs one fetch; load fetches both.
+struct BinPbrtSoAoS {
+    static constexpr bool kSplit = true;
+    __device__ static void load_box(const void *nodes, uint32_t i, const SceneData &, float *lo,
+                                    float *hi) {
+        const float2 *p = static_cast<const float2 *>(nodes) + 3 * (size_t)i;
+        const float2 a = p[0], b = p[1], c = p[2];
+        lo[0] = a.x; lo[1] = a.y; lo[2] = b.x;
+        hi[0] = b.y; hi[1] = c.x; hi[2] = c.y;
+    }
+    __device__ static void load_meta(uint32_t i, const SceneData &sd, uint32_t &cnt, uint32_t &off,
+                                     uint32_t &axis) {
+        const uint2 t = static_cast<const uint2 *>(sd.topo)[i];
+        off = t.x;
+        cnt = t.y & 0xFFFFu;
+        axis = (t.y >> 16) & 3u;
+    }
+    __device__ static void load(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
+                                float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
+        load_box(nodes, i, sd, lo, hi);
+        load_meta(i, sd, cnt, off, axis);
+    }
+};
+
+struct BinPbrtQ16SoAoS {
+    static constexpr bool kSplit = true;
+    // boxes are 12 B: entry i starts at word 3 i (u16 pairs lo_x|lo_y, lo_z|hi_x, hi_y|hi_z)
+    __device__ static void load_box_q(const void *nodes, uint32_t i, uint32_t *q) {
+        const uint32_t *p = static_cast<const uint32_t *>(nodes) + 3 * (size_t)i;
+        const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
+        q[0] = w0 & 0xFFFFu; q[1] = w0 >> 16; q[2] = w1 & 0xFFFFu;
+        q[3] = w1 >> 16;     q[4] = w2 & 0xFFFFu; q[5] = w2 >> 16;
+    }
+    __device__ static void load_box(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
+                                    float *hi) {
+        uint32_t q[6];
+        load_box_q(nodes, i, q);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmaf((float)q[a], sd.fs[a], sd.fo[a]);
+            hi[a] = fmaf((float)q[3 + a], sd.fs[a], sd.fo[a]);
+        }
+    }
+    // the split axis lives in the box (lowest bits of lo_x and lo_y)
+    __device__ static void load_meta_axis(const void *nodes, uint32_t i, const SceneData &sd,
+                                          uint32_t &cnt, uint32_t &off, uint32_t &axis) {
+        const uint32_t m = static_cast<const uint32_t *>(sd.topo)[i];
+        cnt = m & 0xFu;
+        off = m >> 4;
+        const uint32_t w0 = static_cast<const uint32_t *>(nodes)[3 * (size_t)i];
+        axis = (w0 & 1u) | ((w0 >> 16) & 1u) << 1;
+    }
+    __device__ static void load(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
+                                float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
+        uint32_t q[6];
+        load_box_q(nodes, i, q);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmaf((float)q[a], sd.fs[a], sd.fo[a]);
+            hi[a] = fmaf((float)q[3 + a], sd.fs[a], sd.fo[a]);
+        }
+        const uint32_t m = static_cast<const uint32_t *>(sd.topo)[i];
+        cnt = m & 0xFu;
+        off = m >> 4;
+        axis = (q[0] & 1u) | ((q[1] & 1u) << 1);
+    }
+};
+
+// sg-eq records padded to 16 B: one aligned 16-byte fetch.
+struct BinSgEqA16 {
+    static constexpr bool kSplit = false;
+    __device__ static void load(const void *nodes, uint32_t i, const SceneData &sd, float *lo,
+                                float *hi, uint32_t &cnt, uint32_t &off, uint32_t &axis) {
+        const uint4 r = static_cast<const uint4 *>(nodes)[i];
+        const uint32_t ql = r.x, qh = r.y, w = r.z;
+        const uint32_t qlo[3] = {(ql >> 20) & 1023u, (ql >> 10) & 1023u, ql & 1023u};
+        const uint32_t qhi[3] = {(qh >> 20) & 1023u, (qh >> 10) & 1023u, qh & 1023u};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmaf((float)qlo[a], sd.fs[a], sd.fo[a]);
+            hi[a] = fmaf(-(float)qhi[a], sd.fs[a], sd.ft[a]);
+        }
+        cnt = (ql >> 30) | ((qh >> 30) << 2);
+        off = w & 0x3FFFFFFFu;
+        axis = cnt > 0 ? 3u : (w >> 30);
+    }
+};
+
+// Split-layout meta fetch (the pbrt-q16 variant re-reads the box's first word
+// for the axis bits, a cache hit after the box fetch).
+template <class Node>
+__device__ inline void split_meta(const void *nodes, uint32_t i, const SceneData &sd, uint32_t &cnt,
+                                  uint32_t &off, uint32_t &axis) {
+    if constexpr (std::is_same_v<Node, BinPbrtQ16SoAoS>)
+        Node::load_meta_axis(nodes, i, sd, cnt, off, axis);
+    else
+        Node::load_meta(i, sd, cnt, off, axis);
+}
+
 // Visits bs.node; returns the leaf reference when the node is a leaf whose
 // box the ray meets (kRefEmpty otherwise).  bs.node moves on to the next node.
 template <class Node, int Mode, class Stack>
@@ -489,13 +595,17 @@ __device__ inline uint32_t bin_visit(const void *nodes, int64_t n_nodes, const S
         return kRefEmpty;
     }
     float lo[3], hi[3];
-    uint32_t cnt, off, axis;
-    Node::load(nodes, bs.node, sd, lo, hi, cnt, off, axis);
+    uint32_t cnt = 0, off = 0, axis = 0;
+    if constexpr (Node::kSplit)
+        Node::load_box(nodes, bs.node, sd, lo, hi);
+    else
+        Node::load(nodes, bs.node, sd, lo, hi, cnt, off, axis);
     nfetch++;
     const float tcur = best_bound<Mode>(r, bs.best);
     const float tn = fast ? slab<true>(r, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], tcur)
                           : slab<false>(r, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], tcur);
     if (tn != INFINITY) {
+        if constexpr (Node::kSplit) split_meta<Node>(nodes, bs.node, sd, cnt, off, axis);
         if (cnt > 0) {
             bs.node = bin_pop(st);
             return ref_leaf(off, cnt);
@@ -948,6 +1058,18 @@ struct TracerFor<BVH_LAYOUT_SG_EQ> {
     using type = BinTracer<BinSgEq>;
 };
 template <>
+struct TracerFor<BVH_LAYOUT_PBRT_SOAOS> {
+    using type = BinTracer<BinPbrtSoAoS>;
+};
+template <>
+struct TracerFor<BVH_LAYOUT_PBRT_Q16_SOAOS> {
+    using type = BinTracer<BinPbrtQ16SoAoS>;
+};
+template <>
+struct TracerFor<BVH_LAYOUT_SG_EQ_A16> {
+    using type = BinTracer<BinSgEqA16>;
+};
+template <>
 struct TracerFor<BVH_LAYOUT_BVH4> {
     using type = WideTracer<DecodeBVH4>;
 };
@@ -1022,6 +1144,14 @@ __device__ inline void fallback_append(const Fallback &fb, uint32_t ray) {
 // ---------------------------------------------------------------------------
 // Host-side launch helpers of the persistent kernels.
 // ---------------------------------------------------------------------------
+// Per-scene data of a handle for the traversal kernels.
+inline SceneData scene_data(const bvh_handle_s *h) {
+    return SceneData{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris, h->coord_max(),
+                     {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
+                     {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]},
+                     {h->frame_top[0], h->frame_top[1], h->frame_top[2]},
+                     topo_of(h->nodes, h->n_nodes, h->layout)};
+}
 // Spill entries per lane of a persistent launch (beyond the LDS ring).
 constexpr uint32_t kSpillCap = 64;
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 import numpy as np
 
 AABB2, BVH4, BVH8_Q8, BVH8_Q16, PBRT_Q16, SG_EQ = 0, 1, 2, 3, 4, 5
+PBRT_SOAOS, PBRT_Q16_SOAOS, SG_EQ_A16 = 6, 7, 8
 
 AABB2_DT = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("offset", "<u4"), ("meta", "<u4")])
 BVH4_DT = np.dtype([("lo_x", "<f4", 4), ("lo_y", "<f4", 4), ("lo_z", "<f4", 4),
@@ -33,6 +34,41 @@ assert PQ16_DT.itemsize == 16 and SGEQ_DT.itemsize == 12
 
 DTYPES = {AABB2: AABB2_DT, BVH4: BVH4_DT, BVH8_Q8: Q8_DT, BVH8_Q16: Q16_DT, PBRT_Q16: PQ16_DT,
           SG_EQ: SGEQ_DT}
+BOXF_DT = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3)])
+TOPO_DT = np.dtype([("offset", "<u4"), ("meta", "<u4")])
+BOXQ_DT = np.dtype([("lo", "<u2", 3), ("hi", "<u2", 3)])
+SGEQ16_DT = np.dtype([("qlo", "<u4"), ("qhi", "<u4"), ("off", "<u4"), ("pad", "<u4")])
+assert BOXF_DT.itemsize == 24 and TOPO_DT.itemsize == 8 and BOXQ_DT.itemsize == 12
+assert SGEQ16_DT.itemsize == 16
+VARIANT_BYTES = {PBRT_SOAOS: 32, PBRT_Q16_SOAOS: 16, SG_EQ_A16: 16}
+
+
+def as_base(layout, nodes_bytes):
+    """A variant's node buffer re-assembled as the base layout's records:
+    (base layout, records).  SoAoS: n box entries, then n topology entries;
+    align16: sg-eq records plus a zero word."""
+    if layout == PBRT_SOAOS:
+        n = len(nodes_bytes) // 32
+        box = np.frombuffer(nodes_bytes[:24 * n], BOXF_DT)
+        topo = np.frombuffer(nodes_bytes[24 * n:], TOPO_DT)
+        rec = np.zeros(n, AABB2_DT)
+        rec["lo"], rec["hi"] = box["lo"], box["hi"]
+        rec["offset"], rec["meta"] = topo["offset"], topo["meta"]
+        return AABB2, rec
+    if layout == PBRT_Q16_SOAOS:
+        n = len(nodes_bytes) // 16
+        box = np.frombuffer(nodes_bytes[:12 * n], BOXQ_DT)
+        meta = np.frombuffer(nodes_bytes[12 * n:], "<u4")
+        rec = np.zeros(n, PQ16_DT)
+        rec["lo"], rec["hi"], rec["meta"] = box["lo"], box["hi"], meta
+        return PBRT_Q16, rec
+    if layout == SG_EQ_A16:
+        r16 = np.frombuffer(nodes_bytes, SGEQ16_DT)
+        assert (r16["pad"] == 0).all()
+        rec = np.zeros(len(r16), SGEQ_DT)
+        rec["qlo"], rec["qhi"], rec["off"] = r16["qlo"], r16["qhi"], r16["off"]
+        return SG_EQ, rec
+    return layout, np.frombuffer(nodes_bytes, DTYPES[layout])
 
 
 def fma32(q, s, o):
@@ -129,8 +165,7 @@ def walk(layout, nodes_bytes, frame=None):
     """Decodes a packed tree.  Returns a list of leaves (first, n, box or None,
     path boxes) and the count of visited nodes; raises on malformed records.
     frame: the scene frame of PBRT_Q16 (origin[3], scale[3])."""
-    dt = DTYPES[layout]
-    nodes = np.frombuffer(nodes_bytes, dtype=dt)
+    layout, nodes = as_base(layout, nodes_bytes)
     leaves = []
     visited = np.zeros(len(nodes), np.int64)
     if len(nodes) == 0:

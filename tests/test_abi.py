@@ -53,13 +53,14 @@ def test_build_argument_validation(L):
     assert h.value is None
     assert L.bvh_build(None, 3, fake, 1, 0, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
     assert L.bvh_build(fake, 0, fake, 1, 0, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
-    assert L.bvh_build(fake, 3, fake, 1, 7, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
+    assert L.bvh_build(fake, 3, fake, 1, 9, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
     assert b"layout" in L.bvh_last_error()
-    for bad in (bvh.BuildOpts(0, 5), bvh.BuildOpts(17, 0), bvh.BuildOpts(-1, 0)):
+    for bad in (bvh.BuildOpts(0, 5), bvh.BuildOpts(17, 0), bvh.BuildOpts(-1, 0),
+                bvh.BuildOpts(4, 0, 0, 2)):
         assert L.bvh_build(fake, 3, fake, 1, 0, ctypes.byref(bad), None, ctypes.byref(h)) == bvh.EINVAL
     # the pbrt-q16 layout stores the triangle count in 4 bits
     sixteen = bvh.BuildOpts(16, 0)
-    for lay in (bvh.LAYOUT_PBRT_Q16, bvh.LAYOUT_SG_EQ):
+    for lay in (bvh.LAYOUT_PBRT_Q16, bvh.LAYOUT_SG_EQ, bvh.LAYOUT_PBRT_Q16_SOAOS, bvh.LAYOUT_SG_EQ_A16):
         assert L.bvh_build(fake, 3, fake, 1, lay, ctypes.byref(sixteen), None,
                            ctypes.byref(h)) == bvh.EINVAL
         assert b"leaf_size" in L.bvh_last_error()

@@ -19,7 +19,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 LAYOUTS = {"aabb2": LD.AABB2, "bvh4": LD.BVH4, "bvh8_q8": LD.BVH8_Q8, "bvh8_q16": LD.BVH8_Q16,
-           "pbrt_q16": LD.PBRT_Q16, "sg_eq": LD.SG_EQ}
+           "pbrt_q16": LD.PBRT_Q16, "sg_eq": LD.SG_EQ, "pbrt_soaos": LD.PBRT_SOAOS,
+           "pbrt_q16_soaos": LD.PBRT_Q16_SOAOS, "sg_eq_a16": LD.SG_EQ_A16}
 
 
 def _build(v, t, layout, leaf_mode="compact", leaf_size=4):
@@ -77,12 +78,13 @@ def test_round_trip(layout, leaf_mode, scene):
         lo, hi = p.min(0), p.max(0)
         for box in path:
             assert (box[0:3] <= lo).all() and (box[3:6] >= hi).all(), (box, lo, hi)
-        if lid in (LD.AABB2, LD.BVH4):
+        if lid in (LD.AABB2, LD.BVH4, LD.PBRT_SOAOS):
             # f32 layouts: the innermost box is exactly the leaf's box
             assert np.array_equal(path[-1][0:3], lo) and np.array_equal(path[-1][3:6], hi)
     assert (covered == 1).all()
     assert st["max_stack"] >= 1 and st["depth"] >= 2
-    assert st["nodes_buffer_bytes"] == st["n_nodes"] * {0: 32, 1: 128, 2: 128, 3: 160, 4: 16, 5: 12}[lid]
+    assert st["nodes_buffer_bytes"] == st["n_nodes"] * {0: 32, 1: 128, 2: 128, 3: 160, 4: 16, 5: 12,
+                                                        6: 32, 7: 16, 8: 16}[lid]
 
 
 @pytest.mark.parametrize("layout", list(LAYOUTS))
@@ -216,3 +218,26 @@ def test_sg_eq_matches_aabb2(scene):
         assert ((up > a["lo"][:, ax]) | (qlo[:, ax] == 1023)).all()
         dn = LD.fma32(-(qhi[:, ax].astype(np.float64) + 1), s[ax], top[ax])
         assert ((dn < a["hi"][:, ax]) | (qhi[:, ax] == 1023)).all()
+
+
+VARIANTS = [("pbrt_soaos", "aabb2"), ("pbrt_q16_soaos", "pbrt_q16"), ("sg_eq_a16", "sg_eq")]
+
+
+@pytest.mark.parametrize("scene", list(SCENES))
+@pytest.mark.parametrize("variant, base", VARIANTS)
+def test_soaos_and_align16_hold_the_base_records(variant, base, scene):
+    """The SoAoS variants hold exactly the base layout's records, split into a
+    box array followed by a topology array; sg-eq-align16 holds the sg-eq
+    records each followed by a zero word; the scene frame is the base's."""
+    from paper_2511_15028_amd import bvh
+    v, t = SCENES[scene]
+    hv, hb = _build(v, t, variant), _build(v, t, base)
+    sv, sb = hv.stats(), hb.stats()
+    assert sv["n_nodes"] == sb["n_nodes"] and sv["n_leaves"] == sb["n_leaves"]
+    for k in ("frame_origin", "frame_scale", "frame_top"):
+        assert list(sv[k]) == list(sb[k])
+    base_id, rec = LD.as_base(LAYOUTS[variant], hv.read_buffer(bvh.BUF_NODES))
+    assert base_id == LAYOUTS[base]
+    want = np.frombuffer(hb.read_buffer(bvh.BUF_NODES), LD.DTYPES[base_id])
+    assert rec.tobytes() == want.tobytes()
+    assert hv.read_buffer(bvh.BUF_LEAF) == hb.read_buffer(bvh.BUF_LEAF)

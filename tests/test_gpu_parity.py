@@ -17,7 +17,8 @@ from paper_2511_15028_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = ["aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq"]
+LAYOUTS = ["aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq", "pbrt_soaos",
+           "pbrt_q16_soaos", "sg_eq_a16"]
 
 
 def B():
@@ -139,7 +140,7 @@ def test_spheres_parity_closest_and_any(orc, layout, leaf_mode):
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("leaf_size", [1, 2, 7, 16])
 def test_leaf_sizes(orc, layout, leaf_size):
-    if layout in ("pbrt_q16", "sg_eq") and leaf_size > 15:
+    if layout in ("pbrt_q16", "sg_eq", "pbrt_q16_soaos", "sg_eq_a16") and leaf_size > 15:
         leaf_size = 15  # these layouts store the triangle count in 4 bits
     w = W.soup_workload(n_tris=700, seed=5)
     rays = np.concatenate([w["rays"], W.uniform_rays(3000, 12)])
