@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--leaf-size", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-layout table and fwd+bwd")
+    ap.add_argument("--sections", default="per_layout,sah,closest_point,fwd_bwd,spheres,batched",
+                    help="comma-separated extra sections to run (default: all)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run an elementwise kernel over this many MiB (counter calibration)")
     return ap.parse_args()
@@ -223,14 +225,22 @@ def main():
     }
 
     if not args.no_extras:
-        out["per_layout"] = per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
-        out["sah"] = sah_rows(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
-        out["closest_point"] = {"terrain": closest_point_rows(torch, bvh, W, w["verts"], verts,
-                                                              w["tris"], tris, args, 1001)}
-        out["fwd_bwd"] = fwd_bwd(torch, bvh, W)
+        sec = set(args.sections.split(","))
+        if "per_layout" in sec:
+            out["per_layout"] = per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
+        if "sah" in sec:
+            out["sah"] = sah_rows(torch, bvh, verts, tris, prim_rays, bounce_rays, args)
+        cpq = None
+        if "closest_point" in sec:
+            cpq = out["closest_point"] = {"terrain": closest_point_rows(
+                torch, bvh, W, w["verts"], verts, w["tris"], tris, args, 1001)}
+        if "fwd_bwd" in sec:
+            out["fwd_bwd"] = fwd_bwd(torch, bvh, W)
         del verts, tris, prim_rays, bounce_rays, hits_p, hits_b
-        out["spheres"] = spheres(torch, bvh, W, args, out["closest_point"])
-        out["batched"] = batched(torch, bvh, W)
+        if "spheres" in sec:
+            out["spheres"] = spheres(torch, bvh, W, args, cpq)
+        if "batched" in sec:
+            out["batched"] = batched(torch, bvh, W)
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4
