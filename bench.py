@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 RAY_BYTES, HIT_BYTES = 32, 16
 QUERY_BYTES, CLOSEST_BYTES = 16, 16  # bvh_point_query, bvh_closest
 LAYOUTS = ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq", "pbrt_soaos",
-           "pbrt_q16_soaos", "sg_eq_a16")
+           "pbrt_q16_soaos", "sg_eq_a16", "shared_slab")
 LEAF_TRI_BYTES = {"compact": 48, "indexed": 4 + 12 + 36}  # record, or id + index + 3 verts
 
 

@@ -52,7 +52,8 @@ extern "C" {
 #define BVH_LAYOUT_PBRT_SOAOS 6     /* AABB2 as a box array and a topology array, 24 + 8 B */
 #define BVH_LAYOUT_PBRT_Q16_SOAOS 7 /* PBRT_Q16 as a box array and a topology array, 12 + 4 B */
 #define BVH_LAYOUT_SG_EQ_A16 8      /* SG_EQ records padded to 16 B */
-#define BVH_NUM_LAYOUTS 9
+#define BVH_LAYOUT_SHARED_SLAB 9    /* binary, one slab per node refining the inherited box, 16 B */
+#define BVH_NUM_LAYOUTS 10
 
 /* Leaf storage. */
 #define BVH_LEAF_COMPACT 0 /* triangles copied into leaf order (bvh_tri records) */
@@ -281,6 +282,25 @@ typedef struct bvh_node_box_q16 {
 typedef struct bvh_node_sg_eq_a16 {
     uint32_t qlo, qhi, off, pad;
 } bvh_node_sg_eq_a16; /* 16 B */
+
+/*
+ * BVH_LAYOUT_SHARED_SLAB (the tree-carried shared slab of Sec. 8.3): the
+ * AABB2 tree in the same preorder, each node storing one slab [slo, shi]
+ * along one axis instead of a box.  A node's box is the box carried down
+ * from its parent with that axis replaced by the slab (the root's carried
+ * box is the scene box, bvh_stats.scene_lo/hi); the node's children inherit
+ * the result.  The slab axis is the one along which the node's exact box is
+ * narrowest relative to its parent's exact box (the lowest axis on ties),
+ * and the slab is the exact extent there, so every node's box encloses its
+ * triangles.  meta: bits 0..15 triangle count (0: interior), bits 16..17
+ * slab axis, bits 18..19 split axis (near-first order); offset as AABB2.
+ * The traversal carries a box per stack entry (per-lane stacks in a global
+ * work area); bvh_batch_create rejects this layout with EUNSUPPORTED.
+ */
+typedef struct bvh_node_slab {
+    float slo, shi;
+    uint32_t offset, meta;
+} bvh_node_slab; /* 16 B */
 
 typedef struct bvh_handle_s *bvh_handle_t;
 

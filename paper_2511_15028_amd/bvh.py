@@ -17,11 +17,11 @@ LIB_PATH = os.path.join(_PKG, "libbvh.so")
 # enums of bvh.h
 OK, EINVAL, ENOMEM, EHIP, ENODEV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 (LAYOUT_AABB2, LAYOUT_BVH4, LAYOUT_BVH8_Q8, LAYOUT_BVH8_Q16, LAYOUT_PBRT_Q16, LAYOUT_SG_EQ,
- LAYOUT_PBRT_SOAOS, LAYOUT_PBRT_Q16_SOAOS, LAYOUT_SG_EQ_A16) = range(9)
+ LAYOUT_PBRT_SOAOS, LAYOUT_PBRT_Q16_SOAOS, LAYOUT_SG_EQ_A16, LAYOUT_SHARED_SLAB) = range(10)
 LAYOUTS = {"aabb2": LAYOUT_AABB2, "bvh4": LAYOUT_BVH4, "bvh8_q8": LAYOUT_BVH8_Q8,
            "bvh8_q16": LAYOUT_BVH8_Q16, "pbrt_q16": LAYOUT_PBRT_Q16, "sg_eq": LAYOUT_SG_EQ,
            "pbrt_soaos": LAYOUT_PBRT_SOAOS, "pbrt_q16_soaos": LAYOUT_PBRT_Q16_SOAOS,
-           "sg_eq_a16": LAYOUT_SG_EQ_A16}
+           "sg_eq_a16": LAYOUT_SG_EQ_A16, "shared_slab": LAYOUT_SHARED_SLAB}
 LAYOUT_NAMES = {v: k for k, v in LAYOUTS.items()}
 LEAF_COMPACT, LEAF_INDEXED = 0, 1
 LEAF_MODES = {"compact": LEAF_COMPACT, "indexed": LEAF_INDEXED}
@@ -29,7 +29,7 @@ TRACE_CLOSEST, TRACE_ANY = 0, 1
 BUF_NODES, BUF_LEAF = 0, 1
 NODE_BYTES = {LAYOUT_AABB2: 32, LAYOUT_BVH4: 128, LAYOUT_BVH8_Q8: 128, LAYOUT_BVH8_Q16: 160,
               LAYOUT_PBRT_Q16: 16, LAYOUT_SG_EQ: 12, LAYOUT_PBRT_SOAOS: 32,
-              LAYOUT_PBRT_Q16_SOAOS: 16, LAYOUT_SG_EQ_A16: 16}
+              LAYOUT_PBRT_Q16_SOAOS: 16, LAYOUT_SG_EQ_A16: 16, LAYOUT_SHARED_SLAB: 16}
 
 
 class BVHError(RuntimeError):

@@ -612,6 +612,9 @@ extern "C" int32_t bvh_batch_create(const bvh_scene_desc *scenes, int32_t n_scen
             return set_error(BVH_EINVAL, "bvh_batch_create: bad mesh for scene %d", i);
         if (sd.layout < -1 || sd.layout >= BVH_NUM_LAYOUTS)
             return set_error(BVH_EINVAL, "bvh_batch_create: bad layout for scene %d", i);
+        if (sd.layout == BVH_LAYOUT_SHARED_SLAB)
+            return set_error(BVH_EUNSUPPORTED,
+                             "bvh_batch_create: scene %d: the shared-slab layout is not batched", i);
         if (sd.stack_lds != 0 && sd.stack_lds != 8 && sd.stack_lds != 16 && sd.stack_lds != 32)
             return set_error(BVH_EINVAL, "bvh_batch_create: bad stack_lds for scene %d", i);
         if (sd.reserved[0] || sd.reserved[1])

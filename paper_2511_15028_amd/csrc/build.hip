@@ -712,6 +712,38 @@ __global__ __launch_bounds__(kBlock) void k_pack_pbrt_q16(const bvh_node_aabb2 *
     }
 }
 
+// SHARED_SLAB: node c keeps one slab, the exact extent of its box along the
+// axis where that box is narrowest relative to its parent's box (the scene
+// box for the root; lowest axis on ties), written by its parent's thread.
+__device__ inline bvh_node_slab slab_record(const bvh_node_aabb2 &c, const float *plo,
+                                            const float *phi) {
+    int axis = 0;
+    float best = INFINITY;
+    for (int a = 0; a < 3; a++) {
+        const float pe = phi[a] - plo[a], ce = c.hi[a] - c.lo[a];
+        const float ratio = pe > 0.0f ? ce / pe : 1.0f;
+        if (ratio < best) {
+            best = ratio;
+            axis = a;
+        }
+    }
+    const uint32_t cnt = c.meta & 0xFFFFu, split = (c.meta >> 16) & 3u;
+    return bvh_node_slab{c.lo[axis], c.hi[axis], c.offset,
+                         cnt | ((uint32_t)axis << 16) | (split << 18)};
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_slab(const bvh_node_aabb2 *in, uint32_t n_nodes,
+                                                      const BuildInfo *info, bvh_node_slab *out) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_nodes) return;
+    const bvh_node_aabb2 nd = in[i];
+    if (i == 0) out[0] = slab_record(nd, info->slo, info->shi);
+    if ((nd.meta & 0xFFFFu) != 0u) return;
+    const uint32_t kids[2] = {i + 1u, i + nd.offset};
+    for (int k = 0; k < 2; k++)
+        if (kids[k] < n_nodes) out[kids[k]] = slab_record(in[kids[k]], nd.lo, nd.hi);
+}
+
 // AABB2 records split into a box array and a topology array (PBRT_SOAOS).
 __global__ __launch_bounds__(kBlock) void k_split_aabb2(const bvh_node_aabb2 *in, uint32_t n_nodes,
                                                         bvh_node_box_f32 *box, bvh_node_topo *topo) {
@@ -2024,6 +2056,19 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
             const_cast<bvh_node_topo *>(static_cast<const bvh_node_topo *>(
                 topo_of(h->nodes, h->n_nodes, h->layout))));
         BVH_TRY(check_launch("pbrt-soaos packing"));
+    } else if (h->layout == BVH_LAYOUT_SHARED_SLAB) {
+        // the AABB2 tree with one slab per node in place of its box
+        h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
+        Arena ar;
+        bvh_node_aabb2 *tmp = nullptr;
+        ar.request(&tmp, (size_t)h->n_nodes);
+        BVH_TRY(ar.bind(s, kAreaBuildWide));
+        BVH_TRY(alloc_handle_block(h, h->n_nodes));
+        k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
+                                                                      (uint32_t)h->n_nodes, info);
+        k_pack_slab<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
+            tmp, (uint32_t)h->n_nodes, info, static_cast<bvh_node_slab *>(h->nodes));
+        BVH_TRY(check_launch("shared-slab packing"));
     } else if (layout_scene_frame(h->layout)) {
         // the AABB2 tree, re-encoded node by node in the scene frame
         const bool pq = !layout_sg_eq(h->layout);

@@ -594,6 +594,117 @@ __global__ __launch_bounds__(kTraceBlock) void k_cpq_fallback(const void *nodes,
     }
 }
 
+// Shared-slab layout: each stack entry carries its node's own box (the
+// inherited box with the node's slab) and that box's distance.  Visiting an
+// interior node loads both children's slabs, forms their boxes and continues
+// with the nearer; grid-stride over the queries.
+template <int LeafMode, bool Count>
+__global__ __launch_bounds__(kTraceBlock) void k_cpq_slab(const bvh_node_slab *nodes,
+                                                          int64_t n_nodes, SceneData ld,
+                                                          const bvh_point_query *qs, uint64_t n,
+                                                          bvh_closest *out, uint32_t *counts,
+                                                          CarriedStack cs) {
+    const uint32_t lane = blockIdx.x * kTraceBlock + threadIdx.x;
+    for (uint64_t i = lane; i < n; i += cs.lanes) {
+        const Query q = load_query(qs, i);
+        CpqBest best{q.r2, 0.0f, 0.0f, 0xFFFFFFFFu};
+        uint32_t nfetch = 0, ntri = 0, sp = 0;
+        uint32_t cur = kRefEmpty, cnt = 0, off = 0, split = 0;
+        float lo[3], hi[3];  // the current node's own box
+        if (q.live && n_nodes > 0) {
+            const bvh_node_slab r0 = nodes[0];
+            nfetch++;
+            const uint32_t sa = (r0.meta >> 16) & 3u;
+            for (int k = 0; k < 3; k++) {
+                lo[k] = (uint32_t)k == sa ? r0.slo : ld.fo[k];
+                hi[k] = (uint32_t)k == sa ? r0.shi : ld.ft[k];
+            }
+            if (box_d2(q, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]) <= best.d2) {
+                cur = 0;
+                cnt = r0.meta & 0xFFFFu;
+                off = r0.offset;
+                split = (r0.meta >> 18) & 3u;
+            }
+        }
+        for (;;) {
+            if (cur == kRefEmpty) {
+                while (sp > 0) {
+                    sp--;
+                    const float d = cs.box[((size_t)sp * 7 + 6) * cs.lanes + lane];
+                    if (d <= best.d2) {
+                        cur = cs.ref[(size_t)sp * cs.lanes + lane];
+                        for (int k = 0; k < 3; k++) {
+                            lo[k] = cs.box[((size_t)sp * 7 + k) * cs.lanes + lane];
+                            hi[k] = cs.box[((size_t)sp * 7 + 3 + k) * cs.lanes + lane];
+                        }
+                        break;
+                    }
+                }
+                if (cur == kRefEmpty || cur >= (uint64_t)n_nodes) break;
+                const bvh_node_slab nd = nodes[cur];
+                nfetch++;
+                cnt = nd.meta & 0xFFFFu;
+                off = nd.offset;
+                split = (nd.meta >> 18) & 3u;
+            }
+            if (cnt > 0) {
+                cp_leaf<LeafMode>(ld, q, off, cnt, best, ntri);
+                cur = kRefEmpty;
+                continue;
+            }
+            const uint32_t ci[2] = {cur + 1u, cur + off};
+            if (ci[1] >= (uint64_t)n_nodes) break;  // bounds guard; a valid tree never takes it
+            const bvh_node_slab c0 = nodes[ci[0]], c1 = nodes[ci[1]];
+            nfetch += 2;
+            float clo[2][3], chi[2][3], d[2];
+            const bvh_node_slab cr[2] = {c0, c1};
+            for (int c = 0; c < 2; c++) {
+                const uint32_t sa = (cr[c].meta >> 16) & 3u;
+                for (int k = 0; k < 3; k++) {
+                    clo[c][k] = (uint32_t)k == sa ? cr[c].slo : lo[k];
+                    chi[c][k] = (uint32_t)k == sa ? cr[c].shi : hi[k];
+                }
+                d[c] = box_d2(q, clo[c][0], clo[c][1], clo[c][2], chi[c][0], chi[c][1], chi[c][2]);
+            }
+            const bool ok0 = d[0] <= best.d2, ok1 = d[1] <= best.d2;
+            int next = -1;
+            if (ok0 && ok1) {
+                const int nr = d[0] <= d[1] ? 0 : 1, fr = 1 - nr;
+                if (sp < cs.cap) {  // the build bounds the pushes per path by cap - 1
+                    cs.ref[(size_t)sp * cs.lanes + lane] = ci[fr];
+                    for (int k = 0; k < 3; k++) {
+                        cs.box[((size_t)sp * 7 + k) * cs.lanes + lane] = clo[fr][k];
+                        cs.box[((size_t)sp * 7 + 3 + k) * cs.lanes + lane] = chi[fr][k];
+                    }
+                    cs.box[((size_t)sp * 7 + 6) * cs.lanes + lane] = d[fr];
+                    sp++;
+                }
+                next = nr;
+            } else if (ok0 || ok1) {
+                next = ok0 ? 0 : 1;
+            }
+            if (next < 0) {
+                cur = kRefEmpty;
+                continue;
+            }
+            cur = ci[next];
+            cnt = cr[next].meta & 0xFFFFu;
+            off = cr[next].offset;
+            split = (cr[next].meta >> 18) & 3u;
+            for (int k = 0; k < 3; k++) {
+                lo[k] = clo[next][k];
+                hi[k] = chi[next][k];
+            }
+        }
+        (void)split;
+        store_closest(out, i, best);
+        if (Count) {
+            counts[2 * (size_t)i] = nfetch;
+            counts[2 * (size_t)i + 1] = ntri;
+        }
+    }
+}
+
 template <int Layout, int LeafMode, bool Count, int SL>
 int32_t launch_layout(const bvh_handle_s *h, const SceneData &ld, const bvh_point_query *qs,
                       uint64_t n, bvh_closest *out, uint32_t *counts, hipStream_t s) {
@@ -640,10 +751,20 @@ template <int LeafMode, bool Count>
 int32_t launch_mode(const bvh_handle_s *h, const bvh_point_query *qs, uint64_t n, bvh_closest *out,
                     uint32_t *counts, hipStream_t s) {
     const SceneData ld = scene_data(h);
-    // every stack entry carries a distance, so the LDS ring holds at most 16
-    // entries per lane (32 would halve the resident waves)
-    const int32_t rc = h->stack_lds == 8 ? launch_sl<LeafMode, Count, 8>(h, ld, qs, n, out, counts, s)
-                                         : launch_sl<LeafMode, Count, 16>(h, ld, qs, n, out, counts, s);
+    int32_t rc;
+    if (h->layout == BVH_LAYOUT_SHARED_SLAB) {
+        CarriedStack cs;
+        unsigned grid = 0;
+        rc = carried_stack(s, n, h->max_stack, 7, cs, grid);
+        if (rc == BVH_OK)
+            k_cpq_slab<LeafMode, Count><<<grid, kTraceBlock, 0, s>>>(
+                static_cast<const bvh_node_slab *>(h->nodes), h->n_nodes, ld, qs, n, out, counts, cs);
+    } else {
+        // every stack entry carries a distance, so the LDS ring holds at most
+        // 16 entries per lane (32 would halve the resident waves)
+        rc = h->stack_lds == 8 ? launch_sl<LeafMode, Count, 8>(h, ld, qs, n, out, counts, s)
+                               : launch_sl<LeafMode, Count, 16>(h, ld, qs, n, out, counts, s);
+    }
     if (rc != BVH_OK) return rc;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -108,6 +108,7 @@ inline int64_t node_record_bytes(int32_t layout) {
         case BVH_LAYOUT_PBRT_SOAOS: return sizeof(bvh_node_box_f32) + sizeof(bvh_node_topo);
         case BVH_LAYOUT_PBRT_Q16_SOAOS: return sizeof(bvh_node_box_q16) + sizeof(uint32_t);
         case BVH_LAYOUT_SG_EQ_A16: return sizeof(bvh_node_sg_eq_a16);
+        case BVH_LAYOUT_SHARED_SLAB: return sizeof(bvh_node_slab);
         default: return 0;
     }
 }
@@ -120,6 +121,7 @@ inline int32_t layout_arity(int32_t layout) {
         case BVH_LAYOUT_PBRT_SOAOS: return 2;
         case BVH_LAYOUT_PBRT_Q16_SOAOS: return 2;
         case BVH_LAYOUT_SG_EQ_A16: return 2;
+        case BVH_LAYOUT_SHARED_SLAB: return 2;
         case BVH_LAYOUT_BVH4: return 4;
         default: return 8;
     }
@@ -183,6 +185,7 @@ static_assert(sizeof(bvh_node_sg_eq) == 12, "sg-eq node");
 static_assert(sizeof(bvh_node_box_f32) == 24 && sizeof(bvh_node_topo) == 8, "pbrt-soaos arrays");
 static_assert(sizeof(bvh_node_box_q16) == 12, "pbrt-q16-soaos boxes");
 static_assert(sizeof(bvh_node_sg_eq_a16) == 16, "sg-eq-align16 node");
+static_assert(sizeof(bvh_node_slab) == 16, "shared-slab node");
 
 // Layouts whose node buffer is a box array followed by a topology array, and
 // the bytes of one box entry.

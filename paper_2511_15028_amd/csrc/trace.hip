@@ -193,6 +193,85 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_fallback(const void *node
     }
 }
 
+// Shared-slab layout: a node's box is the box inherited from its parent with
+// the node's one slab axis replaced, so every stack entry carries the box its
+// node inherits.  Grid-stride over the rays; single-loop order, near child
+// (split axis and ray sign) first.
+template <int LeafMode, int Mode, bool Count>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_slab(const bvh_node_slab *nodes,
+                                                            int64_t n_nodes, SceneData ld,
+                                                            const bvh_ray *rays, uint64_t n,
+                                                            bvh_hit *hits, uint32_t *counts,
+                                                            CarriedStack cs) {
+    const uint32_t lane = blockIdx.x * kTraceBlock + threadIdx.x;
+    for (uint64_t i = lane; i < n; i += cs.lanes) {
+        const Ray r = load_ray(rays, i, ld.coord_max);
+        Best best{INFINITY, 0.0f, 0.0f, 0xFFFFFFFFu};
+        uint32_t nfetch = 0, ntri = 0, sp = 0;
+        uint32_t cur = n_nodes > 0 ? 0u : kRefEmpty;
+        float lo[3] = {ld.fo[0], ld.fo[1], ld.fo[2]}, hi[3] = {ld.ft[0], ld.ft[1], ld.ft[2]};
+        for (;;) {
+            if (cur == kRefEmpty) {
+                if (sp == 0) break;
+                sp--;
+                cur = cs.ref[(size_t)sp * cs.lanes + lane];
+                for (int k = 0; k < 3; k++) {
+                    lo[k] = cs.box[((size_t)sp * 6 + k) * cs.lanes + lane];
+                    hi[k] = cs.box[((size_t)sp * 6 + 3 + k) * cs.lanes + lane];
+                }
+            }
+            if (cur >= (uint64_t)n_nodes) break;  // bounds guard; a valid tree never takes it
+            const bvh_node_slab nd = nodes[cur];
+            nfetch++;
+            const uint32_t cnt = nd.meta & 0xFFFFu, sa = (nd.meta >> 16) & 3u;
+            const uint32_t split = (nd.meta >> 18) & 3u;
+            for (int k = 0; k < 3; k++) {
+                lo[k] = (uint32_t)k == sa ? nd.slo : lo[k];
+                hi[k] = (uint32_t)k == sa ? nd.shi : hi[k];
+            }
+            const float tcur = best_bound<Mode>(r, best);
+            const float tn = r.fast ? slab<true>(r, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], tcur)
+                                    : slab<false>(r, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], tcur);
+            if (tn == INFINITY) {
+                cur = kRefEmpty;
+                continue;
+            }
+            if (cnt > 0) {
+                if (test_leaf<LeafMode, Mode>(ld, r, nd.offset, cnt, best, ntri)) break;
+                cur = kRefEmpty;
+                continue;
+            }
+            const bool neg = split == 0 ? r.nx : (split == 1 ? r.ny : r.nz);
+            const uint32_t left = cur + 1u, right = cur + nd.offset;
+            if (sp < cs.cap) {  // the build bounds the pushes per path by cap - 1
+                cs.ref[(size_t)sp * cs.lanes + lane] = neg ? left : right;
+                for (int k = 0; k < 3; k++) {
+                    cs.box[((size_t)sp * 6 + k) * cs.lanes + lane] = lo[k];
+                    cs.box[((size_t)sp * 6 + 3 + k) * cs.lanes + lane] = hi[k];
+                }
+                sp++;
+            }
+            cur = neg ? right : left;
+        }
+        store_hit(hits, i, best);
+        if (Count) {
+            counts[2 * (size_t)i] = nfetch;
+            counts[2 * (size_t)i + 1] = ntri;
+        }
+    }
+}
+
+template <int LeafMode, int Mode, bool Count>
+int32_t launch_slab(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *rays, uint64_t n,
+                    bvh_hit *hits, uint32_t *counts, hipStream_t s) {
+    CarriedStack cs;
+    unsigned grid = 0;
+    BVH_TRY(carried_stack(s, n, h->max_stack, 6, cs, grid));
+    k_trace_slab<LeafMode, Mode, Count><<<grid, kTraceBlock, 0, s>>>(
+        static_cast<const bvh_node_slab *>(h->nodes), h->n_nodes, ld, rays, n, hits, counts, cs);
+    return BVH_OK;
+}
+
 constexpr bool kPersistent = true;
 
 template <int Layout, int LeafMode, int Mode, bool Count, int SL>
@@ -257,7 +336,9 @@ int32_t launch_mode(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_
                     uint32_t *counts, hipStream_t s) {
     const SceneData ld = scene_data(h);
     int32_t rc;
-    if (h->stack_lds == 8)
+    if (h->layout == BVH_LAYOUT_SHARED_SLAB)
+        rc = launch_slab<LeafMode, Mode, Count>(h, ld, rays, n, hits, counts, s);
+    else if (h->stack_lds == 8)
         rc = launch_sl<LeafMode, Mode, Count, 8>(h, ld, rays, n, hits, counts, s);
     else if (h->stack_lds == 32)
         rc = launch_sl<LeafMode, Mode, Count, 32>(h, ld, rays, n, hits, counts, s);

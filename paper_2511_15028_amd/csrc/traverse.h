@@ -1144,13 +1144,44 @@ __device__ inline void fallback_append(const Fallback &fb, uint32_t ray) {
 // ---------------------------------------------------------------------------
 // Host-side launch helpers of the persistent kernels.
 // ---------------------------------------------------------------------------
-// Per-scene data of a handle for the traversal kernels.
+// Per-scene data of a handle for the traversal kernels.  SHARED_SLAB carries
+// the scene box (the root's inherited box) in fo (lower) and ft (upper).
 inline SceneData scene_data(const bvh_handle_s *h) {
+    const bool slab = h->layout == BVH_LAYOUT_SHARED_SLAB;
+    const float *lo = slab ? h->scene_lo : h->frame_origin;
+    const float *top = slab ? h->scene_hi : h->frame_top;
     return SceneData{h->leaf, h->verts, h->tris, (uint32_t)h->n_tris, h->coord_max(),
-                     {h->frame_origin[0], h->frame_origin[1], h->frame_origin[2]},
+                     {lo[0], lo[1], lo[2]},
                      {h->frame_scale[0], h->frame_scale[1], h->frame_scale[2]},
-                     {h->frame_top[0], h->frame_top[1], h->frame_top[2]},
+                     {top[0], top[1], top[2]},
                      topo_of(h->nodes, h->n_nodes, h->layout)};
+}
+
+// Per-lane stacks of the shared-slab kernels in a global work area: entry e
+// of lane l is ref[e * lanes + l] and words box[(e * W + k) * lanes + l],
+// k < W, of the box (and, for point queries, distance) it carries.
+struct CarriedStack {
+    uint32_t *ref;
+    float *box;
+    uint32_t lanes, cap;
+};
+
+// Launch shape of the shared-slab kernels: grid-stride over the queries with
+// at most kSlabLanes lanes, each with a stack of cap entries of W words.
+constexpr uint32_t kSlabLanes = 131072;
+inline int32_t carried_stack(hipStream_t s, uint64_t n, int32_t max_stack, int words,
+                             CarriedStack &cs, unsigned &grid) {
+    const uint64_t need = (n + kTraceBlock - 1) / kTraceBlock;
+    grid = (unsigned)std::min<uint64_t>(need, kSlabLanes / kTraceBlock);
+    if (grid == 0) grid = 1;
+    cs.lanes = grid * kTraceBlock;
+    cs.cap = (uint32_t)(max_stack > 0 ? max_stack : 1) + 1u;
+    const size_t ref_bytes = ((size_t)cs.lanes * cs.cap * 4 + 255) & ~(size_t)255;
+    void *ws = nullptr;
+    BVH_TRY(stream_workspace(s, kAreaTrace, ref_bytes + (size_t)cs.lanes * cs.cap * words * 4, &ws));
+    cs.ref = static_cast<uint32_t *>(ws);
+    cs.box = reinterpret_cast<float *>(static_cast<char *>(ws) + ref_bytes);
+    return BVH_OK;
 }
 // Spill entries per lane of a persistent launch (beyond the LDS ring).
 constexpr uint32_t kSpillCap = 64;

@@ -10,7 +10,7 @@ from __future__ import annotations
 import numpy as np
 
 AABB2, BVH4, BVH8_Q8, BVH8_Q16, PBRT_Q16, SG_EQ = 0, 1, 2, 3, 4, 5
-PBRT_SOAOS, PBRT_Q16_SOAOS, SG_EQ_A16 = 6, 7, 8
+PBRT_SOAOS, PBRT_Q16_SOAOS, SG_EQ_A16, SHARED_SLAB = 6, 7, 8, 9
 
 AABB2_DT = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("offset", "<u4"), ("meta", "<u4")])
 BVH4_DT = np.dtype([("lo_x", "<f4", 4), ("lo_y", "<f4", 4), ("lo_z", "<f4", 4),
@@ -41,6 +41,9 @@ SGEQ16_DT = np.dtype([("qlo", "<u4"), ("qhi", "<u4"), ("off", "<u4"), ("pad", "<
 assert BOXF_DT.itemsize == 24 and TOPO_DT.itemsize == 8 and BOXQ_DT.itemsize == 12
 assert SGEQ16_DT.itemsize == 16
 VARIANT_BYTES = {PBRT_SOAOS: 32, PBRT_Q16_SOAOS: 16, SG_EQ_A16: 16}
+SLAB_DT = np.dtype([("slo", "<f4"), ("shi", "<f4"), ("offset", "<u4"), ("meta", "<u4")])
+assert SLAB_DT.itemsize == 16
+DTYPES[SHARED_SLAB] = SLAB_DT
 
 
 def as_base(layout, nodes_bytes):
@@ -169,6 +172,27 @@ def walk(layout, nodes_bytes, frame=None):
     leaves = []
     visited = np.zeros(len(nodes), np.int64)
     if len(nodes) == 0:
+        return nodes, leaves, visited
+    if layout == SHARED_SLAB:
+        # frame = (scene lo, scene hi): the root's inherited box
+        root = np.concatenate([np.asarray(frame[0], np.float32), np.asarray(frame[1], np.float32)])
+        stack = [(0, root, [])]
+        while stack:
+            i, carried, path = stack.pop()
+            visited[i] += 1
+            rec = nodes[i]
+            meta = int(rec["meta"])
+            a = (meta >> 16) & 3
+            assert a < 3
+            box = carried.copy()
+            box[a], box[3 + a] = rec["slo"], rec["shi"]
+            nprim = meta & 0xFFFF
+            if nprim > 0:
+                leaves.append((int(rec["offset"]), nprim, path + [box]))
+            else:
+                assert rec["offset"] >= 2
+                stack.append((i + 1, box, path + [box]))
+                stack.append((i + int(rec["offset"]), box, path + [box]))
         return nodes, leaves, visited
     if layout in (PBRT_Q16, SG_EQ):
         stack = [(0, [])]

@@ -53,7 +53,7 @@ def test_build_argument_validation(L):
     assert h.value is None
     assert L.bvh_build(None, 3, fake, 1, 0, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
     assert L.bvh_build(fake, 0, fake, 1, 0, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
-    assert L.bvh_build(fake, 3, fake, 1, 9, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
+    assert L.bvh_build(fake, 3, fake, 1, 10, ctypes.byref(opts), None, ctypes.byref(h)) == bvh.EINVAL
     assert b"layout" in L.bvh_last_error()
     for bad in (bvh.BuildOpts(0, 5), bvh.BuildOpts(17, 0), bvh.BuildOpts(-1, 0),
                 bvh.BuildOpts(4, 0, 0, 2)):
@@ -127,8 +127,10 @@ def test_batch_argument_validation(L):
     descs = (bvh.SceneDesc * 2)()
     assert L.bvh_batch_create(descs, 0, None, None, ctypes.byref(b)) == bvh.EINVAL
     assert b.value is None
-    descs[0].layout = 9
+    descs[0].layout = 10
     assert L.bvh_batch_create(descs, 2, None, None, ctypes.byref(b)) == bvh.EINVAL
+    descs[0].layout = bvh.LAYOUT_SHARED_SLAB  # carries boxes per stack entry: not batched
+    assert L.bvh_batch_create(descs, 2, None, None, ctypes.byref(b)) == bvh.EUNSUPPORTED
     descs[0].layout = -1
     descs[1].stack_lds = 12
     assert L.bvh_batch_create(descs, 2, None, None, ctypes.byref(b)) == bvh.EINVAL

@@ -28,7 +28,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 LAYOUTS = ["aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq", "pbrt_soaos",
-           "pbrt_q16_soaos", "sg_eq_a16"]
+           "pbrt_q16_soaos", "sg_eq_a16", "shared_slab"]
 TOL = 2.0 ** -19
 
 

@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 
 LAYOUTS = {"aabb2": LD.AABB2, "bvh4": LD.BVH4, "bvh8_q8": LD.BVH8_Q8, "bvh8_q16": LD.BVH8_Q16,
            "pbrt_q16": LD.PBRT_Q16, "sg_eq": LD.SG_EQ, "pbrt_soaos": LD.PBRT_SOAOS,
-           "pbrt_q16_soaos": LD.PBRT_Q16_SOAOS, "sg_eq_a16": LD.SG_EQ_A16}
+           "pbrt_q16_soaos": LD.PBRT_Q16_SOAOS, "sg_eq_a16": LD.SG_EQ_A16,
+           "shared_slab": LD.SHARED_SLAB}
 
 
 def _build(v, t, layout, leaf_mode="compact", leaf_size=4):
@@ -53,8 +54,9 @@ def test_round_trip(layout, leaf_mode, scene):
     lid = LAYOUTS[layout]
     nodes_bytes = h.read_buffer(bvh.BUF_NODES)
     assert len(nodes_bytes) == st["n_nodes"] * st["node_bytes"]
-    nodes, leaves, visited = LD.walk(lid, nodes_bytes,
-                                     (st["frame_origin"], st["frame_scale"], st["frame_top"]))
+    frame = ((st["scene_lo"], st["scene_hi"]) if lid == LD.SHARED_SLAB else
+             (st["frame_origin"], st["frame_scale"], st["frame_top"]))
+    nodes, leaves, visited = LD.walk(lid, nodes_bytes, frame)
     assert (visited == 1).all(), "every node reachable exactly once"
     assert len(leaves) == st["n_leaves"]
     leaf_raw = h.read_buffer(bvh.BUF_LEAF)
@@ -84,7 +86,7 @@ def test_round_trip(layout, leaf_mode, scene):
     assert (covered == 1).all()
     assert st["max_stack"] >= 1 and st["depth"] >= 2
     assert st["nodes_buffer_bytes"] == st["n_nodes"] * {0: 32, 1: 128, 2: 128, 3: 160, 4: 16, 5: 12,
-                                                        6: 32, 7: 16, 8: 16}[lid]
+                                                        6: 32, 7: 16, 8: 16, 9: 16}[lid]
 
 
 @pytest.mark.parametrize("layout", list(LAYOUTS))
@@ -241,3 +243,37 @@ def test_soaos_and_align16_hold_the_base_records(variant, base, scene):
     want = np.frombuffer(hb.read_buffer(bvh.BUF_NODES), LD.DTYPES[base_id])
     assert rec.tobytes() == want.tobytes()
     assert hv.read_buffer(bvh.BUF_LEAF) == hb.read_buffer(bvh.BUF_LEAF)
+
+
+@pytest.mark.parametrize("scene", list(SCENES))
+def test_shared_slab_matches_aabb2(scene):
+    """The shared-slab tree is the AABB2 tree: node i has AABB2 node i's count,
+    offset and split axis, and its slab is AABB2 node i's exact extent along
+    the axis where that box is narrowest relative to its parent's box (the
+    scene box for the root; lowest axis on ties)."""
+    from paper_2511_15028_amd import bvh
+    v, t = SCENES[scene]
+    hs, ha = _build(v, t, "shared_slab"), _build(v, t, "aabb2")
+    sl = np.frombuffer(hs.read_buffer(bvh.BUF_NODES), LD.SLAB_DT)
+    ab = np.frombuffer(ha.read_buffer(bvh.BUF_NODES), LD.AABB2_DT)
+    assert len(sl) == len(ab)
+    st = hs.stats()
+    parent_lo = np.empty((len(ab), 3), np.float32)
+    parent_hi = np.empty((len(ab), 3), np.float32)
+    parent_lo[0], parent_hi[0] = st["scene_lo"], st["scene_hi"]
+    for i in range(len(ab)):
+        if ab["meta"][i] & 0xFFFF == 0:
+            for c in (i + 1, i + int(ab["offset"][i])):
+                parent_lo[c], parent_hi[c] = ab["lo"][i], ab["hi"][i]
+    np.testing.assert_array_equal(sl["offset"], ab["offset"])
+    np.testing.assert_array_equal(sl["meta"] & 0xFFFF, ab["meta"] & 0xFFFF)
+    np.testing.assert_array_equal((sl["meta"] >> 18) & 3, (ab["meta"] >> 16) & 3)
+    pe = (parent_hi - parent_lo).astype(np.float32)
+    ce = (ab["hi"] - ab["lo"]).astype(np.float32)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(pe > 0, (ce / np.where(pe > 0, pe, 1)).astype(np.float32), np.float32(1.0))
+    axis = np.argmin(ratio, axis=1)
+    np.testing.assert_array_equal((sl["meta"] >> 16) & 3, axis)
+    rows = np.arange(len(ab))
+    np.testing.assert_array_equal(sl["slo"], ab["lo"][rows, axis])
+    np.testing.assert_array_equal(sl["shi"], ab["hi"][rows, axis])
