@@ -15,58 +15,102 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Vertex-gradient contributions of a block are first summed in an LDS hash
+// table keyed by vertex index (open addressing, linear probing), then added
+// to grad_verts with one atomic per distinct vertex and component.  Rays of
+// a block (neighbouring pixels) share most of their vertices, so this cuts
+// the global atomics several-fold and removes same-address conflicts within
+// an instruction.  A block touches at most 3 * kBlock vertices, below the
+// table size, so an insertion always finds a slot.
+constexpr int kTableSlots = 1024;
+static_assert(kTableSlots >= 3 * kBlock, "hash table must hold every vertex of a block");
+
+__device__ inline uint32_t slot_of(int32_t v) {
+    return ((uint32_t)v * 2654435761u) >> (32 - 10);  // Fibonacci hashing, 10 bits
+}
+
+// lam and the ray gradient of ray i; false for a miss, an out-of-range
+// primitive or vertex index, or a singular system.
+__device__ inline bool ray_grad(const float *verts, int64_t n_verts, const int32_t *tris,
+                                int64_t n_tris, const bvh_ray *rays, const bvh_hit *hits,
+                                const float *grad_hits, uint64_t i, float *out, int32_t *idx,
+                                float *w, float *lam) {
+    const int4 hw = reinterpret_cast<const int4 *>(hits)[i];
+    const int32_t prim = hw.x;
+    if (prim < 0 || (int64_t)prim >= n_tris) return false;
+    for (int k = 0; k < 3; k++) {
+        idx[k] = tris[3 * (size_t)prim + k];
+        if (idx[k] < 0 || (int64_t)idx[k] >= n_verts) return false;
+    }
+    const float t = __int_as_float(hw.y), u = __int_as_float(hw.z), v = __int_as_float(hw.w);
+    const float4 rb = reinterpret_cast<const float4 *>(rays + i)[1];
+    const float *q0 = verts + 3 * (size_t)idx[0];
+    const float *q1 = verts + 3 * (size_t)idx[1];
+    const float *q2 = verts + 3 * (size_t)idx[2];
+    const float ax = rb.x, ay = rb.y, az = rb.z;                              // d
+    const float bx = q0[0] - q1[0], by = q0[1] - q1[1], bz = q0[2] - q1[2];  // p0 - p1
+    const float cx = q0[0] - q2[0], cy = q0[1] - q2[1], cz = q0[2] - q2[2];  // p0 - p2
+    const float bcx = by * cz - bz * cy, bcy = bz * cx - bx * cz, bcz = bx * cy - by * cx;
+    const float cax = cy * az - cz * ay, cay = cz * ax - cx * az, caz = cx * ay - cy * ax;
+    const float abx = ay * bz - az * by, aby = az * bx - ax * bz, abz = ax * by - ay * bx;
+    const float det = ax * bcx + ay * bcy + az * bcz;
+    if (det == 0.0f) return false;
+    const float gt = grad_hits[3 * i], gu = grad_hits[3 * i + 1], gv = grad_hits[3 * i + 2];
+    const float inv = 1.0f / det;
+    lam[0] = (gt * bcx + gu * cax + gv * abx) * inv;
+    lam[1] = (gt * bcy + gu * cay + gv * aby) * inv;
+    lam[2] = (gt * bcz + gu * caz + gv * abz) * inv;
+    for (int k = 0; k < 3; k++) {
+        out[k] = -lam[k];
+        out[3 + k] = -t * lam[k];
+    }
+    w[0] = 1.0f - u - v;
+    w[1] = u;
+    w[2] = v;
+    return true;
+}
+
 __global__ __launch_bounds__(kBlock) void k_backward(const float *verts, int64_t n_verts,
                                                      const int32_t *tris, int64_t n_tris,
                                                      const bvh_ray *rays, uint64_t n,
                                                      const bvh_hit *hits, const float *grad_hits,
                                                      float *grad_verts, float *grad_rays) {
-    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    float out[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const int4 hw = reinterpret_cast<const int4 *>(hits)[i];
-    const int32_t prim = hw.x;
-    bool ok = prim >= 0 && (int64_t)prim < n_tris;
-    int32_t idx[3] = {0, 0, 0};
-    if (ok) {
-        for (int k = 0; k < 3; k++) {
-            idx[k] = tris[3 * (size_t)prim + k];
-            ok = ok && idx[k] >= 0 && (int64_t)idx[k] < n_verts;
-        }
+    __shared__ int32_t skey[kTableSlots];
+    __shared__ float sval[3][kTableSlots];
+    for (int s = threadIdx.x; s < kTableSlots; s += kBlock) {
+        skey[s] = -1;
+        sval[0][s] = sval[1][s] = sval[2][s] = 0.0f;
     }
-    if (ok) {
-        const float t = __int_as_float(hw.y), u = __int_as_float(hw.z), v = __int_as_float(hw.w);
-        const float4 *rp = reinterpret_cast<const float4 *>(rays + i);
-        const float4 ra = rp[0], rb = rp[1];
-        const float *q0 = verts + 3 * (size_t)idx[0];
-        const float *q1 = verts + 3 * (size_t)idx[1];
-        const float *q2 = verts + 3 * (size_t)idx[2];
-        const float ax = rb.x, ay = rb.y, az = rb.z;                       // d
-        const float bx = q0[0] - q1[0], by = q0[1] - q1[1], bz = q0[2] - q1[2];  // p0 - p1
-        const float cx = q0[0] - q2[0], cy = q0[1] - q2[1], cz = q0[2] - q2[2];  // p0 - p2
-        const float bcx = by * cz - bz * cy, bcy = bz * cx - bx * cz, bcz = bx * cy - by * cx;
-        const float cax = cy * az - cz * ay, cay = cz * ax - cx * az, caz = cx * ay - cy * ax;
-        const float abx = ay * bz - az * by, aby = az * bx - ax * bz, abz = ax * by - ay * bx;
-        const float det = ax * bcx + ay * bcy + az * bcz;
-        (void)ra;
-        if (det != 0.0f) {
-            const float gt = grad_hits[3 * i], gu = grad_hits[3 * i + 1], gv = grad_hits[3 * i + 2];
-            const float inv = 1.0f / det;
-            const float lx = (gt * bcx + gu * cax + gv * abx) * inv;
-            const float ly = (gt * bcy + gu * cay + gv * aby) * inv;
-            const float lz = (gt * bcz + gu * caz + gv * abz) * inv;
-            out[0] = -lx; out[1] = -ly; out[2] = -lz;
-            out[3] = -t * lx; out[4] = -t * ly; out[5] = -t * lz;
-            const float w[3] = {1.0f - u - v, u, v};
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        float out[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, w[3], lam[3];
+        int32_t idx[3];
+        if (ray_grad(verts, n_verts, tris, n_tris, rays, hits, grad_hits, i, out, idx, w, lam)) {
             for (int k = 0; k < 3; k++) {
-                float *g = grad_verts + 3 * (size_t)idx[k];
-                unsafeAtomicAdd(g + 0, w[k] * lx);
-                unsafeAtomicAdd(g + 1, w[k] * ly);
-                unsafeAtomicAdd(g + 2, w[k] * lz);
+                uint32_t h = slot_of(idx[k]);
+                for (int probe = 0; probe < kTableSlots; probe++) {
+                    const int32_t prev = atomicCAS(&skey[h], -1, idx[k]);
+                    if (prev == -1 || prev == idx[k]) break;
+                    h = (h + 1u) & (kTableSlots - 1);
+                }
+                atomicAdd(&sval[0][h], w[k] * lam[0]);
+                atomicAdd(&sval[1][h], w[k] * lam[1]);
+                atomicAdd(&sval[2][h], w[k] * lam[2]);
             }
         }
+        float *gr = grad_rays + 6 * i;
+        for (int k = 0; k < 6; k++) gr[k] = out[k];
     }
-    float *gr = grad_rays + 6 * i;
-    for (int k = 0; k < 6; k++) gr[k] = out[k];
+    __syncthreads();
+    for (int s = threadIdx.x; s < kTableSlots; s += kBlock) {
+        const int32_t key = skey[s];
+        if (key < 0) continue;
+        float *g = grad_verts + 3 * (size_t)key;
+        unsafeAtomicAdd(g + 0, sval[0][s]);
+        unsafeAtomicAdd(g + 1, sval[1][s]);
+        unsafeAtomicAdd(g + 2, sval[2][s]);
+    }
 }
 
 }  // namespace
