@@ -136,11 +136,47 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const uint32_t *in, uint3
     }
 }
 
+// Short arrays (a few tiles) in one block: tile after tile with a carry.
+constexpr uint32_t kScanSingleTiles = 8;
+
+__global__ __launch_bounds__(kBlock) void k_scan_single(const uint32_t *in, uint32_t *out,
+                                                        uint32_t n, uint32_t *total_out) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < n; c += kScanTile) {
+        const uint32_t base = c + threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            v[k] = base + k < n ? in[base + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t tot;
+        uint32_t run = carry + block_excl_scan(sum, &tot, wsum);
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            if (base + k < n) out[base + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+        __syncthreads();  // wsum is reused by the next tile
+    }
+    if (threadIdx.x == 0 && total_out) {
+        *total_out = carry;
+        __threadfence_system();  // the total may live in host memory the host polls
+    }
+}
+
 // Exclusive scan of n values; total (device) receives the sum if non-null.
 // tile_sums must hold ceil(n / kScanTile) entries.
 void scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tile_sums,
               uint32_t *total, hipStream_t s) {
     const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles <= kScanSingleTiles) {
+        k_scan_single<<<1, kBlock, 0, s>>>(in, out, n, total);
+        return;
+    }
     if (ntiles > 0) k_scan_reduce<<<ntiles, kBlock, 0, s>>>(in, n, tile_sums);
     k_scan_tiles<<<1, kBlock, 0, s>>>(tile_sums, ntiles, total);
     if (ntiles > 0) k_scan_final<<<ntiles, kBlock, 0, s>>>(in, out, n, tile_sums);
@@ -470,12 +506,20 @@ __global__ __launch_bounds__(kBlock) void k_leaf_boxes(const Box *pbox, const ui
     if ((threadIdx.x & (kWave - 1)) == kWave - 1 && blk * kRangeBlock < n) table[blk] = box_of(p);
 }
 
-// Sparse-table level k from level k-1: T_k[i] = T_{k-1}[i] u T_{k-1}[i + 2^(k-1)].
-__global__ __launch_bounds__(kBlock) void k_table_level(const Box *prev, Box *cur, int nblocks,
-                                                        int half) {
+// Sparse-table levels k0 .. k0+m-1 (m <= 3) from level k0-1 in one launch:
+// T_{k0-1+d}[i] = union over j < 2^d of T_{k0-1}[i + j 2^(k0-1)], written
+// where the entry's 2^(k0-1+d) blocks lie inside the table.
+__global__ __launch_bounds__(kBlock) void k_table_levels(Box *table, int nblocks, int k0, int m) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i + 2 * half > nblocks) return;
-    cur[i] = box_union(prev[i], prev[i + half]);
+    const int half = 1 << (k0 - 1);
+    const Box *base = table + (size_t)(k0 - 1) * nblocks;
+    Box u = box_empty();
+    for (int d = 1; d <= m; d++) {
+        if (i + (half << d) > nblocks) return;
+        // fold in the entries j in [2^(d-1), 2^d)
+        for (int j = (d == 1 ? 0 : 1 << (d - 1)); j < (1 << d); j++) u = box_union(u, base[i + j * half]);
+        table[(size_t)(k0 - 1 + d) * nblocks + i] = u;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirst,
@@ -1030,7 +1074,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base
 // and emit per level with block barriers instead of kernel launches and host
 // round trips.  Leaves (base, count, frontier buffer) for the multi-block
 // levels in state[0..2] (host-mapped words; state[2] last).
-constexpr uint32_t kTopMaxFrontier = 2048;
+constexpr uint32_t kTopMaxFrontier = 512;
 
 template <int Layout>
 __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, int32_t *fr_node0,
@@ -2006,11 +2050,9 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     }
     {  // a5
         k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table, pre, suf);
-        for (int k = 1; k < levels; k++) {
-            const int half = 1 << (k - 1);
-            k_table_level<<<grid_for(nblocks), kBlock, 0, s>>>(
-                table + (size_t)(k - 1) * nblocks, table + (size_t)k * nblocks, nblocks, half);
-        }
+        for (int k = 1; k < levels; k += 3)
+            k_table_levels<<<grid_for(nblocks), kBlock, 0, s>>>(table, nblocks, k,
+                                                                std::min(3, levels - k));
         if (n > 1)
             k_internal_boxes<<<grid_for(n - 1), kBlock, 0, s>>>(ifirst, icount, n, table, nblocks,
                                                                 pre, suf, nbox, area);
