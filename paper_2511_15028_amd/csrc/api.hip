@@ -43,6 +43,7 @@ extern "C" int32_t bvh_destroy(bvh_handle_t h) {
     if (hipSetDevice(h->device) == hipSuccess) {
         (void)hipDeviceSynchronize();
         if (h->block) (void)hipFree(h->block);
+        if (h->node_block) (void)hipFree(h->node_block);
     }
     if (have_prev) (void)hipSetDevice(prev);
     delete h;

@@ -72,6 +72,14 @@ __device__ inline float wave_min(float v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
     return v;
 }
+// One atomicMax per wave: every lane of the wave must reach the call (lanes
+// with nothing to report pass 0).
+__device__ inline void wave_atomic_max(uint32_t *addr, uint32_t v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicMax(addr, v);
+}
+
 __device__ inline float wave_max(float v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
@@ -594,11 +602,10 @@ __global__ __launch_bounds__(kBlock) void k_mark_leaves(TreeView tv, uint32_t *m
 // collapsed tree is lturns(x) + 2 * leaf_before(x), and the right child of
 // interior x sits 2 * (leaf_before(right) - leaf_before(x)) after x.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_emit_aabb2(TreeView tv, const uint32_t *lbefore,
-                                                       bvh_node_aabb2 *nodes, uint32_t n_nodes,
-                                                       BuildInfo *info) {
-    const int x = blockIdx.x * kBlock + threadIdx.x;
-    if (x >= 2 * tv.n - 1 || !tv.alive(x)) return;
+// Writes node x's record; reports its depth and, for a leaf, its stack need.
+__device__ inline void emit_aabb2_item(const TreeView &tv, int x, const uint32_t *lbefore,
+                                       bvh_node_aabb2 *nodes, uint32_t n_nodes, BuildInfo *info,
+                                       uint32_t *depth_out, uint32_t *stack_out) {
     uint32_t lturns = 0, depth = 1;
     for (int y = x; y != 0; depth++) {
         const int p = tv.parent[y];
@@ -628,8 +635,19 @@ __global__ __launch_bounds__(kBlock) void k_emit_aabb2(TreeView tv, const uint32
         nd.meta = (uint32_t)tv.iaxis[x] << 16;
     }
     nodes[idx] = nd;
-    atomicMax(&info->max_depth, depth);
-    if (tv.is_leaf(x)) atomicMax(&info->max_stack, depth - 1);
+    *depth_out = depth;
+    if (tv.is_leaf(x)) *stack_out = depth - 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit_aabb2(TreeView tv, const uint32_t *lbefore,
+                                                       bvh_node_aabb2 *nodes, uint32_t n_nodes,
+                                                       BuildInfo *info) {
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t depth = 0, stack = 0;
+    if (x < 2 * tv.n - 1 && tv.alive(x))
+        emit_aabb2_item(tv, x, lbefore, nodes, n_nodes, info, &depth, &stack);
+    wave_atomic_max(&info->max_depth, depth);
+    wave_atomic_max(&info->max_stack, stack);
 }
 
 // ---------------------------------------------------------------------------
@@ -1015,7 +1033,8 @@ template <int Layout>
 __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_t count,
                                       uint32_t cap, uint32_t f, int x, uint32_t aux,
                                       const int32_t *cand_f, uint32_t noff_f, void *nodes,
-                                      int32_t *next_node, uint32_t *next_aux, BuildInfo *info) {
+                                      int32_t *next_node, uint32_t *next_aux, BuildInfo *info,
+                                      uint32_t *stack_out, uint32_t *depth_out) {
     constexpr int K = WideOut<Layout>::K;
     if (base + f >= cap) {
         atomicOr(&info->err, 4u);
@@ -1052,8 +1071,8 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
     stack_need += (uint32_t)(nc - 1);
     for (uint32_t k = 0; k < r; k++) next_aux[noff_f + k] = (stack_need & 0xFFFFu) | (depth << 16);
     WideOut<Layout>::write(nodes, base + f, tv.nbox[x], cb, ref, nc, &info->err);
-    atomicMax(&info->max_stack, stack_need);
-    atomicMax(&info->max_depth, depth + 1);  // + the leaf level below
+    *stack_out = max(*stack_out, stack_need);
+    *depth_out = max(*depth_out, depth + 1);  // + the leaf level below
 }
 
 template <int Layout>
@@ -1065,9 +1084,12 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base
                                                       BuildInfo *info) {
     constexpr int K = WideOut<Layout>::K;
     const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= count) return;
-    wide_emit_item<Layout>(tv, base, count, cap, f, fr_node[f], fr_aux[f], cand + (size_t)f * K,
-                           noff[f], nodes, next_node, next_aux, info);
+    uint32_t stack = 0, depth = 0;
+    if (f < count)
+        wide_emit_item<Layout>(tv, base, count, cap, f, fr_node[f], fr_aux[f], cand + (size_t)f * K,
+                               noff[f], nodes, next_node, next_aux, info, &stack, &depth);
+    wave_atomic_max(&info->max_stack, stack);
+    wave_atomic_max(&info->max_depth, depth);
 }
 
 // The top levels, while the frontier is small, in one workgroup: open, scan
@@ -1089,7 +1111,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
         fr_aux0[0] = 0;
     }
     __syncthreads();
-    uint32_t base = 0, count = 1;
+    uint32_t base = 0, count = 1, stack = 0, depth = 0;
     int cur = 0;
     for (int level = 0; level < 64 && count > 0 && count <= kTopMaxFrontier; level++) {
         int32_t *frn = cur ? fr_node1 : fr_node0;
@@ -1110,12 +1132,14 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
         for (uint32_t f = threadIdx.x; f < count; f += kBlock)
             wide_emit_item<Layout>(tv, base, count, cap, f, frn[f], fra[f], cand + (size_t)f * K,
                                    noff[f], nodes, cur ? fr_node0 : fr_node1, cur ? fr_aux0 : fr_aux1,
-                                   info);
+                                   info, &stack, &depth);
         __syncthreads();
         base += count;
         count = carry;
         cur ^= 1;
     }
+    wave_atomic_max(&info->max_stack, stack);
+    wave_atomic_max(&info->max_depth, depth);
     if (threadIdx.x == 0) {
         // state lives in host memory the host polls: state[2] is written
         // last, after base and count are visible
@@ -1239,27 +1263,61 @@ int32_t check_launch(const char *what) {
 
 // One device allocation per handle, carved into the node records, the leaf
 // array and (indexed leaves) the copies of the vertices and triangle indices.
-int32_t alloc_handle_block(bvh_handle_s *h, int64_t n_nodes) {
+// The handle's two allocations.  Their hipMalloc calls block the host, so
+// the build issues each one while queued kernels keep the GPU busy: the leaf
+// block (size known from the input) before the host waits for the leaf
+// count, the node block once the leaf data kernels are queued.
+int32_t alloc_leaf_block(bvh_handle_s *h) {
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t n = (size_t)h->n_tris;
     const bool compact = h->leaf_mode == BVH_LEAF_COMPACT;
-    const size_t b_nodes = up((size_t)n_nodes * (size_t)h->node_bytes);
     const size_t b_leaf = up(n * (compact ? sizeof(bvh_tri) : sizeof(int32_t)));
     const size_t b_verts = compact ? 0 : up((size_t)h->n_verts * 3 * sizeof(float));
     const size_t b_tris = compact ? 0 : up(n * 3 * sizeof(int32_t));
-    BVH_HIP_TRY(hipMalloc(&h->block, b_nodes + b_leaf + b_verts + b_tris));
+    BVH_HIP_TRY(hipMalloc(&h->block, b_leaf + b_verts + b_tris));
     char *p = static_cast<char *>(h->block);
-    h->nodes = p;
-    h->leaf = p + b_nodes;
+    h->leaf = p;
     if (!compact) {
-        h->verts = reinterpret_cast<float *>(p + b_nodes + b_leaf);
-        h->tris = reinterpret_cast<int32_t *>(p + b_nodes + b_leaf + b_verts);
+        h->verts = reinterpret_cast<float *>(p + b_leaf);
+        h->tris = reinterpret_cast<int32_t *>(p + b_leaf + b_verts);
     }
     return BVH_OK;
 }
 
+int32_t alloc_node_block(bvh_handle_s *h, int64_t n_nodes) {
+    BVH_HIP_TRY(hipMalloc(&h->node_block, (size_t)n_nodes * (size_t)h->node_bytes));
+    h->nodes = h->node_block;
+    return BVH_OK;
+}
+
+// Leaf data of the handle (a8): compacted triangles in leaf order, or the
+// permutation plus the handle's own copies of the vertices and indices.
+struct LeafSource {
+    const float *verts;
+    int64_t n_verts;
+    const int32_t *tris;
+    const uint32_t *perm;
+    uint32_t n;
+};
+
+int32_t emit_leaf_data(bvh_handle_s *h, const LeafSource &ls, hipStream_t s) {
+    if (h->leaf_mode == BVH_LEAF_COMPACT) {
+        k_leaf_compact<<<grid_for(ls.n), kBlock, 0, s>>>(ls.verts, ls.tris, ls.perm, ls.n,
+                                                          static_cast<bvh_tri *>(h->leaf));
+    } else {
+        BVH_HIP_TRY(hipMemcpyAsync(h->leaf, ls.perm, (size_t)ls.n * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+        BVH_HIP_TRY(hipMemcpyAsync(h->verts, ls.verts, (size_t)ls.n_verts * 3 * sizeof(float),
+                                   hipMemcpyDeviceToDevice, s));
+        BVH_HIP_TRY(hipMemcpyAsync(h->tris, ls.tris, (size_t)ls.n * 3 * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+    }
+    return check_launch("leaf packing");
+}
+
 template <int Layout>
-int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s *h, hipStream_t s) {
+int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s *h,
+                  const LeafSource &ls, hipStream_t s) {
     constexpr int K = WideOut<Layout>::K;
     const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
     int32_t *fr_node[2], *cand;
@@ -1312,7 +1370,8 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
         return set_error(BVH_EUNSUPPORTED,
                          "bvh_build: wide node buffer of %llu bytes exceeds 4 GiB (raise leaf_size)",
                          (unsigned long long)base * (unsigned long long)h->node_bytes);
-    BVH_TRY(alloc_handle_block(h, base));
+    BVH_TRY(emit_leaf_data(h, ls, s));
+    BVH_TRY(alloc_node_block(h, base));
     BVH_HIP_TRY(hipMemcpyAsync(h->nodes, wnodes, (size_t)base * h->node_bytes,
                                hipMemcpyDeviceToDevice, s));
     return BVH_OK;
@@ -2067,9 +2126,11 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     BuildInfo *pin = pinned_scratch<BuildInfo>();
     if (!pin) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
+    BVH_TRY(alloc_leaf_block(h));  // while the queued kernels run
     BVH_HIP_TRY(hipStreamSynchronize(s));
     hi = *pin;
     if (hi.err & 1u) return set_error(BVH_EINVAL, "bvh_build: a vertex index is outside [0, n_verts)");
+    const LeafSource ls{verts, n_verts, tris, perm, (uint32_t)n};
     for (int a = 0; a < 3; a++) {
         h->scene_lo[a] = hi.slo[a];
         h->scene_hi[a] = hi.shi[a];
@@ -2079,7 +2140,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // a7
     if (h->layout == BVH_LAYOUT_AABB2) {
         h->n_nodes = 2 * (int64_t)hi.n_leaves - 1;
-        BVH_TRY(alloc_handle_block(h, h->n_nodes));
+        BVH_TRY(emit_leaf_data(h, ls, s));
+        BVH_TRY(alloc_node_block(h, h->n_nodes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(
             tv, mark, static_cast<bvh_node_aabb2 *>(h->nodes), (uint32_t)h->n_nodes, info);
         BVH_TRY(check_launch("aabb2 packing"));
@@ -2090,7 +2152,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         bvh_node_aabb2 *tmp = nullptr;
         ar.request(&tmp, (size_t)h->n_nodes);
         BVH_TRY(ar.bind(s, kAreaBuildWide));
-        BVH_TRY(alloc_handle_block(h, h->n_nodes));
+        BVH_TRY(emit_leaf_data(h, ls, s));
+        BVH_TRY(alloc_node_block(h, h->n_nodes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
                                                                       (uint32_t)h->n_nodes, info);
         k_split_aabb2<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
@@ -2105,7 +2168,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         bvh_node_aabb2 *tmp = nullptr;
         ar.request(&tmp, (size_t)h->n_nodes);
         BVH_TRY(ar.bind(s, kAreaBuildWide));
-        BVH_TRY(alloc_handle_block(h, h->n_nodes));
+        BVH_TRY(emit_leaf_data(h, ls, s));
+        BVH_TRY(alloc_node_block(h, h->n_nodes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
                                                                       (uint32_t)h->n_nodes, info);
         k_pack_slab<<<grid_for((uint64_t)h->n_nodes), kBlock, 0, s>>>(
@@ -2125,7 +2189,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         bvh_node_aabb2 *tmp = nullptr;
         ar.request(&tmp, (size_t)h->n_nodes);
         BVH_TRY(ar.bind(s, kAreaBuildWide));
-        BVH_TRY(alloc_handle_block(h, h->n_nodes));
+        BVH_TRY(emit_leaf_data(h, ls, s));
+        BVH_TRY(alloc_node_block(h, h->n_nodes));
         k_emit_aabb2<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark, tmp,
                                                                       (uint32_t)h->n_nodes, info);
         const unsigned g = grid_for((uint64_t)h->n_nodes);
@@ -2144,24 +2209,12 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
             k_pack_sg_eq<true><<<g, kBlock, 0, s>>>(tmp, nn, fr, h->nodes, info);
         BVH_TRY(check_launch("scene-frame packing"));
     } else if (h->layout == BVH_LAYOUT_BVH4) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, h, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, h, ls, s));
     } else if (h->layout == BVH_LAYOUT_BVH8_Q8) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, h, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, h, ls, s));
     } else {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, h, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, h, ls, s));
     }
-
-    // leaf data
-    if (h->leaf_mode == BVH_LEAF_COMPACT) {
-        k_leaf_compact<<<nb, kBlock, 0, s>>>(verts, tris, perm, n, static_cast<bvh_tri *>(h->leaf));
-    } else {
-        BVH_HIP_TRY(hipMemcpyAsync(h->leaf, perm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        BVH_HIP_TRY(hipMemcpyAsync(h->verts, verts, (size_t)n_verts * 3 * sizeof(float),
-                                   hipMemcpyDeviceToDevice, s));
-        BVH_HIP_TRY(hipMemcpyAsync(h->tris, tris, (size_t)n * 3 * sizeof(int32_t),
-                                   hipMemcpyDeviceToDevice, s));
-    }
-    BVH_TRY(check_launch("leaf packing"));
     BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     BVH_HIP_TRY(hipStreamSynchronize(s));
     hi = *pin;

@@ -74,7 +74,8 @@ struct bvh_handle_s {
     float frame_origin[3] = {0, 0, 0};  // PBRT_Q16, SG_EQ: lo = fmaf(q, frame_scale, frame_origin)
     float frame_scale[3] = {0, 0, 0};
     float frame_top[3] = {0, 0, 0};     // SG_EQ: hi = fmaf(-q, frame_scale, frame_top)
-    void *block = nullptr;       // the one device allocation the pointers below point into
+    void *block = nullptr;       // device allocation of leaf, verts and tris
+    void *node_block = nullptr;  // device allocation of the node records
     void *nodes = nullptr;       // node records
     void *leaf = nullptr;        // bvh_tri[n_tris] or int32 prim id[n_tris]
     float *verts = nullptr;      // INDEXED: own copy of the vertices
