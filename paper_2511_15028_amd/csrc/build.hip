@@ -5,6 +5,7 @@
 // its generated constructors (count pass, then fill pass, App. F).
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <string>
 #include <vector>
 
@@ -176,6 +177,40 @@ __global__ __launch_bounds__(kBlock) void k_scan_single(const uint32_t *in, uint
     }
 }
 
+// Middle-sized arrays: after k_scan_reduce, each block adds up the sums of
+// the tiles before it itself (a few thousand at most), so no launch sits
+// between the two passes; the last block writes the total.
+constexpr uint32_t kScanFusedTiles = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_scan_final_fused(const uint32_t *in, uint32_t *out,
+                                                             uint32_t n, const uint32_t *tile_sums,
+                                                             uint32_t *total_out) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    uint32_t part = 0;
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kBlock) part += tile_sums[t];
+    uint32_t before;
+    block_excl_scan(part, &before, wsum);
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = before + block_excl_scan(sum, &tot, wsum);
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0 && total_out) {
+        *total_out = before + tot;
+        __threadfence_system();  // the total may live in host memory the host polls
+    }
+}
+
 // Exclusive scan of n values; total (device) receives the sum if non-null.
 // tile_sums must hold ceil(n / kScanTile) entries.
 void scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tile_sums,
@@ -183,6 +218,11 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tile_sums
     const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
     if (ntiles <= kScanSingleTiles) {
         k_scan_single<<<1, kBlock, 0, s>>>(in, out, n, total);
+        return;
+    }
+    if (ntiles <= kScanFusedTiles) {
+        k_scan_reduce<<<ntiles, kBlock, 0, s>>>(in, n, tile_sums);
+        k_scan_final_fused<<<ntiles, kBlock, 0, s>>>(in, out, n, tile_sums, total);
         return;
     }
     if (ntiles > 0) k_scan_reduce<<<ntiles, kBlock, 0, s>>>(in, n, tile_sums);
@@ -193,37 +233,50 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tile_sums
 // ---------------------------------------------------------------------------
 // a1: triangle boxes, scene box and centre box
 // ---------------------------------------------------------------------------
+// Each thread boxes kPrimItems triangles (block b covers kPrimItems * kBlock
+// consecutive ones), so the single-block final reduction reads few partials.
+constexpr int kPrimItems = 4;
+
 __global__ __launch_bounds__(kBlock) void k_prim_bounds(const float *verts, int64_t n_verts,
                                                         const int32_t *tris, uint32_t n,
                                                         Box *pbox, float *partial,
                                                         BuildInfo *info) {
     __shared__ float red[12][kBlock / kWave];
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    float c[3] = {INFINITY, INFINITY, INFINITY}, cm[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (i < n) {
-        int32_t idx[3] = {tris[3 * (size_t)i], tris[3 * (size_t)i + 1], tris[3 * (size_t)i + 2]};
-        bool ok = true;
-        for (int k = 0; k < 3; k++) ok = ok && idx[k] >= 0 && (int64_t)idx[k] < n_verts;
-        if (!ok) {
-            atomicOr(&info->err, 1u);
-            for (int a = 0; a < 3; a++) lo[a] = hi[a] = 0.0f;
-        } else {
-            for (int k = 0; k < 3; k++) {
-                const float *p = verts + 3 * (size_t)idx[k];
-                for (int a = 0; a < 3; a++) {
-                    lo[a] = fminf(lo[a], p[a]);
-                    hi[a] = fmaxf(hi[a], p[a]);
+    float v[12] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY,
+                   INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int item = 0; item < kPrimItems; item++) {
+        const uint32_t i = (blockIdx.x * kPrimItems + item) * kBlock + threadIdx.x;
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        float c[3] = {INFINITY, INFINITY, INFINITY}, cm[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (i < n) {
+            int32_t idx[3] = {tris[3 * (size_t)i], tris[3 * (size_t)i + 1], tris[3 * (size_t)i + 2]};
+            bool ok = true;
+            for (int k = 0; k < 3; k++) ok = ok && idx[k] >= 0 && (int64_t)idx[k] < n_verts;
+            if (!ok) {
+                atomicOr(&info->err, 1u);
+                for (int a = 0; a < 3; a++) lo[a] = hi[a] = 0.0f;
+            } else {
+                for (int k = 0; k < 3; k++) {
+                    const float *p = verts + 3 * (size_t)idx[k];
+                    for (int a = 0; a < 3; a++) {
+                        lo[a] = fminf(lo[a], p[a]);
+                        hi[a] = fmaxf(hi[a], p[a]);
+                    }
                 }
             }
+            Box b;
+            b.lo = make_float4(lo[0], lo[1], lo[2], 0.0f);
+            b.hi = make_float4(hi[0], hi[1], hi[2], 0.0f);
+            pbox[i] = b;
+            for (int a = 0; a < 3; a++) c[a] = cm[a] = 0.5f * lo[a] + 0.5f * hi[a];
         }
-        Box b;
-        b.lo = make_float4(lo[0], lo[1], lo[2], 0.0f);
-        b.hi = make_float4(hi[0], hi[1], hi[2], 0.0f);
-        pbox[i] = b;
-        for (int a = 0; a < 3; a++) c[a] = cm[a] = 0.5f * lo[a] + 0.5f * hi[a];
+        for (int a = 0; a < 3; a++) {
+            v[a] = fminf(v[a], lo[a]);
+            v[3 + a] = fmaxf(v[3 + a], hi[a]);
+            v[6 + a] = fminf(v[6 + a], c[a]);
+            v[9 + a] = fmaxf(v[9 + a], cm[a]);
+        }
     }
-    float v[12] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], c[0], c[1], c[2], cm[0], cm[1], cm[2]};
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     for (int k = 0; k < 12; k++) {
         bool is_min = (k < 3) || (k >= 6 && k < 9);
@@ -319,13 +372,19 @@ inline int morton_bits(int n) {
 
 // ---------------------------------------------------------------------------
 // a3: stable LSD radix sort of (u64 key, u32 value), 8 bits per pass.
-// Per pass: per-tile digit histograms, one exclusive scan over the
-// digit-major histogram matrix, then a stable scatter that ranks equal
-// digits inside a tile with wave ballots.
+// Per pass three launches: per-tile digit counts (digit-major matrix), one
+// block per digit turning its row into exclusive prefixes over the tiles
+// plus the digit's total, and the scatter.  The scatter ranks its tile's
+// keys stably in LDS (each wave a contiguous quarter of the tile, equal
+// digits found with ballots, no block barrier per round), then writes the
+// tile out in local digit order, so consecutive lanes store consecutive
+// addresses of a digit's run.
 // ---------------------------------------------------------------------------
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kBlock * kSortItems;
+constexpr int kSortWaves = kBlock / kWave;
 constexpr int kRadix = 256;
+static_assert(kRadix == kBlock, "one digit per thread in the per-digit steps");
 
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t *keys, uint32_t n, int shift,
                                                        uint32_t *hist, uint32_t ntiles) {
@@ -341,29 +400,81 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t *keys, uin
     hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Block d: row d of the count matrix -> exclusive prefix over tiles, in
+// place; total[d] = the row's sum.
+__global__ __launch_bounds__(kBlock) void k_radix_offsets(uint32_t *hist, uint32_t ntiles,
+                                                          uint32_t *total) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    uint32_t *row = hist + (size_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < ntiles; c += kBlock) {
+        const uint32_t t = c + threadIdx.x;
+        const uint32_t v = t < ntiles ? row[t] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, &tot, wsum);
+        if (t < ntiles) row[t] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) total[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *keys_in,
                                                           const uint32_t *vals_in,
                                                           uint64_t *keys_out, uint32_t *vals_out,
                                                           uint32_t n, int shift,
-                                                          const uint32_t *offsets,
+                                                          const uint32_t *prefix,
+                                                          const uint32_t *total,
                                                           uint32_t ntiles) {
-    __shared__ uint32_t run[kRadix];
-    __shared__ uint32_t wcnt[kBlock / kWave][kRadix];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+    __shared__ uint32_t wcount[kSortWaves][kRadix];  // digit counts per wave, then run positions
+    __shared__ uint32_t gdst[kRadix];                 // output index of local position 0 of digit d
+    __shared__ uint32_t wsum[kBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    run[threadIdx.x] = offsets[(size_t)threadIdx.x * ntiles + blockIdx.x];
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    const uint32_t base = blockIdx.x * kSortTile;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t base = tile * kSortTile;
+    const uint32_t wbase = base + (uint32_t)w * (kSortItems * kWave);
+#pragma unroll
+    for (int k = 0; k < kSortWaves; k++) wcount[k][threadIdx.x] = 0;
+    __syncthreads();
+    // this wave's quarter of the tile, item r of a lane at wbase + r*64 + lane
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems];
+#pragma unroll
     for (int r = 0; r < kSortItems; r++) {
-        const uint32_t i = base + r * kBlock + threadIdx.x;
-        const bool valid = i < n;
-        uint64_t key = 0;
-        uint32_t val = 0, d = 0;
-        if (valid) {
-            key = keys_in[i];
-            val = vals_in[i];
-            d = (uint32_t)(key >> shift) & (kRadix - 1);
+        const uint32_t i = wbase + r * kWave + lane;
+        key[r] = i < n ? keys_in[i] : 0ull;
+        val[r] = i < n ? vals_in[i] : 0u;
+        if (i < n) atomicAdd(&wcount[w][(uint32_t)(key[r] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    {   // thread d: local start of digit d per wave, and its output offset
+        const uint32_t d = threadIdx.x;
+        uint32_t c[kSortWaves], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; k++) {
+            c[k] = wcount[k][d];
+            sum += c[k];
         }
-        // lanes of this wave holding the same digit
+        uint32_t tot_local;
+        const uint32_t lstart = block_excl_scan(sum, &tot_local, wsum);
+        uint32_t tot_all;
+        const uint32_t gstart = block_excl_scan(total[d], &tot_all, wsum);
+        gdst[d] = gstart + prefix[(size_t)d * ntiles + tile] - lstart;
+        uint32_t run = lstart;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; k++) {
+            wcount[k][d] = run;
+            run += c[k];
+        }
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    uint32_t *wrun = wcount[w];
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const bool valid = wbase + r * kWave + lane < n;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -371,24 +482,25 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *keys_i
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t rank = __popcll(peers & lt_mask);
-        for (int k = 0; k < kBlock / kWave; k++) wcnt[k][threadIdx.x] = 0;
-        __syncthreads();
-        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-        __syncthreads();
+        const uint32_t start = valid ? wrun[d] : 0u;
+        __builtin_amdgcn_wave_barrier();
         if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int k = 0; k < w; k++) pos += wcnt[k][d];
-            if (pos < n) {  // always true for a consistent histogram; guards the write
-                keys_out[pos] = key;
-                vals_out[pos] = val;
-            }
+            const uint32_t pos = start + (uint32_t)__popcll(peers & lt_mask);
+            skey[pos] = key[r];
+            sval[pos] = val[r];
+            if ((peers & lt_mask) == 0) wrun[d] = start + (uint32_t)__popcll(peers);
         }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int k = 0; k < kBlock / kWave; k++) add += wcnt[k][threadIdx.x];
-        run[threadIdx.x] += add;
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    const uint32_t m = min((uint32_t)kSortTile, n - base);
+    for (uint32_t p = threadIdx.x; p < m; p += kBlock) {
+        const uint64_t k = skey[p];
+        const uint32_t o = gdst[(uint32_t)(k >> shift) & (kRadix - 1)] + p;
+        if (o < n) {  // always true for a consistent histogram; guards the write
+            keys_out[o] = k;
+            vals_out[o] = sval[p];
+        }
     }
 }
 
@@ -826,8 +938,11 @@ __global__ __launch_bounds__(kBlock) void k_split_aabb2(const bvh_node_aabb2 *in
 // alive interior binary node that becomes a wide node: its child list starts
 // as its two children and repeatedly replaces the interior candidate of
 // largest surface area by that candidate's two children, up to K children.
-// Pass A forms the lists and counts interior children; an exclusive scan
-// places them; pass B writes the node and the next frontier.
+// The list depends only on the binary node, so one launch forms it for every
+// alive interior node up front (a chain of dependent loads per node, hidden
+// by running all of them at once); per level an exclusive scan of the
+// interior-child counts places the children and one pass writes the nodes,
+// the next frontier and its counts.
 // ---------------------------------------------------------------------------
 // Greedy opening of one wide node (binary node x): returns the number of
 // interior candidates and writes K candidate ids (-1 for unused slots).
@@ -883,13 +998,15 @@ __device__ inline uint32_t wide_open_item(const TreeView &tv, int x, int32_t *ca
     return ni;
 }
 
+// Binary nodes 0 .. m-1 (m = max(n-1, 1)): the root and every alive interior
+// node get their child list (cand_all[x*K ..]) and interior-child count.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_wide_open(TreeView tv, uint32_t count,
-                                                      const int32_t *fr_node, int32_t *cand,
-                                                      uint32_t *ninterior) {
-    const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= count) return;
-    ninterior[f] = wide_open_item<K>(tv, fr_node[f], cand + (size_t)f * K);
+__global__ __launch_bounds__(kBlock) void k_wide_open_all(TreeView tv, uint32_t m, int32_t *cand_all,
+                                                          uint32_t *ni_all) {
+    const uint32_t x = blockIdx.x * kBlock + threadIdx.x;
+    if (x >= m) return;
+    if (x != 0 && !(tv.alive((int)x) && !tv.is_leaf((int)x))) return;
+    ni_all[x] = wide_open_item<K>(tv, (int)x, cand_all + (size_t)x * K);
 }
 
 // Quantisation of one axis of K child intervals (the first nc valid) to QMAX
@@ -936,51 +1053,52 @@ __device__ inline float box_comp(const Box &b, int c) {
     return c == 0 ? b.lo.x : c == 1 ? b.lo.y : c == 2 ? b.lo.z : c == 3 ? b.hi.x : c == 4 ? b.hi.y : b.hi.z;
 }
 
-// Node writers: the record is written straight to global memory, field by
-// field, so no node-sized array lives in private memory.
+// Node writers: the record is assembled as 32-bit words in registers (every
+// index is a compile-time constant after unrolling) and stored with 16-byte
+// stores, so a wave writes whole records instead of one field at a time.
+template <int Words>
+__device__ inline void store_record(void *dst, const uint32_t *r) {
+    static_assert(Words % 4 == 0, "records are whole 16-byte chunks");
+    uint4 *d = static_cast<uint4 *>(dst);
+#pragma unroll
+    for (int i = 0; i < Words / 4; i++)
+        d[i] = make_uint4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
+}
+
 template <int Layout>
 struct WideOut;
 
 template <>
 struct WideOut<BVH_LAYOUT_BVH4> {
     static constexpr int K = 4;
+    static constexpr int kWords = sizeof(bvh_node_bvh4) / 4;
     __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
         (void)pb;
         (void)err;
-        bvh_node_bvh4 *nd = static_cast<bvh_node_bvh4 *>(nodes) + w;
+        uint32_t r[kWords];
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const bool v = k < nc;
-            nd->lo_x[k] = v ? cb[k].lo.x : INFINITY;
-            nd->lo_y[k] = v ? cb[k].lo.y : INFINITY;
-            nd->lo_z[k] = v ? cb[k].lo.z : INFINITY;
-            nd->hi_x[k] = v ? cb[k].hi.x : -INFINITY;
-            nd->hi_y[k] = v ? cb[k].hi.y : -INFINITY;
-            nd->hi_z[k] = v ? cb[k].hi.z : -INFINITY;
-            nd->child[k] = v ? ref[k] : kRefEmpty;
+            r[0 * K + k] = __float_as_uint(v ? cb[k].lo.x : INFINITY);
+            r[1 * K + k] = __float_as_uint(v ? cb[k].lo.y : INFINITY);
+            r[2 * K + k] = __float_as_uint(v ? cb[k].lo.z : INFINITY);
+            r[3 * K + k] = __float_as_uint(v ? cb[k].hi.x : -INFINITY);
+            r[4 * K + k] = __float_as_uint(v ? cb[k].hi.y : -INFINITY);
+            r[5 * K + k] = __float_as_uint(v ? cb[k].hi.z : -INFINITY);
+            r[6 * K + k] = v ? ref[k] : kRefEmpty;
         }
-        nd->nchild = (uint32_t)nc;
-        nd->pad[0] = nd->pad[1] = nd->pad[2] = 0;
+        r[7 * K] = (uint32_t)nc;
+        r[7 * K + 1] = r[7 * K + 2] = r[7 * K + 3] = 0;
+        store_record<kWords>(static_cast<bvh_node_bvh4 *>(nodes) + w, r);
     }
 };
 
-// Packs q values of one plane row (8 children) into 32-bit words.
-template <typename QT>
-__device__ inline void store_row(QT *row, const uint32_t *q) {
-    if (sizeof(QT) == 1) {
-        uint32_t *w = reinterpret_cast<uint32_t *>(row);
-        w[0] = q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24);
-        w[1] = q[4] | (q[5] << 8) | (q[6] << 16) | (q[7] << 24);
-    } else {
-        uint32_t *w = reinterpret_cast<uint32_t *>(row);
-#pragma unroll
-        for (int k = 0; k < 4; k++) w[k] = q[2 * k] | (q[2 * k + 1] << 16);
-    }
-}
-
-template <typename NodeT, int QMAX, typename QT>
-__device__ inline void write_quantized(NodeT *nd, const Box &pb, const Box *cb, const uint32_t *ref,
+// Record words of the quantised 8-wide nodes: origin[3], scale[3], then the
+// six plane rows (qlo_x, qlo_y, qlo_z, qhi_x, qhi_y, qhi_z) of RW words each,
+// child[8], nchild, zero padding.
+template <int QMAX, int RW, int Words>
+__device__ inline void quantized_words(uint32_t *r, const Box &pb, const Box *cb, const uint32_t *ref,
                                        int nc, uint32_t *err) {
     constexpr int K = 8;
 #pragma unroll
@@ -993,37 +1111,60 @@ __device__ inline void write_quantized(NodeT *nd, const Box &pb, const Box *cb, 
             chi[k] = k < nc ? box_comp(cb[k], a + 3) : 0.0f;
         }
         const float plo = box_comp(pb, a), phi = box_comp(pb, a + 3);
-        const float s = quantize_axis<K, QMAX>(plo, phi, clo, chi, nc, qlo, qhi, err);
-        nd->origin[a] = plo;
-        nd->scale[a] = s;
-        store_row<QT>(a == 0 ? nd->qlo_x : a == 1 ? nd->qlo_y : nd->qlo_z, qlo);
-        store_row<QT>(a == 0 ? nd->qhi_x : a == 1 ? nd->qhi_y : nd->qhi_z, qhi);
-    }
+        const float sc = quantize_axis<K, QMAX>(plo, phi, clo, chi, nc, qlo, qhi, err);
+        r[a] = __float_as_uint(plo);
+        r[3 + a] = __float_as_uint(sc);
 #pragma unroll
-    for (int k = 0; k < K; k++) nd->child[k] = k < nc ? ref[k] : kRefEmpty;
-    nd->nchild = (uint32_t)nc;
+        for (int j = 0; j < RW; j++) {
+            const int per = K / RW;  // q values per word: 4 (u8) or 2 (u16)
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int t = 0; t < per; t++) {
+                lo |= qlo[j * per + t] << (t * (32 / per));
+                hi |= qhi[j * per + t] << (t * (32 / per));
+            }
+            r[6 + a * RW + j] = lo;
+            r[6 + (3 + a) * RW + j] = hi;
+        }
+    }
+    constexpr int c0 = 6 + 6 * RW;
+#pragma unroll
+    for (int k = 0; k < K; k++) r[c0 + k] = k < nc ? ref[k] : kRefEmpty;
+    r[c0 + K] = (uint32_t)nc;
+#pragma unroll
+    for (int k = c0 + K + 1; k < Words; k++) r[k] = 0;
 }
+
+static_assert(offsetof(bvh_node_bvh4, child) == 24 * 4 && offsetof(bvh_node_bvh4, nchild) == 28 * 4,
+              "bvh4 record words");
+static_assert(offsetof(bvh_node_bvh8_q8, qlo_x) == 6 * 4 && offsetof(bvh_node_bvh8_q8, qhi_x) == 12 * 4 &&
+                  offsetof(bvh_node_bvh8_q8, child) == 18 * 4 && offsetof(bvh_node_bvh8_q8, nchild) == 26 * 4,
+              "bvh8-q8 record words");
+static_assert(offsetof(bvh_node_bvh8_q16, qlo_x) == 6 * 4 && offsetof(bvh_node_bvh8_q16, qhi_x) == 18 * 4 &&
+                  offsetof(bvh_node_bvh8_q16, child) == 30 * 4 && offsetof(bvh_node_bvh8_q16, nchild) == 38 * 4,
+              "bvh8-q16 record words");
 
 template <>
 struct WideOut<BVH_LAYOUT_BVH8_Q8> {
     static constexpr int K = 8;
+    static constexpr int kWords = sizeof(bvh_node_bvh8_q8) / 4;
     __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
-        bvh_node_bvh8_q8 *nd = static_cast<bvh_node_bvh8_q8 *>(nodes) + w;
-        write_quantized<bvh_node_bvh8_q8, 255, uint8_t>(nd, pb, cb, ref, nc, err);
-#pragma unroll
-        for (int k = 0; k < 5; k++) nd->pad[k] = 0;
+        uint32_t r[kWords];
+        quantized_words<255, 2, kWords>(r, pb, cb, ref, nc, err);
+        store_record<kWords>(static_cast<bvh_node_bvh8_q8 *>(nodes) + w, r);
     }
 };
 
 template <>
 struct WideOut<BVH_LAYOUT_BVH8_Q16> {
     static constexpr int K = 8;
+    static constexpr int kWords = sizeof(bvh_node_bvh8_q16) / 4;
     __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
-        bvh_node_bvh8_q16 *nd = static_cast<bvh_node_bvh8_q16 *>(nodes) + w;
-        write_quantized<bvh_node_bvh8_q16, 65535, uint16_t>(nd, pb, cb, ref, nc, err);
-        nd->pad = 0;
+        uint32_t r[kWords];
+        quantized_words<65535, 4, kWords>(r, pb, cb, ref, nc, err);
+        store_record<kWords>(static_cast<bvh_node_bvh8_q16 *>(nodes) + w, r);
     }
 };
 
@@ -1034,7 +1175,8 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
                                       uint32_t cap, uint32_t f, int x, uint32_t aux,
                                       const int32_t *cand_f, uint32_t noff_f, void *nodes,
                                       int32_t *next_node, uint32_t *next_aux, BuildInfo *info,
-                                      uint32_t *stack_out, uint32_t *depth_out) {
+                                      uint32_t *stack_out, uint32_t *depth_out,
+                                      const uint32_t *ni_all = nullptr, uint32_t *next_ni = nullptr) {
     constexpr int K = WideOut<Layout>::K;
     if (base + f >= cap) {
         atomicOr(&info->err, 4u);
@@ -1065,6 +1207,7 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
             }
             ref[k] = ref_interior(next_base + pos);
             next_node[pos] = c;
+            if (next_ni) next_ni[pos] = ni_all[c];
             r++;
         }
     }
@@ -1078,31 +1221,37 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
 template <int Layout>
 __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base, uint32_t count,
                                                       uint32_t cap, const int32_t *fr_node,
-                                                      const uint32_t *fr_aux, const int32_t *cand,
-                                                      const uint32_t *noff, void *nodes,
-                                                      int32_t *next_node, uint32_t *next_aux,
+                                                      const uint32_t *fr_aux, const int32_t *cand_all,
+                                                      const uint32_t *ni_all, const uint32_t *noff,
+                                                      void *nodes, int32_t *next_node,
+                                                      uint32_t *next_aux, uint32_t *next_ni,
                                                       BuildInfo *info) {
     constexpr int K = WideOut<Layout>::K;
     const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
     uint32_t stack = 0, depth = 0;
-    if (f < count)
-        wide_emit_item<Layout>(tv, base, count, cap, f, fr_node[f], fr_aux[f], cand + (size_t)f * K,
-                               noff[f], nodes, next_node, next_aux, info, &stack, &depth);
+    if (f < count) {
+        const int x = fr_node[f];
+        wide_emit_item<Layout>(tv, base, count, cap, f, x, fr_aux[f], cand_all + (size_t)x * K,
+                               noff[f], nodes, next_node, next_aux, info, &stack, &depth, ni_all,
+                               next_ni);
+    }
     wave_atomic_max(&info->max_stack, stack);
     wave_atomic_max(&info->max_depth, depth);
 }
 
-// The top levels, while the frontier is small, in one workgroup: open, scan
-// and emit per level with block barriers instead of kernel launches and host
-// round trips.  Leaves (base, count, frontier buffer) for the multi-block
-// levels in state[0..2] (host-mapped words; state[2] last).
+// The top levels, while the frontier is small, in one workgroup: gather the
+// counts, scan and emit per level with block barriers instead of kernel
+// launches and host round trips.  Leaves the multi-block levels' first
+// frontier with its counts in noff, and (base, count, frontier buffer) in
+// state[0..2] (host-mapped words; state[2] last).
 constexpr uint32_t kTopMaxFrontier = 512;
 
 template <int Layout>
 __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, int32_t *fr_node0,
                                                      int32_t *fr_node1, uint32_t *fr_aux0,
-                                                     uint32_t *fr_aux1, int32_t *cand,
-                                                     uint32_t *noff, void *nodes, BuildInfo *info,
+                                                     uint32_t *fr_aux1, const int32_t *cand_all,
+                                                     const uint32_t *ni_all, uint32_t *noff,
+                                                     void *nodes, BuildInfo *info,
                                                      uint32_t *state) {
     constexpr int K = WideOut<Layout>::K;
     __shared__ uint32_t wsum[kBlock / kWave];
@@ -1113,12 +1262,12 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
     __syncthreads();
     uint32_t base = 0, count = 1, stack = 0, depth = 0;
     int cur = 0;
-    for (int level = 0; level < 64 && count > 0 && count <= kTopMaxFrontier; level++) {
+    for (int level = 0; count > 0; level++) {
         int32_t *frn = cur ? fr_node1 : fr_node0;
         uint32_t *fra = cur ? fr_aux1 : fr_aux0;
-        for (uint32_t f = threadIdx.x; f < count; f += kBlock)
-            noff[f] = wide_open_item<K>(tv, frn[f], cand + (size_t)f * K);
+        for (uint32_t f = threadIdx.x; f < count; f += kBlock) noff[f] = ni_all[frn[f]];
         __syncthreads();
+        if (count > kTopMaxFrontier || level >= 64) break;  // count is the same in every thread
         uint32_t carry = 0;
         for (uint32_t c = 0; c < count; c += kBlock) {
             const uint32_t f = c + threadIdx.x;
@@ -1130,9 +1279,10 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
         }
         __syncthreads();
         for (uint32_t f = threadIdx.x; f < count; f += kBlock)
-            wide_emit_item<Layout>(tv, base, count, cap, f, frn[f], fra[f], cand + (size_t)f * K,
-                                   noff[f], nodes, cur ? fr_node0 : fr_node1, cur ? fr_aux0 : fr_aux1,
-                                   info, &stack, &depth);
+            wide_emit_item<Layout>(tv, base, count, cap, f, frn[f], fra[f],
+                                   cand_all + (size_t)frn[f] * K, noff[f], nodes,
+                                   cur ? fr_node0 : fr_node1, cur ? fr_aux0 : fr_aux1, info, &stack,
+                                   &depth);
         __syncthreads();
         base += count;
         count = carry;
@@ -1261,8 +1411,6 @@ int32_t check_launch(const char *what) {
     return BVH_OK;
 }
 
-// One device allocation per handle, carved into the node records, the leaf
-// array and (indexed leaves) the copies of the vertices and triangle indices.
 // The handle's two allocations.  Their hipMalloc calls block the host, so
 // the build issues each one while queued kernels keep the GPU busy: the leaf
 // block (size known from the input) before the host waits for the leaf
@@ -1320,25 +1468,28 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
                   const LeafSource &ls, hipStream_t s) {
     constexpr int K = WideOut<Layout>::K;
     const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
-    int32_t *fr_node[2], *cand;
-    uint32_t *fr_aux[2], *noff, *tile;
+    const uint32_t m = std::max<uint32_t>(1, (uint32_t)tv.n - 1);  // binary nodes with a list
+    int32_t *fr_node[2], *cand_all;
+    uint32_t *fr_aux[2], *noff[2], *ni_all, *tile;
     uint8_t *wnodes;
     Arena arena;
     arena.request(&wnodes, (size_t)cap * h->node_bytes);
-    arena.request(&fr_node[0], cap);
-    arena.request(&fr_node[1], cap);
-    arena.request(&fr_aux[0], cap);
-    arena.request(&fr_aux[1], cap);
-    arena.request(&cand, (size_t)cap * K);
-    arena.request(&noff, cap);
+    for (int b = 0; b < 2; b++) {
+        arena.request(&fr_node[b], cap);
+        arena.request(&fr_aux[b], cap);
+        arena.request(&noff[b], cap);
+    }
+    arena.request(&cand_all, (size_t)m * K);
+    arena.request(&ni_all, m);
     arena.request(&tile, (cap + kScanTile - 1) / kScanTile + 1);
     BVH_TRY(arena.bind(s, kAreaBuildWide));
     uint32_t *hw = host_words();
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     volatile uint32_t *vw = hw;
     vw[0] = vw[1] = vw[2] = vw[3] = kPending;
+    k_wide_open_all<K><<<grid_for(m), kBlock, 0, s>>>(tv, m, cand_all, ni_all);
     k_wide_top<Layout><<<1, kBlock, 0, s>>>(tv, cap, fr_node[0], fr_node[1], fr_aux[0], fr_aux[1],
-                                           cand, noff, wnodes, info, hw);
+                                           cand_all, ni_all, noff[0], wnodes, info, hw);
     BVH_TRY(check_launch("wide packing (top levels)"));
     uint32_t base = 0, count = 0, curw = 0;
     BVH_TRY(wait_host_word(vw + 2, s, &curw));  // written last, after base and count
@@ -1346,23 +1497,24 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
     count = vw[1];
     int cur = (int)curw;
     if (base + count > cap) return set_error(BVH_EHIP, "wide packing overflow");
+    int nb = 0;  // noff[nb]: the current level's interior-child counts, then their offsets
     for (int level = 0; count > 0; level++) {
         if (level > 4096) return set_error(BVH_EHIP, "wide packing did not terminate");
         vw[3] = kPending;
-        k_wide_open<K><<<grid_for(count), kBlock, 0, s>>>(tv, count, fr_node[cur], cand, noff);
-        scan_u32(noff, noff, count, tile, hw + 3, s);
+        scan_u32(noff[nb], noff[nb], count, tile, hw + 3, s);
         k_wide_emit<Layout><<<grid_for(count), kBlock, 0, s>>>(
-            tv, base, count, cap, fr_node[cur], fr_aux[cur], cand, noff, wnodes, fr_node[cur ^ 1],
-            fr_aux[cur ^ 1], info);
+            tv, base, count, cap, fr_node[cur], fr_aux[cur], cand_all, ni_all, noff[nb], wnodes,
+            fr_node[cur ^ 1], fr_aux[cur ^ 1], noff[nb ^ 1], info);
         BVH_TRY(check_launch("wide packing"));
-        // the next level's size is known once the scan's middle kernel has run;
-        // the next launches queue behind this level's emit
+        // the next level's size is known once the scan has run; the next
+        // launches queue behind this level's emit
         uint32_t next = 0;
         BVH_TRY(wait_host_word(vw + 3, s, &next));
         base += count;
         if (base + next > cap) return set_error(BVH_EHIP, "wide packing overflow");
         count = next;
         cur ^= 1;
+        nb ^= 1;
     }
     h->n_nodes = base;
     // the wide traversal kernels address node fields with 32-bit byte offsets
@@ -2057,7 +2209,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     arena.request(&keys[1], n);
     arena.request(&vals[0], n);
     arena.request(&vals[1], n);
-    arena.request(&hist, nhist);
+    arena.request(&hist, nhist + kRadix);  // counts, then the digit totals
     arena.request(&tile, (max_scan + kScanTile - 1) / kScanTile + 1);
     arena.request(&ileft, n - 1);
     arena.request(&iright, n - 1);
@@ -2078,8 +2230,9 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     BVH_HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), s));
 
     // a1, a2
-    k_prim_bounds<<<nb, kBlock, 0, s>>>(verts, n_verts, tris, n, pbox, partial, info);
-    k_bounds_final<<<1, kBlock, 0, s>>>(partial, nb, info);
+    const uint32_t nbp = (uint32_t)(((uint64_t)n + kPrimItems * kBlock - 1) / (kPrimItems * kBlock));
+    k_prim_bounds<<<nbp, kBlock, 0, s>>>(verts, n_verts, tris, n, pbox, partial, info);
+    k_bounds_final<<<1, kBlock, 0, s>>>(partial, nbp, info);
     const uint32_t *perm = nullptr;
     if (h->builder == BVH_BUILDER_SAH) {
         // a4 alternative: binned-SAH topology over the primitive boxes
@@ -2095,9 +2248,10 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         int cur = 0;
         for (int shift = 0; shift < 3 * mbits; shift += 8) {
             k_radix_hist<<<nsort, kBlock, 0, s>>>(keys[cur], n, shift, hist, nsort);
-            scan_u32(hist, hist, nhist, tile, nullptr, s);
+            k_radix_offsets<<<kRadix, kBlock, 0, s>>>(hist, nsort, hist + nhist);
             k_radix_scatter<<<nsort, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1],
-                                                     vals[cur ^ 1], n, shift, hist, nsort);
+                                                     vals[cur ^ 1], n, shift, hist, hist + nhist,
+                                                     nsort);
             cur ^= 1;
         }
         BVH_TRY(check_launch("radix sort"));
