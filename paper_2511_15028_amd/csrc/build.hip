@@ -4,8 +4,11 @@
 // (Sec. 5, two-phase construction); the packing kernels here play the part of
 // its generated constructors (count pass, then fill pass, App. F).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstddef>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,9 +21,19 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 
 struct Box {
-    float4 lo;  // w unused
-    float4 hi;  // w unused
+    float4 lo;  // w: unused, except in the node boxes (nbox): the node's triangle count
+    float4 hi;  // w: unused, except in the node boxes (nbox): its first sorted triangle
 };
+
+// The node boxes carry the node's range in their spare words, so a reader of
+// a node's box gets its range from the same 32-byte load.
+__device__ inline Box with_range(Box b, uint32_t first, uint32_t count) {
+    b.lo.w = __uint_as_float(count);
+    b.hi.w = __uint_as_float(first);
+    return b;
+}
+__device__ inline uint32_t range_count(const Box &b) { return __float_as_uint(b.lo.w); }
+__device__ inline uint32_t range_first(const Box &b) { return __float_as_uint(b.hi.w); }
 
 struct BuildInfo {
     float slo[3], shi[3];   // scene box
@@ -611,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_boxes(const Box *pbox, const ui
     Box b = box_empty();
     if (j < n) {
         b = pbox[perm[j]];
-        nbox[(n - 1) + j] = b;
+        nbox[(n - 1) + j] = with_range(b, (uint32_t)j, 1u);
     }
     const float v0[6] = {b.lo.x, b.lo.y, b.lo.z, b.hi.x, b.hi.y, b.hi.z};
     float p[6], q[6];
@@ -651,7 +664,10 @@ __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirs
     if (i >= n - 1) return;
     const Box *leaf = nbox + (n - 1);
     const int a = (int)ifirst[i], b = a + (int)icount[i] - 1;
-    if (a < 0 || b >= n || b < a) return;  // malformed range: leave the box unset
+    if (a < 0 || b >= n || b < a) {  // malformed range: empty box, the range as given
+        nbox[i] = with_range(box_empty(), ifirst[i], icount[i]);
+        return;
+    }
     const int ba = a / kRangeBlock, bb = b / kRangeBlock;
     Box u = box_empty();
     if (ba == bb) {
@@ -672,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirs
             u = box_union(u, box_union(lvl[lo], lvl[hi - (1 << k) + 1]));
         }
     }
-    nbox[i] = u;
+    nbox[i] = with_range(u, (uint32_t)a, (uint32_t)(b - a + 1));
     const float dx = u.hi.x - u.lo.x, dy = u.hi.y - u.lo.y, dz = u.hi.z - u.lo.z;
     area[i] = dx * dy + dy * dz + dz * dx;
 }
@@ -1072,7 +1088,7 @@ template <>
 struct WideOut<BVH_LAYOUT_BVH4> {
     static constexpr int K = 4;
     static constexpr int kWords = sizeof(bvh_node_bvh4) / 4;
-    __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
+    __device__ static void write(void *dst, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
         (void)pb;
         (void)err;
@@ -1090,7 +1106,7 @@ struct WideOut<BVH_LAYOUT_BVH4> {
         }
         r[7 * K] = (uint32_t)nc;
         r[7 * K + 1] = r[7 * K + 2] = r[7 * K + 3] = 0;
-        store_record<kWords>(static_cast<bvh_node_bvh4 *>(nodes) + w, r);
+        store_record<kWords>(dst, r);
     }
 };
 
@@ -1148,11 +1164,11 @@ template <>
 struct WideOut<BVH_LAYOUT_BVH8_Q8> {
     static constexpr int K = 8;
     static constexpr int kWords = sizeof(bvh_node_bvh8_q8) / 4;
-    __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
+    __device__ static void write(void *dst, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
         uint32_t r[kWords];
         quantized_words<255, 2, kWords>(r, pb, cb, ref, nc, err);
-        store_record<kWords>(static_cast<bvh_node_bvh8_q8 *>(nodes) + w, r);
+        store_record<kWords>(dst, r);
     }
 };
 
@@ -1160,11 +1176,24 @@ template <>
 struct WideOut<BVH_LAYOUT_BVH8_Q16> {
     static constexpr int K = 8;
     static constexpr int kWords = sizeof(bvh_node_bvh8_q16) / 4;
-    __device__ static void write(void *nodes, uint32_t w, const Box &pb, const Box *cb,
+    __device__ static void write(void *dst, const Box &pb, const Box *cb,
                                  const uint32_t *ref, int nc, uint32_t *err) {
         uint32_t r[kWords];
         quantized_words<65535, 4, kWords>(r, pb, cb, ref, nc, err);
-        store_record<kWords>(static_cast<bvh_node_bvh8_q16 *>(nodes) + w, r);
+        store_record<kWords>(dst, r);
+    }
+};
+
+// Where wide node w goes: nodes below spec_cap straight into the handle's
+// node block (allocated ahead from an earlier build's count), the rest into
+// the work area (moved into an exact block after the last level).
+struct NodeSink {
+    uint8_t *spec;
+    uint32_t spec_cap;
+    uint8_t *over;
+    uint32_t bytes;
+    __device__ void *at(uint32_t w) const {
+        return w < spec_cap ? spec + (size_t)w * bytes : over + (size_t)w * bytes;
     }
 };
 
@@ -1173,7 +1202,7 @@ struct WideOut<BVH_LAYOUT_BVH8_Q16> {
 template <int Layout>
 __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_t count,
                                       uint32_t cap, uint32_t f, int x, uint32_t aux,
-                                      const int32_t *cand_f, uint32_t noff_f, void *nodes,
+                                      const int32_t *cand_f, uint32_t noff_f, NodeSink sink,
                                       int32_t *next_node, uint32_t *next_aux, BuildInfo *info,
                                       uint32_t *stack_out, uint32_t *depth_out,
                                       const uint32_t *ni_all = nullptr, uint32_t *next_ni = nullptr) {
@@ -1182,7 +1211,23 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
         atomicOr(&info->err, 4u);
         return;
     }
+    // every load first, so the candidates' loads are issued together rather
+    // than one candidate's chain after the other's stores
+    int c[K];
     Box cb[K];
+    uint32_t cnt[K], fst[K], ni[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) c[k] = cand_f[k];  // valid candidates are the first nc slots
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        cb[k] = box_empty();
+        cnt[k] = fst[k] = ni[k] = 0;
+        if (c[k] < 0) continue;
+        cb[k] = tv.nbox[c[k]];  // box and range in one load
+        cnt[k] = range_count(cb[k]);
+        fst[k] = range_first(cb[k]);
+        if (next_ni && !tv.is_prim(c[k])) ni[k] = ni_all[c[k]];  // meaningful for interior candidates only
+    }
     uint32_t ref[K];
     int nc = 0;
     uint32_t r = 0;
@@ -1191,14 +1236,11 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
     uint32_t stack_need = aux & 0xFFFFu;
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        const int c = cand_f[k];  // valid candidates are the first nc slots
         ref[k] = kRefEmpty;
-        cb[k] = box_empty();
-        if (c < 0) continue;
+        if (c[k] < 0) continue;
         nc++;
-        cb[k] = tv.nbox[c];
-        if (tv.is_leaf(c)) {
-            ref[k] = ref_leaf(tv.first(c), tv.count(c));
+        if (cnt[k] <= (uint32_t)tv.leaf_size) {
+            ref[k] = ref_leaf(fst[k], cnt[k]);
         } else {
             const uint32_t pos = noff_f + r;
             if (pos >= cap || next_base + pos >= cap) {
@@ -1206,14 +1248,14 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
                 return;
             }
             ref[k] = ref_interior(next_base + pos);
-            next_node[pos] = c;
-            if (next_ni) next_ni[pos] = ni_all[c];
+            next_node[pos] = c[k];
+            if (next_ni) next_ni[pos] = ni[k];
             r++;
         }
     }
     stack_need += (uint32_t)(nc - 1);
     for (uint32_t k = 0; k < r; k++) next_aux[noff_f + k] = (stack_need & 0xFFFFu) | (depth << 16);
-    WideOut<Layout>::write(nodes, base + f, tv.nbox[x], cb, ref, nc, &info->err);
+    WideOut<Layout>::write(sink.at(base + f), tv.nbox[x], cb, ref, nc, &info->err);
     *stack_out = max(*stack_out, stack_need);
     *depth_out = max(*depth_out, depth + 1);  // + the leaf level below
 }
@@ -1223,7 +1265,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base
                                                       uint32_t cap, const int32_t *fr_node,
                                                       const uint32_t *fr_aux, const int32_t *cand_all,
                                                       const uint32_t *ni_all, const uint32_t *noff,
-                                                      void *nodes, int32_t *next_node,
+                                                      NodeSink sink, int32_t *next_node,
                                                       uint32_t *next_aux, uint32_t *next_ni,
                                                       BuildInfo *info) {
     constexpr int K = WideOut<Layout>::K;
@@ -1232,7 +1274,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base
     if (f < count) {
         const int x = fr_node[f];
         wide_emit_item<Layout>(tv, base, count, cap, f, x, fr_aux[f], cand_all + (size_t)x * K,
-                               noff[f], nodes, next_node, next_aux, info, &stack, &depth, ni_all,
+                               noff[f], sink, next_node, next_aux, info, &stack, &depth, ni_all,
                                next_ni);
     }
     wave_atomic_max(&info->max_stack, stack);
@@ -1251,7 +1293,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
                                                      int32_t *fr_node1, uint32_t *fr_aux0,
                                                      uint32_t *fr_aux1, const int32_t *cand_all,
                                                      const uint32_t *ni_all, uint32_t *noff,
-                                                     void *nodes, BuildInfo *info,
+                                                     NodeSink sink, BuildInfo *info,
                                                      uint32_t *state) {
     constexpr int K = WideOut<Layout>::K;
     __shared__ uint32_t wsum[kBlock / kWave];
@@ -1280,7 +1322,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
         __syncthreads();
         for (uint32_t f = threadIdx.x; f < count; f += kBlock)
             wide_emit_item<Layout>(tv, base, count, cap, f, frn[f], fra[f],
-                                   cand_all + (size_t)frn[f] * K, noff[f], nodes,
+                                   cand_all + (size_t)frn[f] * K, noff[f], sink,
                                    cur ? fr_node0 : fr_node1, cur ? fr_aux0 : fr_aux1, info, &stack,
                                    &depth);
         __syncthreads();
@@ -1463,6 +1505,38 @@ int32_t emit_leaf_data(bvh_handle_s *h, const LeafSource &ls, hipStream_t s) {
     return check_launch("leaf packing");
 }
 
+// Wide node counts of earlier builds, keyed by device, layout, leaf size,
+// builder and triangle count.  A build whose key was seen allocates its node
+// block up front (count + 1/64 + 64 nodes) while queued kernels run, and
+// packs straight into it; without a hint, or when the tree turns out larger,
+// the nodes go to the work area and into an exact block after the last level
+// (a host-blocking hipMalloc with the GPU idle, then a copy).  Repeated
+// builds of one mesh, as in per-frame rebuilds, hit the hint.
+class NodeCountHints {
+  public:
+    using Key = std::array<int64_t, 5>;
+    int64_t get(const Key &k) {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = map_.find(k);
+        return it == map_.end() ? 0 : it->second;
+    }
+    void put(const Key &k, int64_t v) {
+        std::lock_guard<std::mutex> g(mu_);
+        if (map_.size() >= kMaxEntries) map_.clear();
+        map_[k] = v;
+    }
+
+  private:
+    static constexpr size_t kMaxEntries = 4096;
+    std::mutex mu_;
+    std::map<Key, int64_t> map_;
+};
+
+NodeCountHints &node_count_hints() {
+    static NodeCountHints hints;
+    return hints;
+}
+
 template <int Layout>
 int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s *h,
                   const LeafSource &ls, hipStream_t s) {
@@ -1487,9 +1561,25 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     volatile uint32_t *vw = hw;
     vw[0] = vw[1] = vw[2] = vw[3] = kPending;
+    // leaf data and the child lists first: they keep the GPU busy while the
+    // host allocates the node block
+    BVH_TRY(emit_leaf_data(h, ls, s));
     k_wide_open_all<K><<<grid_for(m), kBlock, 0, s>>>(tv, m, cand_all, ni_all);
+    NodeSink sink{nullptr, 0, wnodes, (uint32_t)h->node_bytes};
+    const NodeCountHints::Key key{h->device, h->layout, h->leaf_size, h->builder, h->n_tris};
+    const int64_t hint = node_count_hints().get(key);
+    if (hint > 0) {
+        const uint32_t want = (uint32_t)std::min<int64_t>(cap, hint + hint / 64 + 64);
+        if (hipMalloc(&h->node_block, (size_t)want * h->node_bytes) == hipSuccess) {
+            sink.spec = static_cast<uint8_t *>(h->node_block);
+            sink.spec_cap = want;
+        } else {
+            (void)hipGetLastError();
+            h->node_block = nullptr;
+        }
+    }
     k_wide_top<Layout><<<1, kBlock, 0, s>>>(tv, cap, fr_node[0], fr_node[1], fr_aux[0], fr_aux[1],
-                                           cand_all, ni_all, noff[0], wnodes, info, hw);
+                                           cand_all, ni_all, noff[0], sink, info, hw);
     BVH_TRY(check_launch("wide packing (top levels)"));
     uint32_t base = 0, count = 0, curw = 0;
     BVH_TRY(wait_host_word(vw + 2, s, &curw));  // written last, after base and count
@@ -1503,7 +1593,7 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
         vw[3] = kPending;
         scan_u32(noff[nb], noff[nb], count, tile, hw + 3, s);
         k_wide_emit<Layout><<<grid_for(count), kBlock, 0, s>>>(
-            tv, base, count, cap, fr_node[cur], fr_aux[cur], cand_all, ni_all, noff[nb], wnodes,
+            tv, base, count, cap, fr_node[cur], fr_aux[cur], cand_all, ni_all, noff[nb], sink,
             fr_node[cur ^ 1], fr_aux[cur ^ 1], noff[nb ^ 1], info);
         BVH_TRY(check_launch("wide packing"));
         // the next level's size is known once the scan has run; the next
@@ -1522,11 +1612,32 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
         return set_error(BVH_EUNSUPPORTED,
                          "bvh_build: wide node buffer of %llu bytes exceeds 4 GiB (raise leaf_size)",
                          (unsigned long long)base * (unsigned long long)h->node_bytes);
-    BVH_TRY(emit_leaf_data(h, ls, s));
-    BVH_TRY(alloc_node_block(h, base));
-    BVH_HIP_TRY(hipMemcpyAsync(h->nodes, wnodes, (size_t)base * h->node_bytes,
-                               hipMemcpyDeviceToDevice, s));
-    return BVH_OK;
+    node_count_hints().put(key, base);
+    if (sink.spec && base <= sink.spec_cap) {  // every node is in place
+        h->nodes = h->node_block;
+        return BVH_OK;
+    }
+    void *spec = h->node_block;  // too small (or absent): move into an exact block
+    h->node_block = nullptr;
+    const int32_t rc = alloc_node_block(h, base);
+    if (rc == BVH_OK) {
+        const size_t nb0 = (size_t)std::min(base, sink.spec_cap) * h->node_bytes;
+        const size_t all = (size_t)base * h->node_bytes;
+        hipError_t e = hipSuccess;
+        if (nb0 > 0) e = hipMemcpyAsync(h->nodes, spec, nb0, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(static_cast<uint8_t *>(h->nodes) + nb0, wnodes + nb0, all - nb0,
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && spec) e = hipStreamSynchronize(s);
+        if (spec) (void)hipFree(spec);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(BVH_EHIP, "wide packing: node copy failed: %s", hipGetErrorString(e));
+        }
+        return BVH_OK;
+    }
+    if (spec) (void)hipFree(spec);
+    return rc;
 }
 
 // ---------------------------------------------------------------------------

@@ -277,3 +277,50 @@ def test_shared_slab_matches_aabb2(scene):
     rows = np.arange(len(ab))
     np.testing.assert_array_equal(sl["slo"], ab["lo"][rows, axis])
     np.testing.assert_array_equal(sl["shi"], ab["hi"][rows, axis])
+
+
+def _offset_scene(offs):
+    small = np.array([[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.005]], np.float32)
+    offs = np.asarray(offs, np.float32)
+    v = (small[None] + offs[:, None]).reshape(-1, 3).astype(np.float32)
+    return v, np.arange(len(v), dtype=np.int32).reshape(-1, 3)
+
+
+@pytest.mark.parametrize("layout", ["bvh4", "bvh8_q8", "bvh8_q16"])
+def test_node_block_hint_paths(layout):
+    """The wide packers reuse the node count of an earlier build with the same
+    (layout, leaf size, triangle count) to allocate the node block ahead.
+    Two 4,096-triangle meshes: coincident triangles (a balanced tree, full
+    leaves) and 512 groups of 8 where each group peels off one triangle per
+    level (many small leaves, far more wide nodes).  The second mesh built
+    right after the first overflows the block sized from the first one's
+    count and takes the spill-and-copy path; built again it fits.  Both
+    results must be byte-identical, and the first mesh rebuilt after the
+    second (a larger hint) must match its first build."""
+    from paper_2511_15028_amd import bvh
+    a_v, a_t = _offset_scene(np.zeros((4096, 3)))
+    g = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"), -1)
+    inner = np.array([[0, 0, 0]] * 4 + [[1, 0, 0], [2, 0, 0], [4, 0, 0], [8, 0, 0]], np.float32)
+    b_v, b_t = _offset_scene((g.reshape(-1, 3)[:, None, :] * 16.0 + inner[None]).reshape(-1, 3))
+    ha = _build(a_v, a_t, layout)
+    na = ha.stats()["n_nodes"]
+    hb1 = _build(b_v, b_t, layout)
+    nb = hb1.stats()["n_nodes"]
+    assert nb > na + na // 64 + 64, (na, nb)   # the first mesh's hint is too small
+    hb2 = _build(b_v, b_t, layout)
+    assert hb2.stats()["n_nodes"] == nb
+    assert hb1.read_buffer(bvh.BUF_NODES) == hb2.read_buffer(bvh.BUF_NODES)
+    ha2 = _build(a_v, a_t, layout)
+    assert ha2.read_buffer(bvh.BUF_NODES) == ha.read_buffer(bvh.BUF_NODES)
+    # the spilled build is a tree covering every triangle once
+    st = hb1.stats()
+    raw = hb1.read_buffer(bvh.BUF_NODES)
+    assert len(raw) == nb * st["node_bytes"]
+    frame = (st["frame_origin"], st["frame_scale"], st["frame_top"])
+    _, leaves, visited = LD.walk(LAYOUTS[layout], raw, frame)
+    assert (visited == 1).all() and len(leaves) == st["n_leaves"]
+    tri = np.frombuffer(hb1.read_buffer(bvh.BUF_LEAF), dtype=LD.TRI_DT)
+    covered = np.zeros(len(b_t), np.int64)
+    for first, n, _ in leaves:
+        covered[tri["prim"][first:first + n]] += 1
+    assert (covered == 1).all()
