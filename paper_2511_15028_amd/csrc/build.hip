@@ -655,14 +655,34 @@ __global__ __launch_bounds__(kBlock) void k_table_levels(Box *table, int nblocks
     }
 }
 
+// Internal node i's range has i as one end (Karras order) or contains it
+// (the SAH ids), so a range inside one 64-block lies within 64 leaves of i:
+// the workgroup stages the leaf boxes around its nodes in LDS (coalesced,
+// about 1.5 boxes per node) and unions in-block ranges from there; a range
+// outside the window (the SAH root's remapped id) reads global memory.
+constexpr int kBoxWindow = kBlock + 2 * kRangeBlock;
+
 __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirst,
                                                            const uint32_t *icount, int n,
                                                            const Box *table, int nblocks,
                                                            const Box *pre, const Box *suf,
                                                            Box *nbox, float *area) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n - 1) return;
+    __shared__ float wb[6][kBoxWindow];
+    const int i0 = blockIdx.x * kBlock;
+    const int wlo = max(0, i0 - kRangeBlock), whi = min(n, i0 + kBlock + kRangeBlock);
     const Box *leaf = nbox + (n - 1);
+    for (int j = wlo + (int)threadIdx.x; j < whi; j += kBlock) {
+        const Box x = leaf[j];
+        wb[0][j - wlo] = x.lo.x;
+        wb[1][j - wlo] = x.lo.y;
+        wb[2][j - wlo] = x.lo.z;
+        wb[3][j - wlo] = x.hi.x;
+        wb[4][j - wlo] = x.hi.y;
+        wb[5][j - wlo] = x.hi.z;
+    }
+    __syncthreads();
+    const int i = i0 + (int)threadIdx.x;
+    if (i >= n - 1) return;
     const int a = (int)ifirst[i], b = a + (int)icount[i] - 1;
     if (a < 0 || b >= n || b < a) {  // malformed range: empty box, the range as given
         nbox[i] = with_range(box_empty(), ifirst[i], icount[i]);
@@ -670,7 +690,18 @@ __global__ __launch_bounds__(kBlock) void k_internal_boxes(const uint32_t *ifirs
     }
     const int ba = a / kRangeBlock, bb = b / kRangeBlock;
     Box u = box_empty();
-    if (ba == bb) {
+    if (ba == bb && a >= wlo && b < whi) {
+        float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        for (int j = a - wlo; j <= b - wlo; j++) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                v[c] = fminf(v[c], wb[c][j]);
+                v[3 + c] = fmaxf(v[3 + c], wb[3 + c][j]);
+            }
+        }
+        u.lo = make_float4(v[0], v[1], v[2], 0.0f);
+        u.hi = make_float4(v[3], v[4], v[5], 0.0f);
+    } else if (ba == bb) {
         int j = a;
         for (; j + 3 <= b; j += 4) {
             const Box x0 = leaf[j], x1 = leaf[j + 1], x2 = leaf[j + 2], x3 = leaf[j + 3];
