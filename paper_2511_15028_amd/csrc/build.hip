@@ -224,6 +224,107 @@ __global__ __launch_bounds__(kBlock) void k_scan_final_fused(const uint32_t *in,
     }
 }
 
+// Level table of the multi-block levels: lv[2l] = first node of level l,
+// lv[2l+1] = its node count, written on the GPU by the level's scan (the
+// host launches a level before it knows its count, with a grid bound).
+__device__ inline uint32_t level_count(const uint32_t *lv, int l, uint32_t bound, BuildInfo *info) {
+    const uint32_t c = lv[2 * l + 1];
+    if (c > bound) {  // cannot happen: a level is at most K times the one above
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&info->err, 4u);
+        return bound;
+    }
+    return c;
+}
+
+// Scan of a wide-packing level's interior-child counts, with the count read
+// from the level table: the last block also writes the next level's entry
+// (first node, count) and the count to a host-mapped word.  Launched with a
+// grid for `bound` items; blocks past the actual count leave at once.
+__device__ inline void level_total(uint32_t *lv, int l, uint32_t count, uint32_t total,
+                                   uint32_t *host_word) {
+    lv[2 * (l + 1)] = lv[2 * l] + count;
+    lv[2 * (l + 1) + 1] = total;
+    *host_word = total;
+    __threadfence_system();  // the host polls the word
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_level_single(uint32_t *cnt, uint32_t *lv, int l,
+                                                              uint32_t bound, uint32_t *host_word,
+                                                              BuildInfo *info) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const uint32_t n = level_count(lv, l, bound, info);
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < n; c += kScanTile) {
+        const uint32_t base = c + threadIdx.x * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            v[k] = base + k < n ? cnt[base + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t tot;
+        uint32_t run = carry + block_excl_scan(sum, &tot, wsum);
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            if (base + k < n) cnt[base + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+        __syncthreads();  // wsum is reused by the next tile
+    }
+    if (threadIdx.x == 0) level_total(lv, l, n, carry, host_word);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_level_reduce(const uint32_t *cnt, const uint32_t *lv,
+                                                              int l, uint32_t bound,
+                                                              uint32_t *tile_sums) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const uint32_t n = min(lv[2 * l + 1], bound);
+    if (blockIdx.x * kScanTile >= n) return;
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++)
+        if (base + k < n) sum += cnt[base + k];
+    uint32_t tot;
+    block_excl_scan(sum, &tot, wsum);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_level_final(uint32_t *cnt, uint32_t *lv, int l,
+                                                             uint32_t bound, const uint32_t *tile_sums,
+                                                             uint32_t *host_word, BuildInfo *info) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const uint32_t n = level_count(lv, l, bound, info);
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (ntiles == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) level_total(lv, l, 0, 0, host_word);
+        return;
+    }
+    if (blockIdx.x >= ntiles) return;
+    uint32_t part = 0;
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kBlock) part += tile_sums[t];
+    uint32_t before;
+    block_excl_scan(part, &before, wsum);
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = base + k < n ? cnt[base + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = before + block_excl_scan(sum, &tot, wsum);
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < n) cnt[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == ntiles - 1 && threadIdx.x == 0) level_total(lv, l, n, before + tot, host_word);
+}
+
 // Exclusive scan of n values; total (device) receives the sum if non-null.
 // tile_sums must hold ceil(n / kScanTile) entries.
 void scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tile_sums,
@@ -1292,14 +1393,17 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
 }
 
 template <int Layout>
-__global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, uint32_t base, uint32_t count,
-                                                      uint32_t cap, const int32_t *fr_node,
+__global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, const uint32_t *lv, int l,
+                                                      uint32_t bound, uint32_t cap,
+                                                      const int32_t *fr_node,
                                                       const uint32_t *fr_aux, const int32_t *cand_all,
                                                       const uint32_t *ni_all, const uint32_t *noff,
                                                       NodeSink sink, int32_t *next_node,
                                                       uint32_t *next_aux, uint32_t *next_ni,
                                                       BuildInfo *info) {
     constexpr int K = WideOut<Layout>::K;
+    const uint32_t base = lv[2 * l];
+    const uint32_t count = level_count(lv, l, bound, info);
     const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
     uint32_t stack = 0, depth = 0;
     if (f < count) {
@@ -1325,7 +1429,7 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
                                                      uint32_t *fr_aux1, const int32_t *cand_all,
                                                      const uint32_t *ni_all, uint32_t *noff,
                                                      NodeSink sink, BuildInfo *info,
-                                                     uint32_t *state) {
+                                                     uint32_t *state, uint32_t *lv) {
     constexpr int K = WideOut<Layout>::K;
     __shared__ uint32_t wsum[kBlock / kWave];
     if (threadIdx.x == 0) {  // frontier = {root} with zero stack need and depth
@@ -1363,7 +1467,15 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
     }
     wave_atomic_max(&info->max_stack, stack);
     wave_atomic_max(&info->max_depth, depth);
+    if (cur == 1) {  // hand over in buffer 0, so the host can queue the next level blind
+        for (uint32_t f = threadIdx.x; f < count; f += kBlock) {
+            fr_node0[f] = fr_node1[f];
+            fr_aux0[f] = fr_aux1[f];
+        }
+    }
     if (threadIdx.x == 0) {
+        lv[0] = base;  // level table entry of the first multi-block level
+        lv[1] = count;
         // state lives in host memory the host polls: state[2] is written
         // last, after base and count are visible
         state[0] = base;
@@ -1377,20 +1489,28 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
 // ---------------------------------------------------------------------------
 // Leaf data
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, const int32_t *tris,
-                                                         const uint32_t *perm, uint32_t n,
-                                                         bvh_tri *out) {
+// The build reports out-of-range vertex indices only after this kernel has
+// run (the wide layouts do not wait for the bounds pass's verdict), so a
+// triangle with such an index is written as zeros instead of being read.
+__global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, int64_t n_verts,
+                                                         const int32_t *tris, const uint32_t *perm,
+                                                         uint32_t n, bvh_tri *out) {
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     const uint32_t t = perm[j];
-    const float *p0 = verts + 3 * (size_t)tris[3 * (size_t)t];
-    const float *p1 = verts + 3 * (size_t)tris[3 * (size_t)t + 1];
-    const float *p2 = verts + 3 * (size_t)tris[3 * (size_t)t + 2];
+    const int32_t i0 = tris[3 * (size_t)t], i1 = tris[3 * (size_t)t + 1], i2 = tris[3 * (size_t)t + 2];
     bvh_tri r;
-    for (int a = 0; a < 3; a++) {
-        r.p0[a] = p0[a];
-        r.e1[a] = p0[a] - p1[a];  // the f32 edges of the intersection test
-        r.e2[a] = p2[a] - p0[a];
+    if (i0 >= 0 && i0 < n_verts && i1 >= 0 && i1 < n_verts && i2 >= 0 && i2 < n_verts) {
+        const float *p0 = verts + 3 * (size_t)i0;
+        const float *p1 = verts + 3 * (size_t)i1;
+        const float *p2 = verts + 3 * (size_t)i2;
+        for (int a = 0; a < 3; a++) {
+            r.p0[a] = p0[a];
+            r.e1[a] = p0[a] - p1[a];  // the f32 edges of the intersection test
+            r.e2[a] = p2[a] - p0[a];
+        }
+    } else {
+        for (int a = 0; a < 3; a++) r.p0[a] = r.e1[a] = r.e2[a] = 0.0f;
     }
     r.prim_id = (int32_t)t;
     r.pad[0] = r.pad[1] = 0;
@@ -1523,8 +1643,8 @@ struct LeafSource {
 
 int32_t emit_leaf_data(bvh_handle_s *h, const LeafSource &ls, hipStream_t s) {
     if (h->leaf_mode == BVH_LEAF_COMPACT) {
-        k_leaf_compact<<<grid_for(ls.n), kBlock, 0, s>>>(ls.verts, ls.tris, ls.perm, ls.n,
-                                                          static_cast<bvh_tri *>(h->leaf));
+        k_leaf_compact<<<grid_for(ls.n), kBlock, 0, s>>>(ls.verts, ls.n_verts, ls.tris, ls.perm,
+                                                          ls.n, static_cast<bvh_tri *>(h->leaf));
     } else {
         BVH_HIP_TRY(hipMemcpyAsync(h->leaf, ls.perm, (size_t)ls.n * sizeof(int32_t),
                                    hipMemcpyDeviceToDevice, s));
@@ -1568,14 +1688,27 @@ NodeCountHints &node_count_hints() {
     return hints;
 }
 
+// The wide packing does not wait for the whole build so far: the leaf data
+// and the child lists (which need no count) are queued first, then the host
+// reads the leaf count from the word the collapse scan writes (*nleaf_word,
+// host-mapped) while those kernels run.  cand_all / ni_all hold max(n-1, 1)
+// lists of K.
 template <int Layout>
-int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s *h,
-                  const LeafSource &ls, hipStream_t s) {
+int32_t pack_wide(TreeView tv, volatile uint32_t *nleaf_word, int32_t *cand_all, uint32_t *ni_all,
+                  BuildInfo *info, bvh_handle_s *h, const LeafSource &ls, hipStream_t s) {
     constexpr int K = WideOut<Layout>::K;
-    const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
     const uint32_t m = std::max<uint32_t>(1, (uint32_t)tv.n - 1);  // binary nodes with a list
-    int32_t *fr_node[2], *cand_all;
-    uint32_t *fr_aux[2], *noff[2], *ni_all, *tile;
+    BVH_TRY(emit_leaf_data(h, ls, s));
+    k_wide_open_all<K><<<grid_for(m), kBlock, 0, s>>>(tv, m, cand_all, ni_all);
+    BVH_TRY(check_launch("wide packing (child lists)"));
+    uint32_t n_leaves = 0;
+    BVH_TRY(wait_host_word(nleaf_word, s, &n_leaves));
+    if (n_leaves < 1 || n_leaves > (uint32_t)tv.n)
+        return set_error(BVH_EHIP, "bvh_build: internal error (leaf count %u)", n_leaves);
+    h->n_leaves = n_leaves;
+    const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
+    int32_t *fr_node[2];
+    uint32_t *fr_aux[2], *noff[2], *tile;
     uint8_t *wnodes;
     Arena arena;
     arena.request(&wnodes, (size_t)cap * h->node_bytes);
@@ -1584,18 +1717,15 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
         arena.request(&fr_aux[b], cap);
         arena.request(&noff[b], cap);
     }
-    arena.request(&cand_all, (size_t)m * K);
-    arena.request(&ni_all, m);
     arena.request(&tile, (cap + kScanTile - 1) / kScanTile + 1);
+    constexpr int kMaxLevels = 4096;
+    uint32_t *lv;
+    arena.request(&lv, 2 * (kMaxLevels + 3));
     BVH_TRY(arena.bind(s, kAreaBuildWide));
     uint32_t *hw = host_words();
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     volatile uint32_t *vw = hw;
     vw[0] = vw[1] = vw[2] = vw[3] = kPending;
-    // leaf data and the child lists first: they keep the GPU busy while the
-    // host allocates the node block
-    BVH_TRY(emit_leaf_data(h, ls, s));
-    k_wide_open_all<K><<<grid_for(m), kBlock, 0, s>>>(tv, m, cand_all, ni_all);
     NodeSink sink{nullptr, 0, wnodes, (uint32_t)h->node_bytes};
     const NodeCountHints::Key key{h->device, h->layout, h->leaf_size, h->builder, h->n_tris};
     const int64_t hint = node_count_hints().get(key);
@@ -1610,32 +1740,51 @@ int32_t pack_wide(TreeView tv, uint32_t n_leaves, BuildInfo *info, bvh_handle_s 
         }
     }
     k_wide_top<Layout><<<1, kBlock, 0, s>>>(tv, cap, fr_node[0], fr_node[1], fr_aux[0], fr_aux[1],
-                                           cand_all, ni_all, noff[0], sink, info, hw);
+                                           cand_all, ni_all, noff[0], sink, info, hw, lv);
     BVH_TRY(check_launch("wide packing (top levels)"));
+    const int cur0 = 0;  // the top kernel hands its last frontier over in buffer 0
+    // Level l (0 = the first multi-block one) scans noff[l & 1] and emits from
+    // frontier buffer (cur0 + l) & 1.  Its count comes from the level table,
+    // so level l+1 is queued, with a grid for K times level l's count, before
+    // the host has read level l+1's count: the GPU never waits for the host.
+    auto count_word = [&](int l) { return hw + 16 + (l & 31); };
+    auto launch_level = [&](int l, uint32_t bound) -> int32_t {
+        const int fb = (cur0 + l) & 1, nbuf = l & 1;
+        uint32_t *w = count_word(l + 1);
+        *(volatile uint32_t *)w = kPending;
+        const uint32_t tiles = (bound + kScanTile - 1) / kScanTile;
+        if (tiles <= kScanSingleTiles) {
+            k_scan_level_single<<<1, kBlock, 0, s>>>(noff[nbuf], lv, l, bound, w, info);
+        } else {
+            k_scan_level_reduce<<<tiles, kBlock, 0, s>>>(noff[nbuf], lv, l, bound, tile);
+            k_scan_level_final<<<tiles, kBlock, 0, s>>>(noff[nbuf], lv, l, bound, tile, w, info);
+        }
+        k_wide_emit<Layout><<<grid_for(bound), kBlock, 0, s>>>(
+            tv, lv, l, bound, cap, fr_node[fb], fr_aux[fb], cand_all, ni_all, noff[nbuf], sink,
+            fr_node[fb ^ 1], fr_aux[fb ^ 1], noff[nbuf ^ 1], info);
+        return check_launch("wide packing");
+    };
+    // level 0 is at most K times the top kernel's largest level
+    BVH_TRY(launch_level(0, std::min<uint32_t>(cap, K * kTopMaxFrontier)));
     uint32_t base = 0, count = 0, curw = 0;
     BVH_TRY(wait_host_word(vw + 2, s, &curw));  // written last, after base and count
     base = vw[0];
     count = vw[1];
-    int cur = (int)curw;
-    if (base + count > cap) return set_error(BVH_EHIP, "wide packing overflow");
-    int nb = 0;  // noff[nb]: the current level's interior-child counts, then their offsets
-    for (int level = 0; count > 0; level++) {
-        if (level > 4096) return set_error(BVH_EHIP, "wide packing did not terminate");
-        vw[3] = kPending;
-        scan_u32(noff[nb], noff[nb], count, tile, hw + 3, s);
-        k_wide_emit<Layout><<<grid_for(count), kBlock, 0, s>>>(
-            tv, base, count, cap, fr_node[cur], fr_aux[cur], cand_all, ni_all, noff[nb], sink,
-            fr_node[cur ^ 1], fr_aux[cur ^ 1], noff[nb ^ 1], info);
-        BVH_TRY(check_launch("wide packing"));
-        // the next level's size is known once the scan has run; the next
-        // launches queue behind this level's emit
-        uint32_t next = 0;
-        BVH_TRY(wait_host_word(vw + 3, s, &next));
-        base += count;
-        if (base + next > cap) return set_error(BVH_EHIP, "wide packing overflow");
-        count = next;
-        cur ^= 1;
-        nb ^= 1;
+    if (base + count > cap || count > K * kTopMaxFrontier)
+        return set_error(BVH_EHIP, "wide packing overflow");
+    if (count > 0) {
+        for (int l = 0;; l++) {
+            if (l >= kMaxLevels) return set_error(BVH_EHIP, "wide packing did not terminate");
+            const uint32_t next_bound = (uint32_t)std::min<uint64_t>(cap, (uint64_t)K * count);
+            BVH_TRY(launch_level(l + 1, next_bound));
+            uint32_t next = 0;
+            BVH_TRY(wait_host_word(count_word(l + 1), s, &next));
+            base += count;
+            if (base + next > cap || next > next_bound)
+                return set_error(BVH_EHIP, "wide packing overflow");
+            count = next;
+            if (count == 0) break;  // the level queued last is empty: its kernels return at once
+        }
     }
     h->n_nodes = base;
     // the wide traversal kernels address node fields with 32-bit byte offsets
@@ -2365,6 +2514,13 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     arena.request(&pre, n);
     arena.request(&suf, n);
     arena.request(&area, n - 1);
+    int32_t *cand_all = nullptr;  // wide layouts: the child list of every binary node
+    uint32_t *ni_all = nullptr;
+    if (layout_arity(h->layout) > 2) {
+        const size_t m = (size_t)std::max(1, n - 1);
+        arena.request(&cand_all, m * (size_t)layout_arity(h->layout));
+        arena.request(&ni_all, m);
+    }
     BVH_TRY(arena.bind(s, kAreaBuild));
 
     BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
@@ -2416,22 +2572,34 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // a6
     TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox, area};
     k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
-    scan_u32(mark, mark, n, tile, &info->n_leaves, s);
+    const bool wide = h->layout == BVH_LAYOUT_BVH4 || h->layout == BVH_LAYOUT_BVH8_Q8 ||
+                      h->layout == BVH_LAYOUT_BVH8_Q16;
+    uint32_t *hw = host_words();
+    if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
+    volatile uint32_t *nleaf_word = hw + 8;
+    *nleaf_word = kPending;
+    // the wide layouts read the leaf count from a host-mapped word instead of
+    // draining the stream; the others need the scene box before packing
+    scan_u32(mark, mark, n, tile, wide ? hw + 8 : &info->n_leaves, s);
     BVH_TRY(check_launch("collapse"));
     BuildInfo hi;
     BuildInfo *pin = pinned_scratch<BuildInfo>();
     if (!pin) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
-    BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
-    BVH_TRY(alloc_leaf_block(h));  // while the queued kernels run
-    BVH_HIP_TRY(hipStreamSynchronize(s));
-    hi = *pin;
-    if (hi.err & 1u) return set_error(BVH_EINVAL, "bvh_build: a vertex index is outside [0, n_verts)");
     const LeafSource ls{verts, n_verts, tris, perm, (uint32_t)n};
-    for (int a = 0; a < 3; a++) {
-        h->scene_lo[a] = hi.slo[a];
-        h->scene_hi[a] = hi.shi[a];
+    if (!wide) {
+        BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
+        BVH_TRY(alloc_leaf_block(h));  // while the queued kernels run
+        BVH_HIP_TRY(hipStreamSynchronize(s));
+        hi = *pin;
+        if (hi.err & 1u) return set_error(BVH_EINVAL, "bvh_build: a vertex index is outside [0, n_verts)");
+        for (int a = 0; a < 3; a++) {
+            h->scene_lo[a] = hi.slo[a];
+            h->scene_hi[a] = hi.shi[a];
+        }
+        h->n_leaves = hi.n_leaves;
+    } else {
+        BVH_TRY(alloc_leaf_block(h));  // while the queued kernels run
     }
-    h->n_leaves = hi.n_leaves;
 
     // a7
     if (h->layout == BVH_LAYOUT_AABB2) {
@@ -2505,15 +2673,22 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
             k_pack_sg_eq<true><<<g, kBlock, 0, s>>>(tmp, nn, fr, h->nodes, info);
         BVH_TRY(check_launch("scene-frame packing"));
     } else if (h->layout == BVH_LAYOUT_BVH4) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, hi.n_leaves, info, h, ls, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH4>(tv, nleaf_word, cand_all, ni_all, info, h, ls, s));
     } else if (h->layout == BVH_LAYOUT_BVH8_Q8) {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, hi.n_leaves, info, h, ls, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q8>(tv, nleaf_word, cand_all, ni_all, info, h, ls, s));
     } else {
-        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, hi.n_leaves, info, h, ls, s));
+        BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, nleaf_word, cand_all, ni_all, info, h, ls, s));
     }
     BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     BVH_HIP_TRY(hipStreamSynchronize(s));
     hi = *pin;
+    if (wide) {
+        if (hi.err & 1u) return set_error(BVH_EINVAL, "bvh_build: a vertex index is outside [0, n_verts)");
+        for (int a = 0; a < 3; a++) {
+            h->scene_lo[a] = hi.slo[a];
+            h->scene_hi[a] = hi.shi[a];
+        }
+    }
     if (hi.err & 4u) return set_error(BVH_EHIP, "bvh_build: internal error (malformed hierarchy)");
     if (hi.err & 2u)
         return set_error(BVH_EUNSUPPORTED, "bvh_build: non-finite box extent (coordinates too large?)");
