@@ -86,12 +86,19 @@ __device__ inline float wave_min(float v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
     return v;
 }
-// One atomicMax per wave: every lane of the wave must reach the call (lanes
-// with nothing to report pass 0).
-__device__ inline void wave_atomic_max(uint32_t *addr, uint32_t v) {
+// Build-wide maxima (stack and depth bounds) without contention: one
+// atomicMax per wave into one of kMaxSlots words chosen by the wave's global
+// index, folded by k_fold_max_slots at the end.  Device-scope atomics on a
+// single word from every wave of a launch serialise across the XCDs (tens of
+// microseconds per large launch); spread over 256 words they do not.  Every
+// lane of the wave must reach the call (lanes with nothing to report pass 0).
+constexpr int kMaxSlots = 256;
+
+__device__ inline void wave_max_to_slots(uint32_t *slots, uint32_t v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicMax(addr, v);
+    const uint32_t wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicMax(&slots[wave & (kMaxSlots - 1)], v);
 }
 
 __device__ inline float wave_max(float v) {
@@ -838,6 +845,8 @@ struct TreeView {
     const uint8_t *iaxis;
     const Box *nbox;
     const float *area;     // surface-area measure of internal nodes
+    uint32_t *stack_slots;  // kMaxSlots words each (zeroed at build start): see wave_max_to_slots
+    uint32_t *depth_slots;
     __device__ bool is_prim(int x) const { return x >= n - 1; }
     __device__ uint32_t count(int x) const { return is_prim(x) ? 1u : icount[x]; }
     __device__ uint32_t first(int x) const { return is_prim(x) ? (uint32_t)(x - (n - 1)) : ifirst[x]; }
@@ -906,8 +915,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_aabb2(TreeView tv, const uint32
     uint32_t depth = 0, stack = 0;
     if (x < 2 * tv.n - 1 && tv.alive(x))
         emit_aabb2_item(tv, x, lbefore, nodes, n_nodes, info, &depth, &stack);
-    wave_atomic_max(&info->max_depth, depth);
-    wave_atomic_max(&info->max_stack, stack);
+    wave_max_to_slots(tv.depth_slots, depth);
+    wave_max_to_slots(tv.stack_slots, stack);
 }
 
 // ---------------------------------------------------------------------------
@@ -1412,8 +1421,8 @@ __global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, const uint32_
                                noff[f], sink, next_node, next_aux, info, &stack, &depth, ni_all,
                                next_ni);
     }
-    wave_atomic_max(&info->max_stack, stack);
-    wave_atomic_max(&info->max_depth, depth);
+    wave_max_to_slots(tv.stack_slots, stack);
+    wave_max_to_slots(tv.depth_slots, depth);
 }
 
 // The top levels, while the frontier is small, in one workgroup: gather the
@@ -1465,8 +1474,8 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
         count = carry;
         cur ^= 1;
     }
-    wave_atomic_max(&info->max_stack, stack);
-    wave_atomic_max(&info->max_depth, depth);
+    wave_max_to_slots(tv.stack_slots, stack);
+    wave_max_to_slots(tv.depth_slots, depth);
     if (cur == 1) {  // hand over in buffer 0, so the host can queue the next level blind
         for (uint32_t f = threadIdx.x; f < count; f += kBlock) {
             fr_node0[f] = fr_node1[f];
@@ -1483,6 +1492,36 @@ __global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, 
         __threadfence_system();
         state[2] = (uint32_t)cur;
         __threadfence_system();
+    }
+}
+
+// Folds the per-wave maxima slots into info->max_stack / max_depth.
+__global__ __launch_bounds__(kBlock) void k_fold_max_slots(const uint32_t *stack_slots,
+                                                           const uint32_t *depth_slots,
+                                                           BuildInfo *info) {
+    __shared__ uint32_t red[2][kBlock / kWave];
+    uint32_t a = 0, b = 0;
+    for (int i = threadIdx.x; i < kMaxSlots; i += kBlock) {
+        a = max(a, stack_slots[i]);
+        b = max(b, depth_slots[i]);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        a = max(a, (uint32_t)__shfl_xor((int)a, o, kWave));
+        b = max(b, (uint32_t)__shfl_xor((int)b, o, kWave));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[0][threadIdx.x / kWave] = a;
+        red[1][threadIdx.x / kWave] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // a, b already hold wave 0's maxima
+        for (int w = 1; w < kBlock / kWave; w++) {
+            a = max(a, red[0][w]);
+            b = max(b, red[1][w]);
+        }
+        info->max_stack = max(info->max_stack, a);
+        info->max_depth = max(info->max_depth, b);
     }
 }
 
@@ -2514,6 +2553,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     arena.request(&pre, n);
     arena.request(&suf, n);
     arena.request(&area, n - 1);
+    uint32_t *bound_slots;
+    arena.request(&bound_slots, 2 * kMaxSlots);
     int32_t *cand_all = nullptr;  // wide layouts: the child list of every binary node
     uint32_t *ni_all = nullptr;
     if (layout_arity(h->layout) > 2) {
@@ -2524,6 +2565,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     BVH_TRY(arena.bind(s, kAreaBuild));
 
     BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
+    BVH_HIP_TRY(hipMemsetAsync(bound_slots, 0, 2 * kMaxSlots * sizeof(uint32_t), s));
     BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
     BVH_HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), s));
 
@@ -2570,7 +2612,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     }
     BVH_TRY(check_launch("hierarchy/boxes"));
     // a6
-    TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox, area};
+    TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox, area, bound_slots,
+                bound_slots + kMaxSlots};
     k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
     const bool wide = h->layout == BVH_LAYOUT_BVH4 || h->layout == BVH_LAYOUT_BVH8_Q8 ||
                       h->layout == BVH_LAYOUT_BVH8_Q16;
@@ -2679,6 +2722,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     } else {
         BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, nleaf_word, cand_all, ni_all, info, h, ls, s));
     }
+    k_fold_max_slots<<<1, kBlock, 0, s>>>(tv.stack_slots, tv.depth_slots, info);
+    BVH_TRY(check_launch("stack bound"));
     BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     BVH_HIP_TRY(hipStreamSynchronize(s));
     hi = *pin;

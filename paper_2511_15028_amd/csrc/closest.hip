@@ -492,31 +492,25 @@ __global__ __launch_bounds__(kTraceBlock) void k_cpq_persist(const void *nodes, 
     const uint64_t static_rounds = (n * 3u / 4u) / ((uint64_t)waves * kCpqClaim);
     const uint64_t static_end = static_rounds * waves * kCpqClaim;
     uint64_t round = 0;
+    uint32_t queue = wave % kQueues;  // the wave's current dynamic queue (wave-uniform)
     for (;;) {
         const uint64_t idle = __builtin_amdgcn_ballot_w64(qi == kNoQuery);
         const uint32_t nidle = (uint32_t)__builtin_popcountll(idle);
         if (nidle >= kCpqRefill && !(drained && pool == pool_end)) {
             const uint32_t avail = (uint32_t)(pool_end - pool);
-            uint64_t fresh = 0;
+            uint64_t fresh = 0, fresh_end = 0;  // a newly claimed range
             if (avail < nidle && !drained) {
                 if (round < static_rounds) {
                     fresh = (round * waves + wave) * kCpqClaim;
+                    fresh_end = fresh + kCpqClaim;
                     round++;
-                } else {
-                    const uint32_t leader = (uint32_t)__builtin_ctzll(idle);
-                    uint32_t lo = 0, hi = 0;
-                    if (lane == leader) {
-                        const unsigned long long b = atomicAdd(fb.queue, (unsigned long long)kCpqClaim);
-                        lo = (uint32_t)b;
-                        hi = (uint32_t)(b >> 32);
-                    }
-                    fresh = static_end + (((uint64_t)__builtin_amdgcn_readlane(hi, leader) << 32) |
-                                          __builtin_amdgcn_readlane(lo, leader));
+                } else if (!claim_dynamic(fb, static_end, n, kCpqClaim,
+                                          (uint32_t)__builtin_ctzll(idle), queue, fresh,
+                                          fresh_end)) {
+                    drained = true;
                 }
-                if (fresh >= n) drained = true;
             }
-            const uint32_t fresh_n =
-                (avail < nidle && fresh < n) ? (uint32_t)min((uint64_t)kCpqClaim, n - fresh) : 0u;
+            const uint32_t fresh_n = (uint32_t)(fresh_end - fresh);
             if (qi == kNoQuery) {
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));

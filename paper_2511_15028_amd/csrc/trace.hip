@@ -81,6 +81,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
     const uint64_t static_rounds = (n * 3u / 4u) / ((uint64_t)waves * kClaim);
     const uint64_t static_end = static_rounds * waves * kClaim;
     uint64_t round = 0;  // static chunks taken by this wave
+    uint32_t queue = wave % kQueues;  // the wave's current dynamic queue (wave-uniform)
     bool coherent = true;  // the wave's last rays all pointed into one octant
     for (;;) {
         const uint64_t idle = __builtin_amdgcn_ballot_w64(ray == kNoRay);
@@ -88,26 +89,19 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
         const uint32_t need = coherent ? 64u : kRefillLanes;
         if (nidle >= need && !(drained && pool == pool_end)) {
             const uint32_t avail = (uint32_t)(pool_end - pool);
-            uint64_t fresh = 0;  // start of a newly claimed range
+            uint64_t fresh = 0, fresh_end = 0;  // a newly claimed range
             if (avail < nidle && !drained) {
                 if (round < static_rounds) {
                     fresh = (round * waves + wave) * kClaim;
+                    fresh_end = fresh + kClaim;
                     round++;
-                } else {
-                    const uint32_t leader = (uint32_t)__builtin_ctzll(idle);
-                    uint32_t lo = 0, hi = 0;
-                    if (lane == leader) {
-                        const unsigned long long b = atomicAdd(fb.queue, (unsigned long long)kClaim);
-                        lo = (uint32_t)b;
-                        hi = (uint32_t)(b >> 32);
-                    }
-                    fresh = static_end + (((uint64_t)__builtin_amdgcn_readlane(hi, leader) << 32) |
-                                          __builtin_amdgcn_readlane(lo, leader));
+                } else if (!claim_dynamic(fb, static_end, n, kClaim,
+                                          (uint32_t)__builtin_ctzll(idle), queue, fresh,
+                                          fresh_end)) {
+                    drained = true;
                 }
-                if (fresh >= n) drained = true;
             }
-            const uint32_t fresh_n =
-                (avail < nidle && fresh < n) ? (uint32_t)min((uint64_t)kClaim, n - fresh) : 0u;
+            const uint32_t fresh_n = (uint32_t)(fresh_end - fresh);
             if (ray == kNoRay) {
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                     (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));

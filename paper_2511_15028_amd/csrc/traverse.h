@@ -1109,19 +1109,26 @@ __device__ inline Best trace_ray(const void *nodes, int64_t n_nodes, const Scene
 // overflowed the LDS stack, and one deep stack per fallback lane.
 constexpr int kFallbackBlocks = 128;
 constexpr int kFallbackLanes = kFallbackBlocks * kTraceBlock;
+// The dynamic part of a persistent launch is dealt by kQueues counters, each
+// on a line of its own and each handing out one slice of the part: waves
+// start at different queues, so their claims do not all serialise on one
+// word (device-scope atomics on one address are ordered across the XCDs).
+constexpr uint32_t kQueues = 8;
+constexpr size_t kQueueStride = 256;  // bytes between two queue counters
+
 struct Fallback {
     uint32_t *count;     // rays appended by the fast pass
-    unsigned long long *queue;  // next unclaimed ray of a persistent launch
+    unsigned long long *queue;  // queue q's next unclaimed offset at queue + q * kQueueStride bytes
     uint32_t *list;      // ray indices (capacity: rays of the launch)
     uint32_t *stack_ref; // [kFallbackLanes][kStackMax]
     float *stack_t;      // [kFallbackLanes][kStackMax]
 };
 
-// Bytes of the header (counter and queue) that must be zero before a launch.
-constexpr size_t kFallbackHeaderBytes = 16;
+// Bytes of the header (counter line, queue lines) that must be zero before a launch.
+constexpr size_t kFallbackHeaderBytes = kQueueStride * (1 + kQueues);
 
 inline size_t fallback_bytes(uint64_t n_rays) {
-    return 256 + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 8;
+    return kFallbackHeaderBytes + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 8;
 }
 
 // Carves the work area out of one allocation of fallback_bytes(n_rays).
@@ -1129,11 +1136,43 @@ inline Fallback fallback_view(void *base, uint64_t n_rays) {
     char *p = static_cast<char *>(base);
     Fallback f;
     f.count = reinterpret_cast<uint32_t *>(p);
-    f.queue = reinterpret_cast<unsigned long long *>(p + 8);
-    f.list = reinterpret_cast<uint32_t *>(p + 256);
-    f.stack_ref = reinterpret_cast<uint32_t *>(p + 256 + n_rays * 4);
-    f.stack_t = reinterpret_cast<float *>(p + 256 + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 4);
+    f.queue = reinterpret_cast<unsigned long long *>(p + kQueueStride);
+    char *q = p + kFallbackHeaderBytes;
+    f.list = reinterpret_cast<uint32_t *>(q);
+    f.stack_ref = reinterpret_cast<uint32_t *>(q + n_rays * 4);
+    f.stack_t = reinterpret_cast<float *>(q + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 4);
     return f;
+}
+
+// Claims the calling wave's next chunk of `claim` items of the dynamic part
+// [static_end, n) (wave-uniform call; `leader` is an active lane): from queue
+// q, then from the following queues as they run dry (q is updated).  Returns
+// false once all are exhausted, else the chunk [fresh, fresh_end).
+__device__ inline bool claim_dynamic(const Fallback &fb, uint64_t static_end, uint64_t n,
+                                     uint32_t claim, uint32_t leader, uint32_t &q,
+                                     uint64_t &fresh, uint64_t &fresh_end) {
+    const uint64_t qlen = (n - static_end + kQueues - 1) / kQueues;
+    for (uint32_t tries = 0; tries < kQueues; tries++) {
+        const uint64_t qs = static_end + (uint64_t)q * qlen;
+        const uint64_t qe = qs + qlen < n ? qs + qlen : n;
+        uint32_t lo = 0xFFFFFFFFu, hi = 0x7FFFFFFFu;  // "exhausted" for an empty slice
+        if ((threadIdx.x & 63u) == leader && qs < qe) {
+            unsigned long long *w = reinterpret_cast<unsigned long long *>(
+                reinterpret_cast<char *>(fb.queue) + (size_t)q * kQueueStride);
+            const unsigned long long b = atomicAdd(w, (unsigned long long)claim);
+            lo = (uint32_t)b;
+            hi = (uint32_t)(b >> 32);
+        }
+        const uint64_t b = ((uint64_t)__builtin_amdgcn_readlane(hi, leader) << 32) |
+                           __builtin_amdgcn_readlane(lo, leader);
+        if (qs < qe && b < qe - qs) {
+            fresh = qs + b;
+            fresh_end = fresh + claim < qe ? fresh + claim : qe;
+            return true;
+        }
+        q = (q + 1u) % kQueues;
+    }
+    return false;
 }
 
 __device__ inline void fallback_append(const Fallback &fb, uint32_t ray) {
