@@ -1666,6 +1666,7 @@ int32_t alloc_leaf_block(bvh_handle_s *h) {
 
 int32_t alloc_node_block(bvh_handle_s *h, int64_t n_nodes) {
     BVH_HIP_TRY(hipMalloc(&h->node_block, (size_t)n_nodes * (size_t)h->node_bytes));
+    h->node_block_cap = (uint32_t)n_nodes;
     h->nodes = h->node_block;
     return BVH_OK;
 }
@@ -1727,6 +1728,49 @@ NodeCountHints &node_count_hints() {
     return hints;
 }
 
+NodeCountHints::Key node_hint_key(const bvh_handle_s *h) {
+    return NodeCountHints::Key{h->device, h->layout, h->leaf_size, h->builder, h->n_tris};
+}
+
+// The node block of a wide layout, sized from the hint (none without one);
+// called while queued kernels keep the GPU busy.
+int32_t alloc_node_block_ahead(bvh_handle_s *h) {
+    const int64_t hint = node_count_hints().get(node_hint_key(h));
+    if (hint <= 0) return BVH_OK;
+    const int64_t want = std::min<int64_t>(std::max<int64_t>(1, h->n_tris - 1), hint + hint / 64 + 64);
+    if (hipMalloc(&h->node_block, (size_t)want * h->node_bytes) != hipSuccess) {
+        (void)hipGetLastError();  // no block ahead: the exact one comes after packing
+        h->node_block = nullptr;
+        return BVH_OK;
+    }
+    h->node_block_cap = (uint32_t)want;
+    return BVH_OK;
+}
+
+// A second stream per host thread and device (default priority), with two
+// events, for build work off the critical path: the leaf data needs only the
+// sorted order, so it runs beside the hierarchy and packing kernels, which
+// leave much of the GPU idle.  Null stream when creation fails.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+};
+
+SideStream *side_stream(int device) {
+    static thread_local std::map<int, SideStream> streams;
+    SideStream &ss = streams[device];
+    if (!ss.stream) {
+        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            ss = SideStream{};
+            return nullptr;
+        }
+    }
+    return &ss;
+}
+
 // The wide packing does not wait for the whole build so far: the leaf data
 // and the child lists (which need no count) are queued first, then the host
 // reads the leaf count from the word the collapse scan writes (*nleaf_word,
@@ -1737,7 +1781,7 @@ int32_t pack_wide(TreeView tv, volatile uint32_t *nleaf_word, int32_t *cand_all,
                   BuildInfo *info, bvh_handle_s *h, const LeafSource &ls, hipStream_t s) {
     constexpr int K = WideOut<Layout>::K;
     const uint32_t m = std::max<uint32_t>(1, (uint32_t)tv.n - 1);  // binary nodes with a list
-    BVH_TRY(emit_leaf_data(h, ls, s));
+    (void)ls;  // the leaf data is already queued (build_impl, on the side stream)
     k_wide_open_all<K><<<grid_for(m), kBlock, 0, s>>>(tv, m, cand_all, ni_all);
     BVH_TRY(check_launch("wide packing (child lists)"));
     uint32_t n_leaves = 0;
@@ -1765,19 +1809,9 @@ int32_t pack_wide(TreeView tv, volatile uint32_t *nleaf_word, int32_t *cand_all,
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     volatile uint32_t *vw = hw;
     vw[0] = vw[1] = vw[2] = vw[3] = kPending;
-    NodeSink sink{nullptr, 0, wnodes, (uint32_t)h->node_bytes};
-    const NodeCountHints::Key key{h->device, h->layout, h->leaf_size, h->builder, h->n_tris};
-    const int64_t hint = node_count_hints().get(key);
-    if (hint > 0) {
-        const uint32_t want = (uint32_t)std::min<int64_t>(cap, hint + hint / 64 + 64);
-        if (hipMalloc(&h->node_block, (size_t)want * h->node_bytes) == hipSuccess) {
-            sink.spec = static_cast<uint8_t *>(h->node_block);
-            sink.spec_cap = want;
-        } else {
-            (void)hipGetLastError();
-            h->node_block = nullptr;
-        }
-    }
+    NodeSink sink{static_cast<uint8_t *>(h->node_block), h->node_block ? h->node_block_cap : 0u,
+                  wnodes, (uint32_t)h->node_bytes};
+    const NodeCountHints::Key key = node_hint_key(h);
     k_wide_top<Layout><<<1, kBlock, 0, s>>>(tv, cap, fr_node[0], fr_node[1], fr_aux[0], fr_aux[1],
                                            cand_all, ni_all, noff[0], sink, info, hw, lv);
     BVH_TRY(check_launch("wide packing (top levels)"));
@@ -2574,12 +2608,33 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     k_prim_bounds<<<nbp, kBlock, 0, s>>>(verts, n_verts, tris, n, pbox, partial, info);
     k_bounds_final<<<1, kBlock, 0, s>>>(partial, nbp, info);
     const uint32_t *perm = nullptr;
+    const bool wide = h->layout == BVH_LAYOUT_BVH4 || h->layout == BVH_LAYOUT_BVH8_Q8 ||
+                      h->layout == BVH_LAYOUT_BVH8_Q16;
+    SideStream *side = nullptr;
+    // a8 leaf data for the wide layouts, queued as soon as the order is final,
+    // on the side stream: the leaf block's hipMalloc (and the node block's,
+    // from the hint) block the host while the queued kernels run, then the
+    // leaf kernel overlaps the hierarchy kernels
+    auto leaf_data_early = [&]() -> int32_t {
+        if (!wide) return BVH_OK;
+        BVH_TRY(alloc_leaf_block(h));
+        BVH_TRY(alloc_node_block_ahead(h));
+        const LeafSource early{verts, n_verts, tris, perm, (uint32_t)n};
+        side = side_stream(h->device);
+        if (!side) return emit_leaf_data(h, early, s);
+        BVH_HIP_TRY(hipEventRecord(side->ready, s));
+        BVH_HIP_TRY(hipStreamWaitEvent(side->stream, side->ready, 0));
+        BVH_TRY(emit_leaf_data(h, early, side->stream));
+        BVH_HIP_TRY(hipEventRecord(side->done, side->stream));
+        return BVH_OK;
+    };
     if (h->builder == BVH_BUILDER_SAH) {
         // a4 alternative: binned-SAH topology over the primitive boxes
         BVH_TRY(check_launch("bounds"));
         SahTree tr{ileft, iright, parent, ifirst, icount, iaxis, n};
         BVH_TRY(sah_topology(pbox, (uint32_t)n, vals[0], tr, tile, s));
         perm = vals[0];
+        BVH_TRY(leaf_data_early());
     } else {
         const int mbits = morton_bits(n);
         k_morton<<<nb, kBlock, 0, s>>>(pbox, n, info, mbits, keys[0], vals[0]);
@@ -2596,6 +2651,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         }
         BVH_TRY(check_launch("radix sort"));
         perm = vals[cur];
+        BVH_TRY(leaf_data_early());
+
         // a4
         if (n > 1)
             k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
@@ -2615,8 +2672,6 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox, area, bound_slots,
                 bound_slots + kMaxSlots};
     k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
-    const bool wide = h->layout == BVH_LAYOUT_BVH4 || h->layout == BVH_LAYOUT_BVH8_Q8 ||
-                      h->layout == BVH_LAYOUT_BVH8_Q16;
     uint32_t *hw = host_words();
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     volatile uint32_t *nleaf_word = hw + 8;
@@ -2640,8 +2695,6 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
             h->scene_hi[a] = hi.shi[a];
         }
         h->n_leaves = hi.n_leaves;
-    } else {
-        BVH_TRY(alloc_leaf_block(h));  // while the queued kernels run
     }
 
     // a7
@@ -2724,6 +2777,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     }
     k_fold_max_slots<<<1, kBlock, 0, s>>>(tv.stack_slots, tv.depth_slots, info);
     BVH_TRY(check_launch("stack bound"));
+    if (side) BVH_HIP_TRY(hipStreamWaitEvent(s, side->done, 0));  // the leaf data is part of the build
     BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     BVH_HIP_TRY(hipStreamSynchronize(s));
     hi = *pin;

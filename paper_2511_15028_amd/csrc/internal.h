@@ -76,6 +76,7 @@ struct bvh_handle_s {
     float frame_top[3] = {0, 0, 0};     // SG_EQ: hi = fmaf(-q, frame_scale, frame_top)
     void *block = nullptr;       // device allocation of leaf, verts and tris
     void *node_block = nullptr;  // device allocation of the node records
+    uint32_t node_block_cap = 0; // records node_block holds
     void *nodes = nullptr;       // node records
     void *leaf = nullptr;        // bvh_tri[n_tris] or int32 prim id[n_tris]
     float *verts = nullptr;      // INDEXED: own copy of the vertices
