@@ -87,18 +87,21 @@ __device__ inline float wave_min(float v) {
     return v;
 }
 // Build-wide maxima (stack and depth bounds) without contention: one
-// atomicMax per wave into one of kMaxSlots words chosen by the wave's global
-// index, folded by k_fold_max_slots at the end.  Device-scope atomics on a
-// single word from every wave of a launch serialise across the XCDs (tens of
-// microseconds per large launch); spread over 256 words they do not.  Every
-// lane of the wave must reach the call (lanes with nothing to report pass 0).
+// atomicMax per wave into one of kMaxSlots slots chosen by the wave's global
+// index, each slot on a cache line of its own, folded by k_fold_max_slots at
+// the end.  Device-scope atomics on one word (or one line) from every wave
+// of a launch serialise across the XCDs (tens of microseconds per large
+// launch); spread over 256 lines they do not.  Every lane of the wave must
+// reach the call (lanes with nothing to report pass 0).
 constexpr int kMaxSlots = 256;
+constexpr int kSlotStride = 32;  // words between slots: one 128-byte line each
 
 __device__ inline void wave_max_to_slots(uint32_t *slots, uint32_t v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, kWave));
     const uint32_t wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicMax(&slots[wave & (kMaxSlots - 1)], v);
+    if ((threadIdx.x & (kWave - 1)) == 0 && v)
+        atomicMax(&slots[(wave & (kMaxSlots - 1)) * kSlotStride], v);
 }
 
 __device__ inline float wave_max(float v) {
@@ -851,7 +854,7 @@ struct TreeView {
     const uint8_t *iaxis;
     const Box *nbox;
     const float *area;     // surface-area measure of internal nodes
-    uint32_t *stack_slots;  // kMaxSlots words each (zeroed at build start): see wave_max_to_slots
+    uint32_t *stack_slots;  // kMaxSlots slots each, kSlotStride words apart (zeroed at build start): see wave_max_to_slots
     uint32_t *depth_slots;
     __device__ bool is_prim(int x) const { return x >= n - 1; }
     __device__ uint32_t count(int x) const { return is_prim(x) ? 1u : icount[x]; }
@@ -1508,8 +1511,8 @@ __global__ __launch_bounds__(kBlock) void k_fold_max_slots(const uint32_t *stack
     __shared__ uint32_t red[2][kBlock / kWave];
     uint32_t a = 0, b = 0;
     for (int i = threadIdx.x; i < kMaxSlots; i += kBlock) {
-        a = max(a, stack_slots[i]);
-        b = max(b, depth_slots[i]);
+        a = max(a, stack_slots[i * kSlotStride]);
+        b = max(b, depth_slots[i * kSlotStride]);
     }
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -2594,7 +2597,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     arena.request(&suf, n);
     arena.request(&area, n - 1);
     uint32_t *bound_slots;
-    arena.request(&bound_slots, 2 * kMaxSlots);
+    arena.request(&bound_slots, 2 * kMaxSlots * kSlotStride);
     int32_t *cand_all = nullptr;  // wide layouts: the child list of every binary node
     uint32_t *ni_all = nullptr;
     if (layout_arity(h->layout) > 2) {
@@ -2605,7 +2608,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     BVH_TRY(arena.bind(s, kAreaBuild));
 
     BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
-    BVH_HIP_TRY(hipMemsetAsync(bound_slots, 0, 2 * kMaxSlots * sizeof(uint32_t), s));
+    BVH_HIP_TRY(hipMemsetAsync(bound_slots, 0, 2 * kMaxSlots * kSlotStride * sizeof(uint32_t), s));
     BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
     BVH_HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), s));
 
@@ -2676,7 +2679,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     BVH_TRY(check_launch("hierarchy/boxes"));
     // a6
     TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox, area, bound_slots,
-                bound_slots + kMaxSlots};
+                bound_slots + kMaxSlots * kSlotStride};
     k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
     uint32_t *hw = host_words();
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
