@@ -873,6 +873,29 @@ __global__ __launch_bounds__(kBlock) void k_mark_leaves(TreeView tv, uint32_t *m
     if (tv.alive(x) && tv.is_leaf(x)) mark[tv.first(x)] = 1u;
 }
 
+// The wide layouts need only the number of leaves: per-wave counts added
+// into kMaxSlots slots a line apart, then folded into a host-mapped word.
+__global__ __launch_bounds__(kBlock) void k_count_leaves(TreeView tv, uint32_t *slots) {
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    const bool leaf = x < 2 * tv.n - 1 && tv.alive(x) && tv.is_leaf(x);
+    const uint64_t b = __ballot(leaf);
+    const uint32_t wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0 && b)
+        atomicAdd(&slots[(wave & (kMaxSlots - 1)) * kSlotStride], (uint32_t)__popcll(b));
+}
+
+__global__ __launch_bounds__(kBlock) void k_fold_leaf_count(const uint32_t *slots, uint32_t *host_word) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    uint32_t v = 0;
+    for (int i = threadIdx.x; i < kMaxSlots; i += kBlock) v += slots[i * kSlotStride];
+    uint32_t total;
+    block_excl_scan(v, &total, wsum);
+    if (threadIdx.x == 0) {
+        *host_word = total;
+        __threadfence_system();  // the host polls the word
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a7 (AABB2): preorder packing.  With leaf_before(x) = number of leaves that
 // precede x's range (exclusive scan of mark) and lturns(x) = number of
@@ -2597,7 +2620,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     arena.request(&suf, n);
     arena.request(&area, n - 1);
     uint32_t *bound_slots;
-    arena.request(&bound_slots, 2 * kMaxSlots * kSlotStride);
+    arena.request(&bound_slots, 3 * kMaxSlots * kSlotStride);  // stack, depth, leaf-count slots
     int32_t *cand_all = nullptr;  // wide layouts: the child list of every binary node
     uint32_t *ni_all = nullptr;
     if (layout_arity(h->layout) > 2) {
@@ -2608,8 +2631,10 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     BVH_TRY(arena.bind(s, kAreaBuild));
 
     BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
-    BVH_HIP_TRY(hipMemsetAsync(bound_slots, 0, 2 * kMaxSlots * kSlotStride * sizeof(uint32_t), s));
-    BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
+    BVH_HIP_TRY(hipMemsetAsync(bound_slots, 0, 3 * kMaxSlots * kSlotStride * sizeof(uint32_t), s));
+    const bool wide = h->layout == BVH_LAYOUT_BVH4 || h->layout == BVH_LAYOUT_BVH8_Q8 ||
+                      h->layout == BVH_LAYOUT_BVH8_Q16;
+    if (!wide) BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
     BVH_HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), s));
 
     // a1, a2
@@ -2617,8 +2642,6 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     k_prim_bounds<<<nbp, kBlock, 0, s>>>(verts, n_verts, tris, n, pbox, partial, info);
     k_bounds_final<<<1, kBlock, 0, s>>>(partial, nbp, info);
     const uint32_t *perm = nullptr;
-    const bool wide = h->layout == BVH_LAYOUT_BVH4 || h->layout == BVH_LAYOUT_BVH8_Q8 ||
-                      h->layout == BVH_LAYOUT_BVH8_Q16;
     SideStream *side = nullptr;
     // a8 leaf data for the wide layouts, queued as soon as the order is final,
     // on the side stream: the leaf block's hipMalloc (and the node block's,
@@ -2680,14 +2703,21 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // a6
     TreeView tv{n, L, ileft, iright, parent, ifirst, icount, iaxis, nbox, area, bound_slots,
                 bound_slots + kMaxSlots * kSlotStride};
-    k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
     uint32_t *hw = host_words();
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     volatile uint32_t *nleaf_word = hw + 8;
     *nleaf_word = kPending;
     // the wide layouts read the leaf count from a host-mapped word instead of
-    // draining the stream; the others need the scene box before packing
-    scan_u32(mark, mark, n, tile, wide ? hw + 8 : &info->n_leaves, s);
+    // draining the stream (and need no leaf marks); the others need the scene
+    // box and the marks' exclusive scan before packing
+    if (wide) {
+        uint32_t *leaf_slots = bound_slots + 2 * kMaxSlots * kSlotStride;
+        k_count_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, leaf_slots);
+        k_fold_leaf_count<<<1, kBlock, 0, s>>>(leaf_slots, hw + 8);
+    } else {
+        k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
+        scan_u32(mark, mark, n, tile, &info->n_leaves, s);
+    }
     BVH_TRY(check_launch("collapse"));
     BuildInfo hi;
     BuildInfo *pin = pinned_scratch<BuildInfo>();
