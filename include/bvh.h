@@ -138,9 +138,9 @@ typedef struct bvh_stats {
 } bvh_stats;
 
 /* Compacted leaf triangle (BVH_LEAF_COMPACT), 48 B, in leaf order: the
- * first vertex and the two edges of the Moller-Trumbore test of App. G,
- * e1 = p0 - p1 and e2 = p2 - p0, each component rounded to f32 exactly as
- * the test rounds it (so p1 and p2 are not stored). */
+ * first vertex and the two edges of the ray/triangle test,
+ * e1 = p1 - p0 and e2 = p2 - p0, each component the f32 difference the test
+ * uses (so p1 and p2 are not stored). */
 typedef struct bvh_tri {
     float p0[3], e1[3], e2[3];
     int32_t prim_id; /* index of the triangle in the caller's `tris` */
@@ -353,8 +353,18 @@ int32_t bvh_read_buffer(bvh_handle_t h, int32_t which, void *host_dst, int64_t c
 /*
  * Traces n rays (closest_hit of Fig. 4 / App. G).  CLOSEST returns the hit
  * with the smallest t, ties to the lowest primitive id; ANY returns some hit
- * with t <= tmax, or a miss.  Ray-triangle test: Moller-Trumbore in the
- * operation order of App. G (edges inclusive, 0 < t <= tmax).
+ * with t <= tmax, or a miss.  Ray-triangle test: Moller-Trumbore (the test
+ * of App. G) with App. G's intervals (edges and vertices inclusive, both
+ * faces, 0 < t <= tmax), evaluated in FP32 as follows, every step one
+ * correctly rounded operation (fma = fused multiply-add):
+ *   e1 = p1 - p0, e2 = p2 - p0, S = o - p0;
+ *   a x b = (fma(a.y, b.z, -(a.z b.y)), fma(a.z, b.x, -(a.x b.z)),
+ *            fma(a.x, b.y, -(a.y b.x)));
+ *   a . b = fma(a.z, b.z, fma(a.y, b.y, a.x b.x));
+ *   P = d x e2, det = e1 . P, Q = S x e1;
+ *   U, V, T = S . P, d . Q, e2 . Q, each with the sign bit of det xor-ed in;
+ *   hit iff 0 < |det| < inf, U >= 0, V >= 0, U + V <= |det|, T > 0 and
+ *   T <= |det| tmax; then t, u, v = T, U, V times (1 / |det|).
  *   rays  device, n records;  hits  device, n records (written)
  * Errors: EINVAL for a null handle, n < 0, null pointers with n > 0, an
  * unknown mode.  Rays with tmin != 0 are traced as if tmin were 0.
@@ -373,10 +383,15 @@ int32_t bvh_trace_counts(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit
 
 /*
  * Gradient of a loss L through closest-hit results with each ray's hit
- * primitive held fixed.  For ray i with prim p = hits[i].prim_id >= 0 the
- * Moller-Trumbore quantities of p are recomputed from verts/tris; with
- * g = grad_hits[i] = dL/d(t,u,v) and J = [d | p0-p1 | p0-p2] the solution of
- * J^T lam = g gives
+ * primitive held fixed.  For ray i with p = hits[i].prim_id >= 0 (only the
+ * id is read from hits), the hit (t, u, v) on triangle p is recomputed from
+ * rays[i] and verts/tris with the FP32 arithmetic of the ray/triangle test
+ * of bvh_trace (so it equals the forward's hit bit for bit when the same
+ * inputs were traced; the interval tests are not applied, so a fixed
+ * primitive that the ray now misses still gets the gradient of its
+ * extended-plane solution).  With e1 = p1 - p0, e2 = p2 - p0,
+ * g = grad_hits[i] = dL/d(t,u,v) and J = [d | -e1 | -e2], the solution of
+ * J^T lam = g (by Cramer's rule, FP32) gives
  *   dL/do = -lam, dL/dd = -t lam, dL/dp0 = (1-u-v) lam, dL/dp1 = u lam,
  *   dL/dp2 = v lam
  * (implicit differentiation of o + t d = (1-u-v) p0 + u p1 + v p2).  No
@@ -389,7 +404,8 @@ int32_t bvh_trace_counts(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit
  *   grad_rays   device, n x 6 float (dL/do, dL/dd), OVERWRITTEN; a miss or
  *               a skipped ray gets zeros
  * Rays whose prim_id is outside [0, n_tris), whose triangle has a vertex
- * index outside [0, n_verts), or whose system is singular contribute nothing.
+ * index outside [0, n_verts), or whose system is singular (det = 0 or not
+ * finite) contribute nothing.
  * Errors: EINVAL for negative sizes or null pointers with a nonzero count.
  */
 int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,

@@ -8,8 +8,10 @@
  *
  * What it computes (paper: "Decoupling Data Layouts from Bounding Volume
  * Hierarchies", PLDI 2026):
- *   - orc_mt_f32        Moller-Trumbore ray/triangle test in FP32, in the
- *                       operation order of App. G (intersectsp_ray_tri_mt).
+ *   - orc_mt_f32        ray/triangle test in FP32 (Moller-Trumbore, the test
+ *                       of App. G, with App. G's acceptance intervals),
+ *                       written from the 1997 vector formulation with fused
+ *                       multiply-adds in a fixed order.
  *   - orc_brute_*       closest hit by exhaustive search over all triangles:
  *                       the plain definition of Fig. 4 / App. G closest_hit
  *                       (minimum t over every triangle the MT test accepts),
@@ -42,8 +44,9 @@
  * for the closest-point query: closed forms, the projection inequality,
  * dense sampling of the triangle, and BVH against exhaustive search).
  *
- * Build: gcc -O3 -fopenmp -ffp-contract=off (no FMA contraction, so the FP32
- * MT rounds each product and sum separately, exactly as written).
+ * Build: gcc -O3 -fopenmp -ffp-contract=off (no FMA contraction: every FP32
+ * product and sum rounds exactly as written; the fused multiply-adds of the
+ * ray/triangle test are explicit fmaf calls, each correctly rounded).
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,54 +55,64 @@
 #include <omp.h>
 
 /* ------------------------------------------------------------------------ */
-/* FP32 vector helpers, written out component by component.                 */
+/* FP32 vector helpers.                                                      */
 /* ------------------------------------------------------------------------ */
 typedef struct { float x, y, z; } v3;
 
 static inline v3 v3_load(const float *p) { v3 r = { p[0], p[1], p[2] }; return r; }
 static inline v3 v3_sub(v3 a, v3 b) { v3 r = { a.x - b.x, a.y - b.y, a.z - b.z }; return r; }
-/* cross(a, b) in the textbook order. */
-static inline v3 v3_cross(v3 a, v3 b) {
+/* a x b, each component as one product subtracted from a fused
+ * multiply-add: x = fma(a.y, b.z, -(a.z b.y)), and cyclically. */
+static inline v3 cross_fma(v3 a, v3 b) {
     v3 r;
-    r.x = a.y * b.z - a.z * b.y;
-    r.y = a.z * b.x - a.x * b.z;
-    r.z = a.x * b.y - a.y * b.x;
+    r.x = fmaf(a.y, b.z, -(a.z * b.y));
+    r.y = fmaf(a.z, b.x, -(a.x * b.z));
+    r.z = fmaf(a.x, b.y, -(a.y * b.x));
     return r;
 }
-/* dot(a, b) = (a.x b.x + a.y b.y) + a.z b.z, left to right. */
-static inline float v3_dot(v3 a, v3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+/* a . b accumulated x, then y, then z: fma(a.z, b.z, fma(a.y, b.y, a.x b.x)). */
+static inline float dot_fma(v3 a, v3 b) { return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)); }
 
 static inline uint32_t f2u(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
 static inline float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+/* x with the sign bit s (0 or 0x80000000) xor-ed in: x * (+-1), exactly. */
+static inline float sign_xor(float x, uint32_t s) { return u2f(f2u(x) ^ s); }
 
 /* ------------------------------------------------------------------------ */
-/* Moller-Trumbore, App. G intersectsp_ray_tri_mt.                          */
-/*   e1 = p0 - p1, e2 = p2 - p0, ng = e2 x e1                                */
-/*   c = p0 - o, r = c x d, D = ng . d; D == 0 is a miss                     */
-/*   U, V, T = (r.e2, r.e1, ng.c) with the sign bit of D xor-ed in           */
-/*   accept iff U >= 0, V >= 0, U + V <= |D|, |D|*0 < T <= |D|*tmax          */
-/*   t, u, v = (T, U, V) * (1/|D|)                                           */
-/* The sign fold of T is applied to its bits, as for U and V (the listing's  */
-/* cast order for T is garbled; the fold only makes sense on the bits).      */
+/* Ray/triangle test (the intersection the paper's closest-hit search uses,  */
+/* App. G, where it is Moller-Trumbore).  Written from Moller and Trumbore,  */
+/* "Fast, Minimum Storage Ray/Triangle Intersection" (1997): with the edges   */
+/* e1 = p1 - p0 and e2 = p2 - p0, the hit o + t d = p0 + u e1 + v e2 is a     */
+/* 3x3 linear system whose Cramer solution shares two cross products,        */
+/*   P = d x e2,  det = e1 . P,  S = o - p0,  Q = S x e1,                    */
+/*   u det = S . P,   v det = d . Q,   t det = e2 . Q.                       */
+/* Acceptance (App. G's intervals): u >= 0, v >= 0, u + v <= 1 (edges and     */
+/* vertices count, both faces), and 0 < t <= tmax.  It is decided on the     */
+/* numerators with the sign of det moved onto them (exact), against |det|,   */
+/* so the single division happens only for an accepted hit:                 */
+/*   t, u, v = (T, U, V) * (1 / |det|).                                       */
+/* det = 0 (ray parallel to the plane, or a degenerate triangle) and a       */
+/* non-finite det are misses.  Every product, sum and fused multiply-add is  */
+/* a single correctly rounded FP32 operation in the order written.           */
 /* Returns 1 on a hit and writes t, u, v.                                    */
 /* ------------------------------------------------------------------------ */
 static inline int mt_f32(v3 o, v3 d, float tmax, v3 p0, v3 p1, v3 p2,
                          float *t_out, float *u_out, float *v_out) {
-    v3 e1 = v3_sub(p0, p1);
+    v3 e1 = v3_sub(p1, p0);
     v3 e2 = v3_sub(p2, p0);
-    v3 ng = v3_cross(e2, e1);
-    v3 c = v3_sub(p0, o);
-    v3 r = v3_cross(c, d);
-    float D = v3_dot(ng, d);
-    if (D == 0.0f) return 0;
-    float absD = fabsf(D);
-    uint32_t sgnD = f2u(D) & 0x80000000u;
-    float U = u2f(f2u(v3_dot(r, e2)) ^ sgnD);
-    float V = u2f(f2u(v3_dot(r, e1)) ^ sgnD);
-    if (!(U >= 0.0f && V >= 0.0f && U + V <= absD)) return 0;
-    float T = u2f(f2u(v3_dot(ng, c)) ^ sgnD);
-    if (!(absD * 0.0f < T && T <= absD * tmax)) return 0;
-    float inv = 1.0f / absD;
+    v3 P = cross_fma(d, e2);
+    float det = dot_fma(e1, P);
+    float adet = fabsf(det);
+    if (!(adet > 0.0f && adet < INFINITY)) return 0;
+    uint32_t s = f2u(det) & 0x80000000u;
+    v3 S = v3_sub(o, p0);
+    float U = sign_xor(dot_fma(S, P), s);
+    v3 Q = cross_fma(S, e1);
+    float V = sign_xor(dot_fma(d, Q), s);
+    if (!(U >= 0.0f && V >= 0.0f && U + V <= adet)) return 0;
+    float T = sign_xor(dot_fma(e2, Q), s);
+    if (!(T > 0.0f && T <= adet * tmax)) return 0;
+    float inv = 1.0f / adet;
     *t_out = T * inv;
     *u_out = U * inv;
     *v_out = V * inv;
@@ -348,23 +361,26 @@ void orc_bvh_export(void *h, float *boxes, int32_t *links, int32_t *perm) {
  * the current best distance is never culled. */
 #define ORC_FAR_SCALE 1.000000476837158203125f
 
-/* App. G intersectsp_ray_aabb with the node-cull test folded in:
- *   rdir = 1/d; near/far planes chosen by the sign bit of d;
- *   t_near = max(0, max over axes), t_far = min(t_cur, min over axes);
- *   visit iff t_near <= t_far * FAR_SCALE.
- * fmaxf/fminf drop the NaN of 0*inf (a ray lying in a slab plane). */
+/* Ray/box test on a node's box with the node cull folded in (the slab     */
+/* method of Kay and Kajiya 1986; planes ordered by the sign of d as in      */
+/* Williams et al. 2005).  Along axis a the ray lies between the box's two   */
+/* planes for t between its distance to the plane it crosses first and the   */
+/* plane it crosses last, (plane - o) * (1/d); which plane comes first        */
+/* follows the sign bit of d, so d = -0 (1/d = -inf) pairs with the upper     */
+/* plane.  The box is visited when the largest entry distance, at least 0,   */
+/* does not exceed the smallest exit distance, at most tcur, widened by      */
+/* ORC_FAR_SCALE.  fmaxf/fminf ignore the NaN of 0 * inf (a ray lying in a   */
+/* slab plane), so such an axis culls nothing.                               */
 static inline int slab(v3 o, v3 rd, const int neg[3], const orc_node *n, float tcur) {
     const float *ov = &o.x, *rv = &rd.x;
-    float tn[3], tf[3];
+    float enter = 0.0f, leave = tcur;
     for (int a = 0; a < 3; a++) {
-        float nearp = neg[a] ? n->hi[a] : n->lo[a];
-        float farp = neg[a] ? n->lo[a] : n->hi[a];
-        tn[a] = (nearp - ov[a]) * rv[a];
-        tf[a] = (farp - ov[a]) * rv[a];
+        float first = neg[a] ? n->hi[a] : n->lo[a];
+        float last = neg[a] ? n->lo[a] : n->hi[a];
+        enter = fmaxf(enter, (first - ov[a]) * rv[a]);
+        leave = fminf(leave, (last - ov[a]) * rv[a]);
     }
-    float t_near = fmaxf(0.0f, fmaxf(tn[0], fmaxf(tn[1], tn[2])));
-    float t_far = fminf(tcur, fminf(tf[0], fminf(tf[1], tf[2])));
-    return t_near <= t_far * ORC_FAR_SCALE;
+    return enter <= leave * ORC_FAR_SCALE;
 }
 
 enum { ORC_CLOSEST = 0, ORC_TOP2 = 1, ORC_ANY = 2 };

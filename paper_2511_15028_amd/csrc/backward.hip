@@ -1,14 +1,20 @@
 // Backward pass of closest-hit tracing with the hit primitive held fixed.
 //
-// The hit point obeys F = o + t d - (1-u-v) p0 - u p1 - v p2 = 0 (the
-// barycentric form of App. G's Moller-Trumbore result).  With
-// J = dF/d(t,u,v) = [d | p0-p1 | p0-p2] and g = dL/d(t,u,v), the solution of
+// The hit of ray i on its fixed triangle p is recomputed from the ray and
+// the triangle's vertices with the forward's own ray/triangle arithmetic
+// (tri_numerators, the same FP32 operations), so (t, u, v) are exactly the
+// forward's hit when verts, tris and rays are the ones traced; the hits
+// buffer supplies only the primitive id.  The hit point obeys
+// F = o + t d - p0 - u e1 - v e2 = 0 with e1 = p1 - p0, e2 = p2 - p0 (the
+// barycentric form of App. G: b0 = 1-u-v, b1 = u, b2 = v).  With
+// J = dF/d(t,u,v) = [d | -e1 | -e2] and g = dL/d(t,u,v), the solution of
 // J^T lam = g gives dL/dx = -lam^T dF/dx for every input x:
 //   dL/do = -lam, dL/dd = -t lam, dL/dp0 = (1-u-v) lam, dL/dp1 = u lam,
 //   dL/dp2 = v lam.
-// lam comes from Cramer's rule with the rows a = d, b = p0-p1, c = p0-p2 of
-// J^T: lam = (g_t (b x c) + g_u (c x a) + g_v (a x b)) / (a . (b x c)).
-#include "internal.h"
+// Cramer's rule on the rows d, -e1, -e2 of J^T, whose determinant is
+// d . (e1 x e2) = -det (det = e1 . (d x e2) of the forward test):
+//   lam = -(g_t (e1 x e2) + g_u (d x e2) + g_v (e1 x d)) / det.
+#include "traverse.h"
 
 namespace bvhlib {
 namespace {
@@ -29,42 +35,56 @@ __device__ inline uint32_t slot_of(int32_t v) {
     return ((uint32_t)v * 2654435761u) >> (32 - 10);  // Fibonacci hashing, 10 bits
 }
 
-// lam and the ray gradient of ray i; false for a miss, an out-of-range
-// primitive or vertex index, or a singular system.
+__device__ inline void cross_fma(float ax, float ay, float az, float bx, float by, float bz,
+                                 float &cx, float &cy, float &cz) {
+    cx = fmaf(ay, bz, -(az * by));
+    cy = fmaf(az, bx, -(ax * bz));
+    cz = fmaf(ax, by, -(ay * bx));
+}
+
+// lam, the hit weights and the ray gradient of ray i; false for a miss, an
+// out-of-range primitive or vertex index, or a singular system (det = 0 or
+// not finite).
 __device__ inline bool ray_grad(const float *verts, int64_t n_verts, const int32_t *tris,
                                 int64_t n_tris, const bvh_ray *rays, const bvh_hit *hits,
                                 const float *grad_hits, uint64_t i, float *out, int32_t *idx,
                                 float *w, float *lam) {
-    const int4 hw = reinterpret_cast<const int4 *>(hits)[i];
-    const int32_t prim = hw.x;
+    const int32_t prim = reinterpret_cast<const int32_t *>(hits)[4 * i];
     if (prim < 0 || (int64_t)prim >= n_tris) return false;
     for (int k = 0; k < 3; k++) {
         idx[k] = tris[3 * (size_t)prim + k];
         if (idx[k] < 0 || (int64_t)idx[k] >= n_verts) return false;
     }
-    const float t = __int_as_float(hw.y), u = __int_as_float(hw.z), v = __int_as_float(hw.w);
-    const float4 rb = reinterpret_cast<const float4 *>(rays + i)[1];
+    const float4 *rp = reinterpret_cast<const float4 *>(rays + i);
+    const float4 ra = rp[0], rb = rp[1];
+    Ray r{};
+    r.ox = ra.x; r.oy = ra.y; r.oz = ra.z;
+    r.dx = rb.x; r.dy = rb.y; r.dz = rb.z;
     const float *q0 = verts + 3 * (size_t)idx[0];
     const float *q1 = verts + 3 * (size_t)idx[1];
     const float *q2 = verts + 3 * (size_t)idx[2];
-    const float ax = rb.x, ay = rb.y, az = rb.z;                              // d
-    const float bx = q0[0] - q1[0], by = q0[1] - q1[1], bz = q0[2] - q1[2];  // p0 - p1
-    const float cx = q0[0] - q2[0], cy = q0[1] - q2[1], cz = q0[2] - q2[2];  // p0 - p2
-    const float bcx = by * cz - bz * cy, bcy = bz * cx - bx * cz, bcz = bx * cy - by * cx;
-    const float cax = cy * az - cz * ay, cay = cz * ax - cx * az, caz = cx * ay - cy * ax;
-    const float abx = ay * bz - az * by, aby = az * bx - ax * bz, abz = ax * by - ay * bx;
-    const float det = ax * bcx + ay * bcy + az * bcz;
-    if (det == 0.0f) return false;
+    const float e1x = q1[0] - q0[0], e1y = q1[1] - q0[1], e1z = q1[2] - q0[2];
+    const float e2x = q2[0] - q0[0], e2y = q2[1] - q0[1], e2z = q2[2] - q0[2];
+    const TriNum nm = tri_numerators(r, q0[0], q0[1], q0[2], e1x, e1y, e1z, e2x, e2y, e2z);
+    if (!(nm.adet > 0.0f && nm.adet < INFINITY)) return false;
+    const float inv = 1.0f / nm.adet;
+    const float t = nm.T * inv, u = nm.U * inv, v = nm.V * inv;
+    float nx, ny, nz, px, py, pz, mx, my, mz;
+    cross_fma(e1x, e1y, e1z, e2x, e2y, e2z, nx, ny, nz);     // e1 x e2
+    cross_fma(r.dx, r.dy, r.dz, e2x, e2y, e2z, px, py, pz);  // d x e2
+    cross_fma(e1x, e1y, e1z, r.dx, r.dy, r.dz, mx, my, mz);  // e1 x d
     const float gt = grad_hits[3 * i], gu = grad_hits[3 * i + 1], gv = grad_hits[3 * i + 2];
-    const float inv = 1.0f / det;
-    lam[0] = (gt * bcx + gu * cax + gv * abx) * inv;
-    lam[1] = (gt * bcy + gu * cay + gv * aby) * inv;
-    lam[2] = (gt * bcz + gu * caz + gv * abz) * inv;
+    // 1 / det = sign(det) / |det|: the sign of det is that of e1 . (d x e2)
+    const float det = fmaf(e1z, pz, fmaf(e1y, py, e1x * px));
+    const float ninv = det < 0.0f ? inv : -inv;  // -1 / det
+    lam[0] = fmaf(gv, mx, fmaf(gu, px, gt * nx)) * ninv;
+    lam[1] = fmaf(gv, my, fmaf(gu, py, gt * ny)) * ninv;
+    lam[2] = fmaf(gv, mz, fmaf(gu, pz, gt * nz)) * ninv;
     for (int k = 0; k < 3; k++) {
         out[k] = -lam[k];
         out[3 + k] = -t * lam[k];
     }
-    w[0] = 1.0f - u - v;
+    w[0] = (1.0f - u) - v;
     w[1] = u;
     w[2] = v;
     return true;

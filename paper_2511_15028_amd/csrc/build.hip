@@ -1577,7 +1577,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, int
         const float *p2 = verts + 3 * (size_t)i2;
         for (int a = 0; a < 3; a++) {
             r.p0[a] = p0[a];
-            r.e1[a] = p0[a] - p1[a];  // the f32 edges of the intersection test
+            r.e1[a] = p1[a] - p0[a];  // the f32 edges of the intersection test
             r.e2[a] = p2[a] - p0[a];
         }
     } else {

@@ -150,7 +150,7 @@ __device__ inline float cp_tri(float apx, float apy, float apz, float abx, float
 }
 
 // Triangles [first, first + n) of the leaf order.  Compacted records give
-// p0 and e1 = p0 - p1, e2 = p2 - p0, so ab = -e1 and ac = e2 exactly as the
+// p0 and e1 = p1 - p0, e2 = p2 - p0, which are ab and ac exactly as the
 // indexed path computes them from the vertices (both leaf modes give
 // bit-identical distances).
 template <int LeafMode>
@@ -178,7 +178,7 @@ __device__ inline void cp_leaf(const SceneData &ld, const Query &q, uint32_t fir
                     const float4 a = qa[j], b = qb[j];
                     const float2 c = qc[j];
                     float u, v;
-                    const float d2 = cp_tri(q.x - a.x, q.y - a.y, q.z - a.z, -a.w, -b.x, -b.y, b.z,
+                    const float d2 = cp_tri(q.x - a.x, q.y - a.y, q.z - a.z, a.w, b.x, b.y, b.z,
                                             b.w, c.x, u, v);
                     cp_consider(best, d2, u, v, __float_as_uint(c.y));
                 }

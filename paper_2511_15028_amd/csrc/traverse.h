@@ -105,15 +105,15 @@ __device__ inline bool wave_coherent(const Ray &r) {
     return rays_share_octant(r, true, __builtin_amdgcn_ballot_w64(true));
 }
 
-// Ray/box test of App. G (intersectsp_ray_aabb) on planes already ordered
-// by the ray: (nx, ny, nz) are the planes the ray enters through (the lower
-// plane of an axis where d >= +0, the upper where d <= -0), (fx, fy, fz) the
-// planes it leaves through.  The node cull is folded in: the far end is
+// Ray/box test (the slab method of Kay and Kajiya; the paper's traversal
+// tests node boxes with it, App. G) on planes already ordered by the ray:
+// (nx, ny, nz) are the planes the ray enters through (the lower plane of an
+// axis where d >= +0, the upper where d <= -0), (fx, fy, fz) the planes it
+// leaves through.  The node cull is folded in: the far end is
 // clipped at tcur (the best hit so far, or tmax).  Returns the entry
 // distance, or +inf when the box is culled.
 //
-// Plane distances: the two-rounding form (plane - o) * rdir of App. G, or,
-// when Fast, one FMA plane * rdir - o * rdir with the product o * rdir
+// Plane distances: the two-rounding form (plane - o) * rdir, or, when Fast, one FMA plane * rdir - o * rdir with the product o * rdir
 // bracketed outward (entry planes subtract an upper bound, exit planes a
 // lower bound), so the computed entry distance never exceeds
 // (plane - o) * rdir by more than one rounding and the exit distance never
@@ -147,34 +147,57 @@ __device__ inline float slab(const Ray &r, float lox, float loy, float loz, floa
                          r.nx ? lox : hix, r.ny ? loy : hiy, r.nz ? loz : hiz, tcur);
 }
 
-// Moller-Trumbore of App. G (intersectsp_ray_tri_mt), operation for
-// operation, given p0 and the edges e1 = p0-p1, e2 = p2-p0 (each rounded to
-// f32 exactly as the test computes them): ng = e2 x e1, c = p0-o, r = c x d,
-// D = ng.d, U/V/T sign-folded by D, edges inclusive, 0 < t <= tmax,
-// t, u, v = (T, U, V) * (1/|D|).  Built without FMA contraction.
+// Ray/triangle test: Moller and Trumbore (1997), with App. G's acceptance
+// intervals (u, v >= 0 and u + v <= 1 inclusive, both faces; 0 < t <= tmax).
+// Given p0 and the edges e1 = p1 - p0, e2 = p2 - p0 (as stored in a
+// compacted leaf record), the hit o + t d = p0 + u e1 + v e2 is solved by
+// Cramer's rule through P = d x e2, det = e1 . P, S = o - p0, Q = S x e1:
+// U = S . P, V = d . Q, T = e2 . Q are u, v, t times det.  The interval
+// tests run on those numerators with det's sign bit moved onto them (exact),
+// against |det|, so only an accepted hit pays for the one correctly rounded
+// division: t, u, v = (T, U, V) * (1 / |det|).  Every cross-product
+// component is one product and one fused multiply-add, every dot product
+// one product and two fused multiply-adds, in a fixed order, so the results
+// are a fixed function of the f32 inputs (30 VALU operations up to the
+// tests).
+struct TriNum {
+    float U, V, T, adet;
+};
+
+// The numerators and |det| of the test (no acceptance decision).
+__device__ inline TriNum tri_numerators(const Ray &r, float p0x, float p0y, float p0z, float e1x,
+                                        float e1y, float e1z, float e2x, float e2y, float e2z) {
+    const float px = fmaf(r.dy, e2z, -(r.dz * e2y));
+    const float py = fmaf(r.dz, e2x, -(r.dx * e2z));
+    const float pz = fmaf(r.dx, e2y, -(r.dy * e2x));
+    const float det = fmaf(e1z, pz, fmaf(e1y, py, e1x * px));
+    const uint32_t sgn = __float_as_uint(det) & 0x80000000u;
+    const float sx = r.ox - p0x, sy = r.oy - p0y, sz = r.oz - p0z;
+    const float qx = fmaf(sy, e1z, -(sz * e1y));
+    const float qy = fmaf(sz, e1x, -(sx * e1z));
+    const float qz = fmaf(sx, e1y, -(sy * e1x));
+    TriNum n;
+    n.U = __uint_as_float(__float_as_uint(fmaf(sz, pz, fmaf(sy, py, sx * px))) ^ sgn);
+    n.V = __uint_as_float(__float_as_uint(fmaf(r.dz, qz, fmaf(r.dy, qy, r.dx * qx))) ^ sgn);
+    n.T = __uint_as_float(__float_as_uint(fmaf(e2z, qz, fmaf(e2y, qy, e2x * qx))) ^ sgn);
+    n.adet = fabsf(det);
+    return n;
+}
+
+__device__ inline bool tri_accept(const TriNum &n, float tmax) {
+    return n.adet > 0.0f && n.adet < INFINITY && n.U >= 0.0f && n.V >= 0.0f &&
+           n.U + n.V <= n.adet && n.T > 0.0f && n.T <= n.adet * tmax;
+}
+
 __device__ inline bool mt_edges(const Ray &r, float p0x, float p0y, float p0z, float e1x,
                                 float e1y, float e1z, float e2x, float e2y, float e2z, float &t,
                                 float &u, float &v) {
-    const float ngx = e2y * e1z - e2z * e1y;
-    const float ngy = e2z * e1x - e2x * e1z;
-    const float ngz = e2x * e1y - e2y * e1x;
-    const float cx = p0x - r.ox, cy = p0y - r.oy, cz = p0z - r.oz;
-    const float rrx = cy * r.dz - cz * r.dy;
-    const float rry = cz * r.dx - cx * r.dz;
-    const float rrz = cx * r.dy - cy * r.dx;
-    const float D = (ngx * r.dx + ngy * r.dy) + ngz * r.dz;
-    if (D == 0.0f) return false;
-    const float absD = fabsf(D);
-    const uint32_t sgn = __float_as_uint(D) & 0x80000000u;
-    const float U = __uint_as_float(__float_as_uint((rrx * e2x + rry * e2y) + rrz * e2z) ^ sgn);
-    const float V = __uint_as_float(__float_as_uint((rrx * e1x + rry * e1y) + rrz * e1z) ^ sgn);
-    if (!(U >= 0.0f && V >= 0.0f && U + V <= absD)) return false;
-    const float T = __uint_as_float(__float_as_uint((ngx * cx + ngy * cy) + ngz * cz) ^ sgn);
-    if (!(absD * 0.0f < T && T <= absD * r.tmax)) return false;
-    const float inv = 1.0f / absD;
-    t = T * inv;
-    u = U * inv;
-    v = V * inv;
+    const TriNum n = tri_numerators(r, p0x, p0y, p0z, e1x, e1y, e1z, e2x, e2y, e2z);
+    if (!tri_accept(n, r.tmax)) return false;
+    const float inv = 1.0f / n.adet;
+    t = n.T * inv;
+    u = n.U * inv;
+    v = n.V * inv;
     return true;
 }
 
@@ -182,7 +205,7 @@ __device__ inline bool mt_edges(const Ray &r, float p0x, float p0y, float p0z, f
 __device__ inline bool mt(const Ray &r, float p0x, float p0y, float p0z, float p1x, float p1y,
                           float p1z, float p2x, float p2y, float p2z, float &t, float &u,
                           float &v) {
-    return mt_edges(r, p0x, p0y, p0z, p0x - p1x, p0y - p1y, p0z - p1z, p2x - p0x, p2y - p0y,
+    return mt_edges(r, p0x, p0y, p0z, p1x - p0x, p1y - p0y, p1z - p0z, p2x - p0x, p2y - p0y,
                     p2z - p0z, t, u, v);
 }
 
@@ -202,7 +225,8 @@ __device__ inline void consider(Best &b, float t, float u, float v, uint32_t id)
 }
 
 // Per-scene data the kernels need besides the node buffer.  Leaf storage:
-// COMPACT reads 48-B records {p0, e1, e2, prim id} in leaf order; INDEXED
+// COMPACT reads 48-B records {p0, e1 = p1 - p0, e2 = p2 - p0, prim id} in
+// leaf order; INDEXED
 // reads a primitive id, its three vertex indices and three vertices.
 struct SceneData {
     const void *leaf;

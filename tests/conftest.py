@@ -6,6 +6,9 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# the planted-mistake test points this at a modified copy of the oracle package
+if os.environ.get("ORACLE_PY_DIR"):
+    sys.path.insert(0, os.environ["ORACLE_PY_DIR"])
 
 
 def pytest_configure(config):

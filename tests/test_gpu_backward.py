@@ -1,16 +1,37 @@
 """Backward kernel against the FP64 oracle gradient (itself pinned by FP64
-finite differences in test_oracle_grad.py).
+finite differences in test_oracle_grad.py).  Every tolerance here is computed
+from oracle-side quantities only; nothing is derived from the kernel's output.
 
-The kernel is given the oracle's own FP32 forward hits and compared with the
-FP64 gradient evaluated at those same hit parameters (the gradient is defined
-at the forward result).  Tolerances (no published bound): per-ray dL/do,
-dL/dd within 1e-4 of the ray's FP64 gradient norm on well-conditioned hits
-(min barycentric > 1e-4, |cos(d, n)| > 1e-2); grad_verts within 1e-5
-relative L2 and, per element, the propagated per-ray FP32 error in lam plus
-1e-5 of the summed contribution magnitudes plus 1e-7, which allows for FP32
-atomic accumulation in any order.  Against the fully FP64 gradient (hit
-parameters re-solved in FP64) the gap may add the FP32 forward's own
-rounding of (t, u, v), measured on the oracle side.
+The kernel recomputes each ray's hit on its fixed triangle with the forward's
+FP32 ray/triangle arithmetic, which the oracle's FP32 test reproduces bit for
+bit, so the GPU evaluates the gradient at exactly the oracle's FP32 forward
+hit (t, u, v).  The reference is the FP64 closed form evaluated at that hit
+(orc.grad_f64(..., tuv_at=oracle FP32 hit)).  What remains between the two
+is the FP32 solve of J^T lam = g and the FP32 accumulation:
+
+  * lam: the kernel solves with J = [d | -e1 | -e2] by Cramer's rule in FP32
+    (e1, e2 themselves rounded to f32).  Its error obeys the perturbation
+    bound |dlam| <= c 2^-24 kappa_2(J) |lam| of a 3x3 solve with relative
+    input perturbations of a few ulps; kappa_2 comes from the FP64 J and lam
+    from the FP64 gradient.  c = 4: the FP32 error measured on the CPU for
+    the full differentiable workload stays below 0.04 of the bound with c = 1.
+  * per-ray gradients dL/do = -lam, dL/dd = -t lam: within that bound (plus
+    one rounding of t lam), on every hit ray, grazing ones included; on rays
+    with min barycentric > 1e-4 and |cos(d, n)| > 1e-2 also within 1e-4 of
+    the ray's gradient norm.
+  * grad_verts, per element: the sum over the rays that touch the vertex of
+    |w| times the lam bound, plus the f32 rounding of w = (1-u)-v, plus
+    gamma_K times the summed |w lam| for K float additions in any order
+    (the atomics), plus 1e-12; and 1e-5 relative L2 over the whole array.
+
+Barycentric rounding of the FP32 forward itself (why the gradient is taken at
+the FP32 hit): with u = U / det, the f32 numerators U, V, T carry an error of
+about 2^-24 |S||d||e2| against |det| = |e1 . (d x e2)|, so for a level-7
+icosphere triangle (edge ~0.01) seen from distance 3, u and v are off by
+about 2^-24 * 3 / 0.01 ~ 2e-5 relative.  The test against the gradient with
+(t, u, v) re-solved in FP64 therefore allows that forward gap, measured on
+the oracle side alone (FP64 gradient at the FP32 hit against FP64 gradient
+at the FP64 hit), plus 1e-5.
 """
 import numpy as np
 import pytest
@@ -20,13 +41,15 @@ from paper_2511_15028_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+U32 = 2.0 ** -24
+C_LAM = 4.0
+
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
 def _run(w, hits_np):
-    """Backward kernel on the given (oracle) hits."""
     from paper_2511_15028_amd import bvh
     v, t, rays, wts = w["verts"], w["tris"], w["rays"], w["weights"]
     gv, gr = bvh.trace_backward(dev(v), dev(t), dev(rays), dev(hits_np), dev(wts))
@@ -41,42 +64,63 @@ def _hits_array(prim, tuv):
     return h
 
 
-def _compare(orc, w, prim, tuv, gv, gr):
-    """prim/tuv: the oracle's FP32 forward hits, which the kernel was given."""
+def _bounds(orc, w, prim, tuv):
+    """FP64 reference gradient at the oracle's FP32 hit and the oracle-side
+    error bounds for the kernel's per-ray and per-vertex results."""
     v, t, rays, wts = w["verts"], w["tris"], w["rays"], w["weights"]
-    # the FP64 gradient evaluated at the same FP32 forward result
     gv64, gr64, _ = orc.grad_f64(v, t, rays, prim, wts, tuv_at=tuv)
+    hit = prim >= 0
+    p = v[t[np.maximum(prim, 0)]].astype(np.float64)
+    d = rays[:, 4:7].astype(np.float64)
+    J = np.stack([d, p[:, 0] - p[:, 1], p[:, 0] - p[:, 2]], axis=2)
+    kappa = np.where(hit, np.linalg.cond(np.where(hit[:, None, None], J, np.eye(3))), 0.0)
+    lam = -gr64[:, 0:3]
+    nlam = np.linalg.norm(lam, axis=1)
+    dlam = C_LAM * U32 * kappa * nlam
+    tt = np.abs(tuv[:, 0].astype(np.float64))
+    ray_bound = np.concatenate([dlam[:, None].repeat(3, 1),
+                                (tt * dlam + U32 * tt * nlam)[:, None].repeat(3, 1)], 1)
+    wgt = np.stack([1 - tuv[:, 1].astype(np.float64) - tuv[:, 2], tuv[:, 1], tuv[:, 2]], 1)
+    werr = 2 * U32 * (1 + np.abs(tuv[:, 1]) + np.abs(tuv[:, 2])).astype(np.float64)
+    vb = np.zeros_like(gv64)
+    mag = np.zeros_like(gv64)
+    cnt = np.zeros(len(v), np.int64)
+    for k in range(3):
+        idx = t[prim[hit], k]
+        np.add.at(vb, idx, (np.abs(wgt[hit, k]) * dlam[hit] + werr[hit] * nlam[hit])[:, None]
+                  + U32 * np.abs(wgt[hit, k:k + 1] * lam[hit]))
+        np.add.at(mag, idx, np.abs(wgt[hit, k:k + 1] * lam[hit]))
+        np.add.at(cnt, idx, 1)
+    kk = cnt[:, None].astype(np.float64)
+    gamma = kk * U32 / (1 - kk * U32)
+    vert_bound = vb + gamma * mag + 1e-12
+    return gv64, gr64, ray_bound, vert_bound
+
+
+def _compare(orc, w, prim, tuv, gv, gr):
+    """prim/tuv: the oracle's FP32 forward hits."""
+    v, t, rays, wts = w["verts"], w["tris"], w["rays"], w["weights"]
+    gv64, gr64, ray_bound, vert_bound = _bounds(orc, w, prim, tuv)
+    hit = prim >= 0
+    assert (gr[~hit] == 0).all()
+    assert (np.abs(gr[hit] - gr64[hit]) <= ray_bound[hit]).all(), \
+        np.max(np.abs(gr[hit] - gr64[hit]) / ray_bound[hit])
+    # well-conditioned rays: the survey's 1e-4 of the ray's gradient norm
     p = v[t[np.maximum(prim, 0)]].astype(np.float64)
     ng = np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0])
     d = rays[:, 4:7].astype(np.float64)
     cos = np.abs(np.sum(ng * d, 1)) / (np.linalg.norm(ng, axis=1) * np.linalg.norm(d, axis=1) + 1e-300)
     bmin = np.minimum(np.minimum(tuv[:, 1], tuv[:, 2]), 1 - tuv[:, 1] - tuv[:, 2])
-    good = (prim >= 0) & (bmin > 1e-4) & (cos > 1e-2)
-    assert good.mean() > 0.9
-    norm = np.linalg.norm(gr64[good], axis=1)
+    good = hit & (bmin > 1e-4) & (cos > 1e-2)
+    assert good.sum() >= 0.9 * hit.sum()
     err = np.linalg.norm(gr[good] - gr64[good], axis=1)
-    assert (err <= 1e-4 * norm).all(), err.max()
-    assert (gr[prim < 0] == 0).all()
+    assert (err <= 1e-4 * np.linalg.norm(gr64[good], axis=1)).all(), err.max()
+    assert (np.abs(gv - gv64) <= vert_bound).all(), np.max(np.abs(gv - gv64) / vert_bound)
     rel = np.linalg.norm(gv - gv64) / np.linalg.norm(gv64)
     assert rel <= 1e-5, rel
-    # per element: ray i adds w_k * lam_i to a vertex; the FP32 solve for lam
-    # is off by |dlam| (large only for grazing hits, where J is
-    # ill-conditioned) and the float atomics add rounding, covered by 1e-5 of
-    # the summed contribution magnitudes, plus 1e-7
-    mag = np.zeros_like(gv64)
-    prop = np.zeros_like(gv64)
-    lam = -gr64[:, 0:3]
-    dlam = np.abs(gr[:, 0:3] - gr64[:, 0:3])
-    wgt = np.stack([1 - tuv[:, 1] - tuv[:, 2], tuv[:, 1], tuv[:, 2]], 1).astype(np.float64)
-    hit = prim >= 0
-    for k in range(3):
-        np.add.at(mag, t[prim[hit], k], np.abs(wgt[hit, k:k + 1] * lam[hit]))
-        np.add.at(prop, t[prim[hit], k], np.abs(wgt[hit, k:k + 1]) * dlam[hit])
-    assert (np.abs(gv - gv64) <= prop + 1e-5 * mag + 1e-7).all()
-    # against the fully FP64 gradient (hit parameters re-solved in FP64): the
-    # gap is the FP32 forward's own rounding of (t, u, v), measured on the
-    # oracle side alone
-    gvx, grx, _ = orc.grad_f64(v, t, rays, prim, wts)
+    # against the fully FP64 gradient: the FP32 forward's own rounding of
+    # (t, u, v), measured on the oracle side alone, plus 1e-5
+    gvx, _, _ = orc.grad_f64(v, t, rays, prim, wts)
     fwd = np.linalg.norm(gv64 - gvx) / np.linalg.norm(gvx)
     assert np.linalg.norm(gv - gvx) / np.linalg.norm(gvx) <= fwd + 1e-5
     return rel, fwd
@@ -104,13 +148,29 @@ def test_backward_full_size(orc):
     _compare(orc, w, p1, tuv1, gv, gr)
 
 
+def test_backward_recomputes_the_hit(orc):
+    """Only the primitive id of `hits` is used: garbage t, u, v in the hit
+    records give the same gradients (the hit is recomputed from the rays and
+    vertices)."""
+    w = W.diff_workload(level=4, n_cams=8, res=32)
+    p1, tuv1 = orc.brute_closest(w["verts"], w["tris"], w["rays"])
+    rng = np.random.default_rng(11)
+    junk = rng.uniform(-5, 5, tuv1.shape).astype(np.float32)
+    junk[::7] = np.nan
+    gv, gr = _run(w, _hits_array(p1, junk))
+    _compare(orc, w, p1, tuv1, gv, gr)
+
+
 def test_backward_skips_invalid_prims(orc):
     from paper_2511_15028_amd import bvh
     w = W.diff_workload(level=2, n_cams=2, res=8)
     v, t, rays = w["verts"], w["tris"], w["rays"]
+    p1, _ = orc.brute_closest(v, t, rays)
+    assert (p1 >= 0).all()
     hits = np.zeros((len(rays), 4), np.float32)
-    hits[:, 0] = np.array([-1, len(t), 10 ** 6, 0] * (len(rays) // 4), np.int32).view(np.float32)
-    hits[:, 1:] = [1.0, 0.2, 0.3]
+    bad = np.array([-1, len(t), 10 ** 6, 0] * (len(rays) // 4), np.int32)
+    prim = np.where(bad == 0, p1, bad).astype(np.int32)
+    hits[:, 0] = prim.view(np.float32)
     gv, gr = bvh.trace_backward(dev(v), dev(t), dev(rays), dev(hits), dev(w["weights"]))
     torch.cuda.synchronize()
     gr = gr.cpu().numpy()
@@ -119,17 +179,28 @@ def test_backward_skips_invalid_prims(orc):
 
 
 def test_autograd_function(orc):
+    """BVHTrace forward + backward through torch autograd, against the FP64
+    oracle gradient at the oracle's own forward hits (prims and FP32 hit from
+    OracleBVH.trace), to 1e-4 of each ray's gradient norm per element and
+    1e-5 relative L2 for the vertex gradient."""
     from paper_2511_15028_amd import bvh
     w = W.diff_workload(level=3, n_cams=4, res=16)
+    p_o, tuv_o = orc.OracleBVH(w["verts"], w["tris"]).trace(w["rays"])
     v = dev(w["verts"]).requires_grad_(True)
     t = dev(w["tris"])
     o = dev(w["rays"][:, 0:3]).requires_grad_(True)
     d = dev(w["rays"][:, 4:7]).requires_grad_(True)
     h = bvh.build(v.detach(), t, "bvh4")
     prim, tuv = bvh.BVHTrace.apply(v, t, o, d, h)
+    assert np.array_equal(prim.cpu().numpy(), p_o)
+    assert np.array_equal(tuv.detach().cpu().numpy(), tuv_o)
     loss = (tuv * dev(w["weights"])).sum()
     loss.backward()
-    gv64, gr64, _ = orc.grad_f64(w["verts"], w["tris"], w["rays"], prim.cpu().numpy(), w["weights"])
-    np.testing.assert_allclose(o.grad.cpu().numpy(), gr64[:, 0:3], rtol=1e-3, atol=1e-4)
-    np.testing.assert_allclose(d.grad.cpu().numpy(), gr64[:, 3:6], rtol=1e-3, atol=1e-4)
-    np.testing.assert_allclose(v.grad.cpu().numpy(), gv64, rtol=1e-3, atol=1e-4)
+    gv64, gr64, _ = orc.grad_f64(w["verts"], w["tris"], w["rays"], p_o, w["weights"], tuv_at=tuv_o)
+    hit = p_o >= 0
+    for got, ref in ((o.grad.cpu().numpy(), gr64[:, 0:3]), (d.grad.cpu().numpy(), gr64[:, 3:6])):
+        scale = np.linalg.norm(ref, axis=1, keepdims=True)
+        assert (np.abs(got - ref)[hit] <= 1e-4 * scale[hit]).all()
+        assert (got[~hit] == 0).all()
+    gvg = v.grad.cpu().numpy()
+    assert np.linalg.norm(gvg - gv64) / np.linalg.norm(gv64) <= 1e-5

@@ -64,9 +64,9 @@ def test_round_trip(layout, leaf_mode, scene):
         tri = np.frombuffer(leaf_raw, dtype=LD.TRI_DT)
         order = tri["prim"]
         pts = v[t[order]]
-        # p0 is a bit copy; the edges are the f32 differences p0 - p1, p2 - p0
+        # p0 is a bit copy; the edges are the f32 differences p1 - p0, p2 - p0
         assert np.array_equal(tri["p0"].view(np.uint32), pts[:, 0].view(np.uint32))
-        assert np.array_equal(tri["e1"].view(np.uint32), (pts[:, 0] - pts[:, 1]).view(np.uint32))
+        assert np.array_equal(tri["e1"].view(np.uint32), (pts[:, 1] - pts[:, 0]).view(np.uint32))
         assert np.array_equal(tri["e2"].view(np.uint32), (pts[:, 2] - pts[:, 0]).view(np.uint32))
     else:
         order = np.frombuffer(leaf_raw, dtype=np.int32)

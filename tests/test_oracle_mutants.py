@@ -24,20 +24,23 @@ PINS = [os.path.join(HERE, f) for f in ("test_oracle_mt.py", "test_oracle_closes
 
 MUTANTS = [
     ("edge e2 reversed", "v3 e2 = v3_sub(p2, p0);", "v3 e2 = v3_sub(p0, p2);"),
-    ("cross x operands transposed", "r.x = a.y * b.z - a.z * b.y;", "r.x = a.z * b.y - a.y * b.z;"),
-    ("dot drops the z term", "return (a.x * b.x + a.y * b.y) + a.z * b.z;",
-     "return (a.x * b.x + a.y * b.y);"),
-    ("u and v swapped", "float U = u2f(f2u(v3_dot(r, e2)) ^ sgnD);\n    float V = u2f(f2u(v3_dot(r, e1)) ^ sgnD);",
-     "float U = u2f(f2u(v3_dot(r, e1)) ^ sgnD);\n    float V = u2f(f2u(v3_dot(r, e2)) ^ sgnD);"),
-    ("edges exclusive", "U + V <= absD", "U + V < absD"),
-    ("t = 0 accepted", "absD * 0.0f < T", "absD * 0.0f <= T"),
-    ("tmax exclusive", "T <= absD * tmax", "T < absD * tmax"),
-    ("sign of T not folded", "float T = u2f(f2u(v3_dot(ng, c)) ^ sgnD);", "float T = v3_dot(ng, c);"),
+    ("edge e1 reversed", "v3 e1 = v3_sub(p1, p0);", "v3 e1 = v3_sub(p0, p1);"),
+    ("cross x operands transposed", "r.x = fmaf(a.y, b.z, -(a.z * b.y));",
+     "r.x = fmaf(a.z, b.y, -(a.y * b.z));"),
+    ("dot drops the z term", "return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x));",
+     "return fmaf(a.y, b.y, a.x * b.x);"),
+    ("origin offset reversed", "v3 S = v3_sub(o, p0);", "v3 S = v3_sub(p0, o);"),
+    ("second cross product transposed", "v3 Q = cross_fma(S, e1);", "v3 Q = cross_fma(e1, S);"),
+    ("u and v swapped", "*u_out = U * inv;\n    *v_out = V * inv;", "*u_out = V * inv;\n    *v_out = U * inv;"),
+    ("edges exclusive", "U + V <= adet", "U + V < adet"),
+    ("t = 0 accepted", "T > 0.0f &&", "T >= 0.0f &&"),
+    ("tmax exclusive", "T <= adet * tmax", "T < adet * tmax"),
+    ("sign of T not folded", "float T = sign_xor(dot_fma(e2, Q), s);", "float T = dot_fma(e2, Q);"),
     ("t scaled from U", "*t_out = T * inv;", "*t_out = U * inv;"),
     ("ties to the highest id", "return ta < tb || (ta == tb && ia < ib);",
      "return ta < tb || (ta == tb && ia > ib);"),
-    ("slab entry plane from the wrong side", "float nearp = neg[a] ? n->hi[a] : n->lo[a];",
-     "float nearp = neg[a] ? n->lo[a] : n->hi[a];"),
+    ("slab entry plane from the wrong side", "float first = neg[a] ? n->hi[a] : n->lo[a];",
+     "float first = neg[a] ? n->lo[a] : n->hi[a];"),
     ("right child never visited", "            stack[sp++] = n->right;\n", ""),
     ("last triangle of a leaf skipped", "k < n->first + n->count; k++", "k < n->first + n->count - 1; k++"),
     ("gradient: dL/dd sign", "gr[3] = -t * lam.x;", "gr[3] = t * lam.x;"),
@@ -76,6 +79,21 @@ MUTANTS = [
 ]
 
 
+# Planted mistakes in the oracle's Python part (oracle/__init__.py), run
+# against the collapse and SAH pins.
+PY_PINS = [os.path.join(HERE, f) for f in ("test_oracle_collapse.py", "test_oracle_sah.py")]
+PY_SRC = os.path.join(ROOT, "oracle", "__init__.py")
+PY_MUTANTS = [
+    ("collapse: a subtree of exactly leaf_size stays interior", "if count <= leaf_size:",
+     "if count < leaf_size:"),
+    ("collapse: right child one node early", "stack.append(i + 2 * nl)",
+     "stack.append(i + 2 * nl - 1)"),
+    ("collapse: right subtree emitted before the left",
+     "stack.append(i + 2 * nl)\n        stack.append(i + 1)",
+     "stack.append(i + 1)\n        stack.append(i + 2 * nl)"),
+]
+
+
 def _build(tmp, tag, text):
     c = os.path.join(tmp, f"{tag}.c")
     so = os.path.join(tmp, f"{tag}.so")
@@ -108,4 +126,37 @@ def test_every_planted_mistake_fails_a_pin(tmp_path):
     rc, out = res["original"]
     assert rc == 0, "the unmodified oracle must pass its pins:\n" + out
     survivors = [name for i, (name, _, _) in enumerate(MUTANTS) if res[f"m{i:02d}"][0] == 0]
+    assert not survivors, f"mistakes no pin catches: {survivors}"
+
+
+def _run_py_pins(pkg_dir):
+    import oracle
+    env = dict(os.environ, ORACLE_PY_DIR=pkg_dir, ORACLE_TEST_LIB=oracle.LIB_PATH,
+               OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "-m", "not gpu", *PY_PINS], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    return r.returncode, r.stdout[-2000:]
+
+
+def test_every_planted_python_mistake_fails_a_pin(tmp_path):
+    sys.path.insert(0, ROOT)
+    import oracle
+    oracle.lib()
+    src = open(PY_SRC).read()
+    jobs = [("original", src)]
+    for i, (name, old, new) in enumerate(PY_MUTANTS):
+        assert src.count(old) == 1, f"mutation site not unique or missing: {name}"
+        jobs.append((f"p{i:02d}", src.replace(old, new)))
+    dirs = {}
+    for tag, text in jobs:
+        d = tmp_path / tag / "oracle"
+        d.mkdir(parents=True)
+        (d / "__init__.py").write_text(text)
+        dirs[tag] = str(tmp_path / tag)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+        res = dict(zip(dirs, ex.map(_run_py_pins, dirs.values())))
+    rc, out = res["original"]
+    assert rc == 0, "the unmodified oracle must pass its pins:\n" + out
+    survivors = [name for i, (name, _, _) in enumerate(PY_MUTANTS) if res[f"p{i:02d}"][0] == 0]
     assert not survivors, f"mistakes no pin catches: {survivors}"
