@@ -78,14 +78,20 @@ def test_diff_workload_sizes():
 def test_bounce_rays_leave_the_surface_on_the_incoming_side(orc):
     w = W.terrain_workload(cells=32, width=40, height=30)
     prim, tuv = orc.brute_closest(w["verts"], w["tris"], w["rays"])
-    assert (prim >= 0).all()
+    # Moller-Trumbore is not watertight: a ray running exactly along the
+    # shared (0,0)-(1,1) diagonal of the cells (d.x == d.y from the grid
+    # vertex under the camera) can slip between both triangles.  Every other
+    # primary ray hits.
+    miss = prim < 0
+    d = w["rays"][:, 4:7]
+    assert (d[miss, 0] == d[miss, 1]).all() and miss.sum() <= 4
     b, src = W.bounce_rays(w["rays"], prim, tuv[:, 0], w["verts"], w["tris"], seed=5)
-    assert b.shape == (len(prim), 8) and (src == np.arange(len(prim))).all()
+    assert b.shape == (int((~miss).sum()), 8) and (src == np.nonzero(~miss)[0]).all()
     np.testing.assert_allclose(np.linalg.norm(b[:, 4:7], axis=1), 1.0, rtol=1e-6)
     # each bounce leaves on the side the primary ray came from
-    v = w["verts"].astype(np.float64)[w["tris"][prim]]
+    v = w["verts"].astype(np.float64)[w["tris"][prim[src]]]
     ng = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
-    din = w["rays"][:, 4:7].astype(np.float64)
+    din = w["rays"][src, 4:7].astype(np.float64)
     assert (np.sum(ng * din, 1) * np.sum(ng * b[:, 4:7], 1) < 0).all()
     assert (np.sum(ng * din, 1) * np.sum(ng * (b[:, 0:3] - v[:, 0]), 1) < 0).all()
     b2, _ = W.bounce_rays(w["rays"], prim, tuv[:, 0], w["verts"], w["tris"], seed=5)
