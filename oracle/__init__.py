@@ -54,6 +54,8 @@ _I32 = ctypes.c_int32
 def _declare(L):
     L.orc_mt_f32.argtypes = [_P, _P, ctypes.c_float, _P, _P, _P, _P]
     L.orc_mt_f32.restype = ctypes.c_int
+    L.orc_mt_fixed.argtypes = [_P, _P, _I64, _P, _I64, _P, _P, _P]
+    L.orc_mt_fixed.restype = None
     L.orc_brute_closest.argtypes = [_P, _P, _I64, _P, _I64, _P, _P, ctypes.c_int]
     L.orc_brute_closest.restype = None
     L.orc_brute_top2.argtypes = [_P, _P, _I64, _P, _I64, _P, _P, ctypes.c_int]
@@ -104,6 +106,20 @@ def mt_f32(o, d, tmax, p0, p1, p2):
     hit = lib().orc_mt_f32(_ptr(o), _ptr(d), ctypes.c_float(tmax), _ptr(p0), _ptr(p1),
                            _ptr(p2), _ptr(out))
     return (float(out[0]), float(out[1]), float(out[2])) if hit else None
+
+
+def mt_fixed(verts, tris, rays, prims):
+    """FP32 Moller-Trumbore of each ray against its given triangle prims[i]
+    (negative: none).  Returns (hit[n] bool, tuv[n,3] float32; (inf,0,0) on
+    a miss)."""
+    verts, tris, rays = _c(verts, np.float32), _c(tris, np.int32), _c(rays, np.float32)
+    prims = _c(prims, np.int32)
+    n = rays.shape[0]
+    tuv = np.empty((n, 3), np.float32)
+    hit = np.empty(n, np.int32)
+    lib().orc_mt_fixed(_ptr(verts), _ptr(tris), tris.shape[0], _ptr(rays), n, _ptr(prims),
+                       _ptr(tuv), _ptr(hit))
+    return hit.astype(bool), tuv
 
 
 def brute_closest(verts, tris, rays, nthreads: int = 0):

@@ -12,6 +12,8 @@
  *                       of App. G, with App. G's acceptance intervals),
  *                       written from the 1997 vector formulation with fused
  *                       multiply-adds in a fixed order.
+ *   - orc_mt_fixed      the same test of each ray against one given triangle
+ *                       (checks a claimed hit without a search).
  *   - orc_brute_*       closest hit by exhaustive search over all triangles:
  *                       the plain definition of Fig. 4 / App. G closest_hit
  *                       (minimum t over every triangle the MT test accepts),
@@ -172,6 +174,31 @@ void orc_brute_closest(const float *verts, const int32_t *tris, int64_t ntris,
         out_tuv[3 * r + 0] = bt;
         out_tuv[3 * r + 1] = bu;
         out_tuv[3 * r + 2] = bv;
+    }
+}
+
+/* The ray/triangle test of every ray against one given triangle
+ * (prims[r]; a negative id is a miss): out_hit[r] = 1 and out_tuv[r] = (t,
+ * u, v) where mt_f32 accepts, else out_hit[r] = 0 and out_tuv[r] = (inf, 0,
+ * 0).  Checks a claimed hit without a search. */
+void orc_mt_fixed(const float *verts, const int32_t *tris, int64_t ntris,
+                  const float *rays, int64_t nrays, const int32_t *prims,
+                  float *out_tuv, int32_t *out_hit) {
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrays; r++) {
+        const float *ray = rays + RAY_STRIDE * r;
+        float t = INFINITY, u = 0.0f, v = 0.0f;
+        int hit = 0;
+        if (prims[r] >= 0 && prims[r] < ntris) {
+            v3 p0, p1, p2;
+            tri_fetch(verts, tris, prims[r], &p0, &p1, &p2);
+            hit = mt_f32(v3_load(ray), v3_load(ray + 4), ray[7], p0, p1, p2, &t, &u, &v);
+            if (!hit) { t = INFINITY; u = 0.0f; v = 0.0f; }
+        }
+        out_hit[r] = hit;
+        out_tuv[3 * r + 0] = t;
+        out_tuv[3 * r + 1] = u;
+        out_tuv[3 * r + 2] = v;
     }
 }
 

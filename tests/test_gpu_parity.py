@@ -67,13 +67,14 @@ def check_closest(orc, verts, tris, rays, prim, tuv, ref):
     miss = p1 < 0
     assert (prim[miss] == -1).all() and np.isinf(tuv[miss, 0]).all()
     assert (tuv[miss, 1:] == 0).all()
-    # ungraded rays: a genuine hit within the tie window of the best
-    for r in np.nonzero(~graded)[0][:200]:
-        assert prim[r] >= 0
-        assert abs(tuv[r, 0] - tuv1[r, 0]) <= 1e-5 * tuv1[r, 0]
-        p = verts[tris[prim[r]]]
-        mt = orc.mt_f32(rays[r, 0:3], rays[r, 4:7], float(rays[r, 7]), p[0], p[1], p[2])
-        assert mt is not None and np.array_equal(np.float32(mt), tuv[r])
+    # every ungraded ray: a genuine hit (the oracle's test of that ray against
+    # the GPU's triangle gives exactly the GPU's t, u, v) within the tie
+    # window of the best
+    ug = np.nonzero(~graded)[0]
+    assert (prim[ug] >= 0).all()
+    assert (np.abs(tuv[ug, 0] - tuv1[ug, 0]) <= 1e-5 * tuv1[ug, 0]).all()
+    ok, tuv_g = orc.mt_fixed(verts, tris, rays[ug], prim[ug])
+    assert ok.all() and np.array_equal(tuv_g.view(np.uint32), tuv[ug].view(np.uint32))
     return graded
 
 
@@ -96,7 +97,10 @@ def test_terrain_primary_and_bounce_parity(orc, layout):
     w = W.terrain_workload(cells=96, width=192, height=108)
     v, t = w["verts"], w["tris"]
     p1, tuv1 = orc.brute_closest(v, t, w["rays"])
-    assert (p1 >= 0).all()
+    # Moller-Trumbore is not watertight: a camera ray through a shared cell
+    # edge or grid vertex can miss both triangles (the oracle's own misses;
+    # the GPU must miss them too, checked below).  They are rare.
+    assert (p1 < 0).sum() <= 2e-3 * len(p1)
     bounce, _ = W.bounce_rays(w["rays"], p1, tuv1[:, 0], v, t, seed=21)
     rays = np.concatenate([w["rays"], bounce])
     bvh = orc.OracleBVH(v, t)
@@ -209,64 +213,65 @@ def _sample(n, k, seed):
 
 @pytest.fixture(scope="module")
 def terrain_full(orc):
+    """Full terrain: the oracle's top-2 hits of all 2,073,600 camera rays, the
+    bounce rays made from the oracle's hits, and their top-2 hits."""
     w = W.terrain_workload()
     v, t = w["verts"], w["tris"]
     bvh = orc.OracleBVH(v, t)
-    return w, bvh
+    ref = bvh.trace(w["rays"], orc.TOP2)
+    bounce, src = W.bounce_rays(w["rays"], ref[0], ref[1][:, 0], v, t, seed=1001)
+    refb = bvh.trace(bounce, orc.TOP2)
+    return w, ref, bounce, refb
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_terrain_full_size_sampled(orc, terrain_full, layout):
-    """Full 2.1 M-triangle terrain, all 2,073,600 camera rays traced in one
-    launch, then the bounce rays of those hits; a 4,096-ray sample of each
-    set is checked against the oracle."""
-    w, bvh = terrain_full
+def test_terrain_full_size(orc, terrain_full, layout):
+    """Full 2.1 M-triangle terrain: all 2,073,600 camera rays in one launch,
+    then the bounce rays of the oracle's hits in another; every ray of both
+    sets is checked against the oracle."""
+    w, ref, bounce, refb = terrain_full
     v, t = w["verts"], w["tris"]
     h = gpu_build(v, t, layout)
     prim, tuv = gpu_trace(h, w["rays"])
-    s = _sample(len(prim), 4096, 1)
-    ref = bvh.trace(w["rays"][s], orc.TOP2)
-    check_closest(orc, v, t, w["rays"][s], prim[s], tuv[s], ref)
+    check_closest(orc, v, t, w["rays"], prim, tuv, ref)
     # FP32 Moller-Trumbore is not watertight: a ray through a shared grid
     # vertex or edge can pass between the triangles.  Such misses are rare
-    # and the oracle must miss them too.
-    miss = np.nonzero(prim < 0)[0]
-    assert len(miss) < 1e-4 * len(prim)
-    if len(miss):
-        pm, _ = bvh.trace(w["rays"][miss])
-        assert (pm < 0).all()
-    s = s[prim[s] >= 0]
-    ref = tuple(x[np.isin(_sample(len(prim), 4096, 1), s)] for x in ref)
-    # bounce rays from the oracle's hits of the sample, traced on both sides
-    bounce, _ = W.bounce_rays(w["rays"][s], ref[0], ref[1][:, 0], v, t, seed=1001)
-    refb = bvh.trace(bounce, orc.TOP2)
+    # (319 of the 2,073,600 camera rays) and the oracle misses them too
+    # (checked above: misses are graded).
+    assert (prim < 0).sum() < 5e-4 * len(prim)
     pb, tb = gpu_trace(h, bounce)
     check_closest(orc, v, t, bounce, pb, tb, refb)
 
 
 @pytest.fixture(scope="module")
 def spheres_full(orc):
+    """Full sphere-cluster scene: the oracle's top-2 hits of all 2^23 rays and
+    of the 2^23 shadow rays (closest hit, for the any-hit grading)."""
     w = W.spheres_workload()
     bvh = orc.OracleBVH(w["verts"], w["tris"])
-    return w, bvh
+    ref = bvh.trace(w["rays"], orc.TOP2)
+    pc, tc, _, _ = bvh.trace(w["shadow"], orc.TOP2)
+    return w, ref, pc, tc
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_spheres_full_size_sampled(orc, spheres_full, layout):
+def test_spheres_full_size(orc, spheres_full, layout):
     """Full 4.05 M-triangle scene, all 2^23 rays in one launch (closest and
-    any-hit); a 4,096-ray sample of each is checked against the oracle."""
-    w, bvh = spheres_full
+    any-hit); every ray is checked against the oracle."""
+    w, ref, pc, tc = spheres_full
     v, t = w["verts"], w["tris"]
     h = gpu_build(v, t, layout)
     prim, tuv = gpu_trace(h, w["rays"])
-    s = _sample(len(prim), 4096, 2)
-    ref = bvh.trace(w["rays"][s], orc.TOP2)
-    check_closest(orc, v, t, w["rays"][s], prim[s], tuv[s], ref)
+    check_closest(orc, v, t, w["rays"], prim, tuv, ref)
     pa, ta = gpu_trace(h, w["shadow"], mode=1)
-    sh = w["shadow"][s]
-    pc, tc, _, _ = bvh.trace(sh, orc.TOP2)
+    sh = w["shadow"]
     graded = (pc < 0) | (np.abs(tc[:, 0] - sh[:, 7]) > 1e-5 * sh[:, 7])
-    assert np.array_equal((pa[s] >= 0)[graded], (pc >= 0)[graded])
+    assert graded.mean() > 0.99
+    assert np.array_equal((pa >= 0)[graded], (pc >= 0)[graded])
+    # an occluder reported by any-hit is a genuine hit within tmax
+    occ = np.nonzero(pa >= 0)[0]
+    ok, tuv_a = orc.mt_fixed(v, t, sh[occ], pa[occ])
+    assert ok.all() and np.array_equal(tuv_a.view(np.uint32), ta[occ].view(np.uint32))
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -315,3 +320,16 @@ def test_mixed_coherent_and_scattered_waves(orc, layout):
     s_ = _sample(len(rays), 6000, 3)
     ref = orc.OracleBVH(v, t).trace(rays[s_], orc.TOP2)
     check_closest(orc, v, t, rays[s_], prim[s_], tuv[s_], ref)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_soup_against_stored_golden(layout):
+    """Every layout reproduces the stored golden hits (tests/golden, written
+    by the oracle's exhaustive search) bit for bit."""
+    from test_oracle_golden import load_golden
+    idx, prim_g, tuv_g = load_golden()
+    w = W.soup_workload()
+    h = gpu_build(w["verts"], w["tris"], layout)
+    prim, tuv = gpu_trace(h, w["rays"][idx])
+    assert np.array_equal(prim, prim_g)
+    assert np.array_equal(tuv.view(np.uint32), tuv_g.view(np.uint32))

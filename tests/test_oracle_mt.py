@@ -14,6 +14,8 @@ import math
 import numpy as np
 import pytest
 
+from paper_2511_15028_amd import workloads as W
+
 INF = math.inf
 # Triangle in the plane z = 1 with p0 at the right angle.
 P0, P1, P2 = (0.0, 0.0, 1.0), (1.0, 0.0, 1.0), (0.0, 1.0, 1.0)
@@ -125,3 +127,22 @@ def test_tuv_f64_matches_linear_solve(orc):
         p = verts[tris[i]]
         ref = _solve64(rays[i, 0:3], rays[i, 4:7], p[0], p[1], p[2])
         np.testing.assert_allclose(out[i], ref, rtol=1e-9, atol=1e-9)
+
+
+def test_mt_fixed_reproduces_the_search_and_rejects_misses(orc):
+    """The per-ray test against a given triangle returns, at the exhaustive
+    search's own primitives, exactly the search's (t, u, v); a ray given a
+    triangle it does not meet, or no triangle, gets a miss."""
+    w = W.soup_workload()
+    v, t, rays = w["verts"], w["tris"], w["rays"]
+    prim, tuv = orc.brute_closest(v, t, rays)
+    hit, tuv2 = orc.mt_fixed(v, t, rays, prim)
+    assert np.array_equal(hit, prim >= 0)
+    assert np.array_equal(tuv2.view(np.uint32), tuv.view(np.uint32))
+    # a triangle far behind the camera: every camera ray misses it
+    v2 = np.concatenate([v, np.array([[0, 0, -5], [1, 0, -5], [0, 1, -5]], np.float32)])
+    t2 = np.concatenate([t, np.array([[len(v), len(v) + 1, len(v) + 2]], np.int32)])
+    hit, tuv3 = orc.mt_fixed(v2, t2, rays, np.full(len(rays), len(t), np.int32))
+    assert not hit.any() and np.isinf(tuv3[:, 0]).all() and (tuv3[:, 1:] == 0).all()
+    hit, _ = orc.mt_fixed(v, t, rays, np.full(len(rays), len(t) + 3, np.int32))
+    assert not hit.any()
