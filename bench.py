@@ -35,6 +35,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+# VALU peak in lane operations per second: 256 CUs x 4 SIMDs x 16 lanes, one
+# FP32/integer operation per lane per clock (fused multiply-add counted as
+# one operation; packed FP32 is not used), at 2.4 GHz.
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 39.32 T lane-ops/s
+
+# Algorithmic VALU operations per unit of traversal work (the arithmetic the
+# method needs, address arithmetic, loads, loop control and stack traffic
+# excluded):
+#   one ray/box slab test: 6 plane distances (one FMA each), 3 max for the
+#     entry distance (with 0), 3 min for the exit distance (with the current
+#     best), the exit widening (1 mul), the compare and the select: 15;
+#   dequantising one quantised box: 6 planes x (field extract, int->float
+#     convert, one FMA): 18;
+#   one ray/triangle test: the numerators and |det| (31: 3 cross products of
+#     2 ops per component less the shared ones, 3 dot products of 3 ops, 3
+#     subtractions for o - p0, 3 sign xors, one abs) and the interval tests
+#     (7 compares, one add, one multiply): 40; indexed leaves also form the
+#     two edges from the three gathered vertices (6 subtractions): 46.
+# A node record fetched costs the box tests of every child slot it holds
+# (binary layouts: the node's own box).
+ALU_OPS_BOX, ALU_OPS_DEQUANT = 15, 18
+ALU_OPS_TRI = {"compact": 40, "indexed": 46}
+ALU_OPS_NODE = {
+    "aabb2": ALU_OPS_BOX, "pbrt_soaos": ALU_OPS_BOX, "shared_slab": ALU_OPS_BOX,
+    "pbrt_q16": ALU_OPS_BOX + ALU_OPS_DEQUANT, "sg_eq": ALU_OPS_BOX + ALU_OPS_DEQUANT,
+    "pbrt_q16_soaos": ALU_OPS_BOX + ALU_OPS_DEQUANT, "sg_eq_a16": ALU_OPS_BOX + ALU_OPS_DEQUANT,
+    "bvh4": 4 * ALU_OPS_BOX,
+    "bvh8_q8": 8 * (ALU_OPS_BOX + ALU_OPS_DEQUANT), "bvh8_q16": 8 * (ALU_OPS_BOX + ALU_OPS_DEQUANT),
+}
 RAY_BYTES, HIT_BYTES = 32, 16
 QUERY_BYTES, CLOSEST_BYTES = 16, 16  # bvh_point_query, bvh_closest
 LAYOUTS = ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq", "pbrt_soaos",
@@ -69,6 +98,22 @@ def algorithmic_bytes(counts, layout_bytes, leaf_mode):
     nodes = counts[:, 0].astype(np.float64)
     tris = counts[:, 1].astype(np.float64)
     return RAY_BYTES + HIT_BYTES + nodes * layout_bytes + tris * LEAF_TRI_BYTES[leaf_mode]
+
+
+def algorithmic_ops(counts, layout, leaf_mode):
+    """Per-ray algorithmic VALU lane operations: node records fetched x the
+    layout's box-test cost + triangles tested x the triangle-test cost."""
+    nodes = counts[:, 0].astype(np.float64)
+    tris = counts[:, 1].astype(np.float64)
+    return nodes * ALU_OPS_NODE[layout] + tris * ALU_OPS_TRI[leaf_mode]
+
+
+def trimmed_mean(times):
+    """The paper's protocol (Sec. 9.1): of nine timed runs after a warm-up,
+    drop the two lowest and the two highest and average the middle five."""
+    t = sorted(times)
+    assert len(t) == 9, len(t)
+    return float(np.mean(t[2:7]))
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "trace_kernel_counters.txt")
@@ -180,12 +225,17 @@ def main():
     _, cnt_p = h.trace_counts(prim_rays)
     _, cnt_b = h.trace_counts(bounce_rays)
     torch.cuda.synchronize()
-    bytes_p = algorithmic_bytes(cnt_p.cpu().numpy(), st["node_bytes"], args.leaf_mode)
-    bytes_b = algorithmic_bytes(cnt_b.cpu().numpy(), st["node_bytes"], args.leaf_mode)
+    cnt_p, cnt_b = cnt_p.cpu().numpy(), cnt_b.cpu().numpy()
+    bytes_p = algorithmic_bytes(cnt_p, st["node_bytes"], args.leaf_mode)
+    bytes_b = algorithmic_bytes(cnt_b, st["node_bytes"], args.leaf_mode)
+    ops_p = algorithmic_ops(cnt_p, args.layout, args.leaf_mode)
+    ops_b = algorithmic_ops(cnt_b, args.layout, args.leaf_mode)
     # dominant kernel: the traversal kernel; two launches per step (camera, bounce)
     launch_bytes = bytes_p.sum() + bytes_b.sum()
     launch_s = (dur_p.mean() + dur_b.mean()) / 1000.0
-    achieved = launch_bytes / launch_s / 1e9
+    achieved_gbs = launch_bytes / launch_s / 1e9
+    achieved_tops = (ops_p.sum() + ops_b.sum()) / launch_s / 1e12
+    traffic = measured_traffic(args)
     trace_mrays = n_rays / launch_s / 1e6
     build_ms = ms_step - (dur_p.mean() + dur_b.mean())
     h.close()
@@ -218,10 +268,26 @@ def main():
         "bvh": {"nodes": st["n_nodes"], "node_bytes": st["node_bytes"],
                 "nodes_mb": round(st["nodes_buffer_bytes"] / 1e6, 2),
                 "leaf_mb": round(st["leaf_buffer_bytes"] / 1e6, 2), "depth": st["depth"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args),
-                     "kernel": f"trace ({args.layout}, {args.leaf_mode})"},
+        # The traversal kernel issues VALU work most of the time (counter
+        # VALUBusy) while its node and triangle data stay largely in the
+        # caches (counter HBM bytes well below the algorithmic bytes), so the
+        # bound reported is the VALU lane-operation peak; `achieved` counts the
+        # algorithmic operations of the node and triangle tests per launch.
+        "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                     "unit": "Tops/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 4),
+                     "traffic": traffic,
+                     "kernel": f"trace ({args.layout}, {args.leaf_mode}), camera + bounce launches",
+                     "ops_per_ray": {"camera": round(float(ops_p.mean()), 1),
+                                     "bounce": round(float(ops_b.mean()), 1)},
+                     "hbm": {"peak_gbs": HBM_PEAK_GBS,
+                             "algorithmic_gbs": round(achieved_gbs, 1),
+                             "algorithmic_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                             "counter_gbs": (round(traffic / launch_s / 1e9, 1) if traffic else None),
+                             "counter_frac": (round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+                                              if traffic else None),
+                             "note": "algorithmic bytes count every node and triangle fetch, "
+                                     "most of which the caches serve; counter bytes are HBM "
+                                     "reads and writes (rocprofv3 FETCH_SIZE, WRITE_SIZE)"}},
     }
 
     if not args.no_extras:
@@ -257,23 +323,31 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_trace(torch, h, rays, mode=0, reps=5):
-    """Median event time (ms) of `reps` trace calls after one warm-up call."""
+def timed_events(torch, fn):
+    """Event time (ms) of fn() on the current stream under the paper's
+    protocol: one warm-up run, nine timed runs, trimmed mean of the middle
+    five."""
     stream = torch.cuda.current_stream()
-    hits = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device)
     times = []
-    for _ in range(reps + 1):
+    for _ in range(10):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         e[0].record(stream)
-        h.trace(rays, mode=mode, hits=hits)
+        fn()
         e[1].record(stream)
         torch.cuda.synchronize()
         times.append(e[0].elapsed_time(e[1]))
-    return float(np.median(times[1:]))
+    return trimmed_mean(times[1:])
 
 
-def layout_row(torch, h, leaf_mode, ray_sets):
-    """Per ray set: Mrays/s, algorithmic bytes per ray and roofline fraction."""
+def time_trace(torch, h, rays, mode=0):
+    hits = torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device)
+    return timed_events(torch, lambda: h.trace(rays, mode=mode, hits=hits))
+
+
+def layout_row(torch, h, layout, leaf_mode, ray_sets):
+    """Per ray set: Mrays/s (trimmed mean of nine launches), algorithmic
+    bytes per ray and their rate against the HBM peak, and algorithmic VALU
+    operations per ray and their rate against the VALU peak."""
     st = h.stats()
     row = {"bvh_mb": round((st["nodes_buffer_bytes"] + st["leaf_buffer_bytes"]
                             + st["extra_bytes"]) / 1e6, 1)}
@@ -281,11 +355,18 @@ def layout_row(torch, h, leaf_mode, ray_sets):
         t_ms = time_trace(torch, h, rays, mode)
         _, c = h.trace_counts(rays, mode=mode)
         torch.cuda.synchronize()
-        by = algorithmic_bytes(c.cpu().numpy(), st["node_bytes"], leaf_mode)
+        c = c.cpu().numpy()
+        by = algorithmic_bytes(c, st["node_bytes"], leaf_mode)
+        ops = algorithmic_ops(c, layout, leaf_mode)
         gbs = by.sum() / (t_ms / 1000.0) / 1e9
+        tops = ops.sum() / (t_ms / 1000.0) / 1e12
         row[name] = {"mrays_s": round(rays.shape[0] / (t_ms / 1000.0) / 1e6, 1),
-                     "ms": round(t_ms, 4), "bytes_per_ray": round(float(by.mean()), 1),
-                     "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                     "ms": round(t_ms, 4), "nodes_per_ray": round(float(c[:, 0].mean()), 2),
+                     "tris_per_ray": round(float(c[:, 1].mean()), 2),
+                     "bytes_per_ray": round(float(by.mean()), 1),
+                     "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "ops_per_ray": round(float(ops.mean()), 1), "alu_tops": round(tops, 3),
+                     "alu_frac": round(tops / ALU_PEAK_TOPS, 4)}
     return row
 
 
@@ -298,26 +379,16 @@ def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
         for leaf_mode in ("compact", "indexed"):
             h = bvh.build(verts, tris, layout, args.leaf_size, leaf_mode)
             res[f"{layout}/{leaf_mode}"] = layout_row(
-                torch, h, leaf_mode, [("camera", prim_rays, bvh.TRACE_CLOSEST),
+                torch, h, layout, leaf_mode, [("camera", prim_rays, bvh.TRACE_CLOSEST),
                                       ("bounce", bounce_rays, bvh.TRACE_CLOSEST)])
             h.close()
             log(f"terrain {layout}/{leaf_mode}: {res[f'{layout}/{leaf_mode}']}")
     return res
 
 
-def time_closest(torch, h, q, reps=5):
-    """Median event time (ms) of `reps` closest-point calls after a warm-up."""
-    stream = torch.cuda.current_stream()
+def time_closest(torch, h, q):
     out = torch.empty((q.shape[0], 4), dtype=torch.float32, device=q.device)
-    times = []
-    for _ in range(reps + 1):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        e[0].record(stream)
-        h.closest_point(q, out=out)
-        e[1].record(stream)
-        torch.cuda.synchronize()
-        times.append(e[0].elapsed_time(e[1]))
-    return float(np.median(times[1:]))
+    return timed_events(torch, lambda: h.closest_point(q, out=out))
 
 
 def closest_point_rows(torch, bvh, W, verts_np, verts, tris_np, tris, args, seed):
@@ -384,7 +455,7 @@ def sah_rows(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
         for builder in ("lbvh", "sah"):
             build_ms = timed_build(torch, bvh, verts, tris, layout, args.leaf_size, builder)
             h = bvh.build(verts, tris, layout, args.leaf_size, "compact", builder=builder)
-            r = layout_row(torch, h, "compact", [("camera", prim_rays, bvh.TRACE_CLOSEST),
+            r = layout_row(torch, h, layout, "compact", [("camera", prim_rays, bvh.TRACE_CLOSEST),
                                                  ("bounce", bounce_rays, bvh.TRACE_CLOSEST)])
             r["build_ms"] = round(build_ms, 3)
             r["depth"] = h.stats()["depth"]
@@ -412,15 +483,15 @@ def spheres(torch, bvh, W, args, cpq=None):
                        "uniform closest-hit rays + as many shadow rays (any hit)"}
     for layout in LAYOUTS:
         h = bvh.build(verts, tris, layout, args.leaf_size, "compact")
-        res[layout] = layout_row(torch, h, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
+        res[layout] = layout_row(torch, h, layout, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
                                                        ("shadow_any", shadow, bvh.TRACE_ANY)])
         h.close()
         log(f"spheres {layout}: {res[layout]}")
     for layout in ("aabb2", "bvh4"):
         build_ms = timed_build(torch, bvh, verts, tris, layout, args.leaf_size, "sah")
         h = bvh.build(verts, tris, layout, args.leaf_size, "compact", builder="sah")
-        r = layout_row(torch, h, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
-                                             ("shadow_any", shadow, bvh.TRACE_ANY)])
+        r = layout_row(torch, h, layout, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
+                                                     ("shadow_any", shadow, bvh.TRACE_ANY)])
         r["build_ms"] = round(build_ms, 3)
         h.close()
         res[f"{layout}/sah"] = r
@@ -462,8 +533,8 @@ def fwd_bwd(torch, bvh, W):
 
     for _ in range(2):
         run(False), run(True)
-    f = float(np.median([run(False) for _ in range(7)]))
-    fb = float(np.median([run(True) for _ in range(7)]))
+    f = trimmed_mean([run(False) for _ in range(9)])
+    fb = trimmed_mean([run(True) for _ in range(9)])
     h.close()
     n = r.shape[0]
     return {"workload": "icosphere level 7 (327,680 tris), 1,048,576 rays from 64 cameras",
@@ -494,16 +565,8 @@ def batched(torch, bvh, W):
     infos = [b.info(i) for i in range(len(scenes))]
     handles = [b.handle(i) for i in range(len(scenes))]
 
-    def timed(fn, reps=5):
-        ts = []
-        for _ in range(reps + 1):
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-            e[0].record(stream)
-            fn()
-            e[1].record(stream)
-            torch.cuda.synchronize()
-            ts.append(e[0].elapsed_time(e[1]))
-        return float(np.median(ts[1:]))
+    def timed(fn):
+        return timed_events(torch, fn)
 
     hits_b = torch.empty((n, 4), dtype=torch.float32, device=dev)
     hits_p = torch.empty((n, 4), dtype=torch.float32, device=dev)
@@ -546,17 +609,38 @@ def cpu_baseline(w, W):
     cores = oracle.max_threads()
     rays = w["rays"]
     t0 = time.perf_counter()
-    p, tuv = b.trace(rays)
+    p, tuv = b.trace(rays, nthreads=cores)
     t1 = time.perf_counter()
     bounce, _ = W.bounce_rays(rays, p, tuv[:, 0], w["verts"], w["tris"], seed=1001)
     t2 = time.perf_counter()
-    b.trace(bounce)
+    b.trace(bounce, nthreads=cores)
     t3 = time.perf_counter()
     secs = (t1 - t0) + (t3 - t2)
     n = rays.shape[0] + bounce.shape[0]
+    # one thread on a bounded sample: the first 2^18 camera and 2^18 bounce rays
+    k = 1 << 18
+    t4 = time.perf_counter()
+    b.trace(rays[:k], nthreads=1)
+    b.trace(bounce[:k], nthreads=1)
+    secs1 = time.perf_counter() - t4
     return {"value": round(n / secs / 1e6, 3), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"all {rays.shape[0]} camera rays + {bounce.shape[0]} bounce rays of the "
-                      f"terrain workload, traversal only ({secs:.2f} s wall on {cores} threads)"}
+                      f"terrain workload, traversal only ({secs:.2f} s wall on {cores} threads, "
+                      "OpenMP dynamic,64 over rays; one run)",
+            "one_thread": {"value": round(2 * k / secs1 / 1e6, 3), "unit": "Mrays/s",
+                           "sample": f"first {k} camera + first {k} bounce rays ({secs1:.2f} s)"}}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
