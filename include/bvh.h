@@ -315,10 +315,15 @@ int32_t bvh_version(void);
 
 /*
  * Builds a BVH over n_tris triangles (Sec. 5's two phases: a logical binary
- * tree first, then its packing into the chosen layout).  The logical tree is
- * a linear BVH: 63-bit Morton codes of the triangle box centres, a radix
- * sort, the hierarchy of the sorted codes, a bottom-up box refit, then
- * collapse of every subtree of at most leaf_size triangles into one leaf.
+ * tree first, then its packing into the chosen layout).  With the LBVH
+ * builder the logical tree is a linear BVH: Morton codes of the triangle box
+ * centres with b = ceil(log2(n_tris) / 3) + 4 bits per axis (at most 21,
+ * one fewer where that saves an 8-bit sort pass), a stable radix sort over
+ * the 3b key bits, the hierarchy of the sorted codes (equal codes ordered by
+ * position), node boxes as unions of the leaf boxes of each node's sorted
+ * range (a sparse table of range unions, no bottom-up refit), then collapse
+ * of every subtree of at most leaf_size triangles into one leaf.  The Morton
+ * bit count shapes only the topology; hits do not depend on it.
  *   verts   device, n_verts x 3 float (x, y, z)
  *   tris    device, n_tris x 3 int32 vertex indices, each in [0, n_verts)
  *   layout  BVH_LAYOUT_*
@@ -399,14 +404,22 @@ int32_t bvh_trace_counts(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit
  *   verts       device, n_verts x 3 float;  tris  device, n_tris x 3 int32
  *   rays, hits  device, n records (hits from bvh_trace CLOSEST)
  *   grad_hits   device, n x 3 float (dL/dt, dL/du, dL/dv)
- *   grad_verts  device, n_verts x 3 float, ACCUMULATED (+=) with float atomics,
- *               so the summation order (last bits) varies between runs
+ *   grad_verts  device, n_verts x 3 float, ACCUMULATED (+=).  Meshes of up to
+ *               2^22 vertices: the contributions are grouped by vertex range
+ *               in a work area (16 B per ray contribution; grow-only, kept
+ *               per stream) and each range is summed in one workgroup's
+ *               LDS with float atomics; larger meshes add per-block partial
+ *               sums with device float atomics.  Either way the summation
+ *               order (last bits) varies between runs.
+ *               Calls that share a stream share its work area: they are
+ *               ordered by the stream.
  *   grad_rays   device, n x 6 float (dL/do, dL/dd), OVERWRITTEN; a miss or
  *               a skipped ray gets zeros
  * Rays whose prim_id is outside [0, n_tris), whose triangle has a vertex
  * index outside [0, n_verts), or whose system is singular (det = 0 or not
  * finite) contribute nothing.
- * Errors: EINVAL for negative sizes or null pointers with a nonzero count.
+ * Errors: EINVAL for negative sizes or null pointers with a nonzero count;
+ * ENOMEM when the work area cannot be allocated.
  */
 int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                            const bvh_ray *rays, int64_t n, const bvh_hit *hits,
@@ -529,8 +542,10 @@ int32_t bvh_batch_scene_handle(bvh_batch_t b, int32_t scene, bvh_handle_t *out);
  *   rays, hits   device;  ray_offsets  host, n_scenes + 1 non-decreasing
  * The first call for a given (rays, hits, ray_offsets) builds and
  * instantiates a hipGraph (one small kernel that resets the work-queue
- * counters, then one persistent kernel per layout/stack variant, in
- * parallel branches); later calls with the same arguments replay it.  Calls
+ * counters, then per layout/stack variant one persistent kernel over the
+ * whole GPU followed by its deep-stack fallback pass, the variants chained
+ * one after another); later calls with the same
+ * arguments replay it.  Calls
  * on one batch must not overlap in time (they share the queue counters).
  */
 int32_t bvh_batch_trace(bvh_batch_t b, const bvh_ray *rays, const int64_t *ray_offsets,

@@ -464,9 +464,10 @@ __device__ inline uint32_t quantize_axis_bits(float x, float lo, float inv_ext, 
     return (uint32_t)u;
 }
 
+template <typename KeyT>
 __global__ __launch_bounds__(kBlock) void k_morton(const Box *pbox, uint32_t n,
                                                    const BuildInfo *info, int bits,
-                                                   uint64_t *keys, uint32_t *vals) {
+                                                   KeyT *keys, uint32_t *vals) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     Box b = pbox[i];
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_morton(const Box *pbox, uint32_t n,
         key |= (uint64_t)((q[1] >> bit) & 1u) << (3 * bit + 1);
         key |= (uint64_t)((q[2] >> bit) & 1u) << (3 * bit);
     }
-    keys[i] = key;
+    keys[i] = (KeyT)key;  // 3 * bits <= the key width (checked by the caller)
     vals[i] = i;
 }
 
@@ -516,7 +517,8 @@ constexpr int kSortWaves = kBlock / kWave;
 constexpr int kRadix = 256;
 static_assert(kRadix == kBlock, "one digit per thread in the per-digit steps");
 
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t *keys, uint32_t n, int shift,
+template <typename KeyT>
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const KeyT *keys, uint32_t n, int shift,
                                                        uint32_t *hist, uint32_t ntiles) {
     __shared__ uint32_t h[kRadix];
     h[threadIdx.x] = 0;
@@ -548,14 +550,15 @@ __global__ __launch_bounds__(kBlock) void k_radix_offsets(uint32_t *hist, uint32
     if (threadIdx.x == 0) total[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *keys_in,
+template <typename KeyT>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const KeyT *keys_in,
                                                           const uint32_t *vals_in,
-                                                          uint64_t *keys_out, uint32_t *vals_out,
+                                                          KeyT *keys_out, uint32_t *vals_out,
                                                           uint32_t n, int shift,
                                                           const uint32_t *prefix,
                                                           const uint32_t *total,
                                                           uint32_t ntiles) {
-    __shared__ uint64_t skey[kSortTile];
+    __shared__ KeyT skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
     __shared__ uint32_t wcount[kSortWaves][kRadix];  // digit counts per wave, then run positions
     __shared__ uint32_t gdst[kRadix];                 // output index of local position 0 of digit d
@@ -568,12 +571,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *keys_i
     for (int k = 0; k < kSortWaves; k++) wcount[k][threadIdx.x] = 0;
     __syncthreads();
     // this wave's quarter of the tile, item r of a lane at wbase + r*64 + lane
-    uint64_t key[kSortItems];
+    KeyT key[kSortItems];
     uint32_t val[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const uint32_t i = wbase + r * kWave + lane;
-        key[r] = i < n ? keys_in[i] : 0ull;
+        key[r] = i < n ? keys_in[i] : (KeyT)0;
         val[r] = i < n ? vals_in[i] : 0u;
         if (i < n) atomicAdd(&wcount[w][(uint32_t)(key[r] >> shift) & (kRadix - 1)], 1u);
     }
@@ -625,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *keys_i
     __syncthreads();
     const uint32_t m = min((uint32_t)kSortTile, n - base);
     for (uint32_t p = threadIdx.x; p < m; p += kBlock) {
-        const uint64_t k = skey[p];
+        const KeyT k = skey[p];
         const uint32_t o = gdst[(uint32_t)(k >> shift) & (kRadix - 1)] + p;
         if (o < n) {  // always true for a consistent histogram; guards the write
             keys_out[o] = k;
@@ -640,32 +643,68 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *keys_i
 // keys are separated by their positions.  Node ids: internal i -> i, sorted
 // leaf j -> (n - 1) + j; the root is id 0.
 // ---------------------------------------------------------------------------
-__device__ inline int common_prefix(const uint64_t *keys, int n, int i, int j) {
-    if (j < 0 || j >= n) return -1;
-    const uint64_t a = keys[i], b = keys[j];
+// Sorted keys as seen by one block: keys [w0, w0 + kKarrasWindow) staged in
+// LDS (the block's own nodes and a halo on either side, where nearly all of
+// the searches land), the rest read from global memory.
+constexpr int kKarrasHalo = 512;
+constexpr int kKarrasWindow = kBlock + 2 * kKarrasHalo;
+
+template <typename KeyT>
+struct KeyWindow {
+    const KeyT *g;
+    const KeyT *lds;
+    int w0;
+    __device__ KeyT at(int j) const {
+        const unsigned k = (unsigned)(j - w0);
+        return k < (unsigned)kKarrasWindow ? lds[k] : g[j];
+    }
+};
+
+// Length of the common prefix of sorted keys i and j (positions i and j
+// appended as tie-breaks), -1 when j is out of range.
+__device__ inline int prefix_len(uint64_t a, uint64_t b, int i, int j) {
     if (a != b) return __clzll((long long)(a ^ b));
     return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
 }
+__device__ inline int prefix_len(uint32_t a, uint32_t b, int i, int j) {
+    if (a != b) return __clz((int)(a ^ b));
+    return 32 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+template <typename KeyT>
+__device__ inline int common_prefix(const KeyWindow<KeyT> &kw, KeyT ki, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    return prefix_len(ki, kw.at(j), i, j);
+}
 
-__global__ __launch_bounds__(kBlock) void k_karras(const uint64_t *keys, int n, int32_t *ileft,
+template <typename KeyT>
+__global__ __launch_bounds__(kBlock) void k_karras(const KeyT *keys, int n, int32_t *ileft,
                                                    int32_t *iright, uint32_t *ifirst,
                                                    uint32_t *icount, uint8_t *iaxis,
                                                    int32_t *parent) {
+    __shared__ KeyT sk[kKarrasWindow];
+    const int w0 = (int)(blockIdx.x * kBlock) - kKarrasHalo;
+    for (int k = threadIdx.x; k < kKarrasWindow; k += kBlock) {
+        const int j = w0 + k;
+        if (j >= 0 && j < n) sk[k] = keys[j];
+    }
+    __syncthreads();
+    const KeyWindow<KeyT> kw{keys, sk, w0};
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n - 1) return;
-    const int d = (common_prefix(keys, n, i, i + 1) - common_prefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
-    const int dmin = common_prefix(keys, n, i, i - d);
+    const KeyT ki = kw.at(i);
+    const int d = (common_prefix(kw, ki, n, i, i + 1) - common_prefix(kw, ki, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = common_prefix(kw, ki, n, i, i - d);
     int lmax = 2;
-    while (common_prefix(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+    while (common_prefix(kw, ki, n, i, i + lmax * d) > dmin) lmax *= 2;
     int l = 0;
     for (int t = lmax / 2; t >= 1; t /= 2)
-        if (common_prefix(keys, n, i, i + (l + t) * d) > dmin) l += t;
+        if (common_prefix(kw, ki, n, i, i + (l + t) * d) > dmin) l += t;
     const int j = i + l * d;
-    const int dnode = common_prefix(keys, n, i, j);
+    const int dnode = common_prefix(kw, ki, n, i, j);
     int s = 0, t = l;
     do {
         t = (t + 1) >> 1;
-        if (common_prefix(keys, n, i, i + (s + t) * d) > dnode) s += t;
+        if (common_prefix(kw, ki, n, i, i + (s + t) * d) > dnode) s += t;
     } while (t > 1);
     const int gamma = i + s * d + (d < 0 ? -1 : 0);
     const int first = min(i, j), last = max(i, j);
@@ -677,10 +716,11 @@ __global__ __launch_bounds__(kBlock) void k_karras(const uint64_t *keys, int n, 
     parent[rc] = i;
     ifirst[i] = (uint32_t)first;
     icount[i] = (uint32_t)(last - first + 1);
-    // split axis: key bit 63 - dnode (bit 3b+2 is x, 3b+1 is y, 3b is z)
+    // split axis: key bit (width - 1) - dnode (bit 3b+2 is x, 3b+1 is y, 3b is z)
+    constexpr int kKeyBits = 8 * (int)sizeof(KeyT);
     uint8_t axis = 0;
-    if (dnode < 64) {
-        const int p = 63 - dnode;
+    if (dnode < kKeyBits) {
+        const int p = (kKeyBits - 1) - dnode;
         axis = (p % 3 == 2) ? 0 : (p % 3 == 1 ? 1 : 2);
     }
     iaxis[i] = axis;
@@ -1570,22 +1610,22 @@ __global__ __launch_bounds__(kBlock) void k_leaf_compact(const float *verts, int
     if (j >= n) return;
     const uint32_t t = perm[j];
     const int32_t i0 = tris[3 * (size_t)t], i1 = tris[3 * (size_t)t + 1], i2 = tris[3 * (size_t)t + 2];
-    bvh_tri r;
+    float p0[3] = {0.f, 0.f, 0.f}, e1[3] = {0.f, 0.f, 0.f}, e2[3] = {0.f, 0.f, 0.f};
     if (i0 >= 0 && i0 < n_verts && i1 >= 0 && i1 < n_verts && i2 >= 0 && i2 < n_verts) {
-        const float *p0 = verts + 3 * (size_t)i0;
-        const float *p1 = verts + 3 * (size_t)i1;
-        const float *p2 = verts + 3 * (size_t)i2;
+        const float *q0 = verts + 3 * (size_t)i0;
+        const float *q1 = verts + 3 * (size_t)i1;
+        const float *q2 = verts + 3 * (size_t)i2;
         for (int a = 0; a < 3; a++) {
-            r.p0[a] = p0[a];
-            r.e1[a] = p1[a] - p0[a];  // the f32 edges of the intersection test
-            r.e2[a] = p2[a] - p0[a];
+            p0[a] = q0[a];
+            e1[a] = q1[a] - q0[a];  // the f32 edges of the intersection test
+            e2[a] = q2[a] - q0[a];
         }
-    } else {
-        for (int a = 0; a < 3; a++) r.p0[a] = r.e1[a] = r.e2[a] = 0.0f;
     }
-    r.prim_id = (int32_t)t;
-    r.pad[0] = r.pad[1] = 0;
-    out[j] = r;
+    // the 48-B record as three 16-B stores
+    float4 *o = reinterpret_cast<float4 *>(out + j);
+    o[0] = make_float4(p0[0], p0[1], p0[2], e1[0]);
+    o[1] = make_float4(e1[1], e1[2], e2[0], e2[1]);
+    o[2] = make_float4(e2[2], __int_as_float((int)t), 0.0f, 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -2576,6 +2616,26 @@ int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, ui
     return BVH_OK;
 }
 
+// a2, a3: Morton keys of the box centres, then a stable LSD radix sort of
+// (key, primitive index), 8 bits per pass over the 3 * mbits key bits;
+// returns which of the two buffers holds the sorted pairs.
+template <typename KeyT>
+int sort_morton(const Box *pbox, uint32_t n, const BuildInfo *info, int mbits, KeyT **keys,
+                uint32_t **vals, uint32_t *hist, uint32_t nsort, hipStream_t s) {
+    const uint32_t nhist = nsort * kRadix;
+    k_morton<<<grid_for(n), kBlock, 0, s>>>(pbox, n, info, mbits, keys[0], vals[0]);
+    int cur = 0;
+    for (int shift = 0; shift < 3 * mbits; shift += 8) {
+        k_radix_hist<<<nsort, kBlock, 0, s>>>(keys[cur], n, shift, hist, nsort);
+        k_radix_offsets<<<kRadix, kBlock, 0, s>>>(hist, nsort, hist + nhist);
+        k_radix_scatter<<<nsort, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1],
+                                                 vals[cur ^ 1], n, shift, hist, hist + nhist,
+                                                 nsort);
+        cur ^= 1;
+    }
+    return cur;
+}
+
 int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                    bvh_handle_s *h, hipStream_t s) {
     const int n = (int)n_tris;
@@ -2668,27 +2728,30 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         perm = vals[0];
         BVH_TRY(leaf_data_early());
     } else {
+        // a2, a3: keys of 3 * mbits bits, in 32-bit words when they fit
+        // (the key buffers hold 64-bit words either way)
         const int mbits = morton_bits(n);
-        k_morton<<<nb, kBlock, 0, s>>>(pbox, n, info, mbits, keys[0], vals[0]);
-        BVH_TRY(check_launch("bounds/morton"));
-        // a3: 8 passes of 8 bits
+        const bool narrow = 3 * mbits <= 32;
+        uint32_t *k32[2] = {reinterpret_cast<uint32_t *>(keys[0]),
+                            reinterpret_cast<uint32_t *>(keys[1])};
         int cur = 0;
-        for (int shift = 0; shift < 3 * mbits; shift += 8) {
-            k_radix_hist<<<nsort, kBlock, 0, s>>>(keys[cur], n, shift, hist, nsort);
-            k_radix_offsets<<<kRadix, kBlock, 0, s>>>(hist, nsort, hist + nhist);
-            k_radix_scatter<<<nsort, kBlock, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1],
-                                                     vals[cur ^ 1], n, shift, hist, hist + nhist,
-                                                     nsort);
-            cur ^= 1;
-        }
-        BVH_TRY(check_launch("radix sort"));
+        if (narrow)
+            cur = sort_morton(pbox, (uint32_t)n, info, mbits, k32, vals, hist, nsort, s);
+        else
+            cur = sort_morton(pbox, (uint32_t)n, info, mbits, keys, vals, hist, nsort, s);
+        BVH_TRY(check_launch("morton/radix sort"));
         perm = vals[cur];
         BVH_TRY(leaf_data_early());
 
         // a4
-        if (n > 1)
-            k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst, icount,
-                                                        iaxis, parent);
+        if (n > 1) {
+            if (narrow)
+                k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(k32[cur], n, ileft, iright, ifirst,
+                                                            icount, iaxis, parent);
+            else
+                k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst,
+                                                            icount, iaxis, parent);
+        }
     }
     {  // a5
         k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table, pre, suf);

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
     using Tr = typename TracerFor<Layout>::type;
     __shared__ uint32_t s_ref[SL * kTraceBlock];
     __shared__ float s_t[(Tr::kWithT ? SL : 1) * kTraceBlock];
-    const uint32_t lane = threadIdx.x & 63u;
+    __shared__ WaveLeafLds s_wl[Tr::kBatchLeaves ? kWavesPerBlock : 1];
+    WaveLeafLds *wl = &s_wl[Tr::kBatchLeaves ? (threadIdx.x >> 6) : 0];
     SpillStack<Tr::kWithT, SL> st(s_ref, s_t, sa);
     uint32_t ray = kNoRay;
     Ray r{};
@@ -133,16 +134,21 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
             if (drained && pool == pool_end) break;
             continue;
         }
-        // computed by every lane (converged), so the value stays wave-uniform
+        // computed by every lane (converged), so the values stay wave-uniform
         coherent = rays_share_octant(r, ray != kNoRay, busy);
-        if (ray != kNoRay) {
-            const bool fast = wave_fast(r);
-            if (coherent)
+        const bool fast = __builtin_amdgcn_ballot_w64(ray != kNoRay && !r.fast) == 0;
+        if (coherent) {
+            if (ray != kNoRay)
                 Tr::template round<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
                                                    nfetch, ntri, incomplete);
-            else
-                Tr::template step<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
-                                                  nfetch, ntri, incomplete);
+        } else if constexpr (Tr::kBatchLeaves) {
+            Tr::template step_wave<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
+                                                   ray != kNoRay, wl, nfetch, ntri, incomplete);
+        } else if (ray != kNoRay) {
+            Tr::template step<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts, nfetch,
+                                              ntri, incomplete);
+        }
+        if (ray != kNoRay) {
             if (Tr::done(ts)) {
                 if (incomplete) {
                     fallback_append(fb, ray);
@@ -160,8 +166,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
 }
 
 // Fallback pass: a small fixed grid re-traces the listed rays from the root
-// with a deep stack in global memory.  Launched after every fast pass; it
-// exits at once when the list is empty.
+// with a deep stack in global memory (one stack per thread of the grid).
+// Launched after every fast pass; it exits at once when the list is empty.
 template <int Layout, int LeafMode, int Mode, bool Count>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_fallback(const void *nodes, int64_t n_nodes,
                                                                 SceneData ld, const bvh_ray *rays,
@@ -169,8 +175,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_fallback(const void *node
                                                                 Fallback fb) {
     using Tr = typename TracerFor<Layout>::type;
     const uint32_t lane = blockIdx.x * kTraceBlock + threadIdx.x;
+    const uint32_t lanes = gridDim.x * kTraceBlock;
     const uint32_t total = *fb.count;
-    for (uint32_t k = lane; k < total; k += kFallbackLanes) {
+    for (uint32_t k = lane; k < total; k += lanes) {
         const uint32_t i = fb.list[k];
         const Ray r = load_ray(rays, i, ld.coord_max);
         uint32_t nfetch = 0, ntri = 0;
@@ -268,10 +275,25 @@ int32_t launch_slab(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *r
 
 constexpr bool kPersistent = true;
 
+// Fallback grid of a launch that brings its own (fixed-size) work area.
+constexpr int kFixedFallbackBlocks = 16;
+
+// fixed: when non-null, the launch uses this work area: one ray per lane with
+// the LDS stack only, overflowing rays re-traced by a fallback grid of
+// kFixedFallbackBlocks blocks.  Otherwise the area comes
+// from the stream's grow-only work area and the persistent kernel runs.
 template <int Layout, int LeafMode, int Mode, bool Count, int SL>
 int32_t launch_layout(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *rays, uint64_t n,
-                      bvh_hit *hits, uint32_t *counts, hipStream_t s) {
+                      bvh_hit *hits, uint32_t *counts, const Fallback *fixed, hipStream_t s) {
     const uint64_t need = (n + kTraceBlock - 1) / kTraceBlock;
+    if (fixed) {
+        k_trace<Layout, LeafMode, Mode, Count, SL><<<(unsigned)need, kTraceBlock, 0, s>>>(
+            h->nodes, h->n_nodes, ld, rays, n, hits, counts, *fixed);
+        k_trace_fallback<Layout, LeafMode, Mode, Count>
+            <<<kFixedFallbackBlocks, kTraceBlock, 0, s>>>(h->nodes, h->n_nodes, ld, rays, hits,
+                                                           counts, *fixed);
+        return BVH_OK;
+    }
     TraceArea ta;
     if (kPersistent) {
         auto kernel = k_trace_persist<Layout, LeafMode, Mode, Count, SL>;
@@ -293,51 +315,52 @@ int32_t launch_layout(const bvh_handle_s *h, const SceneData &ld, const bvh_ray 
 
 template <int LeafMode, int Mode, bool Count, int SL>
 int32_t launch_sl(const bvh_handle_s *h, const SceneData &ld, const bvh_ray *rays, uint64_t n,
-                  bvh_hit *hits, uint32_t *counts, hipStream_t s) {
+                  bvh_hit *hits, uint32_t *counts, const Fallback *fixed, hipStream_t s) {
     switch (h->layout) {
         case BVH_LAYOUT_AABB2:
             return launch_layout<BVH_LAYOUT_AABB2, LeafMode, Mode, Count, SL>(h, ld, rays, n, hits,
-                                                                             counts, s);
+                                                                             counts, fixed, s);
         case BVH_LAYOUT_BVH4:
             return launch_layout<BVH_LAYOUT_BVH4, LeafMode, Mode, Count, SL>(h, ld, rays, n, hits,
-                                                                            counts, s);
+                                                                            counts, fixed, s);
         case BVH_LAYOUT_BVH8_Q8:
             return launch_layout<BVH_LAYOUT_BVH8_Q8, LeafMode, Mode, Count, SL>(h, ld, rays, n,
-                                                                               hits, counts, s);
+                                                                               hits, counts, fixed, s);
         case BVH_LAYOUT_PBRT_Q16:
             return launch_layout<BVH_LAYOUT_PBRT_Q16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
-                                                                                hits, counts, s);
+                                                                                hits, counts, fixed, s);
         case BVH_LAYOUT_SG_EQ:
             return launch_layout<BVH_LAYOUT_SG_EQ, LeafMode, Mode, Count, SL>(h, ld, rays, n, hits,
-                                                                             counts, s);
+                                                                             counts, fixed, s);
         case BVH_LAYOUT_PBRT_SOAOS:
             return launch_layout<BVH_LAYOUT_PBRT_SOAOS, LeafMode, Mode, Count, SL>(h, ld, rays, n,
-                                                                                  hits, counts, s);
+                                                                                  hits, counts, fixed, s);
         case BVH_LAYOUT_PBRT_Q16_SOAOS:
             return launch_layout<BVH_LAYOUT_PBRT_Q16_SOAOS, LeafMode, Mode, Count, SL>(
-                h, ld, rays, n, hits, counts, s);
+                h, ld, rays, n, hits, counts, fixed, s);
         case BVH_LAYOUT_SG_EQ_A16:
             return launch_layout<BVH_LAYOUT_SG_EQ_A16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
-                                                                                 hits, counts, s);
+                                                                                 hits, counts, fixed, s);
         default:
             return launch_layout<BVH_LAYOUT_BVH8_Q16, LeafMode, Mode, Count, SL>(h, ld, rays, n,
-                                                                                hits, counts, s);
+                                                                                hits, counts, fixed, s);
     }
 }
 
 template <int LeafMode, int Mode, bool Count>
 int32_t launch_mode(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits,
-                    uint32_t *counts, hipStream_t s) {
+                    uint32_t *counts, const Fallback *fixed, hipStream_t s) {
     const SceneData ld = scene_data(h);
     int32_t rc;
     if (h->layout == BVH_LAYOUT_SHARED_SLAB)
-        rc = launch_slab<LeafMode, Mode, Count>(h, ld, rays, n, hits, counts, s);
+        rc = fixed ? set_error(BVH_EUNSUPPORTED, "shared-slab layout needs a carried-box stack area")
+                   : launch_slab<LeafMode, Mode, Count>(h, ld, rays, n, hits, counts, s);
     else if (h->stack_lds == 8)
-        rc = launch_sl<LeafMode, Mode, Count, 8>(h, ld, rays, n, hits, counts, s);
+        rc = launch_sl<LeafMode, Mode, Count, 8>(h, ld, rays, n, hits, counts, fixed, s);
     else if (h->stack_lds == 32)
-        rc = launch_sl<LeafMode, Mode, Count, 32>(h, ld, rays, n, hits, counts, s);
+        rc = launch_sl<LeafMode, Mode, Count, 32>(h, ld, rays, n, hits, counts, fixed, s);
     else
-        rc = launch_sl<LeafMode, Mode, Count, 16>(h, ld, rays, n, hits, counts, s);
+        rc = launch_sl<LeafMode, Mode, Count, 16>(h, ld, rays, n, hits, counts, fixed, s);
     if (rc != BVH_OK) return rc;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(BVH_EHIP, "bvh_trace: launch failed: %s", hipGetErrorString(e));
@@ -346,14 +369,18 @@ int32_t launch_mode(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_
 
 template <bool Count>
 int32_t launch(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *hits, int32_t mode,
-               uint32_t *counts, hipStream_t s) {
+               uint32_t *counts, hipStream_t s, const Fallback *fixed = nullptr) {
     if (h->leaf_mode == BVH_LEAF_COMPACT)
         return mode == BVH_TRACE_ANY
-                   ? launch_mode<BVH_LEAF_COMPACT, BVH_TRACE_ANY, Count>(h, rays, n, hits, counts, s)
-                   : launch_mode<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST, Count>(h, rays, n, hits, counts, s);
+                   ? launch_mode<BVH_LEAF_COMPACT, BVH_TRACE_ANY, Count>(h, rays, n, hits, counts,
+                                                                         fixed, s)
+                   : launch_mode<BVH_LEAF_COMPACT, BVH_TRACE_CLOSEST, Count>(h, rays, n, hits,
+                                                                             counts, fixed, s);
     return mode == BVH_TRACE_ANY
-               ? launch_mode<BVH_LEAF_INDEXED, BVH_TRACE_ANY, Count>(h, rays, n, hits, counts, s)
-               : launch_mode<BVH_LEAF_INDEXED, BVH_TRACE_CLOSEST, Count>(h, rays, n, hits, counts, s);
+               ? launch_mode<BVH_LEAF_INDEXED, BVH_TRACE_ANY, Count>(h, rays, n, hits, counts,
+                                                                     fixed, s)
+               : launch_mode<BVH_LEAF_INDEXED, BVH_TRACE_CLOSEST, Count>(h, rays, n, hits, counts,
+                                                                         fixed, s);
 }
 
 int32_t validate(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit *hits, int32_t mode,

@@ -298,6 +298,123 @@ __device__ inline bool test_leaf(const SceneData &ld, const Ray &r, uint32_t fir
 }
 
 // ---------------------------------------------------------------------------
+// Wave-level leaf batching: the lanes of a wave that hold a leaf to test
+// publish its triangles, and the wave tests the (ray, triangle) pairs one per
+// lane, so a leaf phase costs one triangle test per 64 pairs instead of one
+// per triangle of the largest leaf.  Per round of up to 64 pairs:
+//   * pair slots are assigned by an exclusive prefix sum of the leaf sizes
+//     over the lanes (five ballots: leaf sizes are below 32);
+//   * each leaf lane writes its lane number into the slots of its pairs (an
+//     LDS table), each pair lane reads its owner and fetches the owner's ray
+//     and leaf start from the owner's registers (ds_bpermute);
+//   * hits are reduced per owner with an LDS 64-bit minimum of
+//     (t bits << 32 | primitive id): t > 0, so the bits order like the
+//     values, and the minimum is the (t, id) lexicographic best; the lane
+//     holding that pair then stores its (u, v) for the owner.
+// The arithmetic of each test is exactly that of test_leaf, so the hits are
+// the same bits.
+// ---------------------------------------------------------------------------
+struct WaveLeafLds {
+    unsigned long long key[64];  // per owner lane: best (t bits, id) of the round
+    float2 uv[64];               // per owner lane: (u, v) of that best
+    uint32_t owner[64];          // per pair slot of the round: owner lane
+};
+constexpr int kWavesPerBlock = kTraceBlock / 64;
+
+// Orders the calling wave's LDS accesses on either side (a wave executes
+// its LDS instructions in order; this keeps the compiler from moving them).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Set bits of m below the calling lane.
+__device__ inline uint32_t count_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline float lane_f(float x, uint32_t src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((int)(src << 2), __float_as_int(x)));
+}
+__device__ inline uint32_t lane_u(uint32_t x, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)x);
+}
+
+// Called by every lane of the wave (converged).  Lanes with `want` set test
+// triangles [first, first + cnt) of the leaf order against their ray; their
+// best is updated and their triangle counter advanced.  Returns true in a
+// want lane whose any-hit query was satisfied.
+template <int LeafMode, int Mode>
+__device__ inline bool wave_test_leaves(const SceneData &ld, const Ray &r, bool want,
+                                        uint32_t first, uint32_t cnt, Best &best, uint32_t &ntri,
+                                        WaveLeafLds *wl) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t c = want ? cnt : 0u;
+    uint32_t pre = 0, total = 0;
+#pragma unroll
+    for (int b = 0; b < 5; b++) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(((c >> b) & 1u) != 0u);
+        pre += count_below(m) << b;
+        total += (uint32_t)__builtin_popcountll(m) << b;
+    }
+    if (total == 0) return false;
+    ntri += c;
+    bool ended = false;
+    for (uint32_t base = 0; base < total; base += 64u) {
+        if (want) {
+            const uint32_t lo = pre > base ? pre : base;
+            const uint32_t hi = min(pre + c, base + 64u);
+            for (uint32_t q = lo; q < hi; q++) wl->owner[q - base] = lane;
+        }
+        wl->key[lane] = ~0ull;
+        wave_lds_sync();
+        const uint32_t pair = base + lane;
+        const bool act = pair < total;
+        const uint32_t o = act ? wl->owner[lane] : lane;
+        Ray ro;
+        ro.ox = lane_f(r.ox, o); ro.oy = lane_f(r.oy, o); ro.oz = lane_f(r.oz, o);
+        ro.dx = lane_f(r.dx, o); ro.dy = lane_f(r.dy, o); ro.dz = lane_f(r.dz, o);
+        ro.tmax = lane_f(r.tmax, o);
+        const uint32_t k = lane_u(first, o) + (pair - lane_u(pre, o));
+        bool hit = false;
+        float t = 0.0f, u = 0.0f, v = 0.0f;
+        uint32_t id = 0;
+        if (act && k < ld.n_tris) {  // bounds guard; a valid tree never fails it
+            if (LeafMode == BVH_LEAF_COMPACT) {
+                const float4 *p = static_cast<const float4 *>(ld.leaf) + 3 * (size_t)k;
+                const float4 a = p[0], b = p[1];
+                const float2 cc = *reinterpret_cast<const float2 *>(p + 2);
+                hit = mt_edges(ro, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, cc.x, t, u, v);
+                id = __float_as_uint(cc.y);
+            } else {
+                id = (uint32_t) static_cast<const int32_t *>(ld.leaf)[k];
+                const int32_t *tv = ld.tris + 3 * (size_t)id;
+                const float *a = ld.verts + 3 * (size_t)tv[0];
+                const float *b = ld.verts + 3 * (size_t)tv[1];
+                const float *cv = ld.verts + 3 * (size_t)tv[2];
+                hit = mt(ro, a[0], a[1], a[2], b[0], b[1], b[2], cv[0], cv[1], cv[2], t, u, v);
+            }
+        }
+        const unsigned long long mine = ((unsigned long long)__float_as_uint(t) << 32) | id;
+        if (hit) atomicMin(&wl->key[o], mine);
+        wave_lds_sync();
+        if (hit && wl->key[o] == mine) wl->uv[o] = make_float2(u, v);
+        wave_lds_sync();
+        if (want) {
+            const unsigned long long kb = wl->key[lane];
+            if (kb != ~0ull) {
+                const float2 q = wl->uv[lane];
+                consider(best, __uint_as_float((uint32_t)(kb >> 32)), q.x, q.y, (uint32_t)kb);
+                if (Mode == BVH_TRACE_ANY) ended = true;
+            }
+        }
+        wave_lds_sync();
+    }
+    return ended;
+}
+
+// ---------------------------------------------------------------------------
 // Traversal stacks.  The fast path keeps SL entries per lane in LDS (one
 // column per lane, so lanes never share a bank) and has no overflow area: a
 // push beyond SL fails, the ray stops and is re-traced by the fallback pass,
@@ -984,11 +1101,15 @@ __device__ inline void wide_round_two_phase(const void *nodes, int64_t n_nodes,
 //   Prep prep(ray)      per-ray layout constants
 //   State start(nodes)  initial state;  done(state);  best(state)
 //   step<LeafMode, Mode>(...)   one node or leaf of the single-loop order
+//   kBatchLeaves, step_wave<LeafMode, Mode>(...)   (wide layouts) one node and
+//                       one wave-batched leaf test of the single-loop order
 //   round<LeafMode, Mode>(...)  one round of the two-phase order (wave-wide)
 // ---------------------------------------------------------------------------
 template <class Dec>
 struct WideTracer {
     static constexpr bool kWithT = true;
+    // incoherent waves batch their leaf tests across the wave (step_wave)
+    static constexpr bool kBatchLeaves = true;
     using State = WideState;
     using Prep = typename Dec::Prep;
     __device__ static Prep prep(const Ray &r) { return Dec::prep(r); }
@@ -1008,11 +1129,40 @@ struct WideTracer {
         wide_round_two_phase<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s,
                                                   nfetch, ntri, incomplete);
     }
+    // single-loop order with wave-level leaf batching (called by every lane
+    // of the wave; `active` lanes have a ray): an interior node is visited,
+    // then every lane whose entry is a leaf takes part in one batched leaf
+    // test and moves on to its next unculled stack entry.
+    template <int LeafMode, int Mode, class Stack>
+    __device__ static void step_wave(const void *nodes, int64_t n_nodes, const SceneData &ld,
+                                     const Ray &r, const Prep &prep, bool fast, Stack &st,
+                                     State &s, bool active, WaveLeafLds *wl, uint32_t &nfetch,
+                                     uint32_t &ntri, bool &incomplete) {
+        if (active && s.cur != kRefEmpty && (s.cur & 1u))
+            wide_visit_interior<Dec, Mode>(nodes, n_nodes, r, prep, fast, st, s, nfetch,
+                                           incomplete);
+        const bool want = active && s.cur != kRefEmpty && !(s.cur & 1u);
+        const uint32_t first = s.cur >> 5, cnt = ((s.cur >> 1) & 0xFu) + 1u;
+        const bool ended =
+            wave_test_leaves<LeafMode, Mode>(ld, r, want, first, cnt, s.best, ntri, wl);
+        if (want) {
+            if (ended) {
+                s.cur = kRefEmpty;
+                s.leaf = kRefEmpty;
+            } else {
+                s.cur = pop_unculled(st, best_bound<Mode>(r, s.best), s.cur_t);
+            }
+        }
+    }
 };
 
 template <class Node>
 struct BinTracer {
     static constexpr bool kWithT = false;
+    // a binary node visit is one box test, so a batched leaf phase per visit
+    // costs more than it saves (measured 3-5 % slower on incoherent rays):
+    // incoherent waves use the per-lane step
+    static constexpr bool kBatchLeaves = false;
     using State = BinState;
     struct Prep {};
     __device__ static Prep prep(const Ray &) { return Prep{}; }
@@ -1151,12 +1301,14 @@ struct Fallback {
 // Bytes of the header (counter line, queue lines) that must be zero before a launch.
 constexpr size_t kFallbackHeaderBytes = kQueueStride * (1 + kQueues);
 
-inline size_t fallback_bytes(uint64_t n_rays) {
-    return kFallbackHeaderBytes + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 8;
+// Bytes of a work area for n_rays rays and `lanes` fallback lanes (the
+// fallback grid's threads).
+constexpr size_t fallback_bytes(uint64_t n_rays, size_t lanes = kFallbackLanes) {
+    return kFallbackHeaderBytes + n_rays * 4 + lanes * kStackMax * 8;
 }
 
-// Carves the work area out of one allocation of fallback_bytes(n_rays).
-inline Fallback fallback_view(void *base, uint64_t n_rays) {
+// Carves the work area out of one allocation of fallback_bytes(n_rays, lanes).
+inline Fallback fallback_view(void *base, uint64_t n_rays, size_t lanes = kFallbackLanes) {
     char *p = static_cast<char *>(base);
     Fallback f;
     f.count = reinterpret_cast<uint32_t *>(p);
@@ -1164,7 +1316,7 @@ inline Fallback fallback_view(void *base, uint64_t n_rays) {
     char *q = p + kFallbackHeaderBytes;
     f.list = reinterpret_cast<uint32_t *>(q);
     f.stack_ref = reinterpret_cast<uint32_t *>(q + n_rays * 4);
-    f.stack_t = reinterpret_cast<float *>(q + n_rays * 4 + (size_t)kFallbackLanes * kStackMax * 4);
+    f.stack_t = reinterpret_cast<float *>(q + n_rays * 4 + lanes * kStackMax * 4);
     return f;
 }
 
