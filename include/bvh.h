@@ -379,6 +379,27 @@ int32_t bvh_trace(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit *hits,
                   void *stream);
 
 /*
+ * bvh_trace for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same hits as bvh_trace, and no call here allocates or frees memory.  The
+ * work area (fallback-pass header, list and deep stacks) is a fixed array of
+ * 16 MiB + 2,304 B in device memory, one per GPU, held from the library's
+ * first use of that GPU until the process ends; each call clears its header
+ * with a small kernel before tracing.  Every call on one GPU uses that GPU's
+ * array, so calls that overlap in time on one GPU (different streams or host
+ * threads) race and give undefined results: serialise them.  Rays run one
+ * per lane with the handle's LDS stack; rays that outgrow it are re-traced
+ * with a deep stack, as in bvh_trace.
+ *   rays  device, n records;  hits  device, n records (written)
+ * Errors: as bvh_trace, plus EINVAL for n > BVH_NOALLOC_MAX_RAYS and
+ * EUNSUPPORTED for the SHARED_SLAB layout (its carried-box stacks do not fit
+ * the fixed area).
+ */
+#define BVH_NOALLOC_MAX_RAYS 2097152
+int32_t bvh_trace_noalloc(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit *hits,
+                          int32_t mode, void *stream);
+
+/*
  * bvh_trace plus per-ray work counters, for measurement: counts[2i] = node
  * records fetched, counts[2i+1] = triangles tested.  Same hits as bvh_trace.
  *   counts  device, 2n uint32 (written)

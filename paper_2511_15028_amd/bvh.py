@@ -26,6 +26,7 @@ LAYOUT_NAMES = {v: k for k, v in LAYOUTS.items()}
 LEAF_COMPACT, LEAF_INDEXED = 0, 1
 LEAF_MODES = {"compact": LEAF_COMPACT, "indexed": LEAF_INDEXED}
 TRACE_CLOSEST, TRACE_ANY = 0, 1
+NOALLOC_MAX_RAYS = 1 << 21  # BVH_NOALLOC_MAX_RAYS
 BUF_NODES, BUF_LEAF = 0, 1
 NODE_BYTES = {LAYOUT_AABB2: 32, LAYOUT_BVH4: 128, LAYOUT_BVH8_Q8: 128, LAYOUT_BVH8_Q16: 160,
               LAYOUT_PBRT_Q16: 16, LAYOUT_SG_EQ: 12, LAYOUT_PBRT_SOAOS: 32,
@@ -107,6 +108,8 @@ def lib() -> ctypes.CDLL:
         L.bvh_read_buffer.restype = _I32
         L.bvh_trace.argtypes = [_P, _P, _I64, _P, _I32, _P]
         L.bvh_trace.restype = _I32
+        L.bvh_trace_noalloc.argtypes = [_P, _P, _I64, _P, _I32, _P]
+        L.bvh_trace_noalloc.restype = _I32
         L.bvh_trace_counts.argtypes = [_P, _P, _I64, _P, _I32, _P, _P]
         L.bvh_trace_counts.restype = _I32
         L.bvh_closest_point.argtypes = [_P, _P, _I64, _P, _P]
@@ -204,6 +207,19 @@ class BVH:
             hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
         _dev(hits, torch.float32, 4, "hits")
         _check(lib().bvh_trace(self._h, rays.data_ptr(), n, hits.data_ptr(), mode, _stream(stream)))
+        return hits
+
+    def trace_noalloc(self, rays: torch.Tensor, hits: torch.Tensor, mode: int = TRACE_CLOSEST,
+                      stream=None) -> torch.Tensor:
+        """bvh_trace_noalloc: like trace, into a caller-provided hits [n,4]
+        tensor, with the library's fixed per-GPU work area (at most
+        NOALLOC_MAX_RAYS rays; calls on one GPU must not overlap)."""
+        _dev(rays, torch.float32, 8, "rays")
+        _dev(hits, torch.float32, 4, "hits")
+        if hits.shape[0] != rays.shape[0]:
+            raise ValueError("hits must have one row per ray")
+        _check(lib().bvh_trace_noalloc(self._h, rays.data_ptr(), rays.shape[0], hits.data_ptr(),
+                                       mode, _stream(stream)))
         return hits
 
     def trace_counts(self, rays: torch.Tensor, mode: int = TRACE_CLOSEST, stream=None):

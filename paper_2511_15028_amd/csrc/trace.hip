@@ -1,6 +1,7 @@
 // Per-scene closest-hit / any-hit traversal kernels (one ray per lane) and
 // the bvh_trace / bvh_trace_counts entry points.
 #include <algorithm>
+#include <mutex>
 
 #include "traverse.h"
 
@@ -278,6 +279,15 @@ constexpr bool kPersistent = true;
 // Fallback grid of a launch that brings its own (fixed-size) work area.
 constexpr int kFixedFallbackBlocks = 16;
 
+// Work area of bvh_trace_noalloc: a file-scope device array (one copy per
+// GPU, kept until the process ends) holding the fallback header, a list of
+// up to kNoAllocMaxRays ray indices and the deep stacks of a fallback grid of
+// kFixedFallbackBlocks blocks: 16 MiB + 2,304 B.
+constexpr uint64_t kNoAllocMaxRays = uint64_t(1) << 21;
+constexpr size_t kNoAllocScratchBytes =
+    fallback_bytes(kNoAllocMaxRays, (size_t)kFixedFallbackBlocks * kTraceBlock);
+static_assert(kNoAllocMaxRays == BVH_NOALLOC_MAX_RAYS, "bvh.h states the limit");
+
 // fixed: when non-null, the launch uses this work area: one ray per lane with
 // the LDS stack only, overflowing rays re-traced by a fallback grid of
 // kFixedFallbackBlocks blocks.  Otherwise the area comes
@@ -383,6 +393,42 @@ int32_t launch(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh_hit *
                                                                          fixed, s);
 }
 
+// ---------------------------------------------------------------------------
+// bvh_trace_noalloc's work area.  In host code `scratch` names a host-side
+// stand-in, not device memory: the kernels get the device address that
+// hipGetSymbolAddress returns, looked up once per device (with that device
+// current) and kept.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(BVH_EUNSUPPORTED, "bvh_trace_noalloc: device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_error(BVH_EHIP, "bvh_trace_noalloc: hipGetSymbolAddress: %s",
+                             hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BVH_OK;
+}
+
+// Clears the first n words at p (the fallback header): a kernel rather than
+// a memset node, so that the call can be captured into a graph.
+__global__ __launch_bounds__(kTraceBlock) void k_zero_words(uint32_t *p, uint32_t n) {
+    for (uint32_t k = threadIdx.x; k < n; k += kTraceBlock) p[k] = 0u;
+}
+
 int32_t validate(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit *hits, int32_t mode,
                  const char *who) {
     if (!h) return set_error(BVH_EINVAL, "%s: null handle", who);
@@ -421,6 +467,25 @@ extern "C" int32_t bvh_trace(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh
     if (n == 0) return BVH_OK;
     BVH_TRY(check_handle_device(h, "bvh_trace"));
     return launch<false>(h, rays, (uint64_t)n, hits, mode, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int32_t bvh_trace_noalloc(bvh_handle_t h, const bvh_ray *rays, int64_t n,
+                                     bvh_hit *hits, int32_t mode, void *stream) {
+    BVH_TRY(validate(h, rays, n, hits, mode, "bvh_trace_noalloc"));
+    if ((uint64_t)n > kNoAllocMaxRays)
+        return set_error(BVH_EINVAL, "bvh_trace_noalloc: %lld rays exceed the fixed work area's "
+                         "%llu", (long long)n, (unsigned long long)kNoAllocMaxRays);
+    if (h->layout == BVH_LAYOUT_SHARED_SLAB)
+        return set_error(BVH_EUNSUPPORTED, "bvh_trace_noalloc: shared-slab layout not supported");
+    if (n == 0) return BVH_OK;
+    BVH_TRY(check_handle_device(h, "bvh_trace_noalloc"));
+    void *ptr = nullptr;
+    BVH_TRY(scratch_address(h->device, &ptr));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const Fallback fb = fallback_view(ptr, (uint64_t)n, (size_t)kFixedFallbackBlocks * kTraceBlock);
+    k_zero_words<<<1, kTraceBlock, 0, s>>>(static_cast<uint32_t *>(ptr),
+                                            (uint32_t)(kFallbackHeaderBytes / 4));
+    return launch<false>(h, rays, (uint64_t)n, hits, mode, nullptr, s, &fb);
 }
 
 extern "C" int32_t bvh_trace_counts(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit *hits,
