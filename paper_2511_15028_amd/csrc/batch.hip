@@ -549,9 +549,7 @@ int32_t make_graph(bvh_batch_s *b, const bvh_ray *rays, const int64_t *offsets, 
             b->g_mem.push_back(spill);
         }
         SpillArea sa;
-        sa.ref = static_cast<uint32_t *>(spill);
-        sa.t = reinterpret_cast<float *>(static_cast<char *>(spill) +
-                                         (size_t)spill_lanes * kBatchSpillCap * 4);
+        sa.ent = static_cast<uint2 *>(spill);
         sa.lanes = lanes;
         sa.cap = kBatchSpillCap;
         void *args[] = {&d_sc, &d_toff, &nsc, (void *)&total, &ctr, &r, &hh, &fb, &sa};

@@ -143,8 +143,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persist(const void *nodes
                 Tr::template round<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
                                                    nfetch, ntri, incomplete);
         } else if constexpr (Tr::kBatchLeaves) {
-            Tr::template step_wave<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
-                                                   ray != kNoRay, wl, nfetch, ntri, incomplete);
+            Tr::template round_wave<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts,
+                                                    ray != kNoRay, wl, nfetch, ntri, incomplete);
         } else if (ray != kNoRay) {
             Tr::template step<LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, ts, nfetch,
                                               ntri, incomplete);

@@ -470,12 +470,14 @@ struct GlobalStack {
 // its oldest half to the spill area; when it is empty, a pop first brings the
 // newest spilled half back.  Entries [0, lo) live in the spill area, entries
 // [lo, sp) in the ring (entry e in slot e mod SL).  A push fails only when
-// the spill area (cap entries) is full.
+// the spill area (cap entries) is full.  A lane's spill entries are
+// contiguous (reference and entry distance side by side), so moving half a
+// ring writes or reads one run of SL/2 * 8 bytes (a 64-byte line for SL = 16)
+// instead of SL scattered words.
 struct SpillArea {
-    uint32_t *ref;    // [cap][lanes]
-    float *t;         // [cap][lanes]
+    uint2 *ent;       // [lanes][cap]: (reference, entry-distance bits)
     uint32_t lanes;   // lanes of the launch (the grid's threads)
-    uint32_t cap;     // spill entries per lane
+    uint32_t cap;     // spill entries per lane (a multiple of SL / 2)
 };
 
 template <bool WithT, int SL>
@@ -488,18 +490,17 @@ struct SpillStack {
     __device__ SpillStack(uint32_t *r, float *t, const SpillArea &a) : lds_ref(r), lds_t(t), area(a) {}
     __device__ void reset() { sp = lo = 0; }
     __device__ static uint32_t slot(uint32_t e) { return (e & (SL - 1)) * kTraceBlock + threadIdx.x; }
-    // this lane's column of the spill area: the lane's index in the grid
+    // entry e of this lane's spill run (the lane's index in the grid)
     __device__ size_t spill_index(uint32_t e) const {
-        return (size_t)e * area.lanes + blockIdx.x * kTraceBlock + threadIdx.x;
+        return ((size_t)blockIdx.x * kTraceBlock + threadIdx.x) * area.cap + e;
     }
     __device__ bool push(uint32_t ref, float t) {
         if (sp - lo == (uint32_t)SL) {
             constexpr uint32_t H = SL / 2;
             if (lo + H > area.cap) return false;
-            for (uint32_t e = lo; e < lo + H; e++) {
-                area.ref[spill_index(e)] = lds_ref[slot(e)];
-                if (WithT) area.t[spill_index(e)] = lds_t[slot(e)];
-            }
+            for (uint32_t e = lo; e < lo + H; e++)
+                area.ent[spill_index(e)] =
+                    make_uint2(lds_ref[slot(e)], WithT ? __float_as_uint(lds_t[slot(e)]) : 0u);
             lo += H;
         }
         lds_ref[slot(sp)] = ref;
@@ -511,8 +512,9 @@ struct SpillStack {
         if (sp == lo) {
             const uint32_t n = lo < (uint32_t)(SL / 2) ? lo : (uint32_t)(SL / 2);
             for (uint32_t e = lo - n; e < lo; e++) {
-                lds_ref[slot(e)] = area.ref[spill_index(e)];
-                if (WithT) lds_t[slot(e)] = area.t[spill_index(e)];
+                const uint2 x = area.ent[spill_index(e)];
+                lds_ref[slot(e)] = x.x;
+                if (WithT) lds_t[slot(e)] = __uint_as_float(x.y);
             }
             lo -= n;
         }
@@ -791,6 +793,11 @@ __device__ inline bool bin_test_leaf(const SceneData &ld, const Ray &r, uint32_t
 // first), so the per-child slab test needs no plane selects.
 struct DecodeBVH4 {
     static constexpr int K = 4;
+    // scattered waves end a round's interior phase at <= kStall progressing
+    // lanes (terrain bounce rays: 0.674 ms with the single-loop order and
+    // batched leaves; 0.616 / 0.600 / 0.577 / 0.559 / 0.563 / 0.585 / 0.646
+    // ms at 8 / 16 / 24 / 32 / 40 / 48 / 56)
+    static constexpr uint32_t kStall = 32;
     struct Prep {
         // byte offsets of the entry-plane arrays in a node; the exit-plane
         // array of an axis is the other one of the pair (lo_a, hi_a), at
@@ -845,6 +852,9 @@ struct SignPrep {
 
 struct DecodeBVH8Q8 {
     static constexpr int K = 8;
+    // as DecodeBVH4::kStall (terrain bounce rays: 0.668 ms single-loop;
+    // 0.705 / 0.653 / 0.620 / 0.632 / 0.665 ms at 16 / 32 / 40 / 48 / 56)
+    static constexpr uint32_t kStall = 40;
     using Prep = SignPrep;
     __device__ static Prep prep(const Ray &r) { return Prep{r.nx, r.ny, r.nz}; }
     template <bool Fast>
@@ -887,6 +897,7 @@ struct DecodeBVH8Q8 {
 
 struct DecodeBVH8Q16 {
     static constexpr int K = 8;
+    static constexpr uint32_t kStall = 40;  // 0.642 ms at 40 (0.688 single-loop)
     using Prep = SignPrep;
     __device__ static Prep prep(const Ray &r) { return Prep{r.nx, r.ny, r.nz}; }
     template <bool Fast>
@@ -1093,6 +1104,48 @@ __device__ inline void wide_round_two_phase(const void *nodes, int64_t n_nodes,
     }
 }
 
+// Two-phase round for scattered rays (called by every lane of the wave;
+// `active` lanes have a ray): lanes visit interior nodes and park the first
+// leaf they meet, continuing speculatively; a lane with a parked leaf whose
+// next entry is a leaf waits.  The interior phase ends once at most `stall`
+// lanes can still make progress (waiting for the last stragglers of an
+// incoherent wave would idle the rest), and the parked leaves are then
+// tested in one wave-batched leaf phase.  Nodes the best hit does not cull
+// are all visited, so the result equals the single-loop order's.
+template <class Dec, int LeafMode, int Mode, class Stack>
+__device__ inline void wide_round_wave(const void *nodes, int64_t n_nodes, const SceneData &ld,
+                                       const Ray &r, const typename Dec::Prep &prep, bool fast,
+                                       Stack &st, WideState &ws, bool active, WaveLeafLds *wl,
+                                       uint32_t stall, uint32_t &nfetch, uint32_t &ntri,
+                                       bool &incomplete) {
+    for (;;) {
+        if (active && ws.cur != kRefEmpty && (ws.cur & 1u))
+            wide_visit_interior<Dec, Mode>(nodes, n_nodes, r, prep, fast, st, ws, nfetch,
+                                           incomplete);
+        if (active && ws.cur != kRefEmpty && !(ws.cur & 1u) && ws.leaf == kRefEmpty) {
+            ws.leaf = ws.cur;
+            ws.cur = pop_unculled(st, best_bound<Mode>(r, ws.best), ws.cur_t);
+        }
+        const uint64_t prog = __builtin_amdgcn_ballot_w64(
+            active && ws.cur != kRefEmpty && ((ws.cur & 1u) || ws.leaf == kRefEmpty));
+        const uint64_t parked = __builtin_amdgcn_ballot_w64(active && ws.leaf != kRefEmpty);
+        if (prog == 0 || ((uint32_t)__builtin_popcountll(prog) <= stall && parked != 0)) break;
+    }
+    const bool want = active && ws.leaf != kRefEmpty;
+    const uint32_t first = ws.leaf >> 5, cnt = ((ws.leaf >> 1) & 0xFu) + 1u;
+    const bool ended = wave_test_leaves<LeafMode, Mode>(ld, r, want, first, cnt, ws.best, ntri, wl);
+    if (want) {
+        ws.leaf = kRefEmpty;
+        if (ended) {
+            ws.cur = kRefEmpty;
+        } else {
+            const float tb = best_bound<Mode>(r, ws.best);
+            if (ws.cur != kRefEmpty && !(ws.cur_t <= tb * kFarScale))
+                ws.cur = pop_unculled(st, tb, ws.cur_t);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Tracer policies: the per-layout state and steps behind one interface, so
 // the kernels (one ray per lane, persistent, fallback, batched) are written
@@ -1101,14 +1154,14 @@ __device__ inline void wide_round_two_phase(const void *nodes, int64_t n_nodes,
 //   Prep prep(ray)      per-ray layout constants
 //   State start(nodes)  initial state;  done(state);  best(state)
 //   step<LeafMode, Mode>(...)   one node or leaf of the single-loop order
-//   kBatchLeaves, step_wave<LeafMode, Mode>(...)   (wide layouts) one node and
-//                       one wave-batched leaf test of the single-loop order
+//   kBatchLeaves, round_wave<LeafMode, Mode>(...)   (wide layouts) one round
+//                       of the two-phase order with a wave-batched leaf phase
 //   round<LeafMode, Mode>(...)  one round of the two-phase order (wave-wide)
 // ---------------------------------------------------------------------------
 template <class Dec>
 struct WideTracer {
     static constexpr bool kWithT = true;
-    // incoherent waves batch their leaf tests across the wave (step_wave)
+    // scattered waves batch their leaf tests across the wave (round_wave)
     static constexpr bool kBatchLeaves = true;
     using State = WideState;
     using Prep = typename Dec::Prep;
@@ -1129,30 +1182,14 @@ struct WideTracer {
         wide_round_two_phase<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s,
                                                   nfetch, ntri, incomplete);
     }
-    // single-loop order with wave-level leaf batching (called by every lane
-    // of the wave; `active` lanes have a ray): an interior node is visited,
-    // then every lane whose entry is a leaf takes part in one batched leaf
-    // test and moves on to its next unculled stack entry.
+    // scattered waves: the two-phase round with a wave-batched leaf phase
     template <int LeafMode, int Mode, class Stack>
-    __device__ static void step_wave(const void *nodes, int64_t n_nodes, const SceneData &ld,
-                                     const Ray &r, const Prep &prep, bool fast, Stack &st,
-                                     State &s, bool active, WaveLeafLds *wl, uint32_t &nfetch,
-                                     uint32_t &ntri, bool &incomplete) {
-        if (active && s.cur != kRefEmpty && (s.cur & 1u))
-            wide_visit_interior<Dec, Mode>(nodes, n_nodes, r, prep, fast, st, s, nfetch,
-                                           incomplete);
-        const bool want = active && s.cur != kRefEmpty && !(s.cur & 1u);
-        const uint32_t first = s.cur >> 5, cnt = ((s.cur >> 1) & 0xFu) + 1u;
-        const bool ended =
-            wave_test_leaves<LeafMode, Mode>(ld, r, want, first, cnt, s.best, ntri, wl);
-        if (want) {
-            if (ended) {
-                s.cur = kRefEmpty;
-                s.leaf = kRefEmpty;
-            } else {
-                s.cur = pop_unculled(st, best_bound<Mode>(r, s.best), s.cur_t);
-            }
-        }
+    __device__ static void round_wave(const void *nodes, int64_t n_nodes, const SceneData &ld,
+                                      const Ray &r, const Prep &prep, bool fast, Stack &st,
+                                      State &s, bool active, WaveLeafLds *wl, uint32_t &nfetch,
+                                      uint32_t &ntri, bool &incomplete) {
+        wide_round_wave<Dec, LeafMode, Mode>(nodes, n_nodes, ld, r, prep, fast, st, s, active, wl,
+                                             Dec::kStall, nfetch, ntri, incomplete);
     }
 };
 
@@ -1461,8 +1498,7 @@ inline int32_t trace_area(hipStream_t s, uint64_t n, uint32_t lanes, TraceArea &
     BVH_TRY(stream_workspace(s, kAreaTrace, fb_bytes + sp_bytes, &ws));
     ta.fb = fallback_view(ws, n);
     char *sp = static_cast<char *>(ws) + fb_bytes;
-    ta.sa.ref = reinterpret_cast<uint32_t *>(sp);
-    ta.sa.t = reinterpret_cast<float *>(sp + (size_t)lanes * kSpillCap * 4);
+    ta.sa.ent = reinterpret_cast<uint2 *>(sp);
     ta.sa.lanes = lanes;
     ta.sa.cap = kSpillCap;
     BVH_HIP_TRY(hipMemsetAsync(ta.fb.count, 0, kFallbackHeaderBytes, s));
