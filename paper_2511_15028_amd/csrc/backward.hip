@@ -133,6 +133,244 @@ __global__ __launch_bounds__(kBlock) void k_backward(const float *verts, int64_t
     }
 }
 
+// ---------------------------------------------------------------------------
+// Vertex gradients without atomics.  Every ray contributes to three vertices,
+// and a vertex collects contributions from rays all over the ray array (for
+// the sphere-of-cameras workload, a 256-ray block reaches 1.26 distinct
+// vertices per ray, a whole camera still 0.82, against 0.16 overall), so
+// per-block pre-summing still leaves millions of scattered read-modify-write
+// updates, and device-scope float atomics on scattered addresses run at
+// about 20 G/s here.  Instead the contributions are partitioned by vertex
+// range and each range is summed in LDS by one workgroup:
+//   k_backward_part: a block of kPartRays rays computes each ray's gradient
+//     (grad_rays written as in k_backward) and its three (vertex, w lam)
+//     records, sorts the block's records by vertex range in LDS (counting
+//     sort over the ranges) and writes them, with the per-range offsets, to
+//     its own segment of a work area;
+//   k_backward_sum: one block per range of 2^shift vertices reads that
+//     range's records from every segment, sums them in a dense LDS
+//     accumulator and adds the sums to grad_verts (the range is its own, so
+//     plain loads and stores).
+// Ranges: shift in [8, 12] with at most kPartMaxRanges ranges, so up to
+// 2^22 vertices; larger meshes use k_backward.
+// ---------------------------------------------------------------------------
+constexpr int kPartThreads = 256;
+constexpr int kPartRaysPerThread = 4;
+constexpr int kPartRays = kPartThreads * kPartRaysPerThread;
+constexpr int kPartRecs = 3 * kPartRays;
+constexpr int kPartMaxRanges = 1024;
+constexpr int kPartMinShift = 8, kPartMaxShift = 12;
+constexpr int kSumThreads = 1024;
+
+struct VertRec {
+    int32_t v;
+    float g[3];
+};
+static_assert(sizeof(VertRec) == 16, "record");
+
+// Exclusive prefix sum over the block (THREADS threads) of one value per
+// thread; wsum holds THREADS / 64 words.
+template <int THREADS>
+__device__ inline uint32_t block_excl_scan_u32(uint32_t x, uint32_t *wsum, uint32_t *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < THREADS / 64; k++) {
+        const uint32_t s = wsum[k];
+        off += k < w ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - x;
+}
+
+__global__ __launch_bounds__(kPartThreads) void k_backward_part(
+    const float *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris, const bvh_ray *rays,
+    uint64_t n, const bvh_hit *hits, const float *grad_hits, float *grad_rays, int shift,
+    uint32_t n_ranges, VertRec *seg, uint32_t *offs) {
+    __shared__ uint32_t cnt[kPartMaxRanges];
+    __shared__ uint32_t wsum[kPartThreads / 64];
+    __shared__ VertRec sorted[kPartRecs];
+    for (uint32_t p = threadIdx.x; p < n_ranges; p += kPartThreads) cnt[p] = 0;
+    __syncthreads();
+    int32_t rv[kPartRecs / kPartThreads];
+    float rg[kPartRecs / kPartThreads][3];
+#pragma unroll
+    for (int k = 0; k < kPartRaysPerThread; k++) {
+        const uint64_t i = (uint64_t)blockIdx.x * kPartRays + k * kPartThreads + threadIdx.x;
+        float out[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, w[3] = {0.f, 0.f, 0.f};
+        float lam[3] = {0.f, 0.f, 0.f};
+        int32_t idx[3] = {0, 0, 0};
+        bool ok = false;
+        if (i < n) {
+            ok = ray_grad(verts, n_verts, tris, n_tris, rays, hits, grad_hits, i, out, idx, w, lam);
+            float *gr = grad_rays + 6 * i;
+            for (int c = 0; c < 6; c++) gr[c] = out[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            rv[3 * k + c] = ok ? idx[c] : -1;
+            rg[3 * k + c][0] = w[c] * lam[0];
+            rg[3 * k + c][1] = w[c] * lam[1];
+            rg[3 * k + c][2] = w[c] * lam[2];
+            if (ok) atomicAdd(&cnt[(uint32_t)idx[c] >> shift], 1u);
+        }
+    }
+    __syncthreads();
+    // exclusive offsets of the ranges; each thread scans a run of them
+    constexpr int kRun = kPartMaxRanges / kPartThreads;
+    uint32_t c[kRun], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kRun; k++) {
+        const uint32_t p = threadIdx.x * kRun + k;
+        c[k] = p < n_ranges ? cnt[p] : 0u;
+        sum += c[k];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan_u32<kPartThreads>(sum, wsum, &total);
+    // offsets range-major: offs[q * n_blocks + block], q = n_ranges holding
+    // the block's total, so the summing block of range q reads two
+    // contiguous rows
+    const size_t nbl = gridDim.x;
+#pragma unroll
+    for (int k = 0; k < kRun; k++) {
+        const uint32_t p = threadIdx.x * kRun + k;
+        if (p < n_ranges) {
+            offs[(size_t)p * nbl + blockIdx.x] = run;
+            cnt[p] = run;  // becomes the range's insertion cursor
+        }
+        run += c[k];
+    }
+    if (threadIdx.x == 0) offs[(size_t)n_ranges * nbl + blockIdx.x] = total;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPartRecs / kPartThreads; r++) {
+        if (rv[r] >= 0) {
+            const uint32_t pos = atomicAdd(&cnt[(uint32_t)rv[r] >> shift], 1u);
+            sorted[pos] = VertRec{rv[r], {rg[r][0], rg[r][1], rg[r][2]}};
+        }
+    }
+    __syncthreads();
+    float4 *dst = reinterpret_cast<float4 *>(seg + (size_t)blockIdx.x * kPartRecs);
+    const float4 *src = reinterpret_cast<const float4 *>(sorted);
+    for (uint32_t q = threadIdx.x; q < total; q += kPartThreads) dst[q] = src[q];
+}
+
+// One block per vertex range.  The range's records are spread over every
+// segment: the block first gathers each segment's record count for the range
+// (start offset and count, kSumMaxBlocks segments per pass) into LDS and
+// scans them, then walks the pass's records as one flat list (a binary
+// search over the scanned counts finds a record's segment), so every thread
+// has several independent record loads in flight instead of a chain per
+// segment.
+constexpr int kSumMaxBlocks = 2048;  // segments per pass
+constexpr int kSumUnroll = 4;
+
+__global__ __launch_bounds__(kSumThreads) void k_backward_sum(const VertRec *seg,
+                                                              const uint32_t *offs,
+                                                              uint32_t n_blocks, int shift,
+                                                              uint32_t n_ranges, int64_t n_verts,
+                                                              float *grad_verts) {
+    extern __shared__ float acc[];  // 3 * 2^shift floats (dynamic)
+    __shared__ uint32_t lo[kSumMaxBlocks];
+    __shared__ uint32_t start[kSumMaxBlocks + 1];
+    __shared__ uint32_t wsum[kSumThreads / 64];
+    const uint32_t p = blockIdx.x;
+    const uint32_t nv = 1u << shift;
+    const int64_t v0 = (int64_t)p << shift;
+    for (uint32_t q = threadIdx.x; q < 3 * nv; q += kSumThreads) acc[q] = 0.0f;
+    constexpr int kPer = kSumMaxBlocks / kSumThreads;
+    for (uint32_t b0 = 0; b0 < n_blocks; b0 += kSumMaxBlocks) {
+        const uint32_t nb = min((uint32_t)kSumMaxBlocks, n_blocks - b0);
+        // this thread's run of kPer segments: their starts and counts
+        uint32_t c[kPer], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const uint32_t j = k * kSumThreads + threadIdx.x;  // coalesced over the rows
+            uint32_t l = 0, h = 0;
+            if (j < nb) {
+                l = offs[(size_t)p * n_blocks + b0 + j];
+                h = min(offs[(size_t)(p + 1) * n_blocks + b0 + j], (uint32_t)kPartRecs);
+                h = h > l ? h : l;
+                lo[j] = l;
+            }
+            c[k] = h - l;
+        }
+        // segment j's start: scan over j (thread t's run is segments t*kPer..)
+        __syncthreads();
+        for (int k = 0; k < kPer; k++) {
+            const uint32_t j = k * kSumThreads + threadIdx.x;
+            start[j] = c[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            c[k] = start[threadIdx.x * kPer + k];
+            sum += c[k];
+        }
+        uint32_t total;
+        uint32_t run = block_excl_scan_u32<kSumThreads>(sum, wsum, &total);
+        __syncthreads();  // every count read before the starts overwrite them
+#pragma unroll
+        for (int k = 0; k < kPer; k++) {
+            const uint32_t j = threadIdx.x * kPer + k;
+            if (j < nb) start[j] = run;
+            run += c[k];
+        }
+        if (threadIdx.x == 0) start[nb] = total;
+        __syncthreads();
+        for (uint32_t q0 = 0; q0 < total; q0 += kSumThreads * kSumUnroll) {
+            float4 x[kSumUnroll];
+            bool ok[kSumUnroll];
+#pragma unroll
+            for (int u = 0; u < kSumUnroll; u++) {
+                const uint32_t q = q0 + u * kSumThreads + threadIdx.x;
+                ok[u] = q < total;
+                if (ok[u]) {
+                    // the segment j with start[j] <= q < start[j + 1]
+                    uint32_t a = 0, b = nb;
+                    while (b - a > 1) {
+                        const uint32_t m = (a + b) >> 1;
+                        if (start[m] <= q) a = m; else b = m;
+                    }
+                    const VertRec *rec = seg + (size_t)(b0 + a) * kPartRecs + lo[a] + (q - start[a]);
+                    x[u] = *reinterpret_cast<const float4 *>(rec);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kSumUnroll; u++) {
+                const uint32_t local = (uint32_t)(__float_as_int(x[u].x) - (int32_t)v0);
+                if (ok[u] && local < nv) {  // always in range for a consistent segment
+                    atomicAdd(&acc[3 * local + 0], x[u].y);
+                    atomicAdd(&acc[3 * local + 1], x[u].z);
+                    atomicAdd(&acc[3 * local + 2], x[u].w);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t cnt = min((int64_t)nv, n_verts - v0);
+    float *g = grad_verts + 3 * v0;
+    for (int64_t q = threadIdx.x; q < 3 * cnt; q += kSumThreads) g[q] += acc[q];
+}
+
+// Smallest range shift (within [kPartMinShift, kPartMaxShift]) that covers
+// n_verts with at most kPartMaxRanges ranges; -1 when none does.
+inline int part_shift(int64_t n_verts) {
+    for (int s = kPartMinShift; s <= kPartMaxShift; s++)
+        if (((n_verts + (int64_t(1) << s) - 1) >> s) <= kPartMaxRanges) return s;
+    return -1;
+}
+
 }  // namespace
 }  // namespace bvhlib
 
@@ -152,9 +390,27 @@ extern "C" int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const
     if (n == 0) return BVH_OK;
     if ((uint64_t)n > (uint64_t)0xFFFFFFFFu * kBlock)
         return set_error(BVH_EUNSUPPORTED, "bvh_trace_backward: too many rays");
-    const unsigned grid = (unsigned)(((uint64_t)n + kBlock - 1) / kBlock);
-    k_backward<<<grid, kBlock, 0, static_cast<hipStream_t>(stream)>>>(
-        verts, n_verts, tris, n_tris, rays, (uint64_t)n, hits, grad_hits, grad_verts, grad_rays);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int shift = part_shift(n_verts);
+    if (n_verts > 0 && shift >= 0) {
+        const uint32_t ranges = (uint32_t)((n_verts + (int64_t(1) << shift) - 1) >> shift);
+        const uint64_t blocks = ((uint64_t)n + kPartRays - 1) / kPartRays;
+        const size_t seg_bytes = (size_t)blocks * kPartRecs * sizeof(VertRec);
+        const size_t off_bytes = (size_t)blocks * (ranges + 1) * sizeof(uint32_t);
+        void *ws = nullptr;
+        BVH_TRY(stream_workspace(s, kAreaBackward, seg_bytes + off_bytes, &ws));
+        VertRec *seg = static_cast<VertRec *>(ws);
+        uint32_t *offs = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + seg_bytes);
+        k_backward_part<<<(unsigned)blocks, kPartThreads, 0, s>>>(
+            verts, n_verts, tris, n_tris, rays, (uint64_t)n, hits, grad_hits, grad_rays, shift,
+            ranges, seg, offs);
+        k_backward_sum<<<ranges, kSumThreads, (3u << shift) * sizeof(float), s>>>(
+            seg, offs, (uint32_t)blocks, shift, ranges, n_verts, grad_verts);
+    } else {
+        const unsigned grid = (unsigned)(((uint64_t)n + kBlock - 1) / kBlock);
+        k_backward<<<grid, kBlock, 0, s>>>(verts, n_verts, tris, n_tris, rays, (uint64_t)n, hits,
+                                           grad_hits, grad_verts, grad_rays);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return set_error(BVH_EHIP, "bvh_trace_backward: launch failed: %s", hipGetErrorString(e));

@@ -146,7 +146,14 @@ int32_t trace_launch(const bvh_handle_s *h, const bvh_ray *rays, uint64_t n, bvh
 // purpose), kept until the process ends.  Callers that use one stream from
 // several host threads must serialise those calls themselves.
 // ---------------------------------------------------------------------------
-enum AreaPurpose { kAreaBuild = 0, kAreaBuildWide = 1, kAreaTrace = 2, kAreaTune = 3, kAreaSah = 4 };
+enum AreaPurpose {
+    kAreaBuild = 0,
+    kAreaBuildWide = 1,
+    kAreaTrace = 2,
+    kAreaTune = 3,
+    kAreaSah = 4,
+    kAreaBackward = 5
+};
 int32_t stream_workspace(hipStream_t s, int purpose, size_t bytes, void **out);
 
 // Carves several device buffers out of one work area: request() them all,

@@ -22,7 +22,8 @@ is the FP32 solve of J^T lam = g and the FP32 accumulation:
   * grad_verts, per element: the sum over the rays that touch the vertex of
     |w| times the lam bound, plus the f32 rounding of w = (1-u)-v, plus
     gamma_K times the summed |w lam| for K float additions in any order
-    (the atomics), plus 1e-12; and 1e-5 relative L2 over the whole array.
+    (LDS or device atomics), plus 1e-12; and 1e-5 relative L2 over the
+    whole array.
 
 Barycentric rounding of the FP32 forward itself (why the gradient is taken at
 the FP32 hit): with u = U / det, the f32 numerators U, V, T carry an error of
@@ -204,3 +205,39 @@ def test_autograd_function(orc):
         assert (got[~hit] == 0).all()
     gvg = v.grad.cpu().numpy()
     assert np.linalg.norm(gvg - gv64) / np.linalg.norm(gv64) <= 1e-5
+
+
+def test_backward_accumulates_into_grad_verts(orc):
+    """grad_verts is accumulated (+=): a second call on the same array adds
+    the same gradient again, on top of arbitrary initial values."""
+    from paper_2511_15028_amd import bvh
+    w = W.diff_workload(level=4, n_cams=8, res=32)
+    p1, tuv1 = orc.brute_closest(w["verts"], w["tris"], w["rays"])
+    v, t, rays, wts = (dev(w[k]) for k in ("verts", "tris", "rays", "weights"))
+    hits = dev(_hits_array(p1, tuv1))
+    init = np.random.default_rng(3).uniform(-1, 1, w["verts"].shape).astype(np.float32)
+    gv = dev(init)
+    bvh.trace_backward(v, t, rays, hits, wts, grad_verts=gv)
+    bvh.trace_backward(v, t, rays, hits, wts, grad_verts=gv)
+    torch.cuda.synchronize()
+    got = gv.cpu().numpy().astype(np.float64) - init
+    gv64, _, _, vert_bound = _bounds(orc, w, p1, tuv1)
+    # each call's sum within its bound, plus the f32 rounding of the two
+    # read-modify-writes on top of init
+    tol = 2 * vert_bound + 4 * U32 * (np.abs(init) + 2 * np.abs(gv64))
+    assert (np.abs(got - 2 * gv64) <= tol).all()
+
+
+def test_backward_mesh_beyond_the_range_partition(orc):
+    """Meshes of more than 2^22 vertices take the per-block atomic path: the
+    small workload's vertex array padded past 2^22 entries (the padding is
+    not referenced) gives the same gradient, and zeros on the padding."""
+    w = W.diff_workload(level=4, n_cams=8, res=32)
+    p1, tuv1 = orc.brute_closest(w["verts"], w["tris"], w["rays"])
+    nv = len(w["verts"])
+    pad = np.zeros(((1 << 22) + 5, 3), np.float32)
+    pad[:nv] = w["verts"]
+    wp = dict(w, verts=pad)
+    gv, gr = _run(wp, _hits_array(p1, tuv1))
+    assert (gv[nv:] == 0).all()
+    _compare(orc, w, p1, tuv1, gv[:nv], gr)
