@@ -85,6 +85,10 @@ def parse():
     ap.add_argument("--leaf-size", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-layout table and fwd+bwd")
+    ap.add_argument("--layouts", default=",".join(LAYOUTS),
+                    help="layouts of the per_layout and spheres sections (comma-separated)")
+    ap.add_argument("--no-sah-rows", action="store_true",
+                    help="skip the SAH-tree rows of the spheres section")
     ap.add_argument("--sections", default="per_layout,sah,closest_point,fwd_bwd,spheres,batched",
                     help="comma-separated extra sections to run (default: all)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -375,7 +379,7 @@ def per_layout(torch, bvh, verts, tris, prim_rays, bounce_rays, args):
     fraction for every layout and leaf mode, camera (coherent) and bounce
     (incoherent) rays separately (median of 5 launches, events on the stream)."""
     res = {}
-    for layout in LAYOUTS:
+    for layout in args.layouts.split(","):
         for leaf_mode in ("compact", "indexed"):
             h = bvh.build(verts, tris, layout, args.leaf_size, leaf_mode)
             res[f"{layout}/{leaf_mode}"] = layout_row(
@@ -481,13 +485,13 @@ def spheres(torch, bvh, W, args, cpq=None):
     log(f"spheres workload: {w['tris'].shape[0]} tris ({time.time() - t0:.1f}s)")
     res = {"workload": f"{len(w['tris'])} tris (512 spheres + 100K slivers), {rays.shape[0]} "
                        "uniform closest-hit rays + as many shadow rays (any hit)"}
-    for layout in LAYOUTS:
+    for layout in args.layouts.split(","):
         h = bvh.build(verts, tris, layout, args.leaf_size, "compact")
         res[layout] = layout_row(torch, h, layout, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
                                                        ("shadow_any", shadow, bvh.TRACE_ANY)])
         h.close()
         log(f"spheres {layout}: {res[layout]}")
-    for layout in ("aabb2", "bvh4"):
+    for layout in () if args.no_sah_rows else ("aabb2", "bvh4"):
         build_ms = timed_build(torch, bvh, verts, tris, layout, args.leaf_size, "sah")
         h = bvh.build(verts, tris, layout, args.leaf_size, "compact", builder="sah")
         r = layout_row(torch, h, layout, "compact", [("closest", rays, bvh.TRACE_CLOSEST),
@@ -547,7 +551,9 @@ def batched(torch, bvh, W):
     """256 scenes of uneven size (1 K-500 K triangles, 1 K-1 M rays each):
     one graph launch of the per-variant persistent kernels vs 256 plain
     bvh_trace launches on one stream (same tuned BVHs), and vs plain launches
-    with one fixed layout.  BVH builds and tuning are excluded."""
+    with one fixed layout (the tuner's own gain).  The tuner probes with rays
+    generated on the device, not with the timed rays.  BVH builds and tuning
+    are excluded."""
     t0 = time.time()
     w = W.batch_workload()
     log(f"batch workload: {len(w['scenes'])} scenes, {int(w['n_tris'].sum())} tris, "
@@ -560,7 +566,9 @@ def batched(torch, bvh, W):
     n = rays.shape[0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b = bvh.Batch(scenes, probe=rays, probe_offsets=off)
+    # tuned on probe rays the library generates on the device (uniform in each
+    # scene's box), not on the rays timed below
+    b = bvh.Batch(scenes)
     create_s = time.perf_counter() - t0
     infos = [b.info(i) for i in range(len(scenes))]
     handles = [b.handle(i) for i in range(len(scenes))]
@@ -595,6 +603,7 @@ def batched(torch, bvh, W):
             "plain_bvh8_q8_mrays_s": round(n / (t_fixed / 1000) / 1e6, 1),
             "speedup_vs_plain_tuned": round(t_plain / t_batch, 3),
             "speedup_vs_plain_fixed": round(t_fixed / t_batch, 3),
+            "tuner_gain_plain": round(t_fixed / t_plain, 3),
             "batched_ms": round(t_batch, 3), "plain_tuned_ms": round(t_plain, 3),
             "plain_fixed_ms": round(t_fixed, 3), "hits_equal_plain": same,
             "create_and_tune_s": round(create_s, 2), "chosen": layouts}
