@@ -2360,7 +2360,8 @@ __global__ __launch_bounds__(kBlock) void k_sah_scatter(SahLevel lv, const uint3
 // current order).  Subtrees are split in turn from a per-wave stack.
 __global__ __launch_bounds__(kBlock) void k_sah_small(const SahTask *small, uint32_t nsmall,
                                                       const Box *pbox, uint32_t *perm, SahTree tr,
-                                                      const uint32_t *root_nat_p, uint32_t *err) {
+                                                      const uint32_t *root_nat_p, uint32_t leaf_size,
+                                                      uint32_t *err) {
     constexpr int W = kBlock / kWave;
     __shared__ int sbins[W][kSahBinWords];
     __shared__ uint32_t sstack[W][kSahSmall][4];
@@ -2394,13 +2395,18 @@ __global__ __launch_bounds__(kBlock) void k_sah_small(const SahTask *small, uint
         const uint32_t sd = sstack[w][sp][3];
         wave_sync();
         const bool act = (uint32_t)lane >= sf && (uint32_t)lane < sf + sc;
+        // a node of at most leaf_size primitives becomes one leaf whatever
+        // its subtree: it is split at the index median without binning (no
+        // reordering), so only the order inside the leaf differs from a full
+        // SAH split
+        const bool in_leaf = sc <= leaf_size;
         float cl[3], ch[3], c[3];
         for (int a = 0; a < 3; a++) {
             c[a] = sah_centroid(b, a);
-            cl[a] = wave_min(act ? c[a] : INFINITY);
-            ch[a] = wave_max(act ? c[a] : -INFINITY);
+            cl[a] = in_leaf ? 0.0f : wave_min(act ? c[a] : INFINITY);
+            ch[a] = in_leaf ? 0.0f : wave_max(act ? c[a] : -INFINITY);
         }
-        const SahFrame f = sah_frame(cl, ch);
+        const SahFrame f = sah_frame(cl, ch);  // no valid axis for a leaf-sized node
         float best = INFINITY;
         int axis = -1, bk = -1;
         uint32_t nl = 0;
@@ -2534,7 +2540,7 @@ __global__ void k_sah_publish(const uint32_t *src, uint32_t *dst, int k) {
 
 // Host side of the binned-SAH topology: fills perm and the tree arrays.
 int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, uint32_t *tile,
-                     hipStream_t s) {
+                     int leaf_size, hipStream_t s) {
     if (n < 2) {
         if (n == 1) BVH_HIP_TRY(hipMemsetAsync(perm, 0, sizeof(uint32_t), s));
         return BVH_OK;
@@ -2606,7 +2612,7 @@ int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, ui
     if (nsmall > n / 2 + 1) return set_error(BVH_EHIP, "bvh_build: internal error (SAH small overflow)");
     if (nsmall > 0)
         k_sah_small<<<(nsmall + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(
-            small, nsmall, pbox, perm, tr, root_nat, err);
+            small, nsmall, pbox, perm, tr, root_nat, (uint32_t)leaf_size, err);
     vw[3] = kPending;
     k_sah_publish<<<1, 64, 0, s>>>(err, hw + 11, 1);
     BVH_TRY(check_launch("sah small nodes"));
@@ -2724,7 +2730,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         // a4 alternative: binned-SAH topology over the primitive boxes
         BVH_TRY(check_launch("bounds"));
         SahTree tr{ileft, iright, parent, ifirst, icount, iaxis, n};
-        BVH_TRY(sah_topology(pbox, (uint32_t)n, vals[0], tr, tile, s));
+        BVH_TRY(sah_topology(pbox, (uint32_t)n, vals[0], tr, tile, L, s));
         perm = vals[0];
         BVH_TRY(leaf_data_early());
     } else {
