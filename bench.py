@@ -65,6 +65,11 @@ ALU_OPS_NODE = {
     "bvh8_q8": 8 * (ALU_OPS_BOX + ALU_OPS_DEQUANT), "bvh8_q16": 8 * (ALU_OPS_BOX + ALU_OPS_DEQUANT),
 }
 RAY_BYTES, HIT_BYTES = 32, 16
+# Backward, algorithmic bytes per ray: the ray (32), its hit record (16), the
+# loss gradient g (12), the triangle's indices (12) and three vertices (36) in;
+# the ray gradient (24) out, and three vertex-gradient rows read and written
+# (2 x 36).
+BWD_BYTES_PER_RAY = 32 + 16 + 12 + 12 + 36 + 24 + 2 * 36
 QUERY_BYTES, CLOSEST_BYTES = 16, 16  # bvh_point_query, bvh_closest
 LAYOUTS = ("aabb2", "bvh4", "bvh8_q8", "bvh8_q16", "pbrt_q16", "sg_eq", "pbrt_soaos",
            "pbrt_q16_soaos", "sg_eq_a16", "shared_slab")
@@ -523,28 +528,38 @@ def fwd_bwd(torch, bvh, W):
     stream = torch.cuda.current_stream()
 
     def run(bwd):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        """(forward [+ backward] ms, backward alone ms); grad_verts is zeroed
+        between the two events, outside the backward's own interval."""
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record(stream)
         h.trace(r, hits=hits)
         if bwd:
             gv.zero_()
+        e[1].record(stream)
+        if bwd:
             bvh.lib().bvh_trace_backward(v.data_ptr(), v.shape[0], t.data_ptr(), t.shape[0],
                                          r.data_ptr(), r.shape[0], hits.data_ptr(), g.data_ptr(),
                                          gv.data_ptr(), gr.data_ptr(), stream.cuda_stream)
-        e[1].record(stream)
+        e[2].record(stream)
         torch.cuda.synchronize()
-        return e[0].elapsed_time(e[1])
+        return e[0].elapsed_time(e[2]), e[1].elapsed_time(e[2])
 
     for _ in range(2):
         run(False), run(True)
-    f = trimmed_mean([run(False) for _ in range(9)])
-    fb = trimmed_mean([run(True) for _ in range(9)])
+    f = trimmed_mean([run(False)[0] for _ in range(9)])
+    both = [run(True) for _ in range(9)]
+    fb = trimmed_mean([x[0] for x in both])
+    b = trimmed_mean([x[1] for x in both])
     h.close()
     n = r.shape[0]
+    gbs = BWD_BYTES_PER_RAY * n / (b / 1000) / 1e9
     return {"workload": "icosphere level 7 (327,680 tris), 1,048,576 rays from 64 cameras",
             "fwd_mrays_s": round(n / (f / 1000) / 1e6, 1),
             "fwd_bwd_mrays_s": round(n / (fb / 1000) / 1e6, 1),
-            "fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4)}
+            "fwd_ms": round(f, 4), "fwd_bwd_ms": round(fb, 4), "bwd_us": round(b * 1000, 1),
+            "bwd_roofline": {"bound": "hbm", "bytes_per_ray": BWD_BYTES_PER_RAY,
+                             "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4)}}
 
 
 def batched(torch, bvh, W):

@@ -429,9 +429,10 @@ int32_t bvh_trace_counts(bvh_handle_t h, const bvh_ray *rays, int64_t n, bvh_hit
  *               2^22 vertices: the contributions are grouped by vertex range
  *               in a work area (16 B per ray contribution; grow-only, kept
  *               per stream) and each range is summed in one workgroup's
- *               LDS with float atomics; larger meshes add per-block partial
- *               sums with device float atomics.  Either way the summation
- *               order (last bits) varies between runs.
+ *               LDS (up to 2^18 vertices: one accumulator per wave, no
+ *               atomics; beyond: LDS float atomics); larger meshes add
+ *               per-block partial sums with device float atomics.  Either
+ *               way the summation order (last bits) varies between runs.
  *               Calls that share a stream share its work area: they are
  *               ordered by the stream.
  *   grad_rays   device, n x 6 float (dL/do, dL/dd), OVERWRITTEN; a miss or

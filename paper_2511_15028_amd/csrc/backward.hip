@@ -160,7 +160,7 @@ constexpr int kPartRays = kPartThreads * kPartRaysPerThread;
 constexpr int kPartRecs = 3 * kPartRays;
 constexpr int kPartMaxRanges = 1024;
 constexpr int kPartMinShift = 8, kPartMaxShift = 12;
-constexpr int kSumThreads = 1024;
+constexpr int kSumThreads = 512;
 
 struct VertRec {
     int32_t v;
@@ -272,22 +272,45 @@ __global__ __launch_bounds__(kPartThreads) void k_backward_part(
 // search over the scanned counts finds a record's segment), so every thread
 // has several independent record loads in flight instead of a chain per
 // segment.
+//
+// Summation.  kPrivate (ranges of 2^kSumPrivShift vertices): every wave owns
+// an LDS accumulator of the range, so no two waves touch one word; within a
+// wave instruction, the lanes holding one vertex find each other with one
+// ballot per bit of the vertex's index in the range, the lowest of them adds
+// the others' values (ds_bpermute) and alone updates the accumulator with a
+// plain read and write.  The copies are added at the end.  LDS float atomics
+// (ds_add_f32) cost about 32 LDS cycles per wave instruction, three per
+// record; the plain update costs a read and a write per record.  Larger
+// ranges (whose copies would not fit in LDS) share one accumulator updated
+// with LDS atomics.
 constexpr int kSumMaxBlocks = 2048;  // segments per pass
 constexpr int kSumUnroll = 4;
+constexpr int kSumPrivShift = 8;
+constexpr int kSumWaves = kSumThreads / 64;
 
+__device__ inline float bperm_f(float x, uint32_t src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((int)(src << 2), __float_as_int(x)));
+}
+
+template <bool kPrivate>
 __global__ __launch_bounds__(kSumThreads) void k_backward_sum(const VertRec *seg,
                                                               const uint32_t *offs,
                                                               uint32_t n_blocks, int shift,
                                                               uint32_t n_ranges, int64_t n_verts,
                                                               float *grad_verts) {
-    extern __shared__ float acc[];  // 3 * 2^shift floats (dynamic)
+    // kPrivate: kSumWaves copies of 3 * 2^kSumPrivShift floats; otherwise one
+    // copy of 3 * 2^shift floats (dynamic)
+    extern __shared__ float acc[];
     __shared__ uint32_t lo[kSumMaxBlocks];
     __shared__ uint32_t start[kSumMaxBlocks + 1];
     __shared__ uint32_t wsum[kSumThreads / 64];
     const uint32_t p = blockIdx.x;
     const uint32_t nv = 1u << shift;
     const int64_t v0 = (int64_t)p << shift;
-    for (uint32_t q = threadIdx.x; q < 3 * nv; q += kSumThreads) acc[q] = 0.0f;
+    const uint32_t n_acc = kPrivate ? kSumWaves : 1;
+    for (uint32_t q = threadIdx.x; q < 3 * nv * n_acc; q += kSumThreads) acc[q] = 0.0f;
+    float *const my = acc + (kPrivate ? (threadIdx.x >> 6) * 3 * nv : 0);
+    const uint32_t lane = threadIdx.x & 63;
     constexpr int kPer = kSumMaxBlocks / kSumThreads;
     for (uint32_t b0 = 0; b0 < n_blocks; b0 += kSumMaxBlocks) {
         const uint32_t nb = min((uint32_t)kSumMaxBlocks, n_blocks - b0);
@@ -349,7 +372,37 @@ __global__ __launch_bounds__(kSumThreads) void k_backward_sum(const VertRec *seg
 #pragma unroll
             for (int u = 0; u < kSumUnroll; u++) {
                 const uint32_t local = (uint32_t)(__float_as_int(x[u].x) - (int32_t)v0);
-                if (ok[u] && local < nv) {  // always in range for a consistent segment
+                const bool mine = ok[u] && local < nv;  // always in range for a consistent segment
+                if constexpr (kPrivate) {
+                    uint64_t peers = __builtin_amdgcn_ballot_w64(mine);
+#pragma unroll
+                    for (int b = 0; b < kSumPrivShift; b++) {
+                        const bool bit = (local >> b) & 1u;
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(bit);
+                        peers &= bit ? m : ~m;
+                    }
+                    const uint64_t self = uint64_t(1) << lane;
+                    const bool leader = mine && (peers & (self - 1)) == 0;
+                    uint64_t rest = leader ? peers & ~self : 0;
+                    float gx = x[u].y, gy = x[u].z, gz = x[u].w;
+                    while (__builtin_amdgcn_ballot_w64(rest != 0)) {
+                        const uint32_t src = rest ? (uint32_t)__builtin_ctzll(rest) : lane;
+                        const float ax = bperm_f(x[u].y, src), ay = bperm_f(x[u].z, src),
+                                    az = bperm_f(x[u].w, src);
+                        if (rest) {
+                            gx += ax;
+                            gy += ay;
+                            gz += az;
+                            rest &= rest - 1;
+                        }
+                    }
+                    if (leader) {
+                        float *a = my + 3 * local;
+                        a[0] += gx;
+                        a[1] += gy;
+                        a[2] += gz;
+                    }
+                } else if (mine) {
                     atomicAdd(&acc[3 * local + 0], x[u].y);
                     atomicAdd(&acc[3 * local + 1], x[u].z);
                     atomicAdd(&acc[3 * local + 2], x[u].w);
@@ -360,7 +413,11 @@ __global__ __launch_bounds__(kSumThreads) void k_backward_sum(const VertRec *seg
     }
     const int64_t cnt = min((int64_t)nv, n_verts - v0);
     float *g = grad_verts + 3 * v0;
-    for (int64_t q = threadIdx.x; q < 3 * cnt; q += kSumThreads) g[q] += acc[q];
+    for (int64_t q = threadIdx.x; q < 3 * cnt; q += kSumThreads) {
+        float a = acc[q];
+        for (uint32_t w = 1; w < n_acc; w++) a += acc[w * 3 * nv + q];
+        g[q] += a;
+    }
 }
 
 // Smallest range shift (within [kPartMinShift, kPartMaxShift]) that covers
@@ -404,8 +461,13 @@ extern "C" int32_t bvh_trace_backward(const float *verts, int64_t n_verts, const
         k_backward_part<<<(unsigned)blocks, kPartThreads, 0, s>>>(
             verts, n_verts, tris, n_tris, rays, (uint64_t)n, hits, grad_hits, grad_rays, shift,
             ranges, seg, offs);
-        k_backward_sum<<<ranges, kSumThreads, (3u << shift) * sizeof(float), s>>>(
-            seg, offs, (uint32_t)blocks, shift, ranges, n_verts, grad_verts);
+        if (shift == kSumPrivShift)
+            k_backward_sum<true><<<ranges, kSumThreads, kSumWaves * (3u << shift) * sizeof(float),
+                                   s>>>(seg, offs, (uint32_t)blocks, shift, ranges, n_verts,
+                                        grad_verts);
+        else
+            k_backward_sum<false><<<ranges, kSumThreads, (3u << shift) * sizeof(float), s>>>(
+                seg, offs, (uint32_t)blocks, shift, ranges, n_verts, grad_verts);
     } else {
         const unsigned grid = (unsigned)(((uint64_t)n + kBlock - 1) / kBlock);
         k_backward<<<grid, kBlock, 0, s>>>(verts, n_verts, tris, n_tris, rays, (uint64_t)n, hits,

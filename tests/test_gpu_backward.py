@@ -228,6 +228,28 @@ def test_backward_accumulates_into_grad_verts(orc):
     assert (np.abs(got - 2 * gv64) <= tol).all()
 
 
+@pytest.mark.parametrize("n_total", [200_003, (1 << 18) + 7, (1 << 20) + 1, (1 << 22) - 3])
+def test_backward_scattered_vertices(orc, n_total):
+    """Every width of vertex range: the small workload's vertices scattered
+    at random over a larger array (the triangles re-indexed), so that the
+    records spread over many ranges.  2^8-vertex ranges (up to 2^18
+    vertices) sum in per-wave accumulators, wider ranges in one accumulator
+    per block; both give the oracle's gradient at the scattered indices and
+    zeros elsewhere."""
+    w = W.diff_workload(level=4, n_cams=8, res=32)
+    p1, tuv1 = orc.brute_closest(w["verts"], w["tris"], w["rays"])
+    nv = len(w["verts"])
+    idx = np.random.default_rng(n_total).choice(n_total, nv, replace=False)
+    big = np.zeros((n_total, 3), np.float32)
+    big[idx] = w["verts"]
+    wp = dict(w, verts=big, tris=idx[w["tris"]].astype(np.int32))
+    gv, gr = _run(wp, _hits_array(p1, tuv1))
+    rest = np.ones(n_total, bool)
+    rest[idx] = False
+    assert (gv[rest] == 0).all()
+    _compare(orc, w, p1, tuv1, gv[idx], gr)
+
+
 def test_backward_mesh_beyond_the_range_partition(orc):
     """Meshes of more than 2^22 vertices take the per-block atomic path: the
     small workload's vertex array padded past 2^22 entries (the padding is
