@@ -63,7 +63,9 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
-// Exclusive scan of one value per thread over the block; *total = block sum.
+// Exclusive scan of one value per thread over the block (THREADS threads,
+// wsum THREADS / kWave words); *total = block sum.
+template <int THREADS = kBlock>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t *wsum) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     uint32_t inc = wave_incl_scan(v);
@@ -71,7 +73,7 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t
     __syncthreads();
     uint32_t off = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; i++) {
+    for (int i = 0; i < THREADS / kWave; i++) {
         uint32_t s = wsum[i];
         off += (i < w) ? s : 0u;
         tot += s;
@@ -232,107 +234,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_final_fused(const uint32_t *in,
         *total_out = before + tot;
         __threadfence_system();  // the total may live in host memory the host polls
     }
-}
-
-// Level table of the multi-block levels: lv[2l] = first node of level l,
-// lv[2l+1] = its node count, written on the GPU by the level's scan (the
-// host launches a level before it knows its count, with a grid bound).
-__device__ inline uint32_t level_count(const uint32_t *lv, int l, uint32_t bound, BuildInfo *info) {
-    const uint32_t c = lv[2 * l + 1];
-    if (c > bound) {  // cannot happen: a level is at most K times the one above
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&info->err, 4u);
-        return bound;
-    }
-    return c;
-}
-
-// Scan of a wide-packing level's interior-child counts, with the count read
-// from the level table: the last block also writes the next level's entry
-// (first node, count) and the count to a host-mapped word.  Launched with a
-// grid for `bound` items; blocks past the actual count leave at once.
-__device__ inline void level_total(uint32_t *lv, int l, uint32_t count, uint32_t total,
-                                   uint32_t *host_word) {
-    lv[2 * (l + 1)] = lv[2 * l] + count;
-    lv[2 * (l + 1) + 1] = total;
-    *host_word = total;
-    __threadfence_system();  // the host polls the word
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_level_single(uint32_t *cnt, uint32_t *lv, int l,
-                                                              uint32_t bound, uint32_t *host_word,
-                                                              BuildInfo *info) {
-    __shared__ uint32_t wsum[kBlock / kWave];
-    const uint32_t n = level_count(lv, l, bound, info);
-    uint32_t carry = 0;
-    for (uint32_t c = 0; c < n; c += kScanTile) {
-        const uint32_t base = c + threadIdx.x * kScanItems;
-        uint32_t v[kScanItems];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int k = 0; k < kScanItems; k++) {
-            v[k] = base + k < n ? cnt[base + k] : 0u;
-            sum += v[k];
-        }
-        uint32_t tot;
-        uint32_t run = carry + block_excl_scan(sum, &tot, wsum);
-#pragma unroll
-        for (int k = 0; k < kScanItems; k++) {
-            if (base + k < n) cnt[base + k] = run;
-            run += v[k];
-        }
-        carry += tot;
-        __syncthreads();  // wsum is reused by the next tile
-    }
-    if (threadIdx.x == 0) level_total(lv, l, n, carry, host_word);
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_level_reduce(const uint32_t *cnt, const uint32_t *lv,
-                                                              int l, uint32_t bound,
-                                                              uint32_t *tile_sums) {
-    __shared__ uint32_t wsum[kBlock / kWave];
-    const uint32_t n = min(lv[2 * l + 1], bound);
-    if (blockIdx.x * kScanTile >= n) return;
-    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++)
-        if (base + k < n) sum += cnt[base + k];
-    uint32_t tot;
-    block_excl_scan(sum, &tot, wsum);
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_level_final(uint32_t *cnt, uint32_t *lv, int l,
-                                                             uint32_t bound, const uint32_t *tile_sums,
-                                                             uint32_t *host_word, BuildInfo *info) {
-    __shared__ uint32_t wsum[kBlock / kWave];
-    const uint32_t n = level_count(lv, l, bound, info);
-    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
-    if (ntiles == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) level_total(lv, l, 0, 0, host_word);
-        return;
-    }
-    if (blockIdx.x >= ntiles) return;
-    uint32_t part = 0;
-    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kBlock) part += tile_sums[t];
-    uint32_t before;
-    block_excl_scan(part, &before, wsum);
-    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        v[k] = base + k < n ? cnt[base + k] : 0u;
-        sum += v[k];
-    }
-    uint32_t tot;
-    uint32_t run = before + block_excl_scan(sum, &tot, wsum);
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-        if (base + k < n) cnt[base + k] = run;
-        run += v[k];
-    }
-    if (blockIdx.x == ntiles - 1 && threadIdx.x == 0) level_total(lv, l, n, before + tot, host_word);
 }
 
 // Exclusive scan of n values; total (device) receives the sum if non-null.
@@ -1218,17 +1119,21 @@ __device__ inline uint32_t wide_open_item(const TreeView &tv, int x, int32_t *ca
             nc++;
         }
     }
-    uint32_t ni = 0;
+    uint32_t ni = 0, mask = 0;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         cand_out[k] = c[k];
-        if (c[k] >= 0 && !tv.is_leaf(c[k])) ni++;
+        if (c[k] >= 0 && !tv.is_leaf(c[k])) {
+            ni++;
+            mask |= 1u << k;
+        }
     }
-    return ni;
+    return ni | (mask << 8);
 }
 
 // Binary nodes 0 .. m-1 (m = max(n-1, 1)): the root and every alive interior
-// node get their child list (cand_all[x*K ..]) and interior-child count.
+// node get their child list (cand_all[x*K ..]) and a word with the number of
+// interior children (low 8 bits) and which slots hold them (bit 8 + slot).
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_wide_open_all(TreeView tv, uint32_t m, int32_t *cand_all,
                                                           uint32_t *ni_all) {
@@ -1410,43 +1315,252 @@ struct NodeSink {
     }
 };
 
-// Writes wide node base+f from its candidate list and appends its interior
-// children to the next frontier at noff_f, noff_f+1, ...
-template <int Layout>
-__device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_t count,
-                                      uint32_t cap, uint32_t f, int x, uint32_t aux,
-                                      const int32_t *cand_f, uint32_t noff_f, NodeSink sink,
-                                      int32_t *next_node, uint32_t *next_aux, BuildInfo *info,
-                                      uint32_t *stack_out, uint32_t *depth_out,
-                                      const uint32_t *ni_all = nullptr, uint32_t *next_ni = nullptr) {
+// ---------------------------------------------------------------------------
+// Wide packing by subtrees.  The wide tree's top levels, while a level holds
+// at most kTopMaxFrontier nodes, are planned breadth-first by one workgroup;
+// every node of the next level roots a subtree, which one workgroup plans
+// breadth-first in a queue of its own.  A subtree's wide nodes number at most
+// its primitive count less one (each has two children or more), so its queue
+// sits at the subtree root's first primitive position in arrays of n entries,
+// and the queues of different subtrees never overlap.  A scan of the subtree
+// sizes then places each subtree contiguously after the top levels, and one
+// launch over all node positions writes every record (a thread finds its
+// subtree by a binary search over the subtree offsets, so uneven subtrees
+// do not leave one workgroup with most of the work).  Node order: the top
+// levels breadth-first, then subtree by subtree in the order of their roots,
+// each breadth-first; a subtree's nodes are thus close together in memory.
+// Only the final node count goes to the host.
+//
+// Plan entries: the binary node x, its aux word (the stack entries its
+// ancestors leave behind in the low 16 bits, its depth in the high 16) and
+// the queue index of its first interior child (the others follow it).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTopMaxFrontier = 1024;
+constexpr uint32_t kTopMaxLevels = 64;
+constexpr uint32_t kTopMaxNodes = kTopMaxFrontier * kTopMaxLevels;
+constexpr int kPlanItems = 4;         // consecutive queue entries per thread and pass
+constexpr int kTopThreads = 512;      // the top levels: one workgroup
+static_assert(kTopMaxFrontier <= kTopThreads * kPlanItems, "a top level is planned in one pass");
+constexpr int kSubThreads = 64;       // a subtree: one wave (its scans need no barrier)
+constexpr uint32_t kPlanBlocks = 8192;  // subtree planning: waves, striding over the roots
+constexpr int kPlaceThreads = 1024;
+constexpr uint32_t kWriteLdsRoots = 4096;  // subtree offsets held in LDS for the search
+
+struct WidePlan {
+    int32_t *t_node;  // top levels, node i at position i (kTopMaxNodes)
+    uint32_t *t_aux, *t_noff;
+    int32_t *f_node;  // subtree roots (K * kTopMaxFrontier)
+    uint32_t *f_aux, *f_size, *f_off, *f_q0;
+    int32_t *s_node;  // subtree queues (n entries, by primitive position)
+    uint32_t *s_aux, *s_noff;
+    uint32_t *meta;   // [0] top nodes, [1] subtrees, [2] all nodes
+};
+
+// One pass over queue entries [c, min(c + THREADS * kPlanItems, hi)), kPlanItems
+// consecutive ones per thread: their child lists and interior-slot words are
+// loaded together, the interior-child counts scanned over the block (child
+// indices from `start`), each entry's first-child index stored in qo.  The
+// entries stay in registers for plan_children.  Every thread calls it.
+template <int K>
+struct PlanRegs {
+    int32_t cand[kPlanItems][K];
+    uint32_t aux[kPlanItems], word[kPlanItems], off[kPlanItems];
+};
+
+template <int K, int THREADS>
+__device__ inline uint32_t plan_pass(const int32_t *qn, const uint32_t *qa, uint32_t *qo, uint32_t c,
+                                     uint32_t hi, uint32_t start, const int32_t *cand_all,
+                                     const uint32_t *ni_all, uint32_t *wsum, PlanRegs<K> &R) {
+    const uint32_t i0 = c + threadIdx.x * kPlanItems;
+    int32_t x[kPlanItems];
+#pragma unroll
+    for (int k = 0; k < kPlanItems; k++) {
+        const bool in = i0 + k < hi;
+        x[k] = in ? qn[i0 + k] : -1;
+        R.aux[k] = in ? qa[i0 + k] : 0u;
+    }
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPlanItems; k++) {
+        R.word[k] = x[k] >= 0 ? ni_all[x[k]] : 0u;
+#pragma unroll
+        for (int j = 0; j < K; j++) R.cand[k][j] = x[k] >= 0 ? cand_all[(size_t)x[k] * K + j] : -1;
+        sum += R.word[k] & 0xFFu;
+    }
+    uint32_t tot;
+    uint32_t run = start + block_excl_scan<THREADS>(sum, &tot, wsum);
+#pragma unroll
+    for (int k = 0; k < kPlanItems; k++) {
+        R.off[k] = run;
+        if (i0 + k < hi) qo[i0 + k] = run;
+        run += R.word[k] & 0xFFu;
+    }
+    return tot;
+}
+
+// Appends the pass's interior children (candidate order) at dst[off - dbase].
+template <int K>
+__device__ inline void plan_children(const PlanRegs<K> &R, uint32_t c, uint32_t hi, int32_t *dst_node,
+                                     uint32_t *dst_aux, uint32_t dbase) {
+    const uint32_t i0 = c + threadIdx.x * kPlanItems;
+#pragma unroll
+    for (int k = 0; k < kPlanItems; k++) {
+        if (i0 + k >= hi) continue;
+        int nc = 0;
+#pragma unroll
+        for (int j = 0; j < K; j++) nc += R.cand[k][j] >= 0;
+        const uint32_t a = R.aux[k];
+        const uint32_t caux = (((a & 0xFFFFu) + (uint32_t)(nc - 1)) & 0xFFFFu) | (((a >> 16) + 1) << 16);
+        const uint32_t mask = R.word[k] >> 8;
+        uint32_t at = R.off[k] - dbase;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            if (!((mask >> j) & 1u)) continue;
+            dst_node[at] = R.cand[k][j];
+            dst_aux[at] = caux;
+            at++;
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kTopThreads) void k_wide_plan_top(const int32_t *cand_all,
+                                                               const uint32_t *ni_all, WidePlan p) {
+    __shared__ uint32_t wsum[kTopThreads / kWave];
+    if (threadIdx.x == 0) {  // level 0 = {root}, nothing stacked, depth 0
+        p.t_node[0] = 0;
+        p.t_aux[0] = 0;
+    }
+    __syncthreads();
+    uint32_t lo = 0, hi = 1, total = 0;
+    bool frontier = false;
+    for (uint32_t level = 0;; level++) {
+        PlanRegs<K> R;
+        total = plan_pass<K, kTopThreads>(p.t_node, p.t_aux, p.t_noff, lo, hi, hi, cand_all, ni_all,
+                                          wsum, R);
+        // the same in every thread: the next level becomes the subtree roots
+        // when it is too wide for one pass or the top is too deep
+        frontier = total > kTopMaxFrontier || level + 1 >= kTopMaxLevels || hi + total > kTopMaxNodes;
+        if (frontier)
+            plan_children<K>(R, lo, hi, p.f_node, p.f_aux, hi);
+        else
+            plan_children<K>(R, lo, hi, p.t_node, p.t_aux, 0);
+        __syncthreads();
+        if (frontier || total == 0) break;
+        lo = hi;
+        hi += total;
+    }
+    if (threadIdx.x == 0) {
+        p.meta[0] = hi;
+        p.meta[1] = frontier ? total : 0u;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kSubThreads) void k_wide_plan_sub(TreeView tv, const int32_t *cand_all,
+                                                               const uint32_t *ni_all, WidePlan p,
+                                                               BuildInfo *info) {
+    __shared__ uint32_t wsum[kSubThreads / kWave];
+    const uint32_t roots = p.meta[1];
+    for (uint32_t b = blockIdx.x; b < roots; b += gridDim.x) {
+        const int32_t x = p.f_node[b];
+        const uint32_t q0 = tv.first(x), qcap = tv.count(x);
+        int32_t *qn = p.s_node + q0;
+        uint32_t *qa = p.s_aux + q0, *qo = p.s_noff + q0;
+        if (threadIdx.x == 0) {
+            qn[0] = x;
+            qa[0] = p.f_aux[b];
+            p.f_q0[b] = q0;
+        }
+        __syncthreads();
+        uint32_t lo = 0, hi = 1;
+        bool bad = false;
+        while (lo < hi && !bad) {
+            uint32_t next = hi;
+            for (uint32_t c = lo; c < hi; c += kSubThreads * kPlanItems) {
+                PlanRegs<K> R;
+                const uint32_t tot =
+                    plan_pass<K, kSubThreads>(qn, qa, qo, c, hi, next, cand_all, ni_all, wsum, R);
+                if (next + tot > qcap) {  // cannot happen (see above): the tree is malformed
+                    bad = true;
+                    break;
+                }
+                plan_children<K>(R, c, hi, qn, qa, 0);
+                next += tot;
+            }
+            __syncthreads();
+            lo = hi;
+            hi = bad ? lo : next;
+        }
+        if (threadIdx.x == 0) {
+            if (bad) atomicOr(&info->err, 4u);
+            p.f_size[b] = hi;
+        }
+    }
+}
+
+// Places the subtrees (f_off = absolute position of a subtree's first node)
+// and publishes the node count (meta[2] and a host-mapped word).
+__global__ __launch_bounds__(kPlaceThreads) void k_wide_place(WidePlan p, uint32_t cap,
+                                                              BuildInfo *info, uint32_t *host_word) {
+    __shared__ uint32_t wsum[kPlaceThreads / kWave];
+    const uint32_t base = p.meta[0], count = p.meta[1];
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < count; c += kPlaceThreads * kPlanItems) {
+        const uint32_t b0 = c + threadIdx.x * kPlanItems;
+        uint32_t v[kPlanItems], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPlanItems; k++) {
+            v[k] = b0 + k < count ? p.f_size[b0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t tot;
+        uint32_t run = base + carry + block_excl_scan<kPlaceThreads>(sum, &tot, wsum);
+#pragma unroll
+        for (int k = 0; k < kPlanItems; k++) {
+            if (b0 + k < count) p.f_off[b0 + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t all = base + carry;
+        if (all > cap) atomicOr(&info->err, 4u);
+        p.meta[2] = all;
+        *host_word = all;
+        __threadfence_system();  // the host polls the word
+    }
+}
+
+// Writes wide node x at position at; pos(r) is the position of its r-th
+// interior child.
+template <int Layout, typename Pos>
+__device__ inline void wide_write(const TreeView &tv, int32_t x, uint32_t aux, uint32_t at,
+                                  uint32_t cap, const int32_t *cand, Pos pos, NodeSink sink,
+                                  BuildInfo *info, uint32_t *stack_out, uint32_t *depth_out) {
     constexpr int K = WideOut<Layout>::K;
-    if (base + f >= cap) {
+    if (at >= cap) {
         atomicOr(&info->err, 4u);
         return;
     }
-    // every load first, so the candidates' loads are issued together rather
-    // than one candidate's chain after the other's stores
+    // every load first, so the candidates' loads are issued together
     int c[K];
     Box cb[K];
-    uint32_t cnt[K], fst[K], ni[K];
+    uint32_t cnt[K], fst[K];
 #pragma unroll
-    for (int k = 0; k < K; k++) c[k] = cand_f[k];  // valid candidates are the first nc slots
+    for (int k = 0; k < K; k++) c[k] = cand[k];  // valid candidates are the first nc slots
 #pragma unroll
     for (int k = 0; k < K; k++) {
         cb[k] = box_empty();
-        cnt[k] = fst[k] = ni[k] = 0;
+        cnt[k] = fst[k] = 0;
         if (c[k] < 0) continue;
         cb[k] = tv.nbox[c[k]];  // box and range in one load
         cnt[k] = range_count(cb[k]);
         fst[k] = range_first(cb[k]);
-        if (next_ni && !tv.is_prim(c[k])) ni[k] = ni_all[c[k]];  // meaningful for interior candidates only
     }
     uint32_t ref[K];
     int nc = 0;
     uint32_t r = 0;
-    const uint32_t next_base = base + count;
-    const uint32_t depth = (aux >> 16) + 1;
-    uint32_t stack_need = aux & 0xFFFFu;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         ref[k] = kRefEmpty;
@@ -1455,116 +1569,60 @@ __device__ inline void wide_emit_item(const TreeView &tv, uint32_t base, uint32_
         if (cnt[k] <= (uint32_t)tv.leaf_size) {
             ref[k] = ref_leaf(fst[k], cnt[k]);
         } else {
-            const uint32_t pos = noff_f + r;
-            if (pos >= cap || next_base + pos >= cap) {
+            const uint32_t q = pos(r++);
+            if (q >= cap) {
                 atomicOr(&info->err, 4u);
                 return;
             }
-            ref[k] = ref_interior(next_base + pos);
-            next_node[pos] = c[k];
-            if (next_ni) next_ni[pos] = ni[k];
-            r++;
+            ref[k] = ref_interior(q);
         }
     }
-    stack_need += (uint32_t)(nc - 1);
-    for (uint32_t k = 0; k < r; k++) next_aux[noff_f + k] = (stack_need & 0xFFFFu) | (depth << 16);
-    WideOut<Layout>::write(sink.at(base + f), tv.nbox[x], cb, ref, nc, &info->err);
-    *stack_out = max(*stack_out, stack_need);
-    *depth_out = max(*depth_out, depth + 1);  // + the leaf level below
+    WideOut<Layout>::write(sink.at(at), tv.nbox[x], cb, ref, nc, &info->err);
+    *stack_out = max(*stack_out, (aux & 0xFFFFu) + (uint32_t)(nc - 1));
+    *depth_out = max(*depth_out, (aux >> 16) + 2);  // its children's level and the leaf level below
 }
 
+// One thread per node position (launched for the largest possible count).
 template <int Layout>
-__global__ __launch_bounds__(kBlock) void k_wide_emit(TreeView tv, const uint32_t *lv, int l,
-                                                      uint32_t bound, uint32_t cap,
-                                                      const int32_t *fr_node,
-                                                      const uint32_t *fr_aux, const int32_t *cand_all,
-                                                      const uint32_t *ni_all, const uint32_t *noff,
-                                                      NodeSink sink, int32_t *next_node,
-                                                      uint32_t *next_aux, uint32_t *next_ni,
-                                                      BuildInfo *info) {
+__global__ __launch_bounds__(kBlock) void k_wide_write(TreeView tv, const int32_t *cand_all,
+                                                       WidePlan p, uint32_t cap, NodeSink sink,
+                                                       BuildInfo *info) {
     constexpr int K = WideOut<Layout>::K;
-    const uint32_t base = lv[2 * l];
-    const uint32_t count = level_count(lv, l, bound, info);
-    const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ uint32_t s_off[kWriteLdsRoots];
+    const uint32_t base = p.meta[0], roots = p.meta[1], all = p.meta[2];
+    const bool lds = roots <= kWriteLdsRoots;
+    const uint32_t at = blockIdx.x * kBlock + threadIdx.x;
+    if (lds && blockIdx.x * kBlock < all && (blockIdx.x + 1) * kBlock > base) {
+        for (uint32_t b = threadIdx.x; b < roots; b += kBlock) s_off[b] = p.f_off[b];
+        __syncthreads();
+    }
     uint32_t stack = 0, depth = 0;
-    if (f < count) {
-        const int x = fr_node[f];
-        wide_emit_item<Layout>(tv, base, count, cap, f, x, fr_aux[f], cand_all + (size_t)x * K,
-                               noff[f], sink, next_node, next_aux, info, &stack, &depth, ni_all,
-                               next_ni);
+    if (at < base) {
+        const uint32_t no = p.t_noff[at];
+        const int32_t x = p.t_node[at];
+        // the last top level's children are subtree roots
+        wide_write<Layout>(tv, x, p.t_aux[at], at, cap, cand_all + (size_t)x * K,
+                           [&](uint32_t r) {
+                               const uint32_t j = no + r;
+                               return j < base ? j : p.f_off[j - base];
+                           },
+                           sink, info, &stack, &depth);
+    } else if (at < all) {
+        // the subtree b with f_off[b] <= at < f_off[b + 1]
+        uint32_t lo = 0, hi = roots;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((lds ? s_off[mid] : p.f_off[mid]) <= at) lo = mid; else hi = mid;
+        }
+        const uint32_t off = lds ? s_off[lo] : p.f_off[lo];
+        const uint32_t q = p.f_q0[lo] + (at - off);
+        const uint32_t no = p.s_noff[q];
+        const int32_t x = p.s_node[q];
+        wide_write<Layout>(tv, x, p.s_aux[q], at, cap, cand_all + (size_t)x * K,
+                           [&](uint32_t r) { return off + no + r; }, sink, info, &stack, &depth);
     }
     wave_max_to_slots(tv.stack_slots, stack);
     wave_max_to_slots(tv.depth_slots, depth);
-}
-
-// The top levels, while the frontier is small, in one workgroup: gather the
-// counts, scan and emit per level with block barriers instead of kernel
-// launches and host round trips.  Leaves the multi-block levels' first
-// frontier with its counts in noff, and (base, count, frontier buffer) in
-// state[0..2] (host-mapped words; state[2] last).
-constexpr uint32_t kTopMaxFrontier = 512;
-
-template <int Layout>
-__global__ __launch_bounds__(kBlock) void k_wide_top(TreeView tv, uint32_t cap, int32_t *fr_node0,
-                                                     int32_t *fr_node1, uint32_t *fr_aux0,
-                                                     uint32_t *fr_aux1, const int32_t *cand_all,
-                                                     const uint32_t *ni_all, uint32_t *noff,
-                                                     NodeSink sink, BuildInfo *info,
-                                                     uint32_t *state, uint32_t *lv) {
-    constexpr int K = WideOut<Layout>::K;
-    __shared__ uint32_t wsum[kBlock / kWave];
-    if (threadIdx.x == 0) {  // frontier = {root} with zero stack need and depth
-        fr_node0[0] = 0;
-        fr_aux0[0] = 0;
-    }
-    __syncthreads();
-    uint32_t base = 0, count = 1, stack = 0, depth = 0;
-    int cur = 0;
-    for (int level = 0; count > 0; level++) {
-        int32_t *frn = cur ? fr_node1 : fr_node0;
-        uint32_t *fra = cur ? fr_aux1 : fr_aux0;
-        for (uint32_t f = threadIdx.x; f < count; f += kBlock) noff[f] = ni_all[frn[f]];
-        __syncthreads();
-        if (count > kTopMaxFrontier || level >= 64) break;  // count is the same in every thread
-        uint32_t carry = 0;
-        for (uint32_t c = 0; c < count; c += kBlock) {
-            const uint32_t f = c + threadIdx.x;
-            const uint32_t v = f < count ? noff[f] : 0u;
-            uint32_t tot;
-            const uint32_t ex = block_excl_scan(v, &tot, wsum);
-            if (f < count) noff[f] = carry + ex;
-            carry += tot;
-        }
-        __syncthreads();
-        for (uint32_t f = threadIdx.x; f < count; f += kBlock)
-            wide_emit_item<Layout>(tv, base, count, cap, f, frn[f], fra[f],
-                                   cand_all + (size_t)frn[f] * K, noff[f], sink,
-                                   cur ? fr_node0 : fr_node1, cur ? fr_aux0 : fr_aux1, info, &stack,
-                                   &depth);
-        __syncthreads();
-        base += count;
-        count = carry;
-        cur ^= 1;
-    }
-    wave_max_to_slots(tv.stack_slots, stack);
-    wave_max_to_slots(tv.depth_slots, depth);
-    if (cur == 1) {  // hand over in buffer 0, so the host can queue the next level blind
-        for (uint32_t f = threadIdx.x; f < count; f += kBlock) {
-            fr_node0[f] = fr_node1[f];
-            fr_aux0[f] = fr_aux1[f];
-        }
-    }
-    if (threadIdx.x == 0) {
-        lv[0] = base;  // level table entry of the first multi-block level
-        lv[1] = count;
-        // state lives in host memory the host polls: state[2] is written
-        // last, after base and count are visible
-        state[0] = base;
-        state[1] = count;
-        __threadfence_system();
-        state[2] = (uint32_t)cur;
-        __threadfence_system();
-    }
 }
 
 // Folds the per-wave maxima slots into info->max_stack / max_depth.
@@ -1847,7 +1905,8 @@ SideStream *side_stream(int device) {
 // and the child lists (which need no count) are queued first, then the host
 // reads the leaf count from the word the collapse scan writes (*nleaf_word,
 // host-mapped) while those kernels run.  cand_all / ni_all hold max(n-1, 1)
-// lists of K.
+// lists of K.  The plan, placement and writing kernels are queued at once;
+// the host waits only for the final node count.
 template <int Layout>
 int32_t pack_wide(TreeView tv, volatile uint32_t *nleaf_word, int32_t *cand_all, uint32_t *ni_all,
                   BuildInfo *info, bvh_handle_s *h, const LeafSource &ls, hipStream_t s) {
@@ -1862,75 +1921,41 @@ int32_t pack_wide(TreeView tv, volatile uint32_t *nleaf_word, int32_t *cand_all,
         return set_error(BVH_EHIP, "bvh_build: internal error (leaf count %u)", n_leaves);
     h->n_leaves = n_leaves;
     const uint32_t cap = std::max<uint32_t>(1, n_leaves - 1);  // alive interior nodes (or 1)
-    int32_t *fr_node[2];
-    uint32_t *fr_aux[2], *noff[2], *tile;
+    constexpr uint32_t kRoots = K * kTopMaxFrontier;
+    const size_t nq = std::max<size_t>(1, (size_t)tv.n);
     uint8_t *wnodes;
+    WidePlan p;
     Arena arena;
     arena.request(&wnodes, (size_t)cap * h->node_bytes);
-    for (int b = 0; b < 2; b++) {
-        arena.request(&fr_node[b], cap);
-        arena.request(&fr_aux[b], cap);
-        arena.request(&noff[b], cap);
-    }
-    arena.request(&tile, (cap + kScanTile - 1) / kScanTile + 1);
-    constexpr int kMaxLevels = 4096;
-    uint32_t *lv;
-    arena.request(&lv, 2 * (kMaxLevels + 3));
+    arena.request(&p.t_node, kTopMaxNodes);
+    arena.request(&p.t_aux, kTopMaxNodes);
+    arena.request(&p.t_noff, kTopMaxNodes);
+    arena.request(&p.f_node, kRoots);
+    arena.request(&p.f_aux, kRoots);
+    arena.request(&p.f_size, kRoots);
+    arena.request(&p.f_off, kRoots);
+    arena.request(&p.f_q0, kRoots);
+    arena.request(&p.s_node, nq);
+    arena.request(&p.s_aux, nq);
+    arena.request(&p.s_noff, nq);
+    arena.request(&p.meta, 4);
     BVH_TRY(arena.bind(s, kAreaBuildWide));
     uint32_t *hw = host_words();
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
     volatile uint32_t *vw = hw;
-    vw[0] = vw[1] = vw[2] = vw[3] = kPending;
+    vw[0] = kPending;
     NodeSink sink{static_cast<uint8_t *>(h->node_block), h->node_block ? h->node_block_cap : 0u,
                   wnodes, (uint32_t)h->node_bytes};
     const NodeCountHints::Key key = node_hint_key(h);
-    k_wide_top<Layout><<<1, kBlock, 0, s>>>(tv, cap, fr_node[0], fr_node[1], fr_aux[0], fr_aux[1],
-                                           cand_all, ni_all, noff[0], sink, info, hw, lv);
-    BVH_TRY(check_launch("wide packing (top levels)"));
-    const int cur0 = 0;  // the top kernel hands its last frontier over in buffer 0
-    // Level l (0 = the first multi-block one) scans noff[l & 1] and emits from
-    // frontier buffer (cur0 + l) & 1.  Its count comes from the level table,
-    // so level l+1 is queued, with a grid for K times level l's count, before
-    // the host has read level l+1's count: the GPU never waits for the host.
-    auto count_word = [&](int l) { return hw + 16 + (l & 31); };
-    auto launch_level = [&](int l, uint32_t bound) -> int32_t {
-        const int fb = (cur0 + l) & 1, nbuf = l & 1;
-        uint32_t *w = count_word(l + 1);
-        *(volatile uint32_t *)w = kPending;
-        const uint32_t tiles = (bound + kScanTile - 1) / kScanTile;
-        if (tiles <= kScanSingleTiles) {
-            k_scan_level_single<<<1, kBlock, 0, s>>>(noff[nbuf], lv, l, bound, w, info);
-        } else {
-            k_scan_level_reduce<<<tiles, kBlock, 0, s>>>(noff[nbuf], lv, l, bound, tile);
-            k_scan_level_final<<<tiles, kBlock, 0, s>>>(noff[nbuf], lv, l, bound, tile, w, info);
-        }
-        k_wide_emit<Layout><<<grid_for(bound), kBlock, 0, s>>>(
-            tv, lv, l, bound, cap, fr_node[fb], fr_aux[fb], cand_all, ni_all, noff[nbuf], sink,
-            fr_node[fb ^ 1], fr_aux[fb ^ 1], noff[nbuf ^ 1], info);
-        return check_launch("wide packing");
-    };
-    // level 0 is at most K times the top kernel's largest level
-    BVH_TRY(launch_level(0, std::min<uint32_t>(cap, K * kTopMaxFrontier)));
-    uint32_t base = 0, count = 0, curw = 0;
-    BVH_TRY(wait_host_word(vw + 2, s, &curw));  // written last, after base and count
-    base = vw[0];
-    count = vw[1];
-    if (base + count > cap || count > K * kTopMaxFrontier)
-        return set_error(BVH_EHIP, "wide packing overflow");
-    if (count > 0) {
-        for (int l = 0;; l++) {
-            if (l >= kMaxLevels) return set_error(BVH_EHIP, "wide packing did not terminate");
-            const uint32_t next_bound = (uint32_t)std::min<uint64_t>(cap, (uint64_t)K * count);
-            BVH_TRY(launch_level(l + 1, next_bound));
-            uint32_t next = 0;
-            BVH_TRY(wait_host_word(count_word(l + 1), s, &next));
-            base += count;
-            if (base + next > cap || next > next_bound)
-                return set_error(BVH_EHIP, "wide packing overflow");
-            count = next;
-            if (count == 0) break;  // the level queued last is empty: its kernels return at once
-        }
-    }
+    k_wide_plan_top<K><<<1, kTopThreads, 0, s>>>(cand_all, ni_all, p);
+    k_wide_plan_sub<K><<<std::min(kRoots, kPlanBlocks), kSubThreads, 0, s>>>(tv, cand_all, ni_all,
+                                                                           p, info);
+    k_wide_place<<<1, kPlaceThreads, 0, s>>>(p, cap, info, hw);
+    k_wide_write<Layout><<<grid_for(cap), kBlock, 0, s>>>(tv, cand_all, p, cap, sink, info);
+    BVH_TRY(check_launch("wide packing"));
+    uint32_t base = 0;
+    BVH_TRY(wait_host_word(vw, s, &base));
+    if (base > cap) return set_error(BVH_EHIP, "wide packing overflow");
     h->n_nodes = base;
     // the wide traversal kernels address node fields with 32-bit byte offsets
     if ((uint64_t)base * (uint64_t)h->node_bytes >= (1ull << 32))
