@@ -577,21 +577,12 @@ __device__ inline int common_prefix(const KeyWindow<KeyT> &kw, KeyT ki, int n, i
     return prefix_len(ki, kw.at(j), i, j);
 }
 
+// Node i of the hierarchy; returns how many leaves of the collapsed tree it
+// accounts for (see k_karras).
 template <typename KeyT>
-__global__ __launch_bounds__(kBlock) void k_karras(const KeyT *keys, int n, int32_t *ileft,
-                                                   int32_t *iright, uint32_t *ifirst,
-                                                   uint32_t *icount, uint8_t *iaxis,
-                                                   int32_t *parent) {
-    __shared__ KeyT sk[kKarrasWindow];
-    const int w0 = (int)(blockIdx.x * kBlock) - kKarrasHalo;
-    for (int k = threadIdx.x; k < kKarrasWindow; k += kBlock) {
-        const int j = w0 + k;
-        if (j >= 0 && j < n) sk[k] = keys[j];
-    }
-    __syncthreads();
-    const KeyWindow<KeyT> kw{keys, sk, w0};
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n - 1) return;
+__device__ inline uint32_t karras_node(const KeyWindow<KeyT> &kw, int n, int i, int32_t *ileft,
+                                       int32_t *iright, uint32_t *ifirst, uint32_t *icount,
+                                       uint8_t *iaxis, int32_t *parent, int L) {
     const KeyT ki = kw.at(i);
     const int d = (common_prefix(kw, ki, n, i, i + 1) - common_prefix(kw, ki, n, i, i - 1)) >= 0 ? 1 : -1;
     const int dmin = common_prefix(kw, ki, n, i, i - d);
@@ -626,7 +617,39 @@ __global__ __launch_bounds__(kBlock) void k_karras(const KeyT *keys, int n, int3
     }
     iaxis[i] = axis;
     if (i == 0) parent[0] = -1;
+    const int cnt = last - first + 1, cl = gamma - first + 1, cr = last - gamma;
+    if (cnt > L) return (uint32_t)(cl <= L) + (uint32_t)(cr <= L);
+    return (i == 0) ? 1u : 0u;  // the root of at most L primitives is the only leaf
 }
+
+// With leaf_slots (the wide layouts): also counts the collapsed tree's leaves
+// (leaf size L), which are the children of at most L primitives of the nodes
+// of more than L, or the root alone when it holds at most L; per-wave counts
+// are added into the kMaxSlots slots a line apart, as in k_count_leaves.
+template <typename KeyT>
+__global__ __launch_bounds__(kBlock) void k_karras(const KeyT *keys, int n, int32_t *ileft,
+                                                   int32_t *iright, uint32_t *ifirst,
+                                                   uint32_t *icount, uint8_t *iaxis,
+                                                   int32_t *parent, int L, uint32_t *leaf_slots) {
+    __shared__ KeyT sk[kKarrasWindow];
+    const int w0 = (int)(blockIdx.x * kBlock) - kKarrasHalo;
+    for (int k = threadIdx.x; k < kKarrasWindow; k += kBlock) {
+        const int j = w0 + k;
+        if (j >= 0 && j < n) sk[k] = keys[j];
+    }
+    __syncthreads();
+    const KeyWindow<KeyT> kw{keys, sk, w0};
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t leaves = 0;
+    if (i < n - 1) leaves = karras_node(kw, n, i, ileft, iright, ifirst, icount, iaxis, parent, L);
+    if (leaf_slots) {  // every lane of the wave arrives here
+        const uint32_t c = (uint32_t)__popcll(__ballot(leaves >= 1)) + (uint32_t)__popcll(__ballot(leaves >= 2));
+        const uint32_t wave = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+        if ((threadIdx.x & (kWave - 1)) == 0 && c)
+            atomicAdd(&leaf_slots[(wave & (kMaxSlots - 1)) * kSlotStride], c);
+    }
+}
+
 
 // ---------------------------------------------------------------------------
 // a5: node boxes.  Every node of the hierarchy covers a contiguous range of
@@ -2751,6 +2774,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         BVH_HIP_TRY(hipEventRecord(side->done, side->stream));
         return BVH_OK;
     };
+    uint32_t *karras_leaves = nullptr;  // leaf-count slots filled by k_karras (else by k_count_leaves)
     if (h->builder == BVH_BUILDER_SAH) {
         // a4 alternative: binned-SAH topology over the primitive boxes
         BVH_TRY(check_launch("bounds"));
@@ -2774,14 +2798,15 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
         perm = vals[cur];
         BVH_TRY(leaf_data_early());
 
-        // a4
+        // a4 (for the wide layouts, also the leaf count of the collapse)
         if (n > 1) {
+            karras_leaves = wide ? bound_slots + 2 * kMaxSlots * kSlotStride : nullptr;
             if (narrow)
                 k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(k32[cur], n, ileft, iright, ifirst,
-                                                            icount, iaxis, parent);
+                                                            icount, iaxis, parent, L, karras_leaves);
             else
                 k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst,
-                                                            icount, iaxis, parent);
+                                                            icount, iaxis, parent, L, karras_leaves);
         }
     }
     {  // a5
@@ -2806,7 +2831,8 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // box and the marks' exclusive scan before packing
     if (wide) {
         uint32_t *leaf_slots = bound_slots + 2 * kMaxSlots * kSlotStride;
-        k_count_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, leaf_slots);
+        if (!karras_leaves)
+            k_count_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, leaf_slots);
         k_fold_leaf_count<<<1, kBlock, 0, s>>>(leaf_slots, hw + 8);
     } else {
         k_mark_leaves<<<grid_for(2 * (uint64_t)n - 1), kBlock, 0, s>>>(tv, mark);
