@@ -83,10 +83,62 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *total, uint32_t
     return off + inc - v;
 }
 
-__device__ inline float wave_min(float v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+__device__ inline float readlane_t(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline uint32_t readlane_t(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Cross-lane steps through DPP (data-parallel primitives of the VALU: one
+// instruction each, no LDS traffic).  dpp<CTRL, ROWS>(old, v) gives each lane
+// of the written rows the value v of its source lane, or `old` where the
+// source is outside the row; GFX9 controls: row_shl:n = 0x100 + n, row_shr:n
+// = 0x110 + n, wave_shl:1 = 0x130, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROWS, typename T>
+__device__ inline T dpp(T old, T v) {
+    static_assert(sizeof(T) == 4, "32-bit lanes");
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                             __builtin_bit_cast(int, v), CTRL,
+                                                             ROWS, 0xf, false));
+}
+// Inclusive scan within each 32-lane half (lanes 0-31 and 32-63): within the
+// 16-lane rows, then the last lane of rows 0 and 2 into rows 1 and 3.
+template <typename T, typename Op>
+__device__ inline T half_scan(T v, T id, Op op) {
+    v = op(v, dpp<0x111, 0xf>(id, v));
+    v = op(v, dpp<0x112, 0xf>(id, v));
+    v = op(v, dpp<0x114, 0xf>(id, v));
+    v = op(v, dpp<0x118, 0xf>(id, v));
+    return op(v, dpp<0x142, 0xa>(id, v));
+}
+// Inclusive suffix scan within each 32-lane half: within the rows, then the
+// first lane of rows 1 and 3 (their row totals by then) into rows 0 and 2.
+template <typename T, typename Op>
+__device__ inline T half_suffix_scan(T v, T id, Op op, int lane) {
+    v = op(v, dpp<0x101, 0xf>(id, v));
+    v = op(v, dpp<0x102, 0xf>(id, v));
+    v = op(v, dpp<0x104, 0xf>(id, v));
+    v = op(v, dpp<0x108, 0xf>(id, v));
+    const T r1 = readlane_t(v, 16), r3 = readlane_t(v, 48);
+    if (lane < 16) v = op(v, r1);
+    else if (lane >= 32 && lane < 48) v = op(v, r3);
     return v;
+}
+// Whole-wave reduction: the row scans, the two broadcasts, then lane 63.
+template <typename T, typename Op>
+__device__ inline T wave_reduce(T v, T id, Op op) {
+    v = op(v, dpp<0x111, 0xf>(id, v));
+    v = op(v, dpp<0x112, 0xf>(id, v));
+    v = op(v, dpp<0x114, 0xf>(id, v));
+    v = op(v, dpp<0x118, 0xf>(id, v));
+    v = op(v, dpp<0x142, 0xa>(id, v));
+    v = op(v, dpp<0x143, 0xc>(id, v));
+    return readlane_t(v, 63);
+}
+
+__device__ inline float wave_min(float v) {
+    return wave_reduce<float>(v, INFINITY, [](float a, float b) { return fminf(a, b); });
 }
 // Build-wide maxima (stack and depth bounds) without contention: one
 // atomicMax per wave into one of kMaxSlots slots chosen by the wave's global
@@ -107,9 +159,7 @@ __device__ inline void wave_max_to_slots(uint32_t *slots, uint32_t v) {
 }
 
 __device__ inline float wave_max(float v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
+    return wave_reduce<float>(v, -INFINITY, [](float a, float b) { return fmaxf(a, b); });
 }
 
 // ---------------------------------------------------------------------------
@@ -2106,60 +2156,37 @@ __device__ inline void wave_sync() {
 __device__ inline void sah_sweep(uint32_t cnt, float lx, float ly, float lz, float hx, float hy,
                                  float hz, float &best_cost, int &best_k, uint32_t &best_nl) {
     const int lane = threadIdx.x & (kWave - 1);
-    // inclusive prefix over lanes 0..k and suffix over lanes k..31
-    uint32_t pc = cnt, sc = cnt;
-    float p[6] = {lx, ly, lz, hx, hy, hz}, q[6] = {lx, ly, lz, hx, hy, hz};
+    // inclusive prefix over lanes 0..k and suffix over lanes k..31 (lanes 32-63
+    // hold empty bins and scan among themselves)
+    const auto add = [](uint32_t x, uint32_t y) { return x + y; };
+    const auto mn = [](float x, float y) { return fminf(x, y); };
+    const auto mx = [](float x, float y) { return fmaxf(x, y); };
+    const uint32_t pc = half_scan<uint32_t>(cnt, 0u, add);
+    const uint32_t sc = half_suffix_scan<uint32_t>(cnt, 0u, add, lane);
+    const float in[6] = {lx, ly, lz, hx, hy, hz};
+    float p[6], q[6];
 #pragma unroll
-    for (int o = 1; o < kSahBins; o <<= 1) {
-        const uint32_t tc = __shfl_up(pc, o, kWave);
-        const uint32_t uc = __shfl_down(sc, o, kWave);
-        float tp[6], tq[6];
-#pragma unroll
-        for (int j = 0; j < 6; j++) {
-            tp[j] = __shfl_up(p[j], o, kWave);
-            tq[j] = __shfl_down(q[j], o, kWave);
-        }
-        if (lane >= o) {
-            pc += tc;
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                p[j] = fminf(p[j], tp[j]);
-                p[3 + j] = fmaxf(p[3 + j], tp[3 + j]);
-            }
-        }
-        if (lane + o < kSahBins) {
-            sc += uc;
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                q[j] = fminf(q[j], tq[j]);
-                q[3 + j] = fmaxf(q[3 + j], tq[3 + j]);
-            }
-        }
+    for (int j = 0; j < 3; j++) {
+        p[j] = half_scan<float>(in[j], INFINITY, mn);
+        q[j] = half_suffix_scan<float>(in[j], INFINITY, mn, lane);
+        p[3 + j] = half_scan<float>(in[3 + j], -INFINITY, mx);
+        q[3 + j] = half_suffix_scan<float>(in[3 + j], -INFINITY, mx, lane);
     }
-    // right side of split k is the suffix starting at bin k + 1
-    const uint32_t rc = __shfl_down(sc, 1, kWave);
+    // right side of split k is the suffix starting at bin k + 1 (wave_shl:1)
+    const uint32_t rc = dpp<0x130, 0xf>(0u, sc);
     float r[6];
 #pragma unroll
-    for (int j = 0; j < 6; j++) r[j] = __shfl_down(q[j], 1, kWave);
+    for (int j = 0; j < 6; j++) r[j] = dpp<0x130, 0xf>(j < 3 ? INFINITY : -INFINITY, q[j]);
     float cost = INFINITY;
     if (lane < kSahBins - 1 && pc > 0 && rc > 0)
         cost = half_area3(p[0], p[1], p[2], p[3], p[4], p[5]) * (float)pc +
                half_area3(r[0], r[1], r[2], r[3], r[4], r[5]) * (float)rc;
     // minimum over the lanes, lowest k on ties
-    float c = cost;
-    int k = lane < kSahBins - 1 ? lane : kSahBins;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const float oc = __shfl_xor(c, o, kWave);
-        const int ok = __shfl_xor(k, o, kWave);
-        if (oc < c || (oc == c && ok < k)) {
-            c = oc;
-            k = ok;
-        }
-    }
+    const float c = wave_min(cost);
+    const uint64_t at = __builtin_amdgcn_ballot_w64(lane < kSahBins - 1 && cost == c);
     best_cost = c;
-    best_k = c < INFINITY ? k : -1;
-    best_nl = __shfl(pc, best_k < 0 ? 0 : best_k, kWave);
+    best_k = (c < INFINITY && at != 0) ? (int)__builtin_ctzll(at) : -1;
+    best_nl = readlane_t(pc, best_k < 0 ? 0 : best_k);
 }
 
 // Id of the node that splits at leaf position m (m-1 naturally; see above).
@@ -2206,16 +2233,19 @@ struct SahLevel {
     int *bins;                // per task: kSahBinWords
     SahSplit *split;          // per task
     uint32_t ntask;
+    const uint32_t *tc0;      // per task: its first chunk (a task's chunks are consecutive)
+    int *cbins;               // per chunk: kSahBinWords (the chunk's partial bins)
+    int *gbins;               // merge groups > 1: per task and group, kSahBinWords
+    uint32_t groups;          // chunk groups per task in the merge (1 or kMergeGroups)
 };
 
-__global__ __launch_bounds__(kBlock) void k_sah_clear(int *cb, int *bins, uint32_t ntask) {
+// Chunk groups of a task of nch chunks in a level merged with `groups` groups.
+__device__ inline uint32_t merge_groups(uint32_t nch, uint32_t groups) { return min(nch, groups); }
+
+__global__ __launch_bounds__(kBlock) void k_sah_clear(int *cb, uint32_t ntask) {
     const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const int inf = f2o(INFINITY), ninf = f2o(-INFINITY);
     if (i < (uint64_t)ntask * 6) cb[i] = (i % 6) < 3 ? inf : ninf;
-    if (i < (uint64_t)ntask * kSahBinWords) {
-        const uint32_t w = (uint32_t)(i % 7);
-        bins[i] = w == 0 ? 0 : (w <= 3 ? inf : ninf);
-    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sah_bounds(SahLevel lv, const uint32_t *ord,
@@ -2257,24 +2287,33 @@ __device__ inline SahFrame sah_task_frame(const int *cb) {
     return sah_frame(cl, ch);
 }
 
+// Binning of one chunk.  Neighbouring primitives (in the current order)
+// mostly fall in one bin, so the lanes of a wave instruction would update the
+// same LDS words: the block keeps kBinCopies copies of the bins, lane i using
+// copy i % kBinCopies (copies a bank apart), which divides those conflicts by
+// kBinCopies; the copies are combined when the chunk is done.
+constexpr int kBinCopies = 8;
+constexpr int kBinCopyStride = kSahBinWords + 1;  // odd: copies in different banks
+
 __global__ __launch_bounds__(kBlock) void k_sah_bin(SahLevel lv, const uint32_t *ord,
                                                     const Box *pbox) {
-    __shared__ int sb[kSahBinWords];
+    __shared__ int sb[kBinCopies * kBinCopyStride];
     const uint32_t t = lv.chunk[blockIdx.x];
     const SahTask tk = lv.task[t];
     const uint32_t p0 = lv.cstart[blockIdx.x], p1 = min(p0 + kSahChunk, tk.first + tk.count);
     const int inf = f2o(INFINITY), ninf = f2o(-INFINITY);
-    for (uint32_t i = threadIdx.x; i < kSahBinWords; i += kBlock) {
-        const uint32_t w = i % 7;
+    for (uint32_t i = threadIdx.x; i < kBinCopies * kBinCopyStride; i += kBlock) {
+        const uint32_t w = (i % kBinCopyStride) % 7;
         sb[i] = w == 0 ? 0 : (w <= 3 ? inf : ninf);
     }
     __syncthreads();
     const SahFrame f = sah_task_frame(lv.cb + 6 * t);
+    int *mine = sb + (threadIdx.x % kBinCopies) * kBinCopyStride;
     for (uint32_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
         const Box b = pbox[ord[p]];
         for (int a = 0; a < 3; a++) {
             if (!f.valid[a]) continue;
-            int *bin = sb + (a * kSahBins + sah_bin(f, a, sah_centroid(b, a))) * 7;
+            int *bin = mine + (a * kSahBins + sah_bin(f, a, sah_centroid(b, a))) * 7;
             atomicAdd(bin, 1);
             atomicMin(bin + 1, f2o(b.lo.x));
             atomicMin(bin + 2, f2o(b.lo.y));
@@ -2285,31 +2324,71 @@ __global__ __launch_bounds__(kBlock) void k_sah_bin(SahLevel lv, const uint32_t 
         }
     }
     __syncthreads();
-    int *gb = lv.bins + (size_t)t * kSahBinWords;
+    // the chunk's partial bins, every word (k_sah_merge combines a task's
+    // chunks; device atomics from every chunk of a large task into one set of
+    // words serialised across the XCDs)
+    int *cbin = lv.cbins + (size_t)blockIdx.x * kSahBinWords;
     for (uint32_t i = threadIdx.x; i < kSahBinWords; i += kBlock) {
-        const uint32_t w = i % 7;
-        const int v = sb[i];
-        if (sb[i - w] == 0) continue;  // empty bin
-        if (w == 0) atomicAdd(gb + i, v);
-        else if (w <= 3) atomicMin(gb + i, v);
-        else atomicMax(gb + i, v);
+        const uint32_t kind = i % 7;
+        int v = sb[i];
+        for (int c = 1; c < kBinCopies; c++) {
+            const int x = sb[c * kBinCopyStride + i];
+            v = kind == 0 ? v + x : (kind <= 3 ? min(v, x) : max(v, x));
+        }
+        cbin[i] = v;
     }
 }
 
-// One wave per node: the sweep over the three axes, then the node's id and
-// record, and its children: single primitives are linked here, small ones
-// queued for the per-wave finisher, large ones queued (with their chunks)
-// for the next level.
-__global__ __launch_bounds__(kBlock) void k_sah_split(SahLevel lv, SahTree tr, uint32_t *root_nat,
-                                                      bool root_level, SahTask *next,
-                                                      uint32_t *next_chunk, uint32_t *next_cstart,
-                                                      uint32_t *counters, SahTask *small,
-                                                      uint32_t *small_count) {
-    const uint32_t t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (t >= lv.ntask) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const SahTask tk = lv.task[t];
-    const int *gb = lv.bins + (size_t)t * kSahBinWords;
+// bins of task t = the combination of its chunks' partial bins: counts
+// added, ordered-int lower corners by minimum, upper corners by maximum (the
+// same integers in any order).  Block (t, g) combines chunk group g of task
+// t: with one group it writes the task's bins, with several its group's
+// partial bins (sah_split_node combines the groups; levels of few, large
+// tasks use several, so that one block does not read all the chunks of the
+// root).  A task of one chunk is read from its chunk directly.
+constexpr uint32_t kMergeGroups = 16;
+constexpr uint32_t kMergeGroupTasks = 256;  // most tasks of a level merged with several groups
+
+__device__ inline int bin_combine(uint32_t kind, int v, int x) {
+    return kind == 0 ? v + x : (kind <= 3 ? min(v, x) : max(v, x));
+}
+
+__global__ __launch_bounds__(kBlock) void k_sah_merge(SahLevel lv) {
+    const uint32_t t = blockIdx.x, g = blockIdx.y;
+    const uint32_t nch = (lv.task[t].count + kSahChunk - 1) / kSahChunk, c0 = lv.tc0[t];
+    const uint32_t ng = merge_groups(nch, lv.groups);
+    if (nch < 2 || g >= ng) return;
+    const uint32_t j0 = (uint32_t)((uint64_t)g * nch / ng), j1 = (uint32_t)((uint64_t)(g + 1) * nch / ng);
+    int *dst = ng > 1 ? lv.gbins + ((size_t)t * kMergeGroups + g) * kSahBinWords
+                      : lv.bins + (size_t)t * kSahBinWords;
+    for (uint32_t w = threadIdx.x; w < (uint32_t)kSahBinWords; w += kBlock) {
+        const int *src = lv.cbins + (size_t)c0 * kSahBinWords + w;
+        const uint32_t kind = w % 7;  // 0: count, 1-3: lower corner, 4-6: upper corner
+        int v = src[(size_t)j0 * kSahBinWords];
+        uint32_t j = j0 + 1;
+        for (; j + 4 <= j1; j += 4) {  // four independent loads in flight
+            const int x0 = src[(size_t)j * kSahBinWords], x1 = src[(size_t)(j + 1) * kSahBinWords];
+            const int x2 = src[(size_t)(j + 2) * kSahBinWords], x3 = src[(size_t)(j + 3) * kSahBinWords];
+            v = bin_combine(kind, v, bin_combine(kind, bin_combine(kind, x0, x1), bin_combine(kind, x2, x3)));
+        }
+        for (; j < j1; j++) v = bin_combine(kind, v, src[(size_t)j * kSahBinWords]);
+        dst[w] = v;
+    }
+}
+
+// The sweep and record of node t (one wave); leaves its task, id and left
+// count in tk, id, nl (the same in every lane).
+__device__ inline void sah_split_node(SahLevel lv, SahTree tr, uint32_t *root_nat, bool root_level,
+                                      uint32_t t, int lane, SahTask &tk, uint32_t &id,
+                                      uint32_t &nl_out) {
+    tk = lv.task[t];
+    const uint32_t nch = (tk.count + kSahChunk - 1) / kSahChunk;
+    const uint32_t ng = nch < 2 ? 1u : merge_groups(nch, lv.groups);
+    // one chunk: its chunk's bins; several in one group: the merged bins;
+    // several groups: the groups' partial bins, combined here
+    const int *gb = nch < 2 ? lv.cbins + (size_t)lv.tc0[t] * kSahBinWords
+                            : (ng > 1 ? lv.gbins + (size_t)t * kMergeGroups * kSahBinWords
+                                      : lv.bins + (size_t)t * kSahBinWords);
     const SahFrame f = sah_task_frame(lv.cb + 6 * t);
     float best = INFINITY;
     int axis = -1, bk = -1;
@@ -2318,13 +2397,17 @@ __global__ __launch_bounds__(kBlock) void k_sah_split(SahLevel lv, SahTree tr, u
         if (!f.valid[a]) continue;
         const int *bin = gb + (a * kSahBins + (lane < kSahBins ? lane : 0)) * 7;
         const bool in = lane < kSahBins;
-        const uint32_t c = in ? (uint32_t)bin[0] : 0u;
+        int wv[7];
+        for (int j = 0; j < 7; j++) wv[j] = bin[j];
+        for (uint32_t g = 1; g < ng; g++)
+            for (int j = 0; j < 7; j++) wv[j] = bin_combine((uint32_t)j, wv[j], bin[(size_t)g * kSahBinWords + j]);
+        const uint32_t c = in ? (uint32_t)wv[0] : 0u;
         float cost;
         int k;
         uint32_t l;
-        sah_sweep(c, in ? o2f(bin[1]) : INFINITY, in ? o2f(bin[2]) : INFINITY,
-                  in ? o2f(bin[3]) : INFINITY, in ? o2f(bin[4]) : -INFINITY,
-                  in ? o2f(bin[5]) : -INFINITY, in ? o2f(bin[6]) : -INFINITY, cost, k, l);
+        sah_sweep(c, in ? o2f(wv[1]) : INFINITY, in ? o2f(wv[2]) : INFINITY,
+                  in ? o2f(wv[3]) : INFINITY, in ? o2f(wv[4]) : -INFINITY,
+                  in ? o2f(wv[5]) : -INFINITY, in ? o2f(wv[6]) : -INFINITY, cost, k, l);
         if (cost < best) {
             best = cost;
             axis = a;
@@ -2340,29 +2423,92 @@ __global__ __launch_bounds__(kBlock) void k_sah_split(SahLevel lv, SahTree tr, u
     const uint32_t m = tk.first + nl;
     if (root_level && lane == 0) *root_nat = m - 1;
     const uint32_t rn = root_level ? m - 1 : *root_nat;
-    const uint32_t id = sah_node_id(m, tk.parent < 0, rn);
+    id = sah_node_id(m, tk.parent < 0, rn);
+    nl_out = nl;
     if (lane == 0) {
         lv.split[t] = SahSplit{axis, bk, nl, id};
         sah_write_node(tr, id, tk.first, tk.count, axis, nl, tk.parent, tk.side);
-        const uint32_t cf[2] = {tk.first, m}, cc[2] = {nl, tk.count - nl};
-        for (int s = 0; s < 2; s++) {
-            if (cc[s] < 2) continue;
-            const SahTask ch{cf[s], cc[s], (int32_t)id, (uint32_t)s};
-            if (cc[s] <= kSahSmall) {
-                small[atomicAdd(small_count, 1u)] = ch;
+    }
+}
+
+// One wave per node: the sweep over the three axes, then the node's id and
+// record, and its children: single primitives are linked here, small ones
+// queued for the per-wave finisher, large ones queued (with their chunks)
+// for the next level.  The queue slots of a block's nodes are taken with one
+// device atomic per queue and block (per-node atomics on the three counters
+// serialised across the XCDs: 0.2-0.45 ms per level with thousands of nodes).
+constexpr int kSplitThreads = 1024;
+constexpr int kSplitWaves = kSplitThreads / kWave;
+
+__global__ __launch_bounds__(kSplitThreads) void k_sah_split(SahLevel lv, SahTree tr,
+                                                             uint32_t *root_nat, bool root_level,
+                                                             SahTask *next, uint32_t *next_chunk,
+                                                             uint32_t *next_cstart,
+                                                             uint32_t *next_tc0,
+                                                             uint32_t *counters, SahTask *small,
+                                                             uint32_t *small_count) {
+    __shared__ uint32_t need[3][kSplitWaves];  // per wave: small tasks, next tasks, next chunks
+    __shared__ uint32_t base[3];
+    const int wv = threadIdx.x / kWave;
+    const uint32_t t = blockIdx.x * kSplitWaves + wv;
+    const bool live = t < lv.ntask;
+    const int lane = threadIdx.x & (kWave - 1);
+    SahTask tk{0, 0, -1, 0};
+    uint32_t id = 0, nl = 0;
+    if (live) sah_split_node(lv, tr, root_nat, root_level, t, lane, tk, id, nl);
+    // the node's children that need queue slots
+    const uint32_t cf[2] = {tk.first, tk.first + nl}, cc[2] = {nl, tk.count - nl};
+    uint32_t ns = 0, nn = 0, nc = 0;
+    if (live) {
+        for (int sd = 0; sd < 2; sd++) {
+            if (cc[sd] < 2) continue;
+            if (cc[sd] <= kSahSmall) {
+                ns++;
             } else {
-                const uint32_t slot = atomicAdd(&counters[0], 1u);
-                next[slot] = ch;
-                const uint32_t nch = (cc[s] + kSahChunk - 1) / kSahChunk;
-                const uint32_t c0 = atomicAdd(&counters[1], nch);
-                for (uint32_t j = 0; j < nch; j++) {
-                    next_chunk[c0 + j] = slot;
-                    next_cstart[c0 + j] = cf[s] + j * kSahChunk;
-                }
+                nn++;
+                nc += (cc[sd] + kSahChunk - 1) / kSahChunk;
             }
         }
     }
+    if (lane == 0) {
+        need[0][wv] = ns;
+        need[1][wv] = nn;
+        need[2][wv] = nc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kSplitWaves; w++) tot += need[threadIdx.x][w];
+        uint32_t *ctr = threadIdx.x == 0 ? small_count : &counters[threadIdx.x - 1];
+        base[threadIdx.x] = tot ? atomicAdd(ctr, tot) : 0u;
+    }
+    __syncthreads();
+    if (!live || lane != 0) return;
+    uint32_t so = base[0], no = base[1], co = base[2];
+    for (int w = 0; w < wv; w++) {
+        so += need[0][w];
+        no += need[1][w];
+        co += need[2][w];
+    }
+    for (int sd = 0; sd < 2; sd++) {
+        if (cc[sd] < 2) continue;
+        const SahTask ch{cf[sd], cc[sd], (int32_t)id, (uint32_t)sd};
+        if (cc[sd] <= kSahSmall) {
+            small[so++] = ch;
+        } else {
+            const uint32_t slot = no++;
+            next[slot] = ch;
+            next_tc0[slot] = co;
+            const uint32_t nch = (cc[sd] + kSahChunk - 1) / kSahChunk;
+            for (uint32_t j = 0; j < nch; j++) {
+                next_chunk[co + j] = slot;
+                next_cstart[co + j] = cf[sd] + j * kSahChunk;
+            }
+            co += nch;
+        }
+    }
 }
+
 
 __global__ __launch_bounds__(kBlock) void k_sah_flags(SahLevel lv, const uint32_t *ord,
                                                       const Box *pbox, uint32_t *flags) {
@@ -2557,7 +2703,8 @@ __global__ __launch_bounds__(kBlock) void k_sah_small(const SahTask *small, uint
 }
 
 __global__ void k_sah_init(uint32_t *ord, uint32_t *perm, uint32_t n, SahTask *task,
-                           uint32_t *chunk, uint32_t *cstart, SahTask *small, uint32_t *nsmall) {
+                           uint32_t *chunk, uint32_t *cstart, uint32_t *tc0, SahTask *small,
+                           uint32_t *nsmall) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) {
         ord[i] = i;
@@ -2567,6 +2714,7 @@ __global__ void k_sah_init(uint32_t *ord, uint32_t *perm, uint32_t n, SahTask *t
         const SahTask root{0u, n, -1, 0u};
         if (n > kSahSmall) {
             task[0] = root;
+            tc0[0] = 0;
         } else {
             small[0] = root;
             *nsmall = 1;
@@ -2595,10 +2743,11 @@ int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, ui
     }
     const uint32_t cap_task = n / (kSahSmall + 1) + 1;
     const uint32_t cap_chunk = (n + kSahChunk - 1) / kSahChunk + cap_task;
-    uint32_t *ord[2], *flags, *offs, *chunk[2], *cstart[2], *counters, *small_count, *root_nat;
+    uint32_t *ord[2], *flags, *offs, *chunk[2], *cstart[2], *tc0[2], *counters, *small_count,
+        *root_nat;
     SahTask *task[2], *small;
     SahSplit *split;
-    int *cb, *bins;
+    int *cb, *bins, *cbins, *gbins;
     Arena ar;
     ar.request(&ord[0], n);
     ar.request(&ord[1], n);
@@ -2613,6 +2762,10 @@ int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, ui
     ar.request(&split, cap_task);
     ar.request(&cb, (size_t)cap_task * 6);
     ar.request(&bins, (size_t)cap_task * kSahBinWords);
+    ar.request(&cbins, (size_t)cap_chunk * kSahBinWords);
+    ar.request(&gbins, (size_t)kMergeGroupTasks * kMergeGroups * kSahBinWords);
+    ar.request(&tc0[0], cap_task);
+    ar.request(&tc0[1], cap_task);
     ar.request(&small, n / 2 + 1);
     ar.request(&counters, 2 * kSahMaxLevels + 4);
     BVH_TRY(ar.bind(s, kAreaSah));
@@ -2621,8 +2774,8 @@ int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, ui
     uint32_t *err = small_count + 2;
     BVH_HIP_TRY(hipMemsetAsync(counters, 0, (2 * kSahMaxLevels + 4) * sizeof(uint32_t), s));
     BVH_HIP_TRY(hipMemsetAsync(flags, 0, (size_t)n * sizeof(uint32_t), s));
-    k_sah_init<<<grid_for(n), kBlock, 0, s>>>(ord[0], perm, n, task[0], chunk[0], cstart[0], small,
-                                              small_count);
+    k_sah_init<<<grid_for(n), kBlock, 0, s>>>(ord[0], perm, n, task[0], chunk[0], cstart[0], tc0[0],
+                                              small, small_count);
     BVH_TRY(check_launch("sah init"));
     uint32_t *hw = host_words();
     if (!hw) return set_error(BVH_ENOMEM, "hipHostMalloc failed");
@@ -2634,13 +2787,17 @@ int32_t sah_topology(const Box *pbox, uint32_t n, uint32_t *perm, SahTree tr, ui
         if (level >= kSahMaxLevels)
             return set_error(BVH_EUNSUPPORTED,
                              "bvh_build: SAH tree deeper than the traversal stack bound %d", kStackMax);
-        SahLevel lv{task[cur], chunk[cur], cstart[cur], cb, bins, split, ntask};
-        k_sah_clear<<<grid_for((uint64_t)ntask * kSahBinWords), kBlock, 0, s>>>(cb, bins, ntask);
+        // few tasks with several chunks each: merge them with several groups
+        const uint32_t groups = (ntask <= kMergeGroupTasks && nchunk >= 2 * ntask) ? kMergeGroups : 1u;
+        SahLevel lv{task[cur], chunk[cur], cstart[cur], cb, bins, split, ntask, tc0[cur], cbins,
+                    gbins, groups};
+        k_sah_clear<<<grid_for((uint64_t)ntask * 6), kBlock, 0, s>>>(cb, ntask);
         k_sah_bounds<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], pbox);
         k_sah_bin<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], pbox);
-        k_sah_split<<<(ntask + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(
+        k_sah_merge<<<dim3(ntask, groups), kBlock, 0, s>>>(lv);
+        k_sah_split<<<(ntask + kSplitWaves - 1) / kSplitWaves, kSplitThreads, 0, s>>>(
             lv, tr, root_nat, level == 0, task[cur ^ 1], chunk[cur ^ 1], cstart[cur ^ 1],
-            counters + 2 * level, small, small_count);
+            tc0[cur ^ 1], counters + 2 * level, small, small_count);
         k_sah_flags<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], pbox, flags);
         scan_u32(flags, offs, n, tile, nullptr, s);
         k_sah_scatter<<<nchunk, kBlock, 0, s>>>(lv, ord[cur], flags, offs, ord[cur ^ 1], perm, err);
