@@ -64,6 +64,23 @@ ALU_OPS_NODE = {
     "bvh4": 4 * ALU_OPS_BOX,
     "bvh8_q8": 8 * (ALU_OPS_BOX + ALU_OPS_DEQUANT), "bvh8_q16": 8 * (ALU_OPS_BOX + ALU_OPS_DEQUANT),
 }
+# Closest-point queries, the same model: one point/box distance (per axis two
+# subtractions and two maxima, then one multiply and two FMAs for the squared
+# distance, the conservative scale and the compare with the best): 17; one
+# point/triangle test (Ericson's regions, written branch-free: the three
+# offsets p - a, p - b, p - c (9), six dot products (18), the three
+# sub-determinants (6), the region flags (26), the chosen region's division
+# as a reciprocal and a multiply with its operand selects (14), the
+# barycentrics and their selects (16), the face check (12), the point, its
+# offset and squared distance (12), the best update (5)): 118.
+ALU_OPS_CP_BOX, ALU_OPS_CP_TRI = 17, 118
+ALU_OPS_CP_NODE = {  # per node record fetched: the distance to every box it holds
+    "aabb2": ALU_OPS_CP_BOX, "pbrt_soaos": ALU_OPS_CP_BOX, "shared_slab": ALU_OPS_CP_BOX,
+    "pbrt_q16": ALU_OPS_CP_BOX + ALU_OPS_DEQUANT, "sg_eq": ALU_OPS_CP_BOX + ALU_OPS_DEQUANT,
+    "pbrt_q16_soaos": ALU_OPS_CP_BOX + ALU_OPS_DEQUANT, "sg_eq_a16": ALU_OPS_CP_BOX + ALU_OPS_DEQUANT,
+    "bvh4": 4 * ALU_OPS_CP_BOX,
+    "bvh8_q8": 8 * (ALU_OPS_CP_BOX + ALU_OPS_DEQUANT), "bvh8_q16": 8 * (ALU_OPS_CP_BOX + ALU_OPS_DEQUANT),
+}
 RAY_BYTES, HIT_BYTES = 32, 16
 # Backward, algorithmic bytes per ray: the ray (32), its hit record (16), the
 # loss gradient g (12), the triangle's indices (12) and three vertices (36) in;
@@ -421,11 +438,15 @@ def closest_point_rows(torch, bvh, W, verts_np, verts, tris_np, tris, args, seed
         c = c.cpu().numpy().astype(np.float64)
         by = QUERY_BYTES + CLOSEST_BYTES + c[:, 0] * st["node_bytes"] + c[:, 1] * LEAF_TRI_BYTES["compact"]
         gbs = by.sum() / (t_ms / 1000.0) / 1e9
+        ops = c[:, 0] * ALU_OPS_CP_NODE[layout] + c[:, 1] * ALU_OPS_CP_TRI
+        tops = ops.sum() / (t_ms / 1000.0) / 1e12
         res[key] = {"mqueries_s": round(q.shape[0] / (t_ms / 1000.0) / 1e6, 1),
                        "ms": round(t_ms, 4), "nodes_per_query": round(float(c[:, 0].mean()), 1),
                        "tris_per_query": round(float(c[:, 1].mean()), 1),
                        "bytes_per_query": round(float(by.mean()), 1),
-                       "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                       "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "ops_per_query": round(float(ops.mean()), 1), "alu_tops": round(tops, 3),
+                       "alu_frac": round(tops / ALU_PEAK_TOPS, 4)}
         h.close()
         log(f"closest point {key}: {res[key]}")
     if not args.no_cpu_baseline:

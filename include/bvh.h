@@ -475,7 +475,8 @@ typedef struct bvh_closest {
  * Collision Detection 5.1.5) in f32, the method of the paper's listing, on
  * a = p0, ab = p1 - p0, ac = p2 - p0; d2, u, v are that computation's f32
  * results.  A degenerate triangle is measured by its edges.  The handle's
- * stack_lds applies with at most 16 entries.
+ * stack_lds applies with at most 16 entries; when the build left it at its
+ * default, the wide layouts use 8.  Results do not depend on it.
  *   queries  device, n records;  out  device, n records (written)
  * A query whose point has a non-finite coordinate, or whose r2 is negative
  * or NaN, gets {-1, +inf, 0, 0}.

@@ -3192,6 +3192,8 @@ extern "C" int32_t bvh_build(const float *verts, int64_t n_verts, const int32_t 
     if (n_tris > kMaxTris)
         return set_error(BVH_EUNSUPPORTED, "bvh_build: %lld triangles exceed %lld",
                          (long long)n_tris, (long long)kMaxTris);
-    return build_handle(verts, n_verts, tris, n_tris, layout, leaf_size, leaf_mode, stack_lds,
-                        builder, static_cast<hipStream_t>(stream), out);
+    const int32_t rc = build_handle(verts, n_verts, tris, n_tris, layout, leaf_size, leaf_mode,
+                                    stack_lds, builder, static_cast<hipStream_t>(stream), out);
+    if (rc == BVH_OK && *out) (*out)->stack_lds_default = !(opts && opts->stack_lds != 0);
+    return rc;
 }

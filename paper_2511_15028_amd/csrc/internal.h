@@ -60,6 +60,7 @@ struct bvh_handle_s {
     int32_t leaf_mode = 0;
     int32_t leaf_size = 4;
     int32_t stack_lds = 16;
+    bool stack_lds_default = false;  // stack_lds left to the build's default
     int32_t builder = BVH_BUILDER_LBVH;
     int32_t arity = 2;
     int64_t n_tris = 0;

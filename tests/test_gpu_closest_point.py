@@ -226,12 +226,13 @@ def test_edge_cases(orc, layout):
 def test_stack_depths_agree_and_fallback_is_exact(orc, layout):
     """Leaf size 1 makes deep trees; with an 8-entry LDS ring many queries
     spill and some reach the deep-stack fallback pass.  Results must be
-    identical for 8, 16 and 32 entries and match the oracle."""
+    identical for 8, 16 and 32 entries and the default (0: 8 for the wide
+    layouts' query, 16 for the binary ones) and match the oracle."""
     w = _small_spheres()
     v, t = w["verts"], w["tris"]
     q = _queries(20000, (-0.5, -0.5, -0.5), (1.5, 1.5, 1.5), 35)
     res = []
-    for sl in (8, 16, 32):
+    for sl in (8, 16, 32, 0):
         res.append(gpu_cpq(gpu_build(v, t, layout, leaf_size=1, stack_lds=sl), q))
     for p, d in res[1:]:
         assert np.array_equal(p, res[0][0]) and np.array_equal(d.view(np.uint32), res[0][1].view(np.uint32))
