@@ -282,7 +282,6 @@ __device__ inline void wave_cp_leaves(const SceneData &ld, const Query &q, bool 
 
 template <class Node>
 struct CpqBin {
-    static constexpr bool kBatchLeaves = false;
     struct State {
         CpqBest best;
         uint32_t cur;       // node to visit next (kRefEmpty: pop one)
@@ -360,6 +359,43 @@ struct CpqBin {
         } else {
             s.cur = kRefEmpty;
         }
+    }
+    // The same step for the whole wave (every lane calls it; `act` lanes have
+    // a query in progress): interior nodes per lane as in step, then the
+    // leaves the lanes reached tested together (wave_cp_leaves).
+    template <int LeafMode, class Stack>
+    __device__ static void wave_step(const void *nodes, const SceneData &ld, const Query &q,
+                                     Stack &st, State &s, uint32_t &nfetch, uint32_t &ntri,
+                                     bool &incomplete, bool act, WaveLeafLds *wl) {
+        bool want = false;
+        uint32_t first = 0, cnt = 0;
+        if (act) {
+            if (s.cur == kRefEmpty) {
+                while (st.sp > 0) {
+                    float d;
+                    const uint32_t i = st.pop(d);
+                    if (d <= s.best.d2) {
+                        float lo[3], hi[3];
+                        uint32_t axis;
+                        Node::load(nodes, i, ld, lo, hi, s.cnt, s.off, axis);
+                        nfetch++;
+                        s.cur = i;
+                        break;
+                    }
+                }
+            }
+            if (s.cur != kRefEmpty) {
+                if (s.cnt > 0) {  // a leaf: its triangles [off, off + cnt)
+                    want = true;
+                    first = s.off;
+                    cnt = s.cnt;
+                    s.cur = kRefEmpty;
+                } else {
+                    step<LeafMode>(nodes, ld, q, st, s, nfetch, ntri, incomplete);
+                }
+            }
+        }
+        wave_cp_leaves<LeafMode>(ld, q, want, first, cnt, s.best, ntri, wl);
     }
 };
 
@@ -453,7 +489,6 @@ template <int Layout>
 struct CpqWide {
     using Ch = WideChildren<Layout>;
     static constexpr int K = Ch::K;
-    static constexpr bool kBatchLeaves = true;
     struct State {
         CpqBest best;
         uint32_t cur;  // tagged child reference to visit next (kRefEmpty: pop one)
@@ -587,9 +622,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_cpq_persist(const void *nodes, 
     using Wk = typename CpqFor<Layout>::type;
     __shared__ uint32_t s_ref[SL * kTraceBlock];
     __shared__ float s_d[SL * kTraceBlock];
-    __shared__ WaveLeafLds s_wl[Wk::kBatchLeaves ? kWavesPerBlock : 1];
+    __shared__ WaveLeafLds s_wl[kWavesPerBlock];
     const uint32_t lane = threadIdx.x & 63u;
-    WaveLeafLds *const wl = s_wl + (Wk::kBatchLeaves ? (threadIdx.x >> 6) : 0u);
+    WaveLeafLds *const wl = s_wl + (threadIdx.x >> 6);
     SpillStack<true, SL> st(s_ref, s_d, sa);
     uint32_t qi = kNoQuery;
     Query q{};
@@ -652,11 +687,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_cpq_persist(const void *nodes, 
             if (drained && pool == pool_end) break;
             continue;
         }
-        if constexpr (Wk::kBatchLeaves) {
+        {  // every lane: the wave's leaves are tested together
             const bool act = qi != kNoQuery && !Wk::done(ws, st);
             Wk::template wave_step<LeafMode>(nodes, ld, q, st, ws, nfetch, ntri, incomplete, act, wl);
-        } else if (qi != kNoQuery && !Wk::done(ws, st)) {
-            Wk::template step<LeafMode>(nodes, ld, q, st, ws, nfetch, ntri, incomplete);
         }
         if (qi != kNoQuery) {
             if (incomplete) {
