@@ -2025,6 +2025,8 @@ int32_t pack_wide(TreeView tv, volatile uint32_t *nleaf_word, int32_t *cand_all,
                                                                            p, info);
     k_wide_place<<<1, kPlaceThreads, 0, s>>>(p, cap, info, hw);
     k_wide_write<Layout><<<grid_for(cap), kBlock, 0, s>>>(tv, cand_all, p, cap, sink, info);
+    // the stack and depth bounds, queued before the host waits for the count
+    k_fold_max_slots<<<1, kBlock, 0, s>>>(tv.stack_slots, tv.depth_slots, info);
     BVH_TRY(check_launch("wide packing"));
     uint32_t base = 0;
     BVH_TRY(wait_host_word(vw, s, &base));
@@ -2918,14 +2920,24 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     // on the side stream: the leaf block's hipMalloc (and the node block's,
     // from the hint) block the host while the queued kernels run, then the
     // leaf kernel overlaps the hierarchy kernels
+    // the point of the stream after which the sorted order is final: the
+    // side stream's leaf data waits for it (and not for the kernels queued
+    // on the build stream after it)
+    bool sorted_marked = false;
+    auto mark_sorted = [&]() -> int32_t {
+        if (!wide || sorted_marked) return BVH_OK;
+        sorted_marked = true;
+        side = side_stream(h->device);
+        if (side) BVH_HIP_TRY(hipEventRecord(side->ready, s));
+        return BVH_OK;
+    };
     auto leaf_data_early = [&]() -> int32_t {
         if (!wide) return BVH_OK;
+        BVH_TRY(mark_sorted());
         BVH_TRY(alloc_leaf_block(h));
         BVH_TRY(alloc_node_block_ahead(h));
         const LeafSource early{verts, n_verts, tris, perm, (uint32_t)n};
-        side = side_stream(h->device);
         if (!side) return emit_leaf_data(h, early, s);
-        BVH_HIP_TRY(hipEventRecord(side->ready, s));
         BVH_HIP_TRY(hipStreamWaitEvent(side->stream, side->ready, 0));
         BVH_TRY(emit_leaf_data(h, early, side->stream));
         BVH_HIP_TRY(hipEventRecord(side->done, side->stream));
@@ -2953,9 +2965,11 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
             cur = sort_morton(pbox, (uint32_t)n, info, mbits, keys, vals, hist, nsort, s);
         BVH_TRY(check_launch("morton/radix sort"));
         perm = vals[cur];
-        BVH_TRY(leaf_data_early());
+        BVH_TRY(mark_sorted());
 
-        // a4 (for the wide layouts, also the leaf count of the collapse)
+        // a4 (for the wide layouts, also the leaf count of the collapse),
+        // queued before the leaf data's allocations so that the GPU does not
+        // wait for them
         if (n > 1) {
             karras_leaves = wide ? bound_slots + 2 * kMaxSlots * kSlotStride : nullptr;
             if (narrow)
@@ -2965,6 +2979,7 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
                 k_karras<<<grid_for(n - 1), kBlock, 0, s>>>(keys[cur], n, ileft, iright, ifirst,
                                                             icount, iaxis, parent, L, karras_leaves);
         }
+        BVH_TRY(leaf_data_early());
     }
     {  // a5
         k_leaf_boxes<<<nb, kBlock, 0, s>>>(pbox, perm, n, nbox, table, pre, suf);
@@ -3091,8 +3106,10 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     } else {
         BVH_TRY(pack_wide<BVH_LAYOUT_BVH8_Q16>(tv, nleaf_word, cand_all, ni_all, info, h, ls, s));
     }
-    k_fold_max_slots<<<1, kBlock, 0, s>>>(tv.stack_slots, tv.depth_slots, info);
-    BVH_TRY(check_launch("stack bound"));
+    if (!wide) {  // pack_wide folds them itself
+        k_fold_max_slots<<<1, kBlock, 0, s>>>(tv.stack_slots, tv.depth_slots, info);
+        BVH_TRY(check_launch("stack bound"));
+    }
     if (side) BVH_HIP_TRY(hipStreamWaitEvent(s, side->done, 0));  // the leaf data is part of the build
     BVH_HIP_TRY(hipMemcpyAsync(pin, info, sizeof(hi), hipMemcpyDeviceToHost, s));
     BVH_HIP_TRY(hipStreamSynchronize(s));
