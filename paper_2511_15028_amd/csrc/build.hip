@@ -1417,7 +1417,6 @@ static_assert(kTopMaxFrontier <= kTopThreads * kPlanItems, "a top level is plann
 constexpr int kSubThreads = 64;       // a subtree: one wave (its scans need no barrier)
 constexpr uint32_t kPlanBlocks = 8192;  // subtree planning: waves, striding over the roots
 constexpr int kPlaceThreads = 1024;
-constexpr uint32_t kWriteLdsRoots = 4096;  // subtree offsets held in LDS for the search
 
 struct WidePlan {
     int32_t *t_node;  // top levels, node i at position i (kTopMaxNodes)
@@ -1656,16 +1655,18 @@ __device__ inline void wide_write(const TreeView &tv, int32_t x, uint32_t aux, u
 }
 
 // One thread per node position (launched for the largest possible count).
+// The subtree offsets (at most K * kTopMaxFrontier) are staged in LDS for the
+// search.
 template <int Layout>
 __global__ __launch_bounds__(kBlock) void k_wide_write(TreeView tv, const int32_t *cand_all,
                                                        WidePlan p, uint32_t cap, NodeSink sink,
                                                        BuildInfo *info) {
     constexpr int K = WideOut<Layout>::K;
-    __shared__ uint32_t s_off[kWriteLdsRoots];
-    const uint32_t base = p.meta[0], roots = p.meta[1], all = p.meta[2];
-    const bool lds = roots <= kWriteLdsRoots;
+    __shared__ uint32_t s_off[K * kTopMaxFrontier];
+    const uint32_t base = p.meta[0], roots = min(p.meta[1], (uint32_t)(K * kTopMaxFrontier)),
+                   all = p.meta[2];
     const uint32_t at = blockIdx.x * kBlock + threadIdx.x;
-    if (lds && blockIdx.x * kBlock < all && (blockIdx.x + 1) * kBlock > base) {
+    if (blockIdx.x * kBlock < all && (blockIdx.x + 1) * kBlock > base) {  // the same in the block
         for (uint32_t b = threadIdx.x; b < roots; b += kBlock) s_off[b] = p.f_off[b];
         __syncthreads();
     }
@@ -1685,9 +1686,9 @@ __global__ __launch_bounds__(kBlock) void k_wide_write(TreeView tv, const int32_
         uint32_t lo = 0, hi = roots;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if ((lds ? s_off[mid] : p.f_off[mid]) <= at) lo = mid; else hi = mid;
+            if (s_off[mid] <= at) lo = mid; else hi = mid;
         }
-        const uint32_t off = lds ? s_off[lo] : p.f_off[lo];
+        const uint32_t off = s_off[lo];
         const uint32_t q = p.f_q0[lo] + (at - off);
         const uint32_t no = p.s_noff[q];
         const int32_t x = p.s_node[q];
