@@ -2122,23 +2122,35 @@ __device__ inline float sah_centroid(const Box &b, int a) {
 // Binning frame of one axis: valid when the centroid extent is positive and
 // finite; then bin(c) = min(31, trunc((c - lo) * scale)), scale = 32 / ext.
 struct SahFrame {
-    float lo[3], scale[3];
-    bool valid[3];
+    float4 lo, scale;  // per axis in x, y, z
+    uint32_t valid;    // bit a: axis a can be binned
+    // the axis is picked among register values, never by indexing memory, so
+    // a run-time axis does not send the frame to scratch memory
+    __device__ bool ok(int a) const { return (valid >> a) & 1u; }
 };
+
+__device__ inline float axis_of(const float4 v, int a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); }
 
 __device__ inline SahFrame sah_frame(const float *cl, const float *ch) {
     SahFrame f;
+    float lo[3], sc[3];
+    f.valid = 0;
+#pragma unroll
     for (int a = 0; a < 3; a++) {
         const float ext = ch[a] - cl[a];
-        f.valid[a] = ext > 0.0f && !isinf(ext);
-        f.lo[a] = cl[a];
-        f.scale[a] = f.valid[a] ? __fdiv_rn((float)kSahBins, ext) : 0.0f;
+        const bool v = ext > 0.0f && !isinf(ext);
+        f.valid |= (v ? 1u : 0u) << a;
+        lo[a] = cl[a];
+        sc[a] = v ? __fdiv_rn((float)kSahBins, ext) : 0.0f;
     }
+    f.lo = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    f.scale = make_float4(sc[0], sc[1], sc[2], 0.0f);
     return f;
 }
 
-__device__ inline int sah_bin(const SahFrame &f, int a, float c) {
-    const int b = (int)((c - f.lo[a]) * f.scale[a]);  // c >= lo: b >= 0 for finite input
+__device__ inline int sah_bin(const SahFrame f, int a, float c) {
+    const float4 lo4 = f.lo, sc4 = f.scale;
+    const int b = (int)((c - axis_of(lo4, a)) * axis_of(sc4, a));  // c >= lo: b >= 0 for finite input
     return b < 0 ? 0 : (b < kSahBins - 1 ? b : kSahBins - 1);
 }
 
@@ -2190,6 +2202,50 @@ __device__ inline void sah_sweep(uint32_t cnt, float lx, float ly, float lz, flo
     best_cost = c;
     best_k = (c < INFINITY && at != 0) ? (int)__builtin_ctzll(at) : -1;
     best_nl = readlane_t(pc, best_k < 0 ? 0 : best_k);
+}
+
+// Two sweeps at once: the bins of one axis in lanes 0-31 and of another in
+// lanes 32-63 (the scans above stay within each half).  Per half: the lowest
+// cost, the lowest bin among equal costs (-1 when no split has a finite
+// cost) and its left count, exactly as sah_sweep gives them for one axis.
+__device__ inline void sah_sweep2(uint32_t cnt, float lx, float ly, float lz, float hx, float hy,
+                                  float hz, float &cost0, int &k0, uint32_t &nl0, float &cost1,
+                                  int &k1, uint32_t &nl1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int hl = lane & (kSahBins - 1);  // the bin in the lane's half
+    const auto add = [](uint32_t x, uint32_t y) { return x + y; };
+    const auto mn = [](float x, float y) { return fminf(x, y); };
+    const auto mx = [](float x, float y) { return fmaxf(x, y); };
+    const uint32_t pc = half_scan<uint32_t>(cnt, 0u, add);
+    const uint32_t sc = half_suffix_scan<uint32_t>(cnt, 0u, add, lane);
+    const float in[6] = {lx, ly, lz, hx, hy, hz};
+    float p[6], q[6];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        p[j] = half_scan<float>(in[j], INFINITY, mn);
+        q[j] = half_suffix_scan<float>(in[j], INFINITY, mn, lane);
+        p[3 + j] = half_scan<float>(in[3 + j], -INFINITY, mx);
+        q[3 + j] = half_suffix_scan<float>(in[3 + j], -INFINITY, mx, lane);
+    }
+    // the right side of split k is the suffix from bin k + 1 (wave_shl:1;
+    // the last bin of each half has no split)
+    const uint32_t rc = dpp<0x130, 0xf>(0u, sc);
+    float r[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) r[j] = dpp<0x130, 0xf>(j < 3 ? INFINITY : -INFINITY, q[j]);
+    float cost = INFINITY;
+    if (hl < kSahBins - 1 && pc > 0 && rc > 0)
+        cost = half_area3(p[0], p[1], p[2], p[3], p[4], p[5]) * (float)pc +
+               half_area3(r[0], r[1], r[2], r[3], r[4], r[5]) * (float)rc;
+    const float m = half_scan<float>(cost, INFINITY, mn);  // each half's minimum at its last lane
+    cost0 = readlane_t(m, kSahBins - 1);
+    cost1 = readlane_t(m, kWave - 1);
+    const uint64_t at = __builtin_amdgcn_ballot_w64(hl < kSahBins - 1 && cost == (lane < kSahBins ? cost0 : cost1));
+    const uint32_t at0 = (uint32_t)at, at1 = (uint32_t)(at >> 32);
+    k0 = (cost0 < INFINITY && at0 != 0) ? (int)__builtin_ctz(at0) : -1;
+    k1 = (cost1 < INFINITY && at1 != 0) ? (int)__builtin_ctz(at1) : -1;
+    nl0 = readlane_t(pc, k0 < 0 ? 0 : k0);
+    nl1 = readlane_t(pc, kSahBins + (k1 < 0 ? 0 : k1));
 }
 
 // Id of the node that splits at leaf position m (m-1 naturally; see above).
@@ -2315,7 +2371,7 @@ __global__ __launch_bounds__(kBlock) void k_sah_bin(SahLevel lv, const uint32_t 
     for (uint32_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
         const Box b = pbox[ord[p]];
         for (int a = 0; a < 3; a++) {
-            if (!f.valid[a]) continue;
+            if (!f.ok(a)) continue;
             int *bin = mine + (a * kSahBins + sah_bin(f, a, sah_centroid(b, a))) * 7;
             atomicAdd(bin, 1);
             atomicMin(bin + 1, f2o(b.lo.x));
@@ -2397,7 +2453,7 @@ __device__ inline void sah_split_node(SahLevel lv, SahTree tr, uint32_t *root_na
     int axis = -1, bk = -1;
     uint32_t nl = 0;
     for (int a = 0; a < 3; a++) {
-        if (!f.valid[a]) continue;
+        if (!f.ok(a)) continue;
         const int *bin = gb + (a * kSahBins + (lane < kSahBins ? lane : 0)) * 7;
         const bool in = lane < kSahBins;
         int wv[7];
@@ -2607,10 +2663,16 @@ __global__ __launch_bounds__(kBlock) void k_sah_small(const SahTask *small, uint
         float best = INFINITY;
         int axis = -1, bk = -1;
         uint32_t nl = 0;
-        for (int a = 0; a < 3; a++) {
-            if (!f.valid[a]) continue;
+        // x and y in one sweep (x's bins in lanes 0-31, y's in lanes 32-63),
+        // then z; the costs are compared in axis order with a strict <, so a
+        // lower axis wins a tie as when the axes are swept one after another
+#pragma unroll
+        for (int pass = 0; pass < 2; pass++) {
+            const int a0 = pass == 0 ? 0 : 2, a1 = pass == 0 ? 1 : -1;
+            const bool v0 = f.ok(a0), v1 = a1 >= 0 && f.ok(a1);
+            if (!v0 && !v1) continue;  // the same in the whole wave
             const int inf = f2o(INFINITY), ninf = f2o(-INFINITY);
-            if (lane < kSahBins) {
+            {  // lane l clears bin l: the low half's axis, then the high half's
                 int *bin = bins + lane * 7;
                 bin[0] = 0;
                 bin[1] = bin[2] = bin[3] = inf;
@@ -2618,31 +2680,42 @@ __global__ __launch_bounds__(kBlock) void k_sah_small(const SahTask *small, uint
             }
             wave_sync();
             if (act) {
-                int *bin = bins + sah_bin(f, a, c[a]) * 7;
-                atomicAdd(bin, 1);
-                atomicMin(bin + 1, f2o(b.lo.x));
-                atomicMin(bin + 2, f2o(b.lo.y));
-                atomicMin(bin + 3, f2o(b.lo.z));
-                atomicMax(bin + 4, f2o(b.hi.x));
-                atomicMax(bin + 5, f2o(b.hi.y));
-                atomicMax(bin + 6, f2o(b.hi.z));
+                const int qlx = f2o(b.lo.x), qly = f2o(b.lo.y), qlz = f2o(b.lo.z);
+                const int qhx = f2o(b.hi.x), qhy = f2o(b.hi.y), qhz = f2o(b.hi.z);
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    if (!(h == 0 ? v0 : v1)) continue;
+                    const int a = h == 0 ? a0 : a1;
+                    const float ca = a == 0 ? c[0] : (a == 1 ? c[1] : c[2]);
+                    int *bin = bins + (h * kSahBins + sah_bin(f, a, ca)) * 7;
+                    atomicAdd(bin, 1);
+                    atomicMin(bin + 1, qlx);
+                    atomicMin(bin + 2, qly);
+                    atomicMin(bin + 3, qlz);
+                    atomicMax(bin + 4, qhx);
+                    atomicMax(bin + 5, qhy);
+                    atomicMax(bin + 6, qhz);
+                }
             }
             wave_sync();
-            const bool in = lane < kSahBins;
-            const int *bin = bins + (in ? lane : 0) * 7;
-            float cost;
-            int k;
-            uint32_t l;
-            sah_sweep(in ? (uint32_t)bin[0] : 0u, in ? o2f(bin[1]) : INFINITY,
-                      in ? o2f(bin[2]) : INFINITY, in ? o2f(bin[3]) : INFINITY,
-                      in ? o2f(bin[4]) : -INFINITY, in ? o2f(bin[5]) : -INFINITY,
-                      in ? o2f(bin[6]) : -INFINITY, cost, k, l);
+            const int *bin = bins + lane * 7;
+            float cost0, cost1;
+            int k0, k1;
+            uint32_t l0, l1;
+            sah_sweep2((uint32_t)bin[0], o2f(bin[1]), o2f(bin[2]), o2f(bin[3]), o2f(bin[4]),
+                       o2f(bin[5]), o2f(bin[6]), cost0, k0, l0, cost1, k1, l1);
             wave_sync();
-            if (cost < best) {
-                best = cost;
-                axis = a;
-                bk = k;
-                nl = l;
+            if (v0 && cost0 < best) {
+                best = cost0;
+                axis = a0;
+                bk = k0;
+                nl = l0;
+            }
+            if (v1 && cost1 < best) {
+                best = cost1;
+                axis = a1;
+                bk = k1;
+                nl = l1;
             }
         }
         bool left;
@@ -2651,7 +2724,7 @@ __global__ __launch_bounds__(kBlock) void k_sah_small(const SahTask *small, uint
             nl = sc / 2;
             left = (uint32_t)lane - sf < nl;
         } else {
-            left = sah_bin(f, axis, c[axis]) <= bk;
+            left = sah_bin(f, axis, axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2])) <= bk;
         }
         const uint32_t m = tk.first + sf + nl;
         const bool is_root = root_task && par < 0;
