@@ -305,6 +305,21 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tile_sums
     if (ntiles > 0) k_scan_final<<<ntiles, kBlock, 0, s>>>(in, out, n, tile_sums);
 }
 
+// The clears at the start of a build, in one launch: the build info and the
+// slot words set to zero, the leaf marks to zero (layouts that mark leaves)
+// and the parent links to -1 (where the topology builder does not write every
+// one of them).
+__global__ __launch_bounds__(kBlock) void k_build_init(BuildInfo *info, uint32_t *slots,
+                                                       uint32_t nslots, uint32_t *mark,
+                                                       uint32_t nmark, int32_t *parent,
+                                                       uint64_t nparent) {
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < sizeof(BuildInfo) / sizeof(uint32_t)) reinterpret_cast<uint32_t *>(info)[i] = 0u;
+    if (i < nslots) slots[i] = 0u;
+    if (i < nmark) mark[i] = 0u;
+    if (i < nparent) parent[i] = -1;
+}
+
 // ---------------------------------------------------------------------------
 // a1: triangle boxes, scene box and centre box
 // ---------------------------------------------------------------------------
@@ -2977,12 +2992,18 @@ int32_t build_impl(const float *verts, int64_t n_verts, const int32_t *tris, int
     }
     BVH_TRY(arena.bind(s, kAreaBuild));
 
-    BVH_HIP_TRY(hipMemsetAsync(info, 0, sizeof(BuildInfo), s));
-    BVH_HIP_TRY(hipMemsetAsync(bound_slots, 0, 3 * kMaxSlots * kSlotStride * sizeof(uint32_t), s));
     const bool wide = h->layout == BVH_LAYOUT_BVH4 || h->layout == BVH_LAYOUT_BVH8_Q8 ||
                       h->layout == BVH_LAYOUT_BVH8_Q16;
-    if (!wide) BVH_HIP_TRY(hipMemsetAsync(mark, 0, sizeof(uint32_t) * n, s));
-    BVH_HIP_TRY(hipMemsetAsync(parent, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), s));
+    {
+        // k_karras writes the parent of every node (the root's too) when n > 1
+        const uint32_t nslots = 3 * kMaxSlots * kSlotStride;
+        const uint32_t nmark = wide ? 0u : (uint32_t)n;
+        const uint64_t nparent =
+            (h->builder == BVH_BUILDER_SAH || n == 1) ? 2 * (uint64_t)n - 1 : 0u;
+        const uint64_t m = std::max<uint64_t>(std::max<uint64_t>(nslots, nmark), nparent);
+        k_build_init<<<grid_for(m), kBlock, 0, s>>>(info, bound_slots, nslots, mark, nmark, parent,
+                                                    nparent);
+    }
 
     // a1, a2
     const uint32_t nbp = (uint32_t)(((uint64_t)n + kPrimItems * kBlock - 1) / (kPrimItems * kBlock));
