@@ -477,7 +477,7 @@ inline int morton_bits(int n) {
 // tile out in local digit order, so consecutive lanes store consecutive
 // addresses of a digit's run.
 // ---------------------------------------------------------------------------
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kSortWaves = kBlock / kWave;
 constexpr int kRadix = 256;
